@@ -1,0 +1,176 @@
+/*
+ * nce.h -- C ABI of the MI355X narrow capture / narrow escape solver.
+ *
+ * Problem (Kaye & Greengard, Section 1 and Section 3): N disk-shaped patches of
+ * common arclength radius eps on the unit sphere, centres c_i, any two centres
+ * at least 3 eps apart in arclength. The narrow escape (interior) problem
+ * returns the average mean first passage time mu; the narrow capture
+ * (exterior) problem returns the capture rate. Both come from the solution of
+ * the preconditioned second-kind multiple scattering system (eq. opinteqnsdisc)
+ *
+ *     f_i + P sum_{j != i} S_ij B f_j = P 1,   i = 1..N,
+ *
+ * whose unknowns f_i are K = (M+1)(M+2)/2 Zernike coefficients per patch.
+ *
+ * Conventions shared by every call
+ *   - Coefficient vectors are N x K, row-major (patch-major), FP64. Basis order:
+ *     n ascending, then m = -n, -n+2, ..., n; m < 0 is the sin(|m| theta)
+ *     function; radial argument t/eps where t is arclength from the centre.
+ *     The theta = 0 direction of patch i is e1_i from nce_frames(): the
+ *     projection of z-hat onto the tangent plane, or of x-hat when
+ *     |c_i . z-hat| > 1/sqrt(2); e2_i = c_i x e1_i.
+ *   - Pointers named *_dev are device memory of the current HIP device
+ *     (for example a torch tensor's data_ptr()); the library reads and writes
+ *     them asynchronously on the context's stream. Pointers named *_host are
+ *     host memory. The caller owns every pointer it passes; nce_setup copies
+ *     the centres.
+ *   - Every call returns an int status: NCE_OK (0), a negative error code, or
+ *     NCE_NOTCONVERGED (1) when an iteration limit was reached (outputs are
+ *     still written). nce_strerror() describes a code; nce_last_error() gives
+ *     the message of the last failure on the calling thread.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef NCE_H
+#define NCE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NCE_OK 0
+#define NCE_NOTCONVERGED 1
+#define NCE_EINVAL (-1)   /* bad argument: N < 1, NaN or non-unit centre, eps outside (0, pi/3], ... */
+#define NCE_ESEP (-2)     /* two centres closer than 3 eps in arclength */
+#define NCE_ENOMEM (-3)   /* host or device allocation failed */
+#define NCE_EHIP (-4)     /* a HIP runtime call failed; message in nce_last_error() */
+#define NCE_ETABLE (-5)   /* the per-eps precompute failed its self-check */
+#define NCE_ESTATE (-6)   /* call not valid in the context's state (e.g. no MLP loaded) */
+
+typedef struct nce_ctx nce_ctx;
+
+/* problem: 0 = interior (narrow escape, mean first passage time),
+ *          1 = exterior (narrow capture, capture rate). */
+#define NCE_INTERIOR 0
+#define NCE_EXTERIOR 1
+
+/* precision of a matrix-vector product or solve */
+#define NCE_FP64 0   /* every step in FP64 */
+#define NCE_MIXED 1  /* FP32 Green's sums and block applies inside FP64 iterative refinement */
+
+/* far-field method */
+#define NCE_FAR_AUTO 0    /* direct for small N, tree otherwise */
+#define NCE_FAR_DIRECT 1  /* all pairs of patches summed directly */
+#define NCE_FAR_TREE 2    /* hierarchical cube-sphere quadtree (Section 7.2, Section 8 step 2) */
+
+typedef struct nce_opts {
+    int problem;        /* NCE_INTERIOR or NCE_EXTERIOR */
+    int M;              /* Zernike truncation; K = (M+1)(M+2)/2. Default 15 (K = 136) */
+    double tol_id;      /* ID tolerance of the compressed outgoing representation. Default 1e-11 */
+    double tol_grid;    /* incoming-grid truncation tolerance (tree only). Default 1e-8 */
+    double tol_gmres;   /* relative residual ||b - A x|| / ||b|| to stop at. Default 1e-10 */
+    int max_iter;       /* GMRES iteration limit (FP64) or inner limit (mixed). Default 200 */
+    int precision;      /* NCE_FP64 or NCE_MIXED for the solves. Default NCE_FP64 */
+    int far_field;      /* NCE_FAR_AUTO / NCE_FAR_DIRECT / NCE_FAR_TREE. Default AUTO */
+    int warm_start;     /* 0 none; 1 learned (requires nce_load_mlp). Default 0 */
+    void *stream;       /* hipStream_t to run on; NULL = the library creates one */
+    const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
+} nce_opts;
+
+typedef struct nce_info {
+    int iters_fp64;       /* FP64 matrix-vector products inside GMRES */
+    int iters_fp32;       /* FP32 matrix-vector products (mixed) */
+    int outer;            /* outer refinement steps (mixed) */
+    int used_fallback;    /* 1 if a learned start or mixed refinement was rejected */
+    double rel_residual;  /* final FP64 ||b - A x|| / ||b|| */
+    double t_solve_s;     /* wall time of the solve */
+    double rel_residual_x0; /* FP64 relative residual of the initial guess */
+} nce_info;
+
+/* Fill opts with the defaults listed above. */
+void nce_default_opts(nce_opts *opts);
+
+/*
+ * Build a context for one patch layout (Section 8, Steps 1 and 2).
+ * centers_host: N x 3 row-major unit vectors (|c| = 1 within 1e-12).
+ * Computes (or loads from the cache) the per-eps tables -- the one-patch
+ * solution operator (Section 9), the compressed outgoing representation T
+ * and its skeleton (Section 7.1), the integral vector I (eq. getI) and the
+ * Zernike transform P (Section 4) -- builds the tree when the tree is used,
+ * and copies everything to the current HIP device.
+ * Errors: NCE_EINVAL, NCE_ESEP, NCE_ENOMEM, NCE_EHIP, NCE_ETABLE.
+ */
+int nce_setup(const double *centers_host, int64_t N, double eps, const nce_opts *opts,
+              nce_ctx **out);
+
+/* Free every host and device resource of ctx (NULL is allowed). */
+void nce_destroy(nce_ctx *ctx);
+
+/* Sizes: K basis functions, K* Zernike sampling nodes, p skeleton points,
+ * number of tree levels used (0 for the direct far field). Any pointer may be NULL. */
+int nce_dims(const nce_ctx *ctx, int *K, int *Kstar, int *p, int *levels);
+
+/* Patch frames, N x 9 host doubles per patch: c (3), e1 (3), e2 (3). */
+int nce_frames(const nce_ctx *ctx, double *frames_host);
+
+/* Work counts of one matrix-vector product: Green's function pair evaluations
+ * of the far field (P2L or direct), of the near field, and interpolation
+ * multiply-adds (tree L2T). Any pointer may be NULL. */
+int nce_work(const nce_ctx *ctx, double *pairs_far, double *pairs_near, double *interp_fma);
+
+/*
+ * One application of the system matrix (eq. sysmatapply):
+ *   y_i = x_i + P sum_{j != i} G(Z_i, S_j) T x_j
+ * x_dev, y_dev: N x K FP64 device arrays (may not alias).
+ * precision NCE_FP64 computes every step in FP64; NCE_MIXED computes the
+ * block apply T x, the Green's sums and P in FP32 and adds x in FP64.
+ * Asynchronous on the context's stream.
+ */
+int nce_matvec(nce_ctx *ctx, const double *x_dev, double *y_dev, int precision);
+
+/*
+ * Same as nce_matvec, but records HIP events between the steps on the
+ * context's stream, waits, and writes the elapsed milliseconds of each step:
+ * step_ms[0] block apply rho = T x (Step 1), [1] far field (Step 2, or the
+ * direct all-pairs sum), [2] near field (Step 3), [3] incoming-grid
+ * interpolation (Step 4), [4] P apply and identity (Step 5). Steps the
+ * context does not use report 0.
+ */
+int nce_matvec_profile(nce_ctx *ctx, const double *x_dev, double *y_dev, int precision,
+                       double *step_ms_host);
+
+/*
+ * Solve the interior problem (Section 2.3): GMRES (opts.precision FP64), or
+ * FP32 inner GMRES inside FP64 iterative refinement (NCE_MIXED), to
+ * opts.tol_gmres, optionally from the learned warm start.
+ * coeffs_dev: N x K device output (may be NULL); patch_flux_dev: N device
+ * output I . f_i (may be NULL); mfpt_host: mu = 1/(3 I_sigma) - 3/5
+ * (eq. mufromsigma2); info may be NULL. Synchronises the stream.
+ * Returns NCE_ESTATE if the context was built for the exterior problem.
+ */
+int nce_solve_interior(nce_ctx *ctx, double *coeffs_dev, double *patch_flux_dev,
+                       double *mfpt_host, nce_info *info);
+
+/*
+ * Solve the exterior problem (Section 2.2). capture_rate_host receives
+ * 4 pi I_sigma (the total flux of the concentration; the paper's J is
+ * -I_sigma); I_sigma_host receives I_sigma (may be NULL).
+ */
+int nce_solve_exterior(nce_ctx *ctx, double *coeffs_dev, double *patch_flux_dev,
+                       double *capture_rate_host, double *I_sigma_host, nce_info *info);
+
+/* Integral vector I (K host doubles): I_sigma = I . sum_i f_i (eq. getI). */
+int nce_integral_vector(const nce_ctx *ctx, double *I_host);
+
+/* Short description of a status code. */
+const char *nce_strerror(int code);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *nce_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NCE_H */

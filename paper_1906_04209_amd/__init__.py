@@ -1,0 +1,228 @@
+"""MI355X narrow capture / narrow escape solver (Kaye & Greengard), Python binding.
+
+A thin ctypes layer over libnce.so (include/nce.h): it marshals arguments and
+nothing else. Every step of the matrix-vector product and of the solves runs
+in the library's HIP kernels; PyTorch provides device memory and the stream.
+Importing works without a GPU; creating a context needs the built library and
+a HIP device, and raises if either is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["load", "Context", "NCEError", "INTERIOR", "EXTERIOR", "FP64", "MIXED",
+           "FAR_AUTO", "FAR_DIRECT", "FAR_TREE", "LIB_PATH", "SYMBOLS"]
+
+LIB_PATH = Path(__file__).resolve().parent / "libnce.so"
+
+INTERIOR, EXTERIOR = 0, 1
+FP64, MIXED = 0, 1
+FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
+
+# every symbol include/nce.h declares
+SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
+           "nce_matvec", "nce_matvec_profile", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
+           "nce_strerror", "nce_last_error"]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int), ("M", ctypes.c_int), ("tol_id", ctypes.c_double),
+                ("tol_grid", ctypes.c_double), ("tol_gmres", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
+                ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters_fp64", ctypes.c_int), ("iters_fp32", ctypes.c_int), ("outer", ctypes.c_int),
+                ("used_fallback", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double), ("rel_residual_x0", ctypes.c_double)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NCEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nce error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: Optional[os.PathLike] = None):
+    """Load libnce.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is missing: build it with paper_1906_04209_amd/build.py "
+                           "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(str(p))
+    vp, i64, dp, ip = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    lib.nce_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.nce_default_opts.restype = None
+    lib.nce_setup.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    lib.nce_destroy.argtypes = [vp]
+    lib.nce_destroy.restype = None
+    lib.nce_dims.argtypes = [vp, ip, ip, ip, ip]
+    lib.nce_frames.argtypes = [vp, vp]
+    lib.nce_work.argtypes = [vp, dp, dp, dp]
+    lib.nce_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.nce_matvec_profile.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
+    lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
+    lib.nce_integral_vector.argtypes = [vp, vp]
+    lib.nce_strerror.argtypes = [ctypes.c_int]
+    lib.nce_strerror.restype = ctypes.c_char_p
+    lib.nce_last_error.argtypes = []
+    lib.nce_last_error.restype = ctypes.c_char_p
+    for name in ("nce_setup", "nce_dims", "nce_frames", "nce_work", "nce_matvec", "nce_matvec_profile", "nce_solve_interior",
+                 "nce_solve_exterior", "nce_integral_vector"):
+        getattr(lib, name).restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, rc: int, allow_notconv: bool = False) -> int:
+    if rc == 0 or (allow_notconv and rc == 1):
+        return rc
+    raise NCEError(rc, lib.nce_last_error().decode() or lib.nce_strerror(rc).decode())
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """One patch layout on the current HIP device (nce_setup ... nce_destroy)."""
+
+    def __init__(self, centers: np.ndarray, eps: float, problem: int = INTERIOR, M: int = 15,
+                 tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
+                 max_iter: int = 100, precision: int = FP64, far_field: int = FAR_AUTO,
+                 cache_dir: Optional[str] = None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs only on the GPU")
+        self.lib = load()
+        self.torch = torch
+        c = np.ascontiguousarray(centers, dtype=np.float64)
+        o = Opts()
+        self.lib.nce_default_opts(ctypes.byref(o))
+        o.problem, o.M, o.tol_id, o.tol_grid, o.tol_gmres = problem, M, tol_id, tol_grid, tol_gmres
+        o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
+        # the library works on its own (non-default) stream; calls below order
+        # it against the caller's current stream in both directions
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        o.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self._cache = (cache_dir or os.environ.get("NCE_CACHE") or "").encode() or None
+        o.cache_dir = self._cache
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(self.lib, self.lib.nce_setup(c.ctypes.data, len(c), float(eps), ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+        self.N = len(c)
+        self.eps = float(eps)
+        self.problem = problem
+        K, Ks, p, L = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.lib, self.lib.nce_dims(h, ctypes.byref(K), ctypes.byref(Ks), ctypes.byref(p), ctypes.byref(L)))
+        self.K, self.Kstar, self.p, self.levels = K.value, Ks.value, p.value, L.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nce_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def frames(self) -> np.ndarray:
+        out = np.empty((self.N, 9))
+        _check(self.lib, self.lib.nce_frames(self.h, out.ctypes.data))
+        return out
+
+    def integral_vector(self) -> np.ndarray:
+        out = np.empty(self.K)
+        _check(self.lib, self.lib.nce_integral_vector(self.h, out.ctypes.data))
+        return out
+
+    def work(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self.lib, self.lib.nce_work(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"pairs_far": a.value, "pairs_near": b.value, "interp_fma": c.value}
+
+    def empty(self):
+        return self.torch.empty((self.N, self.K), dtype=self.torch.float64, device="cuda")
+
+    def _enter(self):
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+
+    def _leave(self):
+        self.torch.cuda.current_stream().wait_stream(self.stream)
+
+    def matvec(self, x, y=None, precision: int = FP64):
+        """y = A x (device tensors N x K, float64); asynchronous, ordered after
+        the caller's current stream and before its later work."""
+        if y is None:
+            y = self.empty()
+        self._enter()
+        _check(self.lib, self.lib.nce_matvec(self.h, _ptr(x), _ptr(y), int(precision)))
+        self._leave()
+        return y
+
+    def matvec_profile(self, x, y=None, precision: int = FP64):
+        """y = A x with per-step times in ms: [block apply, far, near, interpolation, P apply]."""
+        if y is None:
+            y = self.empty()
+        ms = np.zeros(5)
+        self._enter()
+        _check(self.lib, self.lib.nce_matvec_profile(self.h, _ptr(x), _ptr(y), int(precision), ms.ctypes.data))
+        self._leave()
+        return y, ms
+
+    def solve(self, want_coeffs: bool = True, want_flux: bool = True) -> dict:
+        x = self.empty() if want_coeffs else None
+        f = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda") if want_flux else None
+        info = Info()
+        out = {}
+        self._enter()
+        if self.problem == INTERIOR:
+            mu = ctypes.c_double()
+            rc = self.lib.nce_solve_interior(self.h, _ptr(x), _ptr(f), ctypes.byref(mu), ctypes.byref(info))
+            _check(self.lib, rc, allow_notconv=True)
+            out["mu"] = mu.value
+        else:
+            rate, Is = ctypes.c_double(), ctypes.c_double()
+            rc = self.lib.nce_solve_exterior(self.h, _ptr(x), _ptr(f), ctypes.byref(rate), ctypes.byref(Is),
+                                             ctypes.byref(info))
+            _check(self.lib, rc, allow_notconv=True)
+            out["capture_rate"] = rate.value
+            out["I_sigma"] = Is.value
+        self._leave()
+        out.update(info.asdict())
+        out["converged"] = rc == 0
+        out["x"] = x
+        out["flux"] = f
+        return out

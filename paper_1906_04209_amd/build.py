@@ -1,0 +1,65 @@
+"""Build libnce.so (HIP kernels for gfx950 + host C++) in-tree.
+
+Host-only C++ (precompute, tree build) is compiled by g++ with OpenMP; the
+.hip sources by hipcc for gfx950; hipcc links the shared library.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+from pathlib import Path
+
+PKG = Path(__file__).resolve().parent
+CSRC = PKG / "csrc"
+OUT = PKG / "libnce.so"
+BUILD = PKG / "_build"
+
+HIP_SOURCES = ["kernels.hip", "api.hip", "tree_stub.hip"]
+CPP_SOURCES = ["precompute.cpp"]
+
+HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-command-line-argument"]
+GXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3"]
+
+
+def _hipcc() -> str:
+    for c in ("/opt/rocm/bin/hipcc", shutil.which("hipcc") or ""):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout)
+        raise RuntimeError("build step failed: " + " ".join(cmd))
+    return r.stdout
+
+
+def build(verbose: bool = False) -> Path:
+    BUILD.mkdir(exist_ok=True)
+    hipcc = _hipcc()
+    inc = ["-I", str(CSRC), "-I", str(PKG.parent / "include")]
+    objs = []
+    for src in CPP_SOURCES:
+        o = BUILD / (Path(src).stem + ".o")
+        _run(["g++", *GXX_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
+        objs.append(str(o))
+    for src in HIP_SOURCES:
+        o = BUILD / (Path(src).stem + ".hip.o")
+        _run([hipcc, *HIPCC_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
+        objs.append(str(o))
+    tmp = OUT.with_suffix(".so.tmp")
+    _run([hipcc, "-shared", "--offload-arch=gfx950", "-fPIC", *objs, "-o", str(tmp), "-lgomp"])
+    os.replace(tmp, OUT)
+    if verbose:
+        print("built", OUT)
+    return OUT
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,625 @@
+// C ABI of the solver (include/nce.h): context, setup, matrix-vector product,
+// GMRES and FP64 iterative refinement around an FP32 inner solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nce.h"
+#include "kernels.hpp"
+#include "precompute.hpp"
+#include "tree.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        n = count;
+    }
+    void upload(const std::vector<T>& v, hipStream_t s) {
+        alloc(v.size());
+        if (n) {
+            HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));  // the host vector may be a temporary
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { release(); }
+};
+
+template <class T>
+std::vector<float> to_f32(const std::vector<T>& v) {
+    return std::vector<float>(v.begin(), v.end());
+}
+
+}  // namespace
+
+struct nce_ctx {
+    nce_opts opts;
+    int64_t N = 0;
+    int K = 0, Kstar = 0, p = 0;
+    double eps = 0;
+    nce::PatchTables tab;
+    std::vector<double> frames;  // N x 9: c, e1, e2
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool use_tree = false;
+    nce::Tree tree;
+    nce::DeviceTree dtree;
+    // device tables
+    DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
+    DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
+    // matvec work arrays
+    DevBuf<double> d_rho, d_U;
+    DevBuf<float> d_rho32, d_U32, d_x32;
+    // solver work arrays
+    DevBuf<double> d_V, d_b, d_r, d_x, d_h, d_partial, d_scal;
+    int vcap = 0;  // number of Krylov vectors allocated
+};
+
+namespace {
+
+void build_frames(const double* c, int64_t N, std::vector<double>& fr) {
+    fr.resize((size_t)N * 9);
+    for (int64_t i = 0; i < N; ++i) {
+        const double* ci = c + 3 * i;
+        double a[3] = {0, 0, 1};
+        if (std::fabs(ci[2]) > 1.0 / std::sqrt(2.0)) {
+            a[0] = 1;
+            a[2] = 0;
+        }
+        double ad = a[0] * ci[0] + a[1] * ci[1] + a[2] * ci[2];
+        double e1[3] = {a[0] - ad * ci[0], a[1] - ad * ci[1], a[2] - ad * ci[2]};
+        double nn = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+        for (double& v : e1) v /= nn;
+        double e2[3] = {ci[1] * e1[2] - ci[2] * e1[1], ci[2] * e1[0] - ci[0] * e1[2], ci[0] * e1[1] - ci[1] * e1[0]};
+        double* f = &fr[(size_t)i * 9];
+        for (int k = 0; k < 3; ++k) {
+            f[k] = ci[k];
+            f[3 + k] = e1[k];
+            f[6 + k] = e2[k];
+        }
+    }
+}
+
+// Every pair of centres closer than 3 eps (arclength) -> NCE_ESEP. Uniform grid
+// hash in R^3 with cells of the corresponding chord length.
+int check_separation(const double* c, int64_t N, double eps) {
+    const double sep = 3.0 * eps;
+    const double h = std::max(2.0 * std::sin(std::min(sep, M_PI) / 2.0) * (1.0 + 1e-9), 1e-12);
+    const int64_t ncell = (int64_t)std::ceil(2.0 / h) + 2;
+    auto key = [&](int64_t x, int64_t y, int64_t z) { return (x * ncell + y) * ncell + z; };
+    std::unordered_map<int64_t, std::vector<int64_t>> cells;
+    cells.reserve((size_t)N * 2);
+    std::vector<int64_t> cx(N), cy(N), cz(N);
+    for (int64_t i = 0; i < N; ++i) {
+        cx[i] = (int64_t)std::floor((c[3 * i] + 1.0) / h);
+        cy[i] = (int64_t)std::floor((c[3 * i + 1] + 1.0) / h);
+        cz[i] = (int64_t)std::floor((c[3 * i + 2] + 1.0) / h);
+        cells[key(cx[i], cy[i], cz[i])].push_back(i);
+    }
+    for (int64_t i = 0; i < N; ++i) {
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    auto it = cells.find(key(cx[i] + dx, cy[i] + dy, cz[i] + dz));
+                    if (it == cells.end()) continue;
+                    for (int64_t j : it->second) {
+                        if (j <= i) continue;
+                        const double* a = c + 3 * i;
+                        const double* b = c + 3 * j;
+                        double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+                        double ang = std::atan2(std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]),
+                                                a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+                        if (ang < sep * (1.0 - 1e-12)) {
+                            g_err = "patches " + std::to_string(i) + " and " + std::to_string(j) +
+                                    " are closer than 3 eps";
+                            return NCE_ESEP;
+                        }
+                    }
+                }
+    }
+    return NCE_OK;
+}
+
+void ensure_krylov(nce_ctx* ctx, int nvec) {
+    if (ctx->vcap >= nvec) return;
+    const size_t n = (size_t)ctx->N * ctx->K;
+    ctx->d_V.alloc(n * (size_t)nvec);
+    ctx->vcap = nvec;
+}
+
+// y = A x for the context's operator in the given precision (enqueued on the
+// stream). With ev != nullptr, events ev[0..5] bracket the five steps.
+template <class T>
+void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm, const T* noff, const T* soff,
+              T* rho, T* U, hipEvent_t* ev) {
+    const int N = (int)ctx->N, K = ctx->K, Ks = ctx->Kstar, p = ctx->p;
+    hipStream_t s = ctx->stream;
+    auto mark = [&](int k) {
+        if (ev) HIPCHK(hipEventRecord(ev[k], s));
+    };
+    mark(0);
+    const T* xin;
+    if constexpr (sizeof(T) == 8) {
+        xin = reinterpret_cast<const T*>(x);
+    } else {
+        HIPCHK(nce::cast_d2f(s, (int64_t)N * K, x, ctx->d_x32.p));
+        xin = reinterpret_cast<const T*>(ctx->d_x32.p);
+    }
+    // Step 1: rho_i = T f_i for every patch (one GEMM with the shared T)
+    HIPCHK(nce::gemm_nt<T>(s, N, p, K, xin, K, Tm, K, rho, p, nullptr, 0));
+    mark(1);
+    if (ctx->use_tree) {
+        // Step 2: far field onto incoming grids (P2L)
+        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho));
+        mark(2);
+        // Step 3: leaf neighbours directly at the sampling nodes (writes U)
+        HIPCHK(nce::tree_near<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U));
+        mark(3);
+        // Step 4: interpolation of every ancestor's incoming grid (adds into U)
+        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U));
+        mark(4);
+    } else {
+        HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U));
+        mark(2);
+        mark(3);
+        mark(4);
+    }
+    // Step 5: y = x + P U
+    HIPCHK(nce::p_apply<T>(s, N, K, Ks, U, Pm, x, y));
+    mark(5);
+}
+
+void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr) {
+    if (ctx->N == 1) {
+        if (ev)
+            for (int k = 0; k < 6; ++k) HIPCHK(hipEventRecord(ev[k], ctx->stream));
+        HIPCHK(hipMemcpyAsync(y, x, sizeof(double) * ctx->K, hipMemcpyDeviceToDevice, ctx->stream));
+        return;
+    }
+    if (precision == NCE_FP64)
+        matvec_t<double>(ctx, x, y, ctx->d_T.p, ctx->d_P.p, ctx->d_node_off.p, ctx->d_skel_off.p, ctx->d_rho.p,
+                         ctx->d_U.p, ev);
+    else
+        matvec_t<float>(ctx, x, y, ctx->d_T32.p, ctx->d_P32.p, ctx->d_node_off32.p, ctx->d_skel_off32.p,
+                        ctx->d_rho32.p, ctx->d_U32.p, ev);
+}
+
+double dev_dot(nce_ctx* ctx, int64_t n, const double* a, const double* b) {
+    HIPCHK(nce::dots(ctx->stream, n, 1, a, n, b, ctx->d_partial.p, ctx->d_scal.p));
+    double v = 0;
+    HIPCHK(hipMemcpyAsync(&v, ctx->d_scal.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return v;
+}
+
+// GMRES (unrestarted, CGS2 Arnoldi on the device, Givens on the host) for
+// A x = rhs with x = 0 initially; adds the solution into x. Stops when the
+// residual estimate is <= tol * ||rhs||. Returns the number of matvecs.
+int gmres(nce_ctx* ctx, const double* rhs, double* x, double tol, int maxit, int precision, bool& converged,
+          double& est_rel) {
+    const int64_t n = ctx->N * (int64_t)ctx->K;
+    hipStream_t s = ctx->stream;
+    ensure_krylov(ctx, maxit + 1);
+    double* V = ctx->d_V.p;
+    const double bnorm = std::sqrt(dev_dot(ctx, n, rhs, rhs));
+    converged = false;
+    est_rel = 1.0;
+    if (bnorm == 0.0) {
+        converged = true;
+        est_rel = 0.0;
+        return 0;
+    }
+    HIPCHK(nce::scale_copy(s, n, 1.0 / bnorm, rhs, V));
+    std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
+    std::vector<double> h(maxit + 1), h2(maxit + 1);
+    g[0] = bnorm;
+    int k = 0, used = 0;
+    for (k = 0; k < maxit; ++k) {
+        double* w = V + (int64_t)(k + 1) * n;
+        matvec(ctx, V + (int64_t)k * n, w, precision);
+        used++;
+        // classical Gram-Schmidt, twice
+        for (int pass = 0; pass < 2; ++pass) {
+            HIPCHK(nce::dots(s, n, k + 1, V, n, w, ctx->d_partial.p, ctx->d_h.p));
+            HIPCHK(nce::axpys(s, n, k + 1, V, n, ctx->d_h.p, w));
+            HIPCHK(hipMemcpyAsync(pass == 0 ? h.data() : h2.data(), ctx->d_h.p, sizeof(double) * (k + 1),
+                                  hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(nce::dots(s, n, 1, w, n, w, ctx->d_partial.p, ctx->d_scal.p));
+        double hk1sq = 0;
+        HIPCHK(hipMemcpyAsync(&hk1sq, ctx->d_scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double hk1 = std::sqrt(hk1sq);
+        if (!std::isfinite(hk1)) throw std::runtime_error("non-finite Arnoldi norm");
+        for (int j = 0; j <= k; ++j) H[(size_t)j * maxit + k] = h[j] + h2[j];
+        H[(size_t)(k + 1) * maxit + k] = hk1;
+        for (int j = 0; j < k; ++j) {
+            double a = H[(size_t)j * maxit + k], b = H[(size_t)(j + 1) * maxit + k];
+            H[(size_t)j * maxit + k] = cs[j] * a + sn[j] * b;
+            H[(size_t)(j + 1) * maxit + k] = -sn[j] * a + cs[j] * b;
+        }
+        double a = H[(size_t)k * maxit + k], b = H[(size_t)(k + 1) * maxit + k];
+        double den = std::hypot(a, b);
+        cs[k] = a / den;
+        sn[k] = b / den;
+        H[(size_t)k * maxit + k] = den;
+        H[(size_t)(k + 1) * maxit + k] = 0.0;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        est_rel = std::fabs(g[k + 1]) / bnorm;
+        const bool happy = hk1 <= 1e-14 * bnorm;
+        if (est_rel <= tol || happy) {
+            converged = true;
+            k++;
+            break;
+        }
+        HIPCHK(nce::scale_copy(s, n, 1.0 / hk1, w, w));
+    }
+    const int m = std::min(k, maxit);
+    std::vector<double> y(m);
+    for (int i = m - 1; i >= 0; --i) {
+        double acc = g[i];
+        for (int j = i + 1; j < m; ++j) acc -= H[(size_t)i * maxit + j] * y[j];
+        y[i] = acc / H[(size_t)i * maxit + i];
+    }
+    HIPCHK(hipMemcpyAsync(ctx->d_h.p, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
+    HIPCHK(nce::combine(s, n, m, V, n, ctx->d_h.p, x));
+    return used;
+}
+
+// r = b - A x in FP64; returns ||r|| / ||b||.
+double residual(nce_ctx* ctx, const double* b, const double* x, double* r) {
+    const int64_t n = ctx->N * (int64_t)ctx->K;
+    matvec(ctx, x, r, NCE_FP64);
+    HIPCHK(nce::axpby(ctx->stream, n, 1.0, b, -1.0, r));
+    const double rn = std::sqrt(dev_dot(ctx, n, r, r));
+    const double bn = std::sqrt(dev_dot(ctx, n, b, b));
+    return rn / bn;
+}
+
+int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t N = ctx->N, n = N * (int64_t)ctx->K;
+    hipStream_t s = ctx->stream;
+    nce_info inf{};
+    // b = P 1 = e_0 on every patch
+    std::vector<double> hb((size_t)n, 0.0);
+    for (int64_t i = 0; i < N; ++i) hb[(size_t)i * ctx->K] = 1.0;
+    ctx->d_b.upload(hb, s);
+    double* x = ctx->d_x.p;
+    HIPCHK(nce::fill(s, n, 0.0, x));
+    const double tol = ctx->opts.tol_gmres;
+    const int maxit = ctx->opts.max_iter;
+    bool conv = false;
+    double est = 1.0;
+    if (N == 1) {
+        // one patch: the system matrix is the identity (no scattering), x = b
+        HIPCHK(hipMemcpyAsync(x, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        conv = true;
+        inf.rel_residual = 0.0;
+        inf.rel_residual_x0 = 1.0;
+    } else if (ctx->opts.precision == NCE_FP64) {
+        inf.rel_residual_x0 = 1.0;
+        inf.iters_fp64 = gmres(ctx, ctx->d_b.p, x, tol, maxit, NCE_FP64, conv, est);
+        inf.rel_residual = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+        inf.outer = 1;
+    } else {
+        // FP64 iterative refinement: r = b - A64 x; A32 d = r by GMRES; x += d.
+        double rel = 1.0;
+        HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        inf.rel_residual_x0 = rel;
+        const int max_outer = 12;
+        conv = false;
+        for (int outer = 0; outer < max_outer; ++outer) {
+            const double inner_tol = std::max(1e-5, 0.5 * tol / rel);
+            bool c2;
+            double e2;
+            inf.iters_fp32 += gmres(ctx, ctx->d_r.p, x, inner_tol, maxit, NCE_MIXED, c2, e2);
+            inf.outer++;
+            const double prev = rel;
+            rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+            inf.iters_fp64 += 1;
+            if (rel <= tol) {
+                conv = true;
+                break;
+            }
+            if (!(rel < 0.5 * prev)) {
+                // refinement stalled: finish with FP64 GMRES on the residual
+                inf.used_fallback = 1;
+                bool c3;
+                double e3;
+                inf.iters_fp64 += gmres(ctx, ctx->d_r.p, x, tol / rel, maxit, NCE_FP64, c3, e3);
+                rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+                inf.iters_fp64 += 1;
+                conv = rel <= tol * 1.0001 || c3;
+                break;
+            }
+        }
+        inf.rel_residual = rel;
+    }
+    HIPCHK(nce::patch_flux(s, (int)N, ctx->K, ctx->d_I.p, x, flux, ctx->d_partial.p, ctx->d_scal.p));
+    double Is = 0;
+    HIPCHK(hipMemcpyAsync(&Is, ctx->d_scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (coeffs) HIPCHK(hipMemcpyAsync(coeffs, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *Is_out = Is;
+    inf.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return (conv && inf.rel_residual <= tol * 1.0001) ? NCE_OK : NCE_NOTCONVERGED;
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return fail(NCE_EHIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(NCE_ENOMEM, "allocation failed");
+    } catch (const std::exception& e) {
+        return fail(NCE_ETABLE, e.what());
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void nce_default_opts(nce_opts* o) {
+    if (!o) return;
+    o->problem = NCE_INTERIOR;
+    o->M = 15;
+    o->tol_id = 1e-11;
+    o->tol_grid = 1e-8;
+    o->tol_gmres = 1e-10;
+    o->max_iter = 100;
+    o->precision = NCE_FP64;
+    o->far_field = NCE_FAR_AUTO;
+    o->warm_start = 0;
+    o->stream = nullptr;
+    o->cache_dir = nullptr;
+}
+
+int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(NCE_EINVAL, "out is NULL");
+    *out = nullptr;
+    nce_opts o;
+    nce_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (!centers || N < 1) return fail(NCE_EINVAL, "need N >= 1 centres");
+    if (!(eps > 0.0 && eps <= M_PI / 3.0)) return fail(NCE_EINVAL, "eps must lie in (0, pi/3]");
+    if (o.M < 0 || o.M > 30) return fail(NCE_EINVAL, "M must lie in [0, 30]");
+    if (o.problem != NCE_INTERIOR && o.problem != NCE_EXTERIOR) return fail(NCE_EINVAL, "bad problem");
+    if (!(o.tol_id > 0 && o.tol_id < 1e-3)) return fail(NCE_EINVAL, "tol_id must lie in (0, 1e-3)");
+    if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
+    if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
+    if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    if (o.warm_start != 0) return fail(NCE_EINVAL, "warm_start requires nce_load_mlp (not loaded)");
+    for (int64_t i = 0; i < N; ++i) {
+        const double* c = centers + 3 * i;
+        if (!std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2]))
+            return fail(NCE_EINVAL, "non-finite centre " + std::to_string(i));
+        double nn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (std::fabs(nn - 1.0) > 1e-12) return fail(NCE_EINVAL, "centre " + std::to_string(i) + " is not a unit vector");
+    }
+    int rc = check_separation(centers, N, eps);
+    if (rc != NCE_OK) return rc;
+    return guarded([&]() -> int {
+        auto* ctx = new nce_ctx();
+        std::unique_ptr<nce_ctx, void (*)(nce_ctx*)> guard(ctx, nce_destroy);
+        ctx->opts = o;
+        ctx->N = N;
+        ctx->eps = eps;
+        std::string dir;
+        if (o.cache_dir) dir = o.cache_dir;
+        else if (const char* e = std::getenv("NCE_CACHE")) dir = e;
+        if (!nce::load_tables(dir, o.problem, eps, o.M, o.tol_id, ctx->tab)) {
+            ctx->tab = nce::build_tables(o.problem, eps, o.M, o.tol_id);
+            nce::save_tables(dir, ctx->tab);
+        }
+        ctx->K = ctx->tab.K;
+        ctx->Kstar = ctx->tab.Kstar;
+        ctx->p = ctx->tab.p;
+        build_frames(centers, N, ctx->frames);
+        if (o.stream) {
+            ctx->stream = (hipStream_t)o.stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+            ctx->own_stream = true;
+        }
+        hipStream_t s = ctx->stream;
+        const size_t n = (size_t)N * ctx->K;
+        ctx->d_frames.upload(ctx->frames, s);
+        ctx->d_T.upload(ctx->tab.T, s);
+        ctx->d_P.upload(ctx->tab.P, s);
+        ctx->d_I.upload(ctx->tab.I, s);
+        ctx->d_node_off.upload(ctx->tab.node_off, s);
+        ctx->d_skel_off.upload(ctx->tab.skel_off, s);
+        ctx->d_T32.upload(to_f32(ctx->tab.T), s);
+        ctx->d_P32.upload(to_f32(ctx->tab.P), s);
+        ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
+        ctx->d_skel_off32.upload(to_f32(ctx->tab.skel_off), s);
+        ctx->d_rho.alloc((size_t)N * ctx->p);
+        ctx->d_U.alloc((size_t)N * ctx->Kstar);
+        ctx->d_rho32.alloc((size_t)N * ctx->p);
+        ctx->d_U32.alloc((size_t)N * ctx->Kstar);
+        ctx->d_x32.alloc(n);
+        ctx->d_b.alloc(n);
+        ctx->d_r.alloc(n);
+        ctx->d_x.alloc(n);
+        ctx->d_h.alloc((size_t)o.max_iter + 8);
+        ctx->d_partial.alloc((size_t)nce::kReduceBlocks * ((size_t)o.max_iter + 8));
+        ctx->d_scal.alloc(8);
+        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
+        if (want_tree && N > 1) {
+            nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
+            nce::upload_tree(ctx->tree, s, ctx->dtree);
+            ctx->use_tree = true;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        *out = guard.release();
+        return NCE_OK;
+    });
+}
+
+void nce_destroy(nce_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    nce::free_tree(ctx->dtree);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int nce_dims(const nce_ctx* ctx, int* K, int* Kstar, int* p, int* levels) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (K) *K = ctx->K;
+    if (Kstar) *Kstar = ctx->Kstar;
+    if (p) *p = ctx->p;
+    if (levels) *levels = ctx->use_tree ? ctx->tree.nlevels : 0;
+    return NCE_OK;
+}
+
+int nce_frames(const nce_ctx* ctx, double* fr) {
+    if (!ctx || !fr) return fail(NCE_EINVAL, "NULL argument");
+    std::memcpy(fr, ctx->frames.data(), sizeof(double) * ctx->frames.size());
+    return NCE_OK;
+}
+
+int nce_work(const nce_ctx* ctx, double* far, double* near, double* interp) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    double f = 0, nr = 0, it = 0;
+    if (ctx->use_tree) {
+        f = ctx->tree.pairs_far;
+        nr = ctx->tree.pairs_near;
+        it = ctx->tree.interp_fma;
+    } else {
+        f = (double)ctx->N * (double)(ctx->N - 1) * ctx->Kstar * (double)ctx->p;
+    }
+    if (far) *far = f;
+    if (near) *near = nr;
+    if (interp) *interp = it;
+    return NCE_OK;
+}
+
+int nce_matvec(nce_ctx* ctx, const double* x, double* y, int precision) {
+    if (!ctx || !x || !y) return fail(NCE_EINVAL, "NULL argument");
+    if (x == y) return fail(NCE_EINVAL, "x and y may not alias");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    return guarded([&]() -> int {
+        matvec(ctx, x, y, precision);
+        return NCE_OK;
+    });
+}
+
+int nce_matvec_profile(nce_ctx* ctx, const double* x, double* y, int precision, double* step_ms) {
+    if (!ctx || !x || !y || !step_ms) return fail(NCE_EINVAL, "NULL argument");
+    if (x == y) return fail(NCE_EINVAL, "x and y may not alias");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    return guarded([&]() -> int {
+        hipEvent_t ev[6] = {};
+        for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+        try {
+            matvec(ctx, x, y, precision, ev);
+            HIPCHK(hipEventSynchronize(ev[5]));
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+                step_ms[k] = ms;
+            }
+        } catch (...) {
+            for (auto& e : ev) (void)hipEventDestroy(e);
+            throw;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        return NCE_OK;
+    });
+}
+
+int nce_solve_interior(nce_ctx* ctx, double* coeffs, double* flux, double* mfpt, nce_info* info) {
+    if (!ctx || !mfpt) return fail(NCE_EINVAL, "NULL argument");
+    if (ctx->tab.problem != NCE_INTERIOR) return fail(NCE_ESTATE, "context was built for the exterior problem");
+    return guarded([&]() -> int {
+        double Is = 0;
+        int rc = solve(ctx, coeffs, flux, &Is, info);
+        *mfpt = 1.0 / (3.0 * Is) - 0.6;
+        return rc;
+    });
+}
+
+int nce_solve_exterior(nce_ctx* ctx, double* coeffs, double* flux, double* rate, double* Is_out, nce_info* info) {
+    if (!ctx || !rate) return fail(NCE_EINVAL, "NULL argument");
+    if (ctx->tab.problem != NCE_EXTERIOR) return fail(NCE_ESTATE, "context was built for the interior problem");
+    return guarded([&]() -> int {
+        double Is = 0;
+        int rc = solve(ctx, coeffs, flux, &Is, info);
+        *rate = 4.0 * M_PI * Is;
+        if (Is_out) *Is_out = Is;
+        return rc;
+    });
+}
+
+int nce_integral_vector(const nce_ctx* ctx, double* I) {
+    if (!ctx || !I) return fail(NCE_EINVAL, "NULL argument");
+    std::memcpy(I, ctx->tab.I.data(), sizeof(double) * ctx->K);
+    return NCE_OK;
+}
+
+const char* nce_strerror(int code) {
+    switch (code) {
+        case NCE_OK: return "ok";
+        case NCE_NOTCONVERGED: return "iteration limit reached before the tolerance";
+        case NCE_EINVAL: return "invalid argument";
+        case NCE_ESEP: return "patches closer than 3 eps";
+        case NCE_ENOMEM: return "out of memory";
+        case NCE_EHIP: return "HIP runtime error";
+        case NCE_ETABLE: return "precompute failed its self-check";
+        case NCE_ESTATE: return "call not valid in this state";
+        default: return "unknown status";
+    }
+}
+
+const char* nce_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,433 @@
+// Device kernels: block applies (T and P), direct Green's function sums, and
+// Krylov vector operations. gfx950, wave64.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace nce {
+
+// ---------------------------------------------------------------------------
+// Green's function of the unit sphere restricted to the surface, as a function
+// of d^2 (Section 2.1, eqs. Gextonsurface and Gintonsurface). With w = 2/d:
+//   exterior  2/d - log(2/d) - log(1 + d/2) = w - log(1 + w)
+//   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
+template <int PROB>
+__device__ __forceinline__ double green64(double d2) {
+    const double w = 2.0 * rsqrt(d2);
+    if (PROB == 1) return w - log(1.0 + w);
+    return w + log(w * w / (1.0 + w));
+}
+
+// FP32: hardware reciprocal square root, reciprocal and base-2 logarithm.
+// Returns the two parts separately, g = w + sgn * ln2 * l2, so the caller
+// folds the ln2 scale into its accumulator.
+template <int PROB>
+__device__ __forceinline__ void green32_parts(float d2, float& w, float& l2) {
+    w = 2.0f * __builtin_amdgcn_rsqf(d2);
+    if (PROB == 1) {
+        l2 = __builtin_amdgcn_logf(1.0f + w);
+    } else {
+        l2 = __builtin_amdgcn_logf(w * w * __builtin_amdgcn_rcpf(1.0f + w));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// "NT" GEMM: out[i][j] = sum_k A[i][k] B[j][k] (+ add[i][j]); LDS tiles of
+// 64 x 64 outputs, 16-wide k slices, 256 threads, 4 x 4 outputs per thread.
+template <class TI, class TO, bool ADD>
+__global__ __launch_bounds__(256) void k_gemm_nt(int m, int n, int k, const TI* __restrict__ A, int lda,
+                                                 const TI* __restrict__ B, int ldb, TO* __restrict__ C,
+                                                 int ldc, const double* __restrict__ D, int ldd) {
+    __shared__ TI As[16][64 + 1];
+    __shared__ TI Bs[16][64 + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    TI acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = TI(0);
+    for (int k0 = 0; k0 < k; k0 += 16) {
+        // load 64 x 16 of A and of B: 1024 values each, 4 per thread
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            const int row = idx / 16, kk = idx % 16;
+            const int gi = i0 + row, gk = k0 + kk;
+            As[kk][row] = (gi < m && gk < k) ? A[(int64_t)gi * lda + gk] : TI(0);
+            const int gj = j0 + row;
+            Bs[kk][row] = (gj < n && gk < k) ? B[(int64_t)gj * ldb + gk] : TI(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            TI av[4], bv[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int gi = i0 + ty + 16 * a;
+        if (gi >= m) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int gj = j0 + tx + 16 * b;
+            if (gj >= n) continue;
+            if (ADD)
+                C[(int64_t)gi * ldc + gj] = (TO)((double)acc[a][b] + D[(int64_t)gi * ldd + gj]);
+            else
+                C[(int64_t)gi * ldc + gj] = (TO)acc[a][b];
+        }
+    }
+}
+
+template <class T>
+hipError_t gemm_nt(hipStream_t s, int m, int n, int k, const T* A, int lda, const T* B, int ldb, T* C,
+                   int ldc, const double* D, int ldd) {
+    dim3 grid((n + 63) / 64, (m + 63) / 64);
+    if (D)
+        hipLaunchKernelGGL((k_gemm_nt<T, T, true>), grid, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, D, ldd);
+    else
+        hipLaunchKernelGGL((k_gemm_nt<T, T, false>), grid, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, D, ldd);
+    return hipGetLastError();
+}
+template hipError_t gemm_nt<double>(hipStream_t, int, int, int, const double*, int, const double*, int, double*,
+                                    int, const double*, int);
+template hipError_t gemm_nt<float>(hipStream_t, int, int, int, const float*, int, const float*, int, float*, int,
+                                   const double*, int);
+
+template <class T>
+hipError_t p_apply(hipStream_t s, int N, int K, int Kstar, const T* U, const T* P, const double* x, double* y) {
+    dim3 grid((K + 63) / 64, (N + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_nt<T, double, true>), grid, dim3(256), 0, s, N, K, Kstar, U, Kstar, P, Kstar, y, K,
+                       x, K);
+    return hipGetLastError();
+}
+template hipError_t p_apply<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
+                                    double*);
+template hipError_t p_apply<float>(hipStream_t, int, int, int, const float*, const float*, const double*,
+                                   double*);
+
+// ---------------------------------------------------------------------------
+// Direct all-pairs sum. One block per target patch i; each thread owns NPT of
+// its K* Zernike nodes (positions relative to c_i kept in registers). For every
+// source patch j the block stages j's p skeleton points, relative to c_i, and
+// its strengths rho_j in LDS (structure of arrays). Relative positions are
+// formed as (c_j - c_i) [FP64, then rounded] + local offsets, so the FP32
+// variant keeps full relative accuracy of the short near-field distances.
+template <int PROB, int NPT>
+__global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const double* __restrict__ frames,
+                                                  const double* __restrict__ node_off,
+                                                  const double* __restrict__ skel_off,
+                                                  const double* __restrict__ rho, double* __restrict__ U) {
+    extern __shared__ double sm64[];
+    double* sx = sm64;
+    double* sy = sx + p;
+    double* sz = sy + p;
+    double* sr = sz + p;
+    const int i = blockIdx.x;
+    const double* fi = frames + 9 * (int64_t)i;
+    const double cix = fi[0], ciy = fi[1], ciz = fi[2];
+    double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int q = threadIdx.x + r * blockDim.x;
+        acc[r] = 0.0;
+        if (q < Kstar) {
+            const double o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
+            zx[r] = o0 * cix + o1 * fi[3] + o2 * fi[6];
+            zy[r] = o0 * ciy + o1 * fi[4] + o2 * fi[7];
+            zz[r] = o0 * ciz + o1 * fi[5] + o2 * fi[8];
+        } else {
+            zx[r] = zy[r] = zz[r] = 0.0;
+        }
+    }
+    for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const double* fj = frames + 9 * (int64_t)j;
+        const double dcx = fj[0] - cix, dcy = fj[1] - ciy, dcz = fj[2] - ciz;
+        __syncthreads();
+        for (int m = threadIdx.x; m < p; m += blockDim.x) {
+            const double o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+            sx[m] = dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]);
+            sy[m] = dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]);
+            sz[m] = dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]);
+            sr[m] = rho[(int64_t)j * p + m];
+        }
+        __syncthreads();
+        for (int m = 0; m < p; ++m) {
+            const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int q = threadIdx.x + r * blockDim.x;
+        if (q < Kstar) U[(int64_t)i * Kstar + q] = acc[r];
+    }
+}
+
+template <int PROB, int NPT>
+__global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const double* __restrict__ frames,
+                                                  const float* __restrict__ node_off,
+                                                  const float* __restrict__ skel_off,
+                                                  const float* __restrict__ rho, float* __restrict__ U) {
+    extern __shared__ float sm32[];
+    float* sx = sm32;
+    float* sy = sx + p;
+    float* sz = sy + p;
+    float* sr = sz + p;
+    const int i = blockIdx.x;
+    const double* fi = frames + 9 * (int64_t)i;
+    const double cix = fi[0], ciy = fi[1], ciz = fi[2];
+    float zx[NPT], zy[NPT], zz[NPT];
+    double acc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int q = threadIdx.x + r * blockDim.x;
+        acc[r] = 0.0;
+        if (q < Kstar) {
+            const float o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
+            zx[r] = o0 * (float)cix + o1 * (float)fi[3] + o2 * (float)fi[6];
+            zy[r] = o0 * (float)ciy + o1 * (float)fi[4] + o2 * (float)fi[7];
+            zz[r] = o0 * (float)ciz + o1 * (float)fi[5] + o2 * (float)fi[8];
+        } else {
+            zx[r] = zy[r] = zz[r] = 0.0f;
+        }
+    }
+    constexpr float kLn2 = 0.69314718055994530942f;
+    constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
+    for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        const double* fj = frames + 9 * (int64_t)j;
+        const float dcx = (float)(fj[0] - cix), dcy = (float)(fj[1] - ciy), dcz = (float)(fj[2] - ciz);
+        __syncthreads();
+        for (int m = threadIdx.x; m < p; m += blockDim.x) {
+            const float o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+            sx[m] = dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]);
+            sy[m] = dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]);
+            sz[m] = dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]);
+            sr[m] = rho[(int64_t)j * p + m];
+        }
+        __syncthreads();
+        float aw[NPT], al[NPT];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
+        for (int m = 0; m < p; ++m) {
+            const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                float w, l2;
+                green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                aw[r] += w * rr;
+                al[r] += l2 * rr;
+            }
+        }
+        // per-source-patch partial sums are short; carry the running total in FP64
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int q = threadIdx.x + r * blockDim.x;
+        if (q < Kstar) U[(int64_t)i * Kstar + q] = (float)acc[r];
+    }
+}
+
+template <>
+hipError_t direct_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
+                              const double* node_off, const double* skel_off, const double* rho, double* U) {
+    const size_t sh = 4 * sizeof(double) * (size_t)p;
+    if (Kstar > 4 * 256) return hipErrorInvalidValue;
+    if (problem == 1)
+        hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                           rho, U);
+    else
+        hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                           rho, U);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t direct_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
+                             const float* node_off, const float* skel_off, const float* rho, float* U) {
+    const size_t sh = 4 * sizeof(float) * (size_t)p;
+    if (Kstar > 4 * 256) return hipErrorInvalidValue;
+    if (problem == 1)
+        hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                           rho, U);
+    else
+        hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                           rho, U);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Krylov vector operations (FP64). Reductions are two-stage and deterministic:
+// fixed grid, per-block partial sums, then one block sums the partials.
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / 64); ++k) t += red[k];
+    return t;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(256) void k_dots_partial(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                      const double* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double red[4];
+    const int j = blockIdx.y;
+    const double* v = V + (int64_t)j * ldv;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        acc += v[e] * w[e];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[(int64_t)j * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(int nb, const double* __restrict__ partial,
+                                                      double* __restrict__ out) {
+    __shared__ double red[4];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(int64_t)j * nb + b];
+    const double t = block_sum(acc, red);
+    if (threadIdx.x == 0) out[j] = t;
+}
+
+static int reduce_blocks(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return (int)(b < kReduceBlocks ? (b < 1 ? 1 : b) : kReduceBlocks);
+}
+
+hipError_t dots(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* w, double* partial,
+                double* out) {
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, nv), dim3(256), 0, s, n, V, ldv, w, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nv), dim3(256), 0, s, nb, partial, out);
+    return hipGetLastError();
+}
+
+hipError_t nrm2(hipStream_t s, int64_t n, const double* x, double* partial, double* out) {
+    // out = x . x (the caller takes the square root)
+    return dots(s, n, 1, x, n, x, partial, out);
+}
+
+__global__ __launch_bounds__(256) void k_axpys(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                               const double* __restrict__ h, double* __restrict__ w) {
+    extern __shared__ double hs[];
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) hs[j] = h[j];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = w[e];
+        for (int j = 0; j < nv; ++j) acc -= hs[j] * V[(int64_t)j * ldv + e];
+        w[e] = acc;
+    }
+}
+
+hipError_t axpys(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* h, double* w) {
+    const int64_t nb = (n + 255) / 256;
+    const int grid = (int)(nb < 8192 ? nb : 8192);
+    hipLaunchKernelGGL(k_axpys, dim3(grid), dim3(256), nv * sizeof(double), s, n, nv, V, ldv, h, w);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_combine(int64_t n, int nv, const double* __restrict__ V, int64_t ldv,
+                                                 const double* __restrict__ c, double* __restrict__ x) {
+    extern __shared__ double cs[];
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) cs[j] = c[j];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = x[e];
+        for (int j = 0; j < nv; ++j) acc += cs[j] * V[(int64_t)j * ldv + e];
+        x[e] = acc;
+    }
+}
+
+hipError_t combine(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* c, double* x) {
+    const int64_t nb = (n + 255) / 256;
+    const int grid = (int)(nb < 8192 ? nb : 8192);
+    hipLaunchKernelGGL(k_combine, dim3(grid), dim3(256), nv * sizeof(double), s, n, nv, V, ldv, c, x);
+    return hipGetLastError();
+}
+
+__global__ void k_scale_copy(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = a * x[e];
+}
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = a * x[e] + b * y[e];
+}
+__global__ void k_cast(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = (float)x[e];
+}
+__global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] = v;
+}
+
+static dim3 ew_grid(int64_t n) {
+    int64_t nb = (n + 255) / 256;
+    return dim3((unsigned)(nb < 16384 ? (nb < 1 ? 1 : nb) : 16384));
+}
+
+hipError_t scale_copy(hipStream_t s, int64_t n, double a, const double* x, double* y) {
+    hipLaunchKernelGGL(k_scale_copy, ew_grid(n), dim3(256), 0, s, n, a, x, y);
+    return hipGetLastError();
+}
+hipError_t axpby(hipStream_t s, int64_t n, double a, const double* x, double b, double* y) {
+    hipLaunchKernelGGL(k_axpby, ew_grid(n), dim3(256), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+hipError_t cast_d2f(hipStream_t s, int64_t n, const double* x, float* y) {
+    hipLaunchKernelGGL(k_cast, ew_grid(n), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+hipError_t fill(hipStream_t s, int64_t n, double v, double* x) {
+    hipLaunchKernelGGL(k_fill, ew_grid(n), dim3(256), 0, s, n, v, x);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_flux(int N, int K, const double* __restrict__ I, const double* __restrict__ x,
+                                              double* __restrict__ flux, double* __restrict__ partial) {
+    __shared__ double red[4];
+    double mine = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double f = 0.0;
+        for (int k = 0; k < K; ++k) f += I[k] * x[(int64_t)i * K + k];
+        if (flux) flux[i] = f;
+        mine += f;
+    }
+    const double t = block_sum(mine, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+hipError_t patch_flux(hipStream_t s, int N, int K, const double* I, const double* x, double* flux, double* partial,
+                      double* sum) {
+    const int nb = reduce_blocks(N);
+    hipLaunchKernelGGL(k_flux, dim3(nb), dim3(256), 0, s, N, K, I, x, flux, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, nb, partial, sum);
+    return hipGetLastError();
+}
+
+}  // namespace nce

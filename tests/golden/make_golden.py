@@ -1,0 +1,88 @@
+"""Write the oracle's stored expected values used by the GPU parity tests.
+
+Calls only `oracle/` and the seeded generators in `layouts`. Outputs (under
+tests/golden/):
+  tables/<key>.npz      oracle precompute (T, skeleton, I) per (problem, eps, M, tol_id)
+  cfg1.npz              N=10 exterior, eps=0.1, seed 1: matvec of seeded x, dense-LU solve
+  cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
+  MANIFEST.json         SHA-256 of every file, with the command that made it
+
+Run:  python tests/golden/make_golden.py [name ...]
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parents[2]
+sys.path.insert(0, str(ROOT))
+
+import layouts  # noqa: E402
+from oracle import csum, system, tables  # noqa: E402
+
+GOLD = ROOT / "tests" / "golden"
+TOL_ID = 1e-12
+X_SEED = 777          # seed of the matvec input vectors
+ROW_SEED = 4242       # seed of the sampled target patches
+
+
+def _tab(problem, eps):
+    k = tables.key(problem, eps, 15, TOL_ID)
+    f = tables.GOLDEN_DIR / (k + ".npz")
+    if f.exists():
+        return tables.load(f)
+    t0 = time.time()
+    tab, _, _ = tables.compute(problem, eps, 15, TOL_ID)
+    tables.save(tab, f)
+    print(f"  tables {k}: p={tab.p} ({time.time() - t0:.0f} s)", flush=True)
+    return tab
+
+
+def make_cfg1():
+    cfg = layouts.CONFIGS["cfg1"]
+    tab = _tab(cfg["problem"], cfg["eps"])
+    c = layouts.config_layout(cfg)
+    lay = system.Layout(c, tab)
+    x = layouts.random_coeffs(cfg["N"], tab.K, X_SEED, decay=0.1)
+    y = system.matvec_dense(lay, x)
+    r = system.solve_dense(lay)
+    it = system.solve_gmres(lay, tol=1e-10)
+    np.savez(GOLD / "cfg1.npz", y=y, x_seed=X_SEED, capture_rate=r["capture_rate"], I_sigma=r["I_sigma"],
+             flux=r["flux"], gmres_iters=it["iters"])
+    print(f"  cfg1 capture rate {r['capture_rate']:.15g}, GMRES iters {it['iters']}", flush=True)
+
+
+def make_cfg2_rows():
+    cfg = layouts.CONFIGS["cfg2"]
+    tab = _tab(cfg["problem"], cfg["eps"])
+    c = layouts.config_layout(cfg)
+    lay = system.Layout(c, tab)
+    x = layouts.random_coeffs(cfg["N"], tab.K, X_SEED, decay=0.1)
+    rows = np.sort(layouts.rng(ROW_SEED).choice(cfg["N"], 16, replace=False))
+    U = csum.incoming_layout(lay, x, rows)
+    y = x[rows] + U @ tab.P.T
+    np.savez(GOLD / "cfg2_rows.npz", rows=rows, y=y, x_seed=X_SEED)
+    print(f"  cfg2 rows {rows.tolist()}", flush=True)
+
+
+JOBS = {"cfg1": make_cfg1, "cfg2_rows": make_cfg2_rows}
+
+
+def manifest():
+    out = {"command": "python tests/golden/make_golden.py", "files": {}}
+    for f in sorted(GOLD.rglob("*.npz")):
+        out["files"][str(f.relative_to(GOLD))] = hashlib.sha256(f.read_bytes()).hexdigest()
+    (GOLD / "MANIFEST.json").write_text(json.dumps(out, indent=1) + "\n")
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(JOBS)
+    for n in names:
+        print(n, flush=True)
+        JOBS[n]()
+    manifest()

@@ -1,0 +1,81 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+input before touching the GPU (host-side validation only; no compute calls)."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import paper_1906_04209_amd as nce
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def _declared():
+    txt = (ROOT / "include" / "nce.h").read_text()
+    return sorted(set(re.findall(r"\b(nce_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_matches_binding_list():
+    assert _declared() == sorted(nce.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    lib = nce.load()
+    for s in _declared():
+        assert hasattr(lib, s), s
+
+
+def _setup(centers, eps, **kw):
+    lib = nce.load()
+    o = nce.Opts()
+    lib.nce_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    c = np.ascontiguousarray(centers, dtype=np.float64)
+    rc = lib.nce_setup(c.ctypes.data, len(c), eps, ctypes.byref(o), ctypes.byref(h))
+    return rc, lib.nce_last_error().decode(), h
+
+
+def test_default_opts():
+    lib = nce.load()
+    o = nce.Opts()
+    lib.nce_default_opts(ctypes.byref(o))
+    assert (o.M, o.tol_id, o.tol_grid, o.tol_gmres, o.precision) == (15, 1e-11, 1e-8, 1e-10, 0)
+
+
+@pytest.mark.parametrize("case", ["nonunit", "nan", "eps0", "epsbig", "badM", "badprob"])
+def test_invalid_arguments(case):
+    c = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
+    eps, kw = 0.1, {}
+    if case == "nonunit":
+        c = c * 1.001
+    elif case == "nan":
+        c[1, 0] = np.nan
+    elif case == "eps0":
+        eps = 0.0
+    elif case == "epsbig":
+        eps = 1.2
+    elif case == "badM":
+        kw = {"M": -1}
+    elif case == "badprob":
+        kw = {"problem": 3}
+    rc, msg, h = _setup(c, eps, **kw)
+    assert rc == -1 and not h.value and msg
+
+
+def test_separation_rule():
+    # centres 2.9 eps apart in arclength violate the 3 eps rule (Section 3)
+    eps = 0.05
+    a = 2.9 * eps
+    c = np.array([[0.0, 0.0, 1.0], [np.sin(a), 0.0, np.cos(a)]])
+    rc, msg, h = _setup(c, eps)
+    assert rc == -2 and "closer than 3 eps" in msg
+
+
+def test_strerror_codes():
+    lib = nce.load()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.nce_strerror(code)

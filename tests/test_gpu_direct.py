@@ -1,0 +1,106 @@
+"""GPU parity of the direct (all-pairs) system apply and the solves against
+the oracle's stored values (tests/golden, written by make_golden.py).
+
+The library and the oracle build their compressed outgoing representations
+independently (different training grids, sketches and skeletons); both
+approximate the same uncompressed operator to within the ID tolerance
+(1e-12 here), so the FP64 results agree to about that level. FP32 inner
+products carry single-precision rounding (relative 1e-7 per pair sum).
+"""
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import layouts
+
+pytestmark = pytest.mark.gpu
+GOLD = Path(__file__).resolve().parent / "golden"
+TOL_ID = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _ctx(cfg, **kw):
+    import paper_1906_04209_amd as nce
+    c = layouts.config_layout(cfg)
+    kw.setdefault("far_field", nce.FAR_DIRECT)
+    return nce.Context(c, cfg["eps"], problem=cfg["problem"], tol_id=TOL_ID, **kw)
+
+
+def _x(torch, N, K):
+    x = layouts.random_coeffs(N, K, 777, decay=0.1)
+    return x, torch.from_numpy(x).cuda()
+
+
+def test_cfg1_matvec_fp64(torch):
+    g = np.load(GOLD / "cfg1.npz")
+    cfg = layouts.CONFIGS["cfg1"]
+    ctx = _ctx(cfg)
+    x, xd = _x(torch, cfg["N"], ctx.K)
+    y = ctx.matvec(xd).cpu().numpy()
+    ref = g["y"]
+    err = np.max(np.abs(y - ref)) / np.max(np.abs(ref - x))
+    print("cfg1 FP64 matvec rel err", err)
+    assert err < 1e-10
+
+
+def test_cfg1_matvec_mixed(torch):
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / "cfg1.npz")
+    cfg = layouts.CONFIGS["cfg1"]
+    ctx = _ctx(cfg)
+    x, xd = _x(torch, cfg["N"], ctx.K)
+    y = ctx.matvec(xd, precision=nce.MIXED).cpu().numpy()
+    err = np.max(np.abs(y - g["y"])) / np.max(np.abs(g["y"] - x))
+    print("cfg1 FP32 matvec rel err", err)
+    assert err < 2e-5
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_cfg1_capture_rate(torch, mixed):
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / "cfg1.npz")
+    cfg = layouts.CONFIGS["cfg1"]
+    ctx = _ctx(cfg, precision=nce.MIXED if mixed else nce.FP64)
+    r = ctx.solve()
+    rel = abs(r["capture_rate"] - float(g["capture_rate"])) / float(g["capture_rate"])
+    print("cfg1 capture rate", r["capture_rate"], "oracle", float(g["capture_rate"]), "rel", rel, r)
+    assert r["converged"] and r["rel_residual"] <= 1e-10
+    assert rel < 1e-9
+    flux = r["flux"].cpu().numpy()
+    assert np.max(np.abs(flux - g["flux"])) < 1e-9 * np.max(np.abs(g["flux"]))
+    if not mixed:
+        assert abs(r["iters_fp64"] - int(g["gmres_iters"])) <= 1
+
+
+def test_cfg2_rows_fp64(torch):
+    g = np.load(GOLD / "cfg2_rows.npz")
+    cfg = layouts.CONFIGS["cfg2"]
+    ctx = _ctx(cfg)
+    x, xd = _x(torch, cfg["N"], ctx.K)
+    y = ctx.matvec(xd).cpu().numpy()
+    rows = g["rows"]
+    err = np.max(np.abs(y[rows] - g["y"])) / np.max(np.abs(g["y"] - x[rows]))
+    print("cfg2 FP64 rows rel err", err)
+    assert err < 1e-10
+
+
+def test_single_patch_and_pair(torch):
+    import paper_1906_04209_amd as nce
+    c1 = np.array([[0.0, 0.6, 0.8]])
+    ctx = nce.Context(c1, 0.05, problem=nce.INTERIOR, tol_id=TOL_ID)
+    I = ctx.integral_vector()
+    r = ctx.solve()
+    assert r["iters_fp64"] == 0 and abs(r["mu"] - (1 / (3 * I[0]) - 0.6)) < 1e-12 * r["mu"]
+    # antipodal pair: equal fluxes
+    c2 = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, -1.0]])
+    r2 = nce.Context(c2, 0.05, problem=nce.EXTERIOR, tol_id=TOL_ID).solve()
+    f = r2["flux"].cpu().numpy()
+    assert abs(f[0] - f[1]) < 1e-14 * abs(f[0])
