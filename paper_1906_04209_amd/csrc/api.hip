@@ -495,7 +495,7 @@ int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts
         const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
         if (want_tree && N > 1) {
             nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
-            nce::upload_tree(ctx->tree, s, ctx->dtree);
+            nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, s, ctx->dtree);
             ctx->use_tree = true;
         }
         HIPCHK(hipStreamSynchronize(s));

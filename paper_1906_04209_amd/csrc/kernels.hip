@@ -1,35 +1,11 @@
 // Device kernels: block applies (T and P), direct Green's function sums, and
 // Krylov vector operations. gfx950, wave64.
 #include "kernels.hpp"
+#include "greens.hpp"
 
 #include <hip/hip_runtime.h>
 
 namespace nce {
-
-// ---------------------------------------------------------------------------
-// Green's function of the unit sphere restricted to the surface, as a function
-// of d^2 (Section 2.1, eqs. Gextonsurface and Gintonsurface). With w = 2/d:
-//   exterior  2/d - log(2/d) - log(1 + d/2) = w - log(1 + w)
-//   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
-template <int PROB>
-__device__ __forceinline__ double green64(double d2) {
-    const double w = 2.0 * rsqrt(d2);
-    if (PROB == 1) return w - log(1.0 + w);
-    return w + log(w * w / (1.0 + w));
-}
-
-// FP32: hardware reciprocal square root, reciprocal and base-2 logarithm.
-// Returns the two parts separately, g = w + sgn * ln2 * l2, so the caller
-// folds the ln2 scale into its accumulator.
-template <int PROB>
-__device__ __forceinline__ void green32_parts(float d2, float& w, float& l2) {
-    w = 2.0f * __builtin_amdgcn_rsqf(d2);
-    if (PROB == 1) {
-        l2 = __builtin_amdgcn_logf(1.0f + w);
-    } else {
-        l2 = __builtin_amdgcn_logf(w * w * __builtin_amdgcn_rcpf(1.0f + w));
-    }
-}
 
 // ---------------------------------------------------------------------------
 // "NT" GEMM: out[i][j] = sum_k A[i][k] B[j][k] (+ add[i][j]); LDS tiles of
@@ -127,7 +103,8 @@ template <int PROB, int NPT>
 __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const double* __restrict__ frames,
                                                   const double* __restrict__ node_off,
                                                   const double* __restrict__ skel_off,
-                                                  const double* __restrict__ rho, double* __restrict__ U) {
+                                                  const double* __restrict__ rho, double* __restrict__ U,
+                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
     extern __shared__ double sm64[];
     double* sx = sm64;
     double* sy = sx + p;
@@ -150,7 +127,10 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
             zx[r] = zy[r] = zz[r] = 0.0;
         }
     }
-    for (int j = 0; j < N; ++j) {
+    // sources: every other patch, or the CSR list of patch i
+    const int64_t q0 = lptr ? lptr[i] : 0, q1 = lptr ? lptr[i + 1] : N;
+    for (int64_t qq = q0; qq < q1; ++qq) {
+        const int j = lptr ? lsrc[qq] : (int)qq;
         if (j == i) continue;
         const double* fj = frames + 9 * (int64_t)j;
         const double dcx = fj[0] - cix, dcy = fj[1] - ciy, dcz = fj[2] - ciz;
@@ -183,7 +163,8 @@ template <int PROB, int NPT>
 __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const double* __restrict__ frames,
                                                   const float* __restrict__ node_off,
                                                   const float* __restrict__ skel_off,
-                                                  const float* __restrict__ rho, float* __restrict__ U) {
+                                                  const float* __restrict__ rho, float* __restrict__ U,
+                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
     extern __shared__ float sm32[];
     float* sx = sm32;
     float* sy = sx + p;
@@ -209,7 +190,10 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
     }
     constexpr float kLn2 = 0.69314718055994530942f;
     constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
-    for (int j = 0; j < N; ++j) {
+    // sources: every other patch, or the CSR list of patch i
+    const int64_t q0 = lptr ? lptr[i] : 0, q1 = lptr ? lptr[i + 1] : N;
+    for (int64_t qq = q0; qq < q1; ++qq) {
+        const int j = lptr ? lsrc[qq] : (int)qq;
         if (j == i) continue;
         const double* fj = frames + 9 * (int64_t)j;
         const float dcx = (float)(fj[0] - cix), dcy = (float)(fj[1] - ciy), dcz = (float)(fj[2] - ciz);
@@ -248,32 +232,44 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
 }
 
 template <>
-hipError_t direct_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                              const double* node_off, const double* skel_off, const double* rho, double* U) {
+hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
+                            const double* node_off, const double* skel_off, const double* rho, double* U,
+                            const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     if (problem == 1)
         hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U);
+                           rho, U, lptr, lsrc);
     else
         hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U);
+                           rho, U, lptr, lsrc);
     return hipGetLastError();
 }
 
 template <>
-hipError_t direct_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                             const float* node_off, const float* skel_off, const float* rho, float* U) {
+hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
+                           const float* node_off, const float* skel_off, const float* rho, float* U,
+                           const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     if (problem == 1)
         hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U);
+                           rho, U, lptr, lsrc);
     else
         hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U);
+                           rho, U, lptr, lsrc);
     return hipGetLastError();
 }
+
+template <class T>
+hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
+                      const T* skel_off, const T* rho, T* U) {
+    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, U, nullptr, nullptr);
+}
+template hipError_t direct_sum<double>(hipStream_t, int, int, int, int, const double*, const double*, const double*,
+                                       const double*, double*);
+template hipError_t direct_sum<float>(hipStream_t, int, int, int, int, const double*, const float*, const float*,
+                                      const float*, float*);
 
 // ---------------------------------------------------------------------------
 // Krylov vector operations (FP64). Reductions are two-stage and deterministic:

@@ -1,0 +1,439 @@
+// Device side of the hierarchical far field: P2L onto incoming grids,
+// per-grid reduction and Chebyshev-Fourier transform, direct-list sums, and
+// interpolation at the sampling nodes (Section 8, Step 3 items 2-4). gfx950.
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+
+#include "greens.hpp"
+#include "kernels.hpp"
+#include "tree.hpp"
+
+namespace nce {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// grid point t = a * nt + b of a grid with nr radial Chebyshev nodes on [0, R]
+// (positive half of the 2 nr first-kind nodes on [-R, R]) and nt angles;
+// returns its local offset (cos r - 1, sin r cos th, sin r sin th).
+__device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, double& o0, double& o1, double& o2) {
+    const int a = t / nt, b = t - a * nt;
+    const double x = cospi((2.0 * a + 1.0) / (4.0 * nr));
+    const double r = R * x;
+    double sb, cb;
+    sincospi(2.0 * b / nt, &sb, &cb);
+    const double sr = sin(0.5 * r);
+    o0 = -2.0 * sr * sr;
+    const double s = sin(r);
+    o1 = s * cb;
+    o2 = s * sb;
+}
+
+// ----------------------------------------------------------------- P2L
+// One block per work item (one grid, up to kSrcPerItem source patches); each
+// thread owns NPT grid points; source skeleton points and strengths are staged
+// in LDS relative to the grid's cap centre. Partial sums per item.
+template <int PROB, int NPT>
+__global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
+                                               const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
+                                               const int* __restrict__ src, const double* __restrict__ g_frame,
+                                               const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                               const int* __restrict__ g_nt, const double* __restrict__ frames,
+                                               const double* __restrict__ skel_off, const double* __restrict__ rho,
+                                               int p, double* __restrict__ part) {
+    extern __shared__ double sh64[];
+    double* sx = sh64;
+    double* sy = sx + p;
+    double* sz = sy + p;
+    double* sr = sz + p;
+    const int item = blockIdx.x;
+    const int g = it_grid[item];
+    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const double R = g_R[g];
+    const double* fg = g_frame + 9 * (int64_t)g;
+    double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int t = threadIdx.x + r * blockDim.x;
+        acc[r] = 0.0;
+        zx[r] = zy[r] = zz[r] = 0.0;
+        if (t < q) {
+            double o0, o1, o2;
+            grid_point(t, nr, nt, R, o0, o1, o2);
+            zx[r] = o0 * fg[0] + o1 * fg[3] + o2 * fg[6];
+            zy[r] = o0 * fg[1] + o1 * fg[4] + o2 * fg[7];
+            zz[r] = o0 * fg[2] + o1 * fg[5] + o2 * fg[8];
+        }
+    }
+    for (int qq = it_src0[item]; qq < it_src1[item]; ++qq) {
+        const int j = src[qq];
+        const double* fj = frames + 9 * (int64_t)j;
+        const double dcx = fj[0] - fg[0], dcy = fj[1] - fg[1], dcz = fj[2] - fg[2];
+        __syncthreads();
+        for (int m = threadIdx.x; m < p; m += blockDim.x) {
+            const double o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+            sx[m] = dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]);
+            sy[m] = dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]);
+            sz[m] = dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]);
+            sr[m] = rho[(int64_t)j * p + m];
+        }
+        __syncthreads();
+        for (int m = 0; m < p; ++m) {
+            const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+            }
+        }
+    }
+    const int64_t off = it_off[item];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int t = threadIdx.x + r * blockDim.x;
+        if (t < q) part[off + t] = acc[r];
+    }
+}
+
+template <int PROB, int NPT>
+__global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
+                                               const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
+                                               const int* __restrict__ src, const double* __restrict__ g_frame,
+                                               const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                               const int* __restrict__ g_nt, const double* __restrict__ frames,
+                                               const float* __restrict__ skel_off, const float* __restrict__ rho,
+                                               int p, float* __restrict__ part) {
+    extern __shared__ float sh32[];
+    float* sx = sh32;
+    float* sy = sx + p;
+    float* sz = sy + p;
+    float* sr = sz + p;
+    const int item = blockIdx.x;
+    const int g = it_grid[item];
+    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const double R = g_R[g];
+    const double* fg = g_frame + 9 * (int64_t)g;
+    float zx[NPT], zy[NPT], zz[NPT];
+    double acc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int t = threadIdx.x + r * blockDim.x;
+        acc[r] = 0.0;
+        zx[r] = zy[r] = zz[r] = 0.0f;
+        if (t < q) {
+            double o0, o1, o2;
+            grid_point(t, nr, nt, R, o0, o1, o2);
+            zx[r] = (float)(o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
+            zy[r] = (float)(o0 * fg[1] + o1 * fg[4] + o2 * fg[7]);
+            zz[r] = (float)(o0 * fg[2] + o1 * fg[5] + o2 * fg[8]);
+        }
+    }
+    constexpr float kLn2 = 0.69314718055994530942f;
+    constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
+    for (int qq = it_src0[item]; qq < it_src1[item]; ++qq) {
+        const int j = src[qq];
+        const double* fj = frames + 9 * (int64_t)j;
+        const float dcx = (float)(fj[0] - fg[0]), dcy = (float)(fj[1] - fg[1]), dcz = (float)(fj[2] - fg[2]);
+        __syncthreads();
+        for (int m = threadIdx.x; m < p; m += blockDim.x) {
+            const float o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+            sx[m] = dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]);
+            sy[m] = dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]);
+            sz[m] = dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]);
+            sr[m] = rho[(int64_t)j * p + m];
+        }
+        __syncthreads();
+        float aw[NPT], al[NPT];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
+        for (int m = 0; m < p; ++m) {
+            const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                float w, l2;
+                green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                aw[r] += w * rr;
+                al[r] += l2 * rr;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+    }
+    const int64_t off = it_off[item];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int t = threadIdx.x + r * blockDim.x;
+        if (t < q) part[off + t] = (float)acc[r];
+    }
+}
+
+// ---------------------------------------------------- reduce + transform
+// One block per grid: sum the items' partial sums, then the angular DFT and
+// the parity-restricted radial Chebyshev transform. Coefficient layout:
+// mode m = 0..nt-1 (m <= nt/2: cos(m th); m > nt/2: sin((m - nt/2) th)),
+// radial index n' (Chebyshev degree 2 n' + parity of the angular order).
+template <class T>
+__global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_nr, const int* __restrict__ g_nt,
+                                                     const int64_t* __restrict__ g_off,
+                                                     const int* __restrict__ g_item0, const int* __restrict__ g_item1,
+                                                     const int64_t* __restrict__ it_off, const T* __restrict__ part,
+                                                     T* __restrict__ vals, T* __restrict__ coef) {
+    __shared__ double sv[kMaxGridQ];
+    __shared__ double sa[kMaxGridQ];
+    const int g = blockIdx.x;
+    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const int i0 = g_item0[g], i1 = g_item1[g];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) {
+        double s = 0.0;
+        for (int it = i0; it < i1; ++it) s += (double)part[it_off[it] + t];
+        sv[t] = s;
+        vals[g_off[g] + t] = (T)s;
+    }
+    __syncthreads();
+    const int half = nt / 2;
+    // angular transform: sa[m * nr + a]
+    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
+        const int m = idx / nr, a = idx - m * nr;
+        const bool is_sin = m > half;
+        const int k = is_sin ? m - half : m;
+        const double wgt = (k == 0 || k == half) ? 1.0 / nt : 2.0 / nt;
+        double s = 0.0;
+        for (int b = 0; b < nt; ++b) {
+            const int red = (k * b) % nt;
+            double sn, cs;
+            sincospi(2.0 * red / nt, &sn, &cs);
+            s += sv[a * nt + b] * (is_sin ? sn : cs);
+        }
+        sa[idx] = wgt * s;
+    }
+    __syncthreads();
+    // radial transform on the positive first-kind Chebyshev nodes (parity)
+    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
+        const int m = idx / nr, np = idx - m * nr;
+        const int k = m > half ? m - half : m;
+        const int n = 2 * np + (k & 1);
+        double s = 0.0;
+        for (int a = 0; a < nr; ++a) {
+            const int red = (n * (2 * a + 1)) % (8 * nr);
+            s += sa[m * nr + a] * cospi(2.0 * red / (8.0 * nr));
+        }
+        coef[g_off[g] + idx] = (T)((n == 0 ? 1.0 : 2.0) / nr * s);
+    }
+}
+
+// ------------------------------------------------------------------ L2T
+// One block per patch; for every grid in the patch's list, stage the grid's
+// coefficients in LDS and evaluate the expansion at the patch's K* nodes in
+// the grid's geodesic polar coordinates; add into U.
+template <class T, int NPT>
+__global__ __launch_bounds__(256) void k_l2t(int Kstar, const double* __restrict__ frames,
+                                             const T* __restrict__ node_off, const int64_t* __restrict__ l2t_ptr,
+                                             const int* __restrict__ l2t_grid, const double* __restrict__ g_frame,
+                                             const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                             const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
+                                             const T* __restrict__ coef, T* __restrict__ U) {
+    __shared__ T cs[kMaxGridQ];
+    const int i = blockIdx.x;
+    const int64_t a0 = l2t_ptr[i], a1 = l2t_ptr[i + 1];
+    if (a0 == a1) return;
+    const double* fi = frames + 9 * (int64_t)i;
+    T ox[NPT], oy[NPT], oz[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        const int q = threadIdx.x + r * blockDim.x;
+        ox[r] = oy[r] = oz[r] = T(0);
+        if (q < Kstar) {
+            const T o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
+            ox[r] = o0 * (T)fi[0] + o1 * (T)fi[3] + o2 * (T)fi[6];
+            oy[r] = o0 * (T)fi[1] + o1 * (T)fi[4] + o2 * (T)fi[7];
+            oz[r] = o0 * (T)fi[2] + o1 * (T)fi[5] + o2 * (T)fi[8];
+        }
+    }
+    for (int64_t aa = a0; aa < a1; ++aa) {
+        const int g = l2t_grid[aa];
+        const int nr = g_nr[g], nt = g_nt[g], q = nr * nt, half = nt / 2;
+        const double* fg = g_frame + 9 * (int64_t)g;
+        __syncthreads();
+        for (int t = threadIdx.x; t < q; t += blockDim.x) cs[t] = coef[g_off[g] + t];
+        __syncthreads();
+        const T dcx = (T)(fi[0] - fg[0]), dcy = (T)(fi[1] - fg[1]), dcz = (T)(fi[2] - fg[2]);
+        const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
+        const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
+        const T cgx = (T)fg[0], cgy = (T)fg[1], cgz = (T)fg[2];
+        const T invR = (T)(1.0 / g_R[g]);
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int qn = threadIdx.x + r * blockDim.x;
+            if (qn >= Kstar) continue;
+            const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
+            const T x1 = vx * e1x + vy * e1y + vz * e1z;
+            const T x2 = vx * e2x + vy * e2y + vz * e2z;
+            const T x3 = vx * cgx + vy * cgy + vz * cgz;
+            const T rh = sqrt(x1 * x1 + x2 * x2);
+            const T ang = atan2(rh, T(1) + x3);
+            T xs = ang * invR;
+            xs = xs > T(1) ? T(1) : xs;
+            const T ct = rh > T(0) ? x1 / rh : T(1);
+            const T st = rh > T(0) ? x2 / rh : T(0);
+            // Chebyshev degrees of one parity: T_{2j}(x) = T_j(y), T_{2j+1} follow the
+            // same three-term recurrence in y = T_2(x) = 2 x^2 - 1
+            const T y2 = T(2) * (T(2) * xs * xs - T(1));
+            const T t1e = T(2) * xs * xs - T(1), t1o = xs * (T(4) * xs * xs - T(3));
+            T val = T(0);
+            T ck = T(1), sk = T(0);
+            for (int k = 0; k <= half; ++k) {
+                const bool odd = k & 1;
+                const bool has_sin = (k > 0 && k < half);
+                const T* cc = cs + k * nr;
+                const T* sc = cs + (half + k) * nr;
+                T tp = odd ? xs : T(1), tc = odd ? t1o : t1e;  // degrees par, par + 2
+                T rc = cc[0] * tp, rs = has_sin ? sc[0] * tp : T(0);
+                for (int np = 1; np < nr; ++np) {
+                    rc += cc[np] * tc;
+                    if (has_sin) rs += sc[np] * tc;
+                    const T tn = y2 * tc - tp;
+                    tp = tc;
+                    tc = tn;
+                }
+                val += ck * rc + sk * rs;
+                const T cn = ck * ct - sk * st;
+                sk = sk * ct + ck * st;
+                ck = cn;
+            }
+            U[(int64_t)i * Kstar + qn] += val;
+        }
+    }
+}
+
+template <class T>
+T* dev_copy(const std::vector<T>& v) {
+    T* p = nullptr;
+    if (v.empty()) return nullptr;
+    if (hipMalloc((void**)&p, v.size() * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    if (hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+        throw std::runtime_error("hipMemcpy failed (tree upload)");
+    return p;
+}
+
+template <class T>
+T* dev_alloc(int64_t n) {
+    T* p = nullptr;
+    if (n <= 0) return nullptr;
+    if (hipMalloc((void**)&p, (size_t)n * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    return p;
+}
+
+}  // namespace
+
+void upload_tree(const Tree& t, int Kstar, int p, hipStream_t, DeviceTree& d) {
+    d.ngrid = t.ngrid;
+    d.nitems = (int)t.it_grid.size();
+    d.N = t.N;
+    d.Kstar = Kstar;
+    d.p = p;
+    d.g_frame = dev_copy(t.g_frame);
+    d.g_R = dev_copy(t.g_R);
+    d.g_nr = dev_copy(t.g_nr);
+    d.g_nt = dev_copy(t.g_nt);
+    d.g_off = dev_copy(t.g_off);
+    d.g_item0 = dev_copy(t.g_item0);
+    d.g_item1 = dev_copy(t.g_item1);
+    d.it_grid = dev_copy(t.it_grid);
+    d.it_src0 = dev_copy(t.it_src0);
+    d.it_src1 = dev_copy(t.it_src1);
+    d.it_off = dev_copy(t.it_off);
+    d.p2l_src = dev_copy(t.p2l_src);
+    d.dl_ptr = dev_copy(t.dl_ptr);
+    d.dl_src = dev_copy(t.dl_src);
+    d.l2t_ptr = dev_copy(t.l2t_ptr);
+    d.l2t_grid = dev_copy(t.l2t_grid);
+    d.vals64 = dev_alloc<double>(t.total_q);
+    d.coef64 = dev_alloc<double>(t.total_q);
+    d.part64 = dev_alloc<double>(t.total_partial);
+    d.vals32 = dev_alloc<float>(t.total_q);
+    d.coef32 = dev_alloc<float>(t.total_q);
+    d.part32 = dev_alloc<float>(t.total_partial);
+}
+
+void free_tree(DeviceTree& d) {
+    void* ptrs[] = {d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
+                    d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
+                    d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    d = DeviceTree();
+}
+
+template <>
+hipError_t tree_far<double>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
+                            const double* skel_off, const double* rho) {
+    if (d.nitems > 0) {
+        const size_t sh = 4 * sizeof(double) * (size_t)d.p;
+        if (problem == 1)
+            hipLaunchKernelGGL((k_p2l64<1, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
+                               d.part64);
+        else
+            hipLaunchKernelGGL((k_p2l64<0, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
+                               d.part64);
+    }
+    if (d.ngrid > 0)
+        hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
+                           d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
+                           const float* skel_off, const float* rho) {
+    if (d.nitems > 0) {
+        const size_t sh = 4 * sizeof(float) * (size_t)d.p;
+        if (problem == 1)
+            hipLaunchKernelGGL((k_p2l32<1, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
+                               d.part32);
+        else
+            hipLaunchKernelGGL((k_p2l32<0, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
+                               d.part32);
+    }
+    if (d.ngrid > 0)
+        hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
+                           d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
+                     const T* skel_off, const T* rho, T* U) {
+    return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, U, d.dl_ptr, d.dl_src);
+}
+template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
+                                      const double*, const double*, double*);
+template hipError_t tree_near<float>(hipStream_t, const DeviceTree&, int, const double*, const float*, const float*,
+                                     const float*, float*);
+
+template <>
+hipError_t tree_interp<double>(hipStream_t s, const DeviceTree& d, const double* frames, const double* node_off,
+                               double* U) {
+    if (d.ngrid == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_l2t<double, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
+                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef64, U);
+    return hipGetLastError();
+}
+
+template <>
+hipError_t tree_interp<float>(hipStream_t s, const DeviceTree& d, const double* frames, const float* node_off,
+                              float* U) {
+    if (d.ngrid == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_l2t<float, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
+                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef32, U);
+    return hipGetLastError();
+}
+
+}  // namespace nce

@@ -1,38 +1,53 @@
-// Hierarchical far field on a cube-sphere quadtree (Section 7.2, 7.3 and
-// Section 8 Step 2 and Step 3, items 2-4).
+// Device side of the hierarchical far field (see tree_build.hpp).
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include <cstdint>
-#include <vector>
-
-#include "precompute.hpp"
+#include "tree_build.hpp"
 
 namespace nce {
 
-struct Tree {
-    int nlevels = 0;
-    double pairs_far = 0, pairs_near = 0, interp_fma = 0;
-};
-
 struct DeviceTree {
-    int dummy = 0;
+    int ngrid = 0, nitems = 0;
+    int64_t N = 0;
+    int Kstar = 0, p = 0;
+    double* g_frame = nullptr;
+    double* g_R = nullptr;
+    int* g_nr = nullptr;
+    int* g_nt = nullptr;
+    int64_t* g_off = nullptr;
+    int* g_item0 = nullptr;
+    int* g_item1 = nullptr;
+    int* it_grid = nullptr;
+    int* it_src0 = nullptr;
+    int* it_src1 = nullptr;
+    int64_t* it_off = nullptr;
+    int* p2l_src = nullptr;
+    int64_t* dl_ptr = nullptr;
+    int* dl_src = nullptr;
+    int64_t* l2t_ptr = nullptr;
+    int* l2t_grid = nullptr;
+    // work buffers (FP64 and FP32)
+    double* vals64 = nullptr;
+    double* coef64 = nullptr;
+    double* part64 = nullptr;
+    float* vals32 = nullptr;
+    float* coef32 = nullptr;
+    float* part32 = nullptr;
 };
 
-void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab,
-                double tol_grid, Tree& out);
-void upload_tree(const Tree& t, hipStream_t s, DeviceTree& d);
+void upload_tree(const Tree& t, int Kstar, int p, hipStream_t s, DeviceTree& d);
 void free_tree(DeviceTree& d);
 
-// Step 2: outgoing skeleton sums onto every group's incoming grid (P2L).
+// Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per
+// grid and turned into Chebyshev-Fourier coefficients.
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
                     const T* rho);
-// Step 3 (direct form): neighbours' skeleton sums at each patch's sampling nodes; writes U.
+// Step 3 (direct form): direct-list sums at each patch's sampling nodes; writes U.
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
                      const T* skel_off, const T* rho, T* U);
-// Step 4: interpolate every ancestor group's incoming grid at the sampling nodes; adds into U.
+// Step 4: interpolate every listed incoming grid at the sampling nodes; adds into U.
 template <class T>
 hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U);
 

@@ -1,0 +1,342 @@
+// Host construction of the cube-sphere quadtree, interaction lists, bounding
+// caps, incoming-grid sizes and the device work lists (see tree_build.hpp).
+#include "tree_build.hpp"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <stdexcept>
+#include <unordered_map>
+
+namespace nce {
+
+namespace {
+
+constexpr int kLmax = 24;  // key resolution per face axis (bits)
+constexpr double kPi = 3.14159265358979323846;
+
+uint64_t spread24(uint64_t v) {
+    uint64_t r = 0;
+    for (int b = 0; b < 24; ++b) r |= ((v >> b) & 1ull) << (2 * b);
+    return r;
+}
+
+inline double geodesic(const double* a, const double* b) {
+    double cr0 = a[1] * b[2] - a[2] * b[1], cr1 = a[2] * b[0] - a[0] * b[2], cr2 = a[0] * b[1] - a[1] * b[0];
+    return std::atan2(std::sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+}
+
+void frame_of(const double* c, double* f9) {
+    double a[3] = {0, 0, 1};
+    if (std::fabs(c[2]) > 1.0 / std::sqrt(2.0)) {
+        a[0] = 1;
+        a[2] = 0;
+    }
+    double ad = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+    double e1[3] = {a[0] - ad * c[0], a[1] - ad * c[1], a[2] - ad * c[2]};
+    double n = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double& v : e1) v /= n;
+    double e2[3] = {c[1] * e1[2] - c[2] * e1[1], c[2] * e1[0] - c[0] * e1[2], c[0] * e1[1] - c[1] * e1[0]};
+    for (int k = 0; k < 3; ++k) {
+        f9[k] = c[k];
+        f9[3 + k] = e1[k];
+        f9[6 + k] = e2[k];
+    }
+}
+
+struct CornerHash {
+    size_t operator()(const std::array<int64_t, 3>& a) const {
+        uint64_t h = 1469598103934665603ull;
+        for (int64_t v : a) {
+            h ^= (uint64_t)v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+            h *= 1099511628211ull;
+        }
+        return (size_t)h;
+    }
+};
+
+struct Box {
+    int64_t first, count;  // members: sorted[first .. first+count)
+    int face;
+    int64_t ix, iy;
+    int parent;
+    std::vector<int> children;
+    std::vector<int> nbrs;
+};
+
+}  // namespace
+
+void grid_size(double rho, double tol, int& nr, int& nt) {
+    // Fourier modes of a point source at distance rho R decay like rho^-k on the
+    // circle of radius R; Chebyshev coefficients in r on [-R, R] decay like
+    // (rho + sqrt(rho^2 - 1))^-n. A margin C covers the growth of 1/d.
+    const double C = 4.0 * rho / (rho - 1.0);
+    const double lt = std::log(C / tol);
+    int kmax = (int)std::ceil(lt / std::log(rho));
+    nt = 2 * kmax + 2;
+    if (nt % 2) nt++;
+    const double rb = rho + std::sqrt(rho * rho - 1.0);
+    int ncheb = (int)std::ceil(lt / std::log(rb)) + 2;
+    nr = ncheb / 2 + 1;
+}
+
+void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab, double tol_grid,
+                Tree& out) {
+    out = Tree();
+    out.N = N;
+    const int Kstar = tab.Kstar, p = tab.p;
+    const double rho_min = 2.0;
+    const double cpair = 40.0;  // one Green's function pair in multiply-add units (cost model only)
+
+    // 1. project to the cube, face-local keys, sort
+    std::vector<uint64_t> key(N);
+    std::vector<int> face(N);
+    std::vector<int64_t> fx(N), fy(N);
+    const double scale = std::ldexp(1.0, kLmax);
+    for (int64_t i = 0; i < N; ++i) {
+        const double* c = &frames[(size_t)i * 9];
+        int a = 0;
+        for (int k = 1; k < 3; ++k)
+            if (std::fabs(c[k]) > std::fabs(c[a])) a = k;
+        const int b = (a + 1) % 3, cc = (a + 2) % 3;
+        const double u = c[b] / std::fabs(c[a]), v = c[cc] / std::fabs(c[a]);
+        face[i] = 2 * a + (c[a] >= 0 ? 0 : 1);
+        int64_t ix = (int64_t)std::floor((u + 1.0) * 0.5 * scale), iy = (int64_t)std::floor((v + 1.0) * 0.5 * scale);
+        ix = std::min<int64_t>(std::max<int64_t>(ix, 0), (1ll << kLmax) - 1);
+        iy = std::min<int64_t>(std::max<int64_t>(iy, 0), (1ll << kLmax) - 1);
+        fx[i] = ix;
+        fy[i] = iy;
+        key[i] = ((uint64_t)face[i] << 48) | spread24((uint64_t)ix) | (spread24((uint64_t)iy) << 1);
+    }
+    std::vector<int> sorted(N);
+    for (int64_t i = 0; i < N; ++i) sorted[i] = (int)i;
+    std::sort(sorted.begin(), sorted.end(), [&](int x, int y) { return key[x] < key[y]; });
+    // 2. depth: one past the deepest level at which two patches share a box
+    int L = 0;
+    for (int64_t s = 1; s < N; ++s) {
+        const uint64_t k1 = key[sorted[s - 1]], k2 = key[sorted[s]];
+        if ((k1 >> 48) != (k2 >> 48)) continue;
+        const uint64_t x = (k1 ^ k2) & ((1ull << 48) - 1);
+        if (x == 0) throw std::runtime_error("two patch centres project to the same cube point");
+        const int h = 63 - __builtin_clzll(x);
+        const int common = kLmax - 1 - h / 2;
+        L = std::max(L, common + 1);
+    }
+    if (L > 22) throw std::runtime_error("tree deeper than 22 levels");
+    out.nlevels = L + 1;
+
+    // 3. boxes per level (contiguous runs of the sorted order)
+    std::vector<std::vector<Box>> lev(L + 1);
+    std::vector<std::vector<int>> box_of(L + 1, std::vector<int>(N));  // by sorted position
+    for (int l = 0; l <= L; ++l) {
+        const int sh = 2 * (kLmax - l);
+        int64_t s = 0;
+        while (s < N) {
+            const uint64_t id = key[sorted[s]] >> sh;
+            int64_t e = s + 1;
+            while (e < N && (key[sorted[e]] >> sh) == id) ++e;
+            Box bx;
+            bx.first = s;
+            bx.count = e - s;
+            const int i0 = sorted[s];
+            bx.face = face[i0];
+            bx.ix = fx[i0] >> (kLmax - l);
+            bx.iy = fy[i0] >> (kLmax - l);
+            bx.parent = l > 0 ? box_of[l - 1][s] : -1;
+            const int idx = (int)lev[l].size();
+            for (int64_t q = s; q < e; ++q) box_of[l][q] = idx;
+            if (l > 0) lev[l - 1][bx.parent].children.push_back(idx);
+            lev[l].push_back(std::move(bx));
+            s = e;
+        }
+        // neighbours: boxes whose closed regions share a lattice corner on the cube
+        const int64_t S = 1ll << l;
+        std::unordered_map<std::array<int64_t, 3>, std::vector<int>, CornerHash> corners;
+        corners.reserve(lev[l].size() * 4);
+        auto corner = [&](const Box& bx, int di, int dj) {
+            const int a = bx.face / 2;
+            const int64_t sg = (bx.face % 2 == 0) ? 1 : -1;
+            const int b = (a + 1) % 3, cc = (a + 2) % 3;
+            std::array<int64_t, 3> P{};
+            P[a] = sg * S;
+            P[b] = 2 * (bx.ix + di) - S;
+            P[cc] = 2 * (bx.iy + dj) - S;
+            return P;
+        };
+        for (int bi = 0; bi < (int)lev[l].size(); ++bi)
+            for (int di = 0; di < 2; ++di)
+                for (int dj = 0; dj < 2; ++dj) corners[corner(lev[l][bi], di, dj)].push_back(bi);
+        for (int bi = 0; bi < (int)lev[l].size(); ++bi) {
+            std::vector<int>& nb = lev[l][bi].nbrs;
+            for (int di = 0; di < 2; ++di)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int o : corners[corner(lev[l][bi], di, dj)])
+                        if (o != bi) nb.push_back(o);
+            std::sort(nb.begin(), nb.end());
+            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        }
+    }
+
+    // 4. per patch lists
+    std::vector<std::vector<int>> direct(N);
+    std::vector<std::vector<int>> l2t(N);
+    const double* F = frames.data();
+    // grid staging
+    std::vector<std::vector<int>> grid_src;
+
+    for (int l = 0; l <= L; ++l) {
+        for (int gi = 0; gi < (int)lev[l].size(); ++gi) {
+            const Box& g = lev[l][gi];
+            // interaction list
+            std::vector<int> il;
+            if (l == 0) {
+                for (int o = 0; o < (int)lev[0].size(); ++o)
+                    if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
+            } else {
+                const Box& P = lev[l - 1][g.parent];
+                std::vector<int> cand(P.children);
+                for (int pn : P.nbrs)
+                    for (int ch : lev[l - 1][pn].children) cand.push_back(ch);
+                for (int o : cand)
+                    if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
+            }
+            if (il.empty()) continue;
+            std::vector<int> src;
+            for (int o : il)
+                for (int64_t q = lev[l][o].first; q < lev[l][o].first + lev[l][o].count; ++q) src.push_back(sorted[q]);
+            // bounding cap of the members' disks (Badoiu-Clarkson iteration, then dilation by eps)
+            double cc[3] = {0, 0, 0};
+            const int64_t m0 = g.first, mc = g.count;
+            for (int64_t q = m0; q < m0 + mc; ++q)
+                for (int k = 0; k < 3; ++k) cc[k] += F[(size_t)sorted[q] * 9 + k];
+            double nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
+            for (double& v : cc) v /= nn;
+            double best[3] = {cc[0], cc[1], cc[2]}, bestR = 1e300;
+            if (mc > 1) {
+                for (int it = 0; it < 40; ++it) {
+                    double far = -1;
+                    int64_t fi = m0;
+                    for (int64_t q = m0; q < m0 + mc; ++q) {
+                        double d = geodesic(cc, &F[(size_t)sorted[q] * 9]);
+                        if (d > far) {
+                            far = d;
+                            fi = q;
+                        }
+                    }
+                    if (far < bestR) {
+                        bestR = far;
+                        best[0] = cc[0];
+                        best[1] = cc[1];
+                        best[2] = cc[2];
+                    }
+                    const double* fp = &F[(size_t)sorted[fi] * 9];
+                    const double t = 1.0 / (it + 2.0);
+                    for (int k = 0; k < 3; ++k) cc[k] += t * (fp[k] - cc[k]);
+                    nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
+                    for (double& v : cc) v /= nn;
+                }
+            } else {
+                bestR = 0.0;
+                for (int k = 0; k < 3; ++k) best[k] = F[(size_t)sorted[m0] * 9 + k];
+            }
+            const double R = bestR + eps;
+            // sources valid for a grid: the whole cap must lie in the source's
+            // far-field region (arclength > 2 eps) and be well separated
+            std::vector<int> ok, bad;
+            double rho = 1e300;
+            for (int j : src) {
+                const double d = geodesic(best, &F[(size_t)j * 9]);
+                const double ratio = (d - eps) / R;
+                if (d - R > 2.0 * eps * (1.0 + 1e-9) && ratio >= rho_min) {
+                    ok.push_back(j);
+                    rho = std::min(rho, ratio);
+                } else {
+                    bad.push_back(j);
+                }
+            }
+            bool use_grid = false;
+            int nr = 0, nt = 0;
+            if (!ok.empty()) {
+                grid_size(rho, tol_grid, nr, nt);
+                const double q = (double)nr * nt;
+                if (nr <= kMaxGridNr && q <= kMaxGridQ) {
+                    const double cost_grid = ok.size() * q * p * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
+                    const double cost_direct = ok.size() * (double)mc * Kstar * p * cpair;
+                    use_grid = cost_grid < cost_direct;
+                }
+            }
+            if (!use_grid) {
+                bad.insert(bad.end(), ok.begin(), ok.end());
+                ok.clear();
+            }
+            for (int64_t q = m0; q < m0 + mc; ++q) {
+                std::vector<int>& dl = direct[sorted[q]];
+                dl.insert(dl.end(), bad.begin(), bad.end());
+            }
+            if (use_grid) {
+                const int gid = out.ngrid++;
+                double f9[9];
+                frame_of(best, f9);
+                out.g_frame.insert(out.g_frame.end(), f9, f9 + 9);
+                out.g_R.push_back(R);
+                out.g_nr.push_back(nr);
+                out.g_nt.push_back(nt);
+                out.g_level.push_back(l);
+                grid_src.push_back(std::move(ok));
+                for (int64_t q = m0; q < m0 + mc; ++q) l2t[sorted[q]].push_back(gid);
+            }
+        }
+    }
+    // 5. near field: neighbours at the finest level (one patch per box)
+    for (int bi = 0; bi < (int)lev[L].size(); ++bi) {
+        const Box& b = lev[L][bi];
+        const int i = sorted[b.first];
+        for (int o : b.nbrs) {
+            const Box& ob = lev[L][o];
+            for (int64_t q = ob.first; q < ob.first + ob.count; ++q) direct[i].push_back(sorted[q]);
+        }
+    }
+    // 6. flatten
+    out.g_off.resize(out.ngrid);
+    out.g_item0.resize(out.ngrid);
+    out.g_item1.resize(out.ngrid);
+    int64_t qoff = 0, poff = 0;
+    for (int g = 0; g < out.ngrid; ++g) {
+        const int q = out.g_nr[g] * out.g_nt[g];
+        out.max_q = std::max(out.max_q, q);
+        out.g_off[g] = qoff;
+        qoff += q;
+        out.g_item0[g] = (int)out.it_grid.size();
+        const std::vector<int>& s = grid_src[g];
+        for (size_t a = 0; a < s.size(); a += kSrcPerItem) {
+            const size_t e = std::min(s.size(), a + kSrcPerItem);
+            out.it_grid.push_back(g);
+            out.it_src0.push_back((int)(out.p2l_src.size() + a));
+            out.it_src1.push_back((int)(out.p2l_src.size() + e));
+            out.it_off.push_back(poff);
+            poff += q;
+        }
+        out.p2l_src.insert(out.p2l_src.end(), s.begin(), s.end());
+        out.g_item1[g] = (int)out.it_grid.size();
+        out.pairs_far += (double)s.size() * q * p;
+    }
+    out.total_q = qoff;
+    out.total_partial = poff;
+    out.dl_ptr.assign(N + 1, 0);
+    out.l2t_ptr.assign(N + 1, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        std::sort(direct[i].begin(), direct[i].end());
+        out.dl_ptr[i + 1] = out.dl_ptr[i] + (int64_t)direct[i].size();
+        out.l2t_ptr[i + 1] = out.l2t_ptr[i] + (int64_t)l2t[i].size();
+        out.pairs_near += (double)direct[i].size() * Kstar * p;
+        for (int g : l2t[i]) out.interp_fma += (double)Kstar * out.g_nr[g] * out.g_nt[g];
+    }
+    out.dl_src.reserve(out.dl_ptr[N]);
+    out.l2t_grid.reserve(out.l2t_ptr[N]);
+    for (int64_t i = 0; i < N; ++i) {
+        out.dl_src.insert(out.dl_src.end(), direct[i].begin(), direct[i].end());
+        out.l2t_grid.insert(out.l2t_grid.end(), l2t[i].begin(), l2t[i].end());
+    }
+}
+
+}  // namespace nce

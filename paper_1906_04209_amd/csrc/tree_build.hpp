@@ -1,0 +1,68 @@
+// Hierarchical far field on a cube-sphere quadtree (Section 7.2 quadtree on
+// the sphere, Section 7.3 incoming representations, Section 8 Step 2 and
+// Step 3 items 2-4).
+//
+// Patch centres are projected radially onto the circumscribed cube; each face
+// carries a quadtree refined uniformly to the depth L at which no box holds two
+// patches (empty boxes pruned). Neighbours are boxes of the same level whose
+// closed regions on the cube surface touch, so they wrap across cube edges and
+// corners. The interaction list of a box is the set of children of its
+// parent's neighbours that are not its own neighbours; at level 0 (the six
+// faces, children of the whole sphere) it is the opposite face. For every
+// ordered pair of patches the source is then either a level-L neighbour of the
+// target or in exactly one interaction list on the target's ancestor path.
+//
+// A group with interaction-list sources gets an incoming grid -- a
+// parity-restricted Chebyshev (radius in [-R, R]) x Fourier (angle) polar grid
+// in geodesic polar coordinates about its bounding cap -- when that is cheaper
+// than evaluating its sources directly at its members' sampling nodes; sources
+// too close to the cap for the grid (or outside the validity region of their
+// compressed representation, arclength > 2 eps) are summed directly instead.
+// Grid sizes follow from the distance ratio of the closest grid source and the
+// grid tolerance.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "precompute.hpp"
+
+namespace nce {
+
+constexpr int kMaxGridQ = 1024;   // grid points per incoming grid (4 per thread x 256)
+constexpr int kMaxGridNr = 16;
+constexpr int kSrcPerItem = 32;   // source patches per P2L work item
+
+struct Tree {
+    int nlevels = 0;
+    int64_t N = 0;
+    // incoming grids
+    int ngrid = 0;
+    std::vector<double> g_frame;          // ngrid x 9: cap centre, e1, e2
+    std::vector<double> g_R;              // cap radius (arclength)
+    std::vector<int> g_nr, g_nt, g_level;
+    std::vector<int64_t> g_off;           // offset of the grid's q values
+    std::vector<int> g_item0, g_item1;    // P2L items of the grid
+    int64_t total_q = 0;
+    // P2L work items: source patches p2l_src[src0 .. src1) onto grid it_grid
+    std::vector<int> it_grid, it_src0, it_src1;
+    std::vector<int64_t> it_off;          // offset of the item's partial sums
+    std::vector<int> p2l_src;
+    int64_t total_partial = 0;
+    // direct lists (near field plus far sources summed directly), CSR over targets
+    std::vector<int64_t> dl_ptr;
+    std::vector<int> dl_src;
+    // grids to interpolate at each patch's sampling nodes, CSR over patches
+    std::vector<int64_t> l2t_ptr;
+    std::vector<int> l2t_grid;
+    // work per matrix-vector product
+    double pairs_far = 0, pairs_near = 0, interp_fma = 0;
+    int max_q = 0;
+};
+
+// Grid size (n_r radial nodes on [0, R], n_theta angles) for a source at
+// distance ratio rho = (distance from the cap centre - eps) / R.
+void grid_size(double rho, double tol, int& nr, int& nt);
+
+void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab,
+                double tol_grid, Tree& out);
+}  // namespace nce

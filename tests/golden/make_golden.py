@@ -5,6 +5,8 @@ tests/golden/):
   tables/<key>.npz      oracle precompute (T, skeleton, I) per (problem, eps, M, tol_id)
   cfg1.npz              N=10 exterior, eps=0.1, seed 1: matvec of seeded x, dense-LU solve
   cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
+  cfg3_rows.npz         N=10000 exterior clustered, eps=0.005, seed 3: 12 sampled rows
+  cfg5_rows.npz         N=100000 interior, eps=0.001, seed 5: 6 sampled rows (tol_id 1e-11)
   MANIFEST.json         SHA-256 of every file, with the command that made it
 
 Run:  python tests/golden/make_golden.py [name ...]
@@ -70,7 +72,30 @@ def make_cfg2_rows():
     print(f"  cfg2 rows {rows.tolist()}", flush=True)
 
 
-JOBS = {"cfg1": make_cfg1, "cfg2_rows": make_cfg2_rows}
+def _rows_job(name, nrows, tol_id):
+    def job():
+        cfg = layouts.CONFIGS[name]
+        k = tables.key(cfg["problem"], cfg["eps"], 15, tol_id)
+        f = tables.GOLDEN_DIR / (k + ".npz")
+        if f.exists():
+            tab = tables.load(f)
+        else:
+            tab, _, _ = tables.compute(cfg["problem"], cfg["eps"], 15, tol_id)
+            tables.save(tab, f)
+        c = layouts.config_layout(cfg)
+        lay = system.Layout(c, tab)
+        x = layouts.random_coeffs(cfg["N"], tab.K, X_SEED, decay=0.1)
+        rows = np.sort(layouts.rng(ROW_SEED).choice(cfg["N"], nrows, replace=False))
+        t0 = time.time()
+        U = csum.incoming_layout(lay, x, rows)
+        y = x[rows] + U @ tab.P.T
+        np.savez(GOLD / f"{name}_rows.npz", rows=rows, y=y, x_seed=X_SEED, tol_id=tol_id)
+        print(f"  {name} rows {rows.tolist()} ({time.time() - t0:.0f} s)", flush=True)
+    return job
+
+
+JOBS = {"cfg1": make_cfg1, "cfg2_rows": make_cfg2_rows, "cfg3_rows": _rows_job("cfg3", 12, 1e-12),
+        "cfg5_rows": _rows_job("cfg5", 6, 1e-11)}
 
 
 def manifest():

@@ -1,0 +1,84 @@
+"""GPU checks of the hierarchical far field (Sections 7.2-7.3, Section 8 Step 3).
+
+The tree approximates the dense compressed sum; its error is controlled by the
+incoming-grid tolerance tol_grid (plus the ID tolerance against the oracle).
+Checks: tree vs the GPU's own direct all-pairs sum (same tables, so only the
+tree's error remains), tree vs the oracle's sampled rows at the N=1000,
+N=10000 (clustered) and N=100000 workloads, FP32 tree vs FP64 tree, and a
+tree solve against the direct solve."""
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import layouts
+
+pytestmark = pytest.mark.gpu
+GOLD = Path(__file__).resolve().parent / "golden"
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _rel(y, ref, x):
+    return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref - x)))
+
+
+@pytest.mark.parametrize("layout,N,eps,problem,tol_grid", [
+    ("uniform", 2000, 0.005, 0, 1e-8),
+    ("uniform", 2000, 0.005, 1, 1e-10),
+    ("vmf", 2000, 0.005, 1, 1e-8),
+])
+def test_tree_matches_direct(torch, layout, N, eps, problem, tol_grid):
+    import paper_1906_04209_amd as nce
+    c = layouts.uniform_centers(N, eps, 11) if layout == "uniform" else layouts.vmf_centers(N, eps, 12)
+    d = nce.Context(c, eps, problem=problem, tol_id=1e-12, far_field=nce.FAR_DIRECT)
+    t = nce.Context(c, eps, problem=problem, tol_id=1e-12, tol_grid=tol_grid, far_field=nce.FAR_TREE)
+    x_np = layouts.random_coeffs(N, d.K, 5, decay=0.1)
+    x = torch.from_numpy(x_np).cuda()
+    yd = d.matvec(x).cpu().numpy()
+    yt = t.matvec(x).cpu().numpy()
+    err = _rel(yt, yd, x_np)
+    print(f"{layout} N={N} problem={problem} tol_grid={tol_grid}: levels {t.levels} work {t.work()} err {err:.3e}")
+    assert err < 10 * tol_grid
+    ym = t.matvec(x, precision=nce.MIXED).cpu().numpy()
+    errm = _rel(ym, yd, x_np)
+    print(f"  FP32 tree vs FP64 direct {errm:.3e}")
+    assert errm < 2e-5
+
+
+@pytest.mark.parametrize("name,far", [("cfg2", "tree"), ("cfg3", "tree"), ("cfg5", "tree")])
+def test_tree_rows_vs_oracle(torch, name, far):
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / f"{name}_rows.npz")
+    cfg = layouts.CONFIGS[name]
+    tol_id = float(g["tol_id"]) if "tol_id" in g.files else 1e-12
+    c = layouts.config_layout(cfg)
+    ctx = nce.Context(c, cfg["eps"], problem=cfg["problem"], tol_id=tol_id, tol_grid=1e-8,
+                      far_field=nce.FAR_TREE)
+    x_np = layouts.random_coeffs(cfg["N"], ctx.K, 777, decay=0.1)
+    x = torch.from_numpy(x_np).cuda()
+    y = ctx.matvec(x).cpu().numpy()
+    rows = g["rows"]
+    err = _rel(y[rows], g["y"], x_np[rows])
+    print(f"{name}: levels {ctx.levels} work {ctx.work()} rows err {err:.3e}")
+    assert err < 1e-7
+
+
+def test_tree_solve_matches_direct(torch):
+    import paper_1906_04209_amd as nce
+    cfg = layouts.CONFIGS["cfg2"]
+    c = layouts.config_layout(cfg)
+    rd = nce.Context(c, cfg["eps"], problem=0, tol_id=1e-12, far_field=nce.FAR_DIRECT).solve()
+    rt = nce.Context(c, cfg["eps"], problem=0, tol_id=1e-12, tol_grid=1e-10, far_field=nce.FAR_TREE).solve()
+    rm = nce.Context(c, cfg["eps"], problem=0, tol_id=1e-12, tol_grid=1e-10, far_field=nce.FAR_TREE,
+                     precision=nce.MIXED).solve()
+    print("mu direct", rd["mu"], rd["iters_fp64"], "tree", rt["mu"], rt["iters_fp64"], "tree mixed", rm["mu"],
+          rm["iters_fp32"], rm["outer"])
+    assert rd["converged"] and rt["converged"] and rm["converged"]
+    assert abs(rt["mu"] - rd["mu"]) < 1e-9 * rd["mu"]
+    assert abs(rm["mu"] - rd["mu"]) < 1e-9 * rd["mu"]

@@ -1,0 +1,57 @@
+"""Host (CPU) checks of the library's cube-sphere tree construction: every
+ordered pair of patches is summed exactly once (near list or one interaction
+list on the target's ancestor path, as in Section 8 Step 3's note), every
+incoming grid covers its members and lies in its sources' far-field regions."""
+import subprocess
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import layouts
+
+ROOT = Path(__file__).resolve().parents[1]
+CSRC = ROOT / "paper_1906_04209_amd" / "csrc"
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    d = tmp_path_factory.mktemp("tree")
+    out = d / "tree_check"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", str(CSRC), str(ROOT / "tests" / "host" / "tree_check.cpp"),
+                           str(CSRC / "tree_build.cpp"), "-o", str(out)])
+    return out
+
+
+def _run(exe, tmp_path, c, eps, tol=1e-8):
+    f = tmp_path / "c.txt"
+    with open(f, "w") as fh:
+        fh.write(f"{len(c)}\n")
+        np.savetxt(fh, c, fmt="%.17g")
+    r = subprocess.run([str(exe), str(f), repr(eps), repr(tol)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("OK"), r.stdout
+    return r.stdout
+
+
+@pytest.mark.parametrize("N,eps,seed", [(2, 0.1, 1), (10, 0.1, 1), (300, 0.02, 3), (2000, 0.005, 4)])
+def test_uniform_coverage(exe, tmp_path, N, eps, seed):
+    print(_run(exe, tmp_path, layouts.uniform_centers(N, eps, seed), eps))
+
+
+def test_clustered_coverage(exe, tmp_path):
+    print(_run(exe, tmp_path, layouts.vmf_centers(1500, 0.005, 9), 0.005))
+
+
+def test_cube_corner_and_edges(exe, tmp_path):
+    # centres on cube edges and corners exercise the wrap-around neighbours
+    v = []
+    for s in [(1, 1, 1), (1, 1, -1), (1, -1, 1), (-1, 1, 1), (1, 0, 1), (0, 1, 1), (1, 1, 0), (-1, -1, -1)]:
+        x = np.array(s, float)
+        v.append(x / np.linalg.norm(x))
+    c = np.vstack([v, layouts.uniform_centers(200, 0.01, 12)])
+    keep = [0]
+    for i in range(1, len(c)):
+        if all(np.arccos(np.clip(c[i] @ c[k], -1, 1)) >= 0.031 for k in keep):
+            keep.append(i)
+    print(_run(exe, tmp_path, c[keep], 0.01))
