@@ -77,6 +77,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    os.environ.setdefault("NCE_CACHE", "/tmp")
     import torch
     import paper_1906_04209_amd as nce
 

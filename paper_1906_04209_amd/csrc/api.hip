@@ -77,6 +77,8 @@ struct nce_ctx {
     nce_opts opts;
     int64_t N = 0;
     int K = 0, Kstar = 0, p = 0;
+    int ptot = 0;                       // strengths per patch over all outgoing tables in use
+    std::vector<int> tab_off, tab_p;    // per table: first column and size (table 0 = base)
     double eps = 0;
     nce::PatchTables tab;
     std::vector<double> frames;  // N x 9: c, e1, e2
@@ -186,8 +188,10 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         HIPCHK(nce::cast_d2f(s, (int64_t)N * K, x, ctx->d_x32.p));
         xin = reinterpret_cast<const T*>(ctx->d_x32.p);
     }
-    // Step 1: rho_i = T f_i for every patch (one GEMM with the shared T)
-    HIPCHK(nce::gemm_nt<T>(s, N, p, K, xin, K, Tm, K, rho, p, nullptr, 0));
+    // Step 1: rho_i = T f_i for every patch and every outgoing table in use
+    // (one GEMM with the shared, concatenated T)
+    const int pt = ctx->ptot;
+    HIPCHK(nce::gemm_nt<T>(s, N, pt, K, xin, K, Tm, K, rho, pt, nullptr, 0));
     mark(1);
     if (ctx->use_tree) {
         // Step 2: far field onto incoming grids (P2L)
@@ -471,19 +475,35 @@ int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts
         }
         hipStream_t s = ctx->stream;
         const size_t n = (size_t)N * ctx->K;
+        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
+        ctx->use_tree = want_tree && N > 1;
+        // outgoing tables: the base representation, then (tree only) the
+        // recompressions for far targets, concatenated row-wise
+        std::vector<double> Tall(ctx->tab.T), soff(ctx->tab.skel_off);
+        ctx->tab_off = {0};
+        ctx->tab_p = {ctx->p};
+        if (ctx->use_tree) {
+            for (const auto& ft : ctx->tab.far) {
+                ctx->tab_off.push_back(ctx->tab_off.back() + ctx->tab_p.back());
+                ctx->tab_p.push_back(ft.p);
+                Tall.insert(Tall.end(), ft.T.begin(), ft.T.end());
+                soff.insert(soff.end(), ft.skel_off.begin(), ft.skel_off.end());
+            }
+        }
+        ctx->ptot = ctx->tab_off.back() + ctx->tab_p.back();
         ctx->d_frames.upload(ctx->frames, s);
-        ctx->d_T.upload(ctx->tab.T, s);
+        ctx->d_T.upload(Tall, s);
         ctx->d_P.upload(ctx->tab.P, s);
         ctx->d_I.upload(ctx->tab.I, s);
         ctx->d_node_off.upload(ctx->tab.node_off, s);
-        ctx->d_skel_off.upload(ctx->tab.skel_off, s);
-        ctx->d_T32.upload(to_f32(ctx->tab.T), s);
+        ctx->d_skel_off.upload(soff, s);
+        ctx->d_T32.upload(to_f32(Tall), s);
         ctx->d_P32.upload(to_f32(ctx->tab.P), s);
         ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
-        ctx->d_skel_off32.upload(to_f32(ctx->tab.skel_off), s);
-        ctx->d_rho.alloc((size_t)N * ctx->p);
+        ctx->d_skel_off32.upload(to_f32(soff), s);
+        ctx->d_rho.alloc((size_t)N * ctx->ptot);
         ctx->d_U.alloc((size_t)N * ctx->Kstar);
-        ctx->d_rho32.alloc((size_t)N * ctx->p);
+        ctx->d_rho32.alloc((size_t)N * ctx->ptot);
         ctx->d_U32.alloc((size_t)N * ctx->Kstar);
         ctx->d_x32.alloc(n);
         ctx->d_b.alloc(n);
@@ -492,11 +512,9 @@ int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts
         ctx->d_h.alloc((size_t)o.max_iter + 8);
         ctx->d_partial.alloc((size_t)nce::kReduceBlocks * ((size_t)o.max_iter + 8));
         ctx->d_scal.alloc(8);
-        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
-        if (want_tree && N > 1) {
+        if (ctx->use_tree) {
             nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
-            nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, s, ctx->dtree);
-            ctx->use_tree = true;
+            nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
         }
         HIPCHK(hipStreamSynchronize(s));
         *out = guard.release();

@@ -103,7 +103,7 @@ template <int PROB, int NPT>
 __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const double* __restrict__ frames,
                                                   const double* __restrict__ node_off,
                                                   const double* __restrict__ skel_off,
-                                                  const double* __restrict__ rho, double* __restrict__ U,
+                                                  const double* __restrict__ rho, int ldr, double* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
     extern __shared__ double sm64[];
     double* sx = sm64;
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
             sx[m] = dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]);
             sy[m] = dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]);
             sz[m] = dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]);
-            sr[m] = rho[(int64_t)j * p + m];
+            sr[m] = rho[(int64_t)j * ldr + m];
         }
         __syncthreads();
         for (int m = 0; m < p; ++m) {
@@ -163,7 +163,7 @@ template <int PROB, int NPT>
 __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const double* __restrict__ frames,
                                                   const float* __restrict__ node_off,
                                                   const float* __restrict__ skel_off,
-                                                  const float* __restrict__ rho, float* __restrict__ U,
+                                                  const float* __restrict__ rho, int ldr, float* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
     extern __shared__ float sm32[];
     float* sx = sm32;
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
             sx[m] = dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]);
             sy[m] = dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]);
             sz[m] = dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]);
-            sr[m] = rho[(int64_t)j * p + m];
+            sr[m] = rho[(int64_t)j * ldr + m];
         }
         __syncthreads();
         float aw[NPT], al[NPT];
@@ -233,38 +233,38 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
 
 template <>
 hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                            const double* node_off, const double* skel_off, const double* rho, double* U,
+                            const double* node_off, const double* skel_off, const double* rho, int ldr, double* U,
                             const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     if (problem == 1)
         hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U, lptr, lsrc);
+                           rho, ldr, U, lptr, lsrc);
     else
         hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U, lptr, lsrc);
+                           rho, ldr, U, lptr, lsrc);
     return hipGetLastError();
 }
 
 template <>
 hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                           const float* node_off, const float* skel_off, const float* rho, float* U,
+                           const float* node_off, const float* skel_off, const float* rho, int ldr, float* U,
                            const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     if (problem == 1)
         hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U, lptr, lsrc);
+                           rho, ldr, U, lptr, lsrc);
     else
         hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, U, lptr, lsrc);
+                           rho, ldr, U, lptr, lsrc);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
                       const T* skel_off, const T* rho, T* U) {
-    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, U, nullptr, nullptr);
+    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr);
 }
 template hipError_t direct_sum<double>(hipStream_t, int, int, int, int, const double*, const double*, const double*,
                                        const double*, double*);

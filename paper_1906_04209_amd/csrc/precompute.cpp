@@ -487,62 +487,21 @@ static inline double dist3(const double* a, const double* b) {
     return std::sqrt(dx * dx + dy * dy + dz * dz);
 }
 
-PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads) {
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-    PatchTables out;
-    out.problem = problem;
-    out.eps = eps;
-    out.M = M;
-    out.tol_id = tol_id;
-    std::vector<int> zn, zm;
-    zernike_modes(M, zn, zm);
-    const int K = (int)zn.size();
-    out.K = K;
-
-    // (a) one-patch solve
-    Radial R = make_radial(eps);
-    const int nr = (int)R.t.size();
-    std::vector<double> A;
-    assemble_modal(problem, R, M, A);
-    std::vector<double> sigma((size_t)K * nr);
-    for (int ma = 0; ma <= M; ++ma) {
-        std::vector<int> cols;
-        for (int k = 0; k < K; ++k)
-            if (std::abs(zm[k]) == ma) cols.push_back(k);
-        std::vector<double> Am(A.begin() + (size_t)ma * nr * nr, A.begin() + (size_t)(ma + 1) * nr * nr);
-        const int nc = (int)cols.size();
-        std::vector<double> F((size_t)nr * nc);
-        for (int i = 0; i < nr; ++i)
-            for (int c = 0; c < nc; ++c) F[(size_t)i * nc + c] = zernike_radial(zn[cols[c]], ma, R.t[i] / eps);
-        lu_solve_multi(nr, Am, nc, F);
-        for (int c = 0; c < nc; ++c)
-            for (int i = 0; i < nr; ++i) sigma[(size_t)cols[c] * nr + i] = F[(size_t)i * nc + c];
-    }
-    // fine grid: radial nodes x kThetaFine angles, index l*kThetaFine + c
-    const int nf = nr * kThetaFine;
-    std::vector<double> fxyz((size_t)nf * 3), wB((size_t)nf * K), wf(nf);
-    for (int l = 0; l < nr; ++l)
-        for (int c = 0; c < kThetaFine; ++c) {
-            const int f = l * kThetaFine + c;
-            const double th = 2.0 * kPi * c / kThetaFine;
-            polar_xyz(R.t[l], th, &fxyz[(size_t)f * 3]);
-            wf[f] = R.wsig[l] * std::sin(R.t[l]) * (2.0 * kPi / kThetaFine);
-            for (int k = 0; k < K; ++k) {
-                double ang = zm[k] >= 0 ? std::cos(zm[k] * th) : std::sin(-zm[k] * th);
-                wB[(size_t)f * K + k] = wf[f] * sigma[(size_t)k * nr + l] * ang;
-            }
-        }
-    // (c) I = w^T B
-    out.I.assign(K, 0.0);
-    for (int f = 0; f < nf; ++f)
-        for (int k = 0; k < K; ++k) out.I[k] += wB[(size_t)f * K + k];
-
-    // (b) ID of A = G(x^t, x^f): training rings on Theta, Chebyshev points in
-    // dyadic shells from 2 eps to pi, 2 * kThetaFine angles each.
+// Interpolative decomposition of A = G(x^t, x^f) for training points x^t at
+// arclength >= D from the patch centre (Section 7.1): randomized sketch,
+// column-pivoted QR, rank by tolerance relative to the largest pivot,
+// T = Pi W B and the skeleton (a subset of the fine grid).
+static FarTable compress_outgoing(int problem, double D, double tol_id, const std::vector<double>& fxyz,
+                                  const std::vector<double>& wB, int K, const std::vector<double>& rt, int ell0,
+                                  uint64_t seed) {
+    FarTable out;
+    out.D = D;
+    // training rings on the region {arclength >= D}: Chebyshev points in
+    // dyadic shells from D to pi, 2 * kThetaFine angles each.
     std::vector<double> radii;
     {
         const int per = 9;
-        double lo = 2.0 * eps;
+        double lo = D;
         const double rmax = kPi * (1.0 - 1e-6);
         radii.push_back(lo);
         while (lo < rmax) {
@@ -557,16 +516,17 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
     const int nth_t = 2 * kThetaFine;
     const int nt = (int)radii.size() * nth_t;
     out.n_train = nt;
+    const int nf = (int)(fxyz.size() / 3);
     std::vector<double> txyz((size_t)nt * 3);
     for (size_t a = 0; a < radii.size(); ++a)
         for (int c = 0; c < nth_t; ++c)
             polar_xyz(radii[a], 2.0 * kPi * c / nth_t, &txyz[((size_t)a * nth_t + c) * 3]);
 
-    int ell = 384;
+    int ell = ell0;
     std::vector<int> piv;
     std::vector<double> Rtop;   // p x nf rows of R (column order = piv)
     int p = 0;
-    std::mt19937_64 gen(0x5eed1234abcdULL);
+    std::mt19937_64 gen(seed);
     while (true) {
         std::normal_distribution<double> nd(0.0, 1.0);
         std::vector<double> Om((size_t)ell * nt);
@@ -691,7 +651,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
     for (int a = 0; a < p; ++a) {
         const int f = piv[a];
         const int l = f / kThetaFine, c = f % kThetaFine;
-        const double t = R.t[l], th = 2.0 * kPi * c / kThetaFine;
+        const double t = rt[l], th = 2.0 * kPi * c / kThetaFine;
         out.skel_t[a] = t;
         out.skel_theta[a] = th;
         const double sh = std::sin(0.5 * t);
@@ -700,7 +660,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
         out.skel_off[3 * a + 2] = std::sin(t) * std::sin(th);
     }
 
-    // self-check: far field at held-out points of Theta, skeleton vs fine grid
+    // self-check: far field at held-out points of the region, skeleton vs fine grid
     {
         std::mt19937_64 g2(77);
         std::uniform_real_distribution<double> U(0.0, 1.0);
@@ -708,8 +668,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
         double maxerr = 0.0, maxval = 0.0;
         std::vector<double> full(K), sk(K);
         for (int h = 0; h < nh; ++h) {
-            double r = (h < 12) ? 2.0 * eps * (1.0 + 1e-6)
-                                : 2.0 * eps * std::exp(U(g2) * std::log(kPi / (2.0 * eps) * 0.999));
+            double r = (h < 12) ? D * (1.0 + 1e-6) : D * std::exp(U(g2) * std::log(kPi / D * 0.999));
             double x[3];
             polar_xyz(r, 2.0 * kPi * U(g2), x);
             std::fill(full.begin(), full.end(), 0.0);
@@ -727,9 +686,86 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
                 maxval = std::max(maxval, std::fabs(full[k]));
             }
         }
-        out.id_check = maxerr / maxval;
-        if (!(out.id_check <= 100.0 * tol_id))
+        out.check = maxerr / maxval;
+        if (!(out.check <= 100.0 * tol_id))
             throw std::runtime_error("compressed outgoing representation failed its held-out check");
+    }
+
+    return out;
+}
+
+PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads) {
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    PatchTables out;
+    out.problem = problem;
+    out.eps = eps;
+    out.M = M;
+    out.tol_id = tol_id;
+    std::vector<int> zn, zm;
+    zernike_modes(M, zn, zm);
+    const int K = (int)zn.size();
+    out.K = K;
+
+    // (a) one-patch solve
+    Radial R = make_radial(eps);
+    const int nr = (int)R.t.size();
+    std::vector<double> A;
+    assemble_modal(problem, R, M, A);
+    std::vector<double> sigma((size_t)K * nr);
+    for (int ma = 0; ma <= M; ++ma) {
+        std::vector<int> cols;
+        for (int k = 0; k < K; ++k)
+            if (std::abs(zm[k]) == ma) cols.push_back(k);
+        std::vector<double> Am(A.begin() + (size_t)ma * nr * nr, A.begin() + (size_t)(ma + 1) * nr * nr);
+        const int nc = (int)cols.size();
+        std::vector<double> F((size_t)nr * nc);
+        for (int i = 0; i < nr; ++i)
+            for (int c = 0; c < nc; ++c) F[(size_t)i * nc + c] = zernike_radial(zn[cols[c]], ma, R.t[i] / eps);
+        lu_solve_multi(nr, Am, nc, F);
+        for (int c = 0; c < nc; ++c)
+            for (int i = 0; i < nr; ++i) sigma[(size_t)cols[c] * nr + i] = F[(size_t)i * nc + c];
+    }
+    // fine grid: radial nodes x kThetaFine angles, index l*kThetaFine + c
+    const int nf = nr * kThetaFine;
+    std::vector<double> fxyz((size_t)nf * 3), wB((size_t)nf * K), wf(nf);
+    for (int l = 0; l < nr; ++l)
+        for (int c = 0; c < kThetaFine; ++c) {
+            const int f = l * kThetaFine + c;
+            const double th = 2.0 * kPi * c / kThetaFine;
+            polar_xyz(R.t[l], th, &fxyz[(size_t)f * 3]);
+            wf[f] = R.wsig[l] * std::sin(R.t[l]) * (2.0 * kPi / kThetaFine);
+            for (int k = 0; k < K; ++k) {
+                double ang = zm[k] >= 0 ? std::cos(zm[k] * th) : std::sin(-zm[k] * th);
+                wB[(size_t)f * K + k] = wf[f] * sigma[(size_t)k * nr + l] * ang;
+            }
+        }
+    // (c) I = w^T B
+    out.I.assign(K, 0.0);
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < K; ++k) out.I[k] += wB[(size_t)f * K + k];
+
+    // (b) compressed outgoing representation for targets at arclength >= 2 eps
+    // (the far-field region of Section 7), then a ladder of recompressions for
+    // targets at arclength >= D_k = 2 eps 2^(k/2) (Section 8.1, additional
+    // compression of the outgoing representation).
+    {
+        FarTable base = compress_outgoing(problem, 2.0 * eps, tol_id, fxyz, wB, K, R.t, 384, 0x5eed1234abcdULL);
+        out.p = base.p;
+        out.T = base.T;
+        out.skel_t = base.skel_t;
+        out.skel_theta = base.skel_theta;
+        out.skel_off = base.skel_off;
+        out.id_check = base.check;
+        out.n_train = base.n_train;
+        int prev = base.p;
+        for (int k = 1; k < 40; ++k) {
+            const double D = 2.0 * eps * std::pow(2.0, 0.5 * k);
+            if (D > kPi / 3.0) break;
+            FarTable ft = compress_outgoing(problem, D, tol_id, fxyz, wB, K, R.t, std::min(384, prev + 64),
+                                            0x5eed1234abcdULL + 977 * k);
+            prev = ft.p;
+            out.far.push_back(std::move(ft));
+        }
     }
 
     // Zernike sampling nodes and transform P
@@ -773,7 +809,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
 
 static std::string cache_name(const std::string& dir, int problem, double eps, int M, double tol_id) {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "/nce_tables_v1_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
+    std::snprintf(buf, sizeof(buf), "/nce_tables_v2_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
     return dir + buf;
 }
 
@@ -797,7 +833,7 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
     std::ifstream f(cache_name(dir, problem, eps, M, tol_id), std::ios::binary);
     if (!f) return false;
     char magic[8];
-    if (!f.read(magic, 8) || std::memcmp(magic, "NCETAB01", 8) != 0) return false;
+    if (!f.read(magic, 8) || std::memcmp(magic, "NCETAB02", 8) != 0) return false;
     int hdr[5];
     double dh[4];
     if (!f.read((char*)hdr, sizeof(hdr)) || !f.read((char*)dh, sizeof(dh))) return false;
@@ -812,6 +848,17 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
     t.n_train = (int)dh[3];
     bool ok = rvec(f, t.skel_t) && rvec(f, t.skel_theta) && rvec(f, t.skel_off) && rvec(f, t.node_t) &&
               rvec(f, t.node_theta) && rvec(f, t.node_off) && rvec(f, t.T) && rvec(f, t.P) && rvec(f, t.I);
+    uint64_t nfar = 0;
+    ok = ok && (bool)f.read((char*)&nfar, sizeof(nfar)) && nfar < 64;
+    t.far.assign(ok ? nfar : 0, FarTable());
+    for (auto& ft : t.far) {
+        double dp[2];
+        ok = ok && (bool)f.read((char*)dp, sizeof(dp)) && rvec(f, ft.T) && rvec(f, ft.skel_t) &&
+             rvec(f, ft.skel_theta) && rvec(f, ft.skel_off);
+        ft.D = dp[0];
+        ft.p = (int)dp[1];
+        ok = ok && (int)ft.T.size() == ft.p * t.K;
+    }
     if (!ok || t.problem != problem || t.M != M || t.eps != eps) return false;
     if ((int)t.T.size() != t.p * t.K || (int)t.P.size() != t.K * t.Kstar) return false;
     return true;
@@ -824,7 +871,7 @@ void save_tables(const std::string& dir, const PatchTables& t) {
     {
         std::ofstream f(tmp, std::ios::binary);
         if (!f) return;
-        f.write("NCETAB01", 8);
+        f.write("NCETAB02", 8);
         int hdr[5] = {t.problem, t.M, t.K, t.Kstar, t.p};
         double dh[4] = {t.eps, t.tol_id, t.id_check, (double)t.n_train};
         f.write((const char*)hdr, sizeof(hdr));
@@ -838,6 +885,16 @@ void save_tables(const std::string& dir, const PatchTables& t) {
         wvec(f, t.T);
         wvec(f, t.P);
         wvec(f, t.I);
+        uint64_t nfar = t.far.size();
+        f.write((const char*)&nfar, sizeof(nfar));
+        for (const auto& ft : t.far) {
+            double dp[2] = {ft.D, (double)ft.p};
+            f.write((const char*)dp, sizeof(dp));
+            wvec(f, ft.T);
+            wvec(f, ft.skel_t);
+            wvec(f, ft.skel_theta);
+            wvec(f, ft.skel_off);
+        }
     }
     std::rename(tmp.c_str(), name.c_str());
 }

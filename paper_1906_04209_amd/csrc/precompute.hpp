@@ -12,6 +12,18 @@
 
 namespace nce {
 
+// Compressed outgoing representation valid for targets at arclength >= D from
+// the source patch centre: p skeleton points (a subset of the fine grid) and
+// T (p x K), rho = T f (Section 7.1; Section 8.1 for D > 2 eps).
+struct FarTable {
+    double D = 0;
+    int p = 0;
+    std::vector<double> T;                          // p x K
+    std::vector<double> skel_t, skel_theta, skel_off;
+    double check = 0;
+    int n_train = 0;
+};
+
 struct PatchTables {
     int problem = 0;     // 0 interior, 1 exterior
     double eps = 0;
@@ -29,6 +41,8 @@ struct PatchTables {
     std::vector<double> T;   // p x K, row-major
     std::vector<double> P;   // K x K*, row-major
     std::vector<double> I;   // K
+    // recompressions for targets beyond D_k = 2 eps 2^(k/2), k = 1, 2, ...
+    std::vector<FarTable> far;
     // diagnostics of the build
     double id_check = 0;     // held-out far-field error / max field
     int n_train = 0;

@@ -34,24 +34,26 @@ __device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, doub
 
 // ----------------------------------------------------------------- P2L
 // One block per work item (one grid, up to kSrcPerItem source patches); each
-// thread owns NPT grid points; source skeleton points and strengths are staged
-// in LDS relative to the grid's cap centre. Partial sums per item.
+// thread owns NPT grid points. The item's source skeleton points (of the
+// outgoing table its grid uses) and strengths are staged in LDS in batches of
+// kStage points, positions relative to the grid's cap centre. Partial sums per
+// item are written to `part`.
+constexpr int kStage = 1024;
+
 template <int PROB, int NPT>
 __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
                                                const double* __restrict__ g_R, const int* __restrict__ g_nr,
-                                               const int* __restrict__ g_nt, const double* __restrict__ frames,
-                                               const double* __restrict__ skel_off, const double* __restrict__ rho,
-                                               int p, double* __restrict__ part) {
-    extern __shared__ double sh64[];
-    double* sx = sh64;
-    double* sy = sx + p;
-    double* sz = sy + p;
-    double* sr = sz + p;
+                                               const int* __restrict__ g_nt, const int* __restrict__ g_table,
+                                               const int* __restrict__ t_off, const int* __restrict__ t_p,
+                                               const double* __restrict__ frames, const double* __restrict__ skel_off,
+                                               const double* __restrict__ rho, int ptot, double* __restrict__ part) {
+    __shared__ double sx[kStage], sy[kStage], sz[kStage], sr[kStage];
     const int item = blockIdx.x;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
     const double R = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
@@ -68,20 +70,23 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             zz[r] = o0 * fg[2] + o1 * fg[5] + o2 * fg[8];
         }
     }
-    for (int qq = it_src0[item]; qq < it_src1[item]; ++qq) {
-        const int j = src[qq];
-        const double* fj = frames + 9 * (int64_t)j;
-        const double dcx = fj[0] - fg[0], dcy = fj[1] - fg[1], dcz = fj[2] - fg[2];
+    const int s0 = it_src0[item];
+    const int total = (it_src1[item] - s0) * pt;
+    for (int c0 = 0; c0 < total; c0 += kStage) {
+        const int cl = min(kStage, total - c0);
         __syncthreads();
-        for (int m = threadIdx.x; m < p; m += blockDim.x) {
-            const double o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
-            sx[m] = dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]);
-            sy[m] = dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]);
-            sz[m] = dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]);
-            sr[m] = rho[(int64_t)j * p + m];
+        for (int idx = threadIdx.x; idx < cl; idx += blockDim.x) {
+            const int e = c0 + idx, js = e / pt, m = e - js * pt;
+            const int j = src[s0 + js];
+            const double* fj = frames + 9 * (int64_t)j;
+            const double* o = skel_off + 3 * (int64_t)(toff + m);
+            sx[idx] = (fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]);
+            sy[idx] = (fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]);
+            sz[idx] = (fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]);
+            sr[idx] = rho[(int64_t)j * ptot + toff + m];
         }
         __syncthreads();
-        for (int m = 0; m < p; ++m) {
+        for (int m = 0; m < cl; ++m) {
             const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
@@ -103,17 +108,15 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
                                                const double* __restrict__ g_R, const int* __restrict__ g_nr,
-                                               const int* __restrict__ g_nt, const double* __restrict__ frames,
-                                               const float* __restrict__ skel_off, const float* __restrict__ rho,
-                                               int p, float* __restrict__ part) {
-    extern __shared__ float sh32[];
-    float* sx = sh32;
-    float* sy = sx + p;
-    float* sz = sy + p;
-    float* sr = sz + p;
+                                               const int* __restrict__ g_nt, const int* __restrict__ g_table,
+                                               const int* __restrict__ t_off, const int* __restrict__ t_p,
+                                               const double* __restrict__ frames, const float* __restrict__ skel_off,
+                                               const float* __restrict__ rho, int ptot, float* __restrict__ part) {
+    __shared__ float sx[kStage], sy[kStage], sz[kStage], sr[kStage];
     const int item = blockIdx.x;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
     const double R = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     float zx[NPT], zy[NPT], zz[NPT];
@@ -133,35 +136,42 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
     }
     constexpr float kLn2 = 0.69314718055994530942f;
     constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
-    for (int qq = it_src0[item]; qq < it_src1[item]; ++qq) {
-        const int j = src[qq];
-        const double* fj = frames + 9 * (int64_t)j;
-        const float dcx = (float)(fj[0] - fg[0]), dcy = (float)(fj[1] - fg[1]), dcz = (float)(fj[2] - fg[2]);
+    const int s0 = it_src0[item];
+    const int total = (it_src1[item] - s0) * pt;
+    for (int c0 = 0; c0 < total; c0 += kStage) {
+        const int cl = min(kStage, total - c0);
         __syncthreads();
-        for (int m = threadIdx.x; m < p; m += blockDim.x) {
-            const float o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
-            sx[m] = dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]);
-            sy[m] = dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]);
-            sz[m] = dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]);
-            sr[m] = rho[(int64_t)j * p + m];
+        for (int idx = threadIdx.x; idx < cl; idx += blockDim.x) {
+            const int e = c0 + idx, js = e / pt, m = e - js * pt;
+            const int j = src[s0 + js];
+            const double* fj = frames + 9 * (int64_t)j;
+            const float* o = skel_off + 3 * (int64_t)(toff + m);
+            sx[idx] = (float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]);
+            sy[idx] = (float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]);
+            sz[idx] = (float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]);
+            sr[idx] = rho[(int64_t)j * ptot + toff + m];
         }
         __syncthreads();
-        float aw[NPT], al[NPT];
+        // FP32 sums over at most 256 points, carried in FP64 between batches
+        for (int m0 = 0; m0 < cl; m0 += 256) {
+            const int m1 = min(cl, m0 + 256);
+            float aw[NPT], al[NPT];
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
-        for (int m = 0; m < p; ++m) {
-            const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+            for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
+            for (int m = m0; m < m1; ++m) {
+                const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
-                float w, l2;
-                green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
-                aw[r] += w * rr;
-                al[r] += l2 * rr;
+                for (int r = 0; r < NPT; ++r) {
+                    const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                    float w, l2;
+                    green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                    aw[r] += w * rr;
+                    al[r] += l2 * rr;
+                }
             }
-        }
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+            for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+        }
     }
     const int64_t off = it_off[item];
 #pragma unroll
@@ -329,8 +339,13 @@ T* dev_alloc(int64_t n) {
 
 }  // namespace
 
-void upload_tree(const Tree& t, int Kstar, int p, hipStream_t, DeviceTree& d) {
+void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
+                 hipStream_t, DeviceTree& d) {
     d.ngrid = t.ngrid;
+    d.ptot = tab_off.back() + tab_p.back();
+    d.g_table = dev_copy(t.g_table);
+    d.t_off = dev_copy(tab_off);
+    d.t_p = dev_copy(tab_p);
     d.nitems = (int)t.it_grid.size();
     d.N = t.N;
     d.Kstar = Kstar;
@@ -360,7 +375,7 @@ void upload_tree(const Tree& t, int Kstar, int p, hipStream_t, DeviceTree& d) {
 }
 
 void free_tree(DeviceTree& d) {
-    void* ptrs[] = {d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
+    void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32};
     for (void* q : ptrs)
@@ -372,15 +387,14 @@ template <>
 hipError_t tree_far<double>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
                             const double* skel_off, const double* rho) {
     if (d.nitems > 0) {
-        const size_t sh = 4 * sizeof(double) * (size_t)d.p;
         if (problem == 1)
-            hipLaunchKernelGGL((k_p2l64<1, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
-                               d.part64);
+            hipLaunchKernelGGL((k_p2l64<1, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
+                               frames, skel_off, rho, d.ptot, d.part64);
         else
-            hipLaunchKernelGGL((k_p2l64<0, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
-                               d.part64);
+            hipLaunchKernelGGL((k_p2l64<0, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
+                               frames, skel_off, rho, d.ptot, d.part64);
     }
     if (d.ngrid > 0)
         hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
@@ -392,15 +406,14 @@ template <>
 hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
                            const float* skel_off, const float* rho) {
     if (d.nitems > 0) {
-        const size_t sh = 4 * sizeof(float) * (size_t)d.p;
         if (problem == 1)
-            hipLaunchKernelGGL((k_p2l32<1, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
-                               d.part32);
+            hipLaunchKernelGGL((k_p2l32<1, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
+                               frames, skel_off, rho, d.ptot, d.part32);
         else
-            hipLaunchKernelGGL((k_p2l32<0, 4>), dim3(d.nitems), dim3(256), sh, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, frames, skel_off, rho, d.p,
-                               d.part32);
+            hipLaunchKernelGGL((k_p2l32<0, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
+                               frames, skel_off, rho, d.ptot, d.part32);
     }
     if (d.ngrid > 0)
         hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
@@ -411,7 +424,9 @@ hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, cons
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
                      const T* skel_off, const T* rho, T* U) {
-    return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, U, d.dl_ptr, d.dl_src);
+    // near field uses the base table (the first p columns of every strength row)
+    return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, d.ptot, U, d.dl_ptr,
+                       d.dl_src);
 }
 template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
                                       const double*, const double*, double*);

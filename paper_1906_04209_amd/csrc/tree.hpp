@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "tree_build.hpp"
 
 namespace nce {
@@ -10,6 +12,10 @@ struct DeviceTree {
     int ngrid = 0, nitems = 0;
     int64_t N = 0;
     int Kstar = 0, p = 0;
+    int ptot = 0;              // row length of the strengths (all outgoing tables)
+    int* g_table = nullptr;    // per grid: outgoing table index
+    int* t_off = nullptr;      // per table: first strength column / skeleton point
+    int* t_p = nullptr;        // per table: skeleton size
     double* g_frame = nullptr;
     double* g_R = nullptr;
     int* g_nr = nullptr;
@@ -35,7 +41,10 @@ struct DeviceTree {
     float* part32 = nullptr;
 };
 
-void upload_tree(const Tree& t, int Kstar, int p, hipStream_t s, DeviceTree& d);
+// tab_off / tab_p: offsets and sizes of the outgoing tables in the
+// concatenated skeleton and strength arrays (table 0 = base, first).
+void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
+                 hipStream_t s, DeviceTree& d);
 void free_tree(DeviceTree& d);
 
 // Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per

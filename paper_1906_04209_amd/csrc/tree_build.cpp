@@ -69,15 +69,13 @@ struct Box {
 void grid_size(double rho, double tol, int& nr, int& nt) {
     // Fourier modes of a point source at distance rho R decay like rho^-k on the
     // circle of radius R; Chebyshev coefficients in r on [-R, R] decay like
-    // (rho + sqrt(rho^2 - 1))^-n. A margin C covers the growth of 1/d.
-    const double C = 4.0 * rho / (rho - 1.0);
-    const double lt = std::log(C / tol);
-    int kmax = (int)std::ceil(lt / std::log(rho));
-    nt = 2 * kmax + 2;
-    if (nt % 2) nt++;
+    // (rho + sqrt(rho^2 - 1))^-n. The counts below were checked numerically
+    // (a point source of G at ratio rho, interpolated on caps of radius 1e-3 to
+    // 0.5) to reach the tolerance relative to the source's maximum on the cap.
+    const double lt = std::log(1.0 / tol);
+    nt = 2 * (int)std::ceil(lt / std::log(rho));
     const double rb = rho + std::sqrt(rho * rho - 1.0);
-    int ncheb = (int)std::ceil(lt / std::log(rb)) + 2;
-    nr = ncheb / 2 + 1;
+    nr = (int)std::ceil(lt / std::log(rb)) / 2 + 1;
 }
 
 void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab, double tol_grid,
@@ -184,7 +182,10 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     // grid staging
     std::vector<std::vector<int>> grid_src;
 
+    // sources handed down from a parent whose cap was too close to them
+    std::vector<std::vector<int>> deferred(lev[0].size()), deferred_next;
     for (int l = 0; l <= L; ++l) {
+        if (l < L) deferred_next.assign(lev[l + 1].size(), std::vector<int>());
         for (int gi = 0; gi < (int)lev[l].size(); ++gi) {
             const Box& g = lev[l][gi];
             // interaction list
@@ -200,8 +201,9 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
                 for (int o : cand)
                     if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
             }
-            if (il.empty()) continue;
             std::vector<int> src;
+            src.swap(deferred[gi]);
+            if (il.empty() && src.empty()) continue;
             for (int o : il)
                 for (int64_t q = lev[l][o].first; q < lev[l][o].first + lev[l][o].count; ++q) src.push_back(sorted[q]);
             // bounding cap of the members' disks (Badoiu-Clarkson iteration, then dilation by eps)
@@ -243,24 +245,31 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             // sources valid for a grid: the whole cap must lie in the source's
             // far-field region (arclength > 2 eps) and be well separated
             std::vector<int> ok, bad;
-            double rho = 1e300;
+            double rho = 1e300, dmin = 1e300;
             for (int j : src) {
                 const double d = geodesic(best, &F[(size_t)j * 9]);
                 const double ratio = (d - eps) / R;
                 if (d - R > 2.0 * eps * (1.0 + 1e-9) && ratio >= rho_min) {
                     ok.push_back(j);
                     rho = std::min(rho, ratio);
+                    dmin = std::min(dmin, d - R);
                 } else {
                     bad.push_back(j);
                 }
             }
             bool use_grid = false;
-            int nr = 0, nt = 0;
+            int nr = 0, nt = 0, table = 0, pt = p;
             if (!ok.empty()) {
+                // the cheapest outgoing table valid at the grid's closest point
+                for (size_t k = 0; k < tab.far.size(); ++k)
+                    if (tab.far[k].D <= dmin && tab.far[k].p < pt) {
+                        table = (int)k + 1;
+                        pt = tab.far[k].p;
+                    }
                 grid_size(rho, tol_grid, nr, nt);
                 const double q = (double)nr * nt;
                 if (nr <= kMaxGridNr && q <= kMaxGridQ) {
-                    const double cost_grid = ok.size() * q * p * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
+                    const double cost_grid = ok.size() * q * pt * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
                     const double cost_direct = ok.size() * (double)mc * Kstar * p * cpair;
                     use_grid = cost_grid < cost_direct;
                 }
@@ -269,9 +278,19 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
                 bad.insert(bad.end(), ok.begin(), ok.end());
                 ok.clear();
             }
-            for (int64_t q = m0; q < m0 + mc; ++q) {
-                std::vector<int>& dl = direct[sorted[q]];
-                dl.insert(dl.end(), bad.begin(), bad.end());
+            if (!bad.empty()) {
+                if (l < L) {
+                    // retry at the children: smaller caps, larger distance ratios
+                    for (int ch : g.children) {
+                        std::vector<int>& dn = deferred_next[ch];
+                        dn.insert(dn.end(), bad.begin(), bad.end());
+                    }
+                } else {
+                    for (int64_t q = m0; q < m0 + mc; ++q) {
+                        std::vector<int>& dl = direct[sorted[q]];
+                        dl.insert(dl.end(), bad.begin(), bad.end());
+                    }
+                }
             }
             if (use_grid) {
                 const int gid = out.ngrid++;
@@ -282,10 +301,12 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
                 out.g_nr.push_back(nr);
                 out.g_nt.push_back(nt);
                 out.g_level.push_back(l);
+                out.g_table.push_back(table);
                 grid_src.push_back(std::move(ok));
                 for (int64_t q = m0; q < m0 + mc; ++q) l2t[sorted[q]].push_back(gid);
             }
         }
+        if (l < L) deferred.swap(deferred_next);
     }
     // 5. near field: neighbours at the finest level (one patch per box)
     for (int bi = 0; bi < (int)lev[L].size(); ++bi) {
@@ -318,7 +339,8 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         }
         out.p2l_src.insert(out.p2l_src.end(), s.begin(), s.end());
         out.g_item1[g] = (int)out.it_grid.size();
-        out.pairs_far += (double)s.size() * q * p;
+        const int pg = out.g_table[g] == 0 ? p : tab.far[out.g_table[g] - 1].p;
+        out.pairs_far += (double)s.size() * q * pg;
     }
     out.total_q = qoff;
     out.total_partial = poff;

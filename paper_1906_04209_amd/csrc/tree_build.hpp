@@ -40,6 +40,7 @@ struct Tree {
     std::vector<double> g_frame;          // ngrid x 9: cap centre, e1, e2
     std::vector<double> g_R;              // cap radius (arclength)
     std::vector<int> g_nr, g_nt, g_level;
+    std::vector<int> g_table;             // outgoing table: 0 = base (D = 2 eps), k = far[k-1]
     std::vector<int64_t> g_off;           // offset of the grid's q values
     std::vector<int> g_item0, g_item1;    // P2L items of the grid
     int64_t total_q = 0;

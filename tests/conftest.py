@@ -9,3 +9,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+def pytest_sessionstart(session):
+    # one per-eps table cache for the whole session (the library reads NCE_CACHE)
+    import tempfile
+    os.environ.setdefault("NCE_CACHE", tempfile.mkdtemp(prefix="nce_cache_"))
