@@ -33,14 +33,24 @@ __device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, doub
 }
 
 // ----------------------------------------------------------------- P2L
-// One block per work item (one grid, up to kSrcPerItem source patches); each
-// thread owns NPT grid points. The item's source skeleton points (of the
-// outgoing table its grid uses) and strengths are staged in LDS in batches of
-// kStage points, positions relative to the grid's cap centre. Partial sums per
-// item are written to `part`.
+// One block per work item (one grid, up to kSrcPerItem source patches). The
+// 256 threads are split into ns groups; each thread owns up to 4 grid points
+// (spaced qq = ceil(q/4) apart) and takes every ns-th staged source point, so
+// small grids still keep every lane busy. The item's source skeleton points
+// (of the outgoing table its grid uses) and strengths are staged in LDS in
+// batches of kStage points, positions relative to the grid's cap centre. The
+// groups' partial sums are combined in LDS and written per item to `part`.
 constexpr int kStage = 1024;
 
-template <int PROB, int NPT>
+__device__ __forceinline__ void p2l_layout(int q, int& qq, int& ns, int& split, int& t0) {
+    qq = (q + 3) / 4;
+    ns = 256 / qq;
+    ns = ns < 1 ? 1 : (ns > 64 ? 64 : ns);
+    split = threadIdx.x / qq;
+    t0 = threadIdx.x - split * qq;
+}
+
+template <int PROB>
 __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
@@ -56,13 +66,16 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
     const double R = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
-    double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
+    int qq, ns, split, t0;
+    p2l_layout(q, qq, ns, split, t0);
+    const bool active = split < ns;
+    double zx[4], zy[4], zz[4], acc[4];
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int t = threadIdx.x + r * blockDim.x;
+    for (int r = 0; r < 4; ++r) {
+        const int t = t0 + r * qq;
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
-        if (t < q) {
+        if (active && t < q) {
             double o0, o1, o2;
             grid_point(t, nr, nt, R, o0, o1, o2);
             zx[r] = o0 * fg[0] + o1 * fg[3] + o2 * fg[6];
@@ -86,24 +99,35 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             sr[idx] = rho[(int64_t)j * ptot + toff + m];
         }
         __syncthreads();
-        for (int m = 0; m < cl; ++m) {
-            const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+        if (active) {
+            for (int m = split; m < cl; m += ns) {
+                const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
-                acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+                for (int r = 0; r < 4; ++r) {
+                    const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                    acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+                }
             }
         }
     }
-    const int64_t off = it_off[item];
+    __syncthreads();
+    double* red = sx;  // ns * q <= 1024 partial sums
+    if (active)
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int t = threadIdx.x + r * blockDim.x;
-        if (t < q) part[off + t] = acc[r];
+        for (int r = 0; r < 4; ++r) {
+            const int t = t0 + r * qq;
+            if (t < q) red[split * q + t] = acc[r];
+        }
+    __syncthreads();
+    const int64_t off = it_off[item];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) {
+        double v = 0.0;
+        for (int sp = 0; sp < ns; ++sp) v += red[sp * q + t];
+        part[off + t] = v;
     }
 }
 
-template <int PROB, int NPT>
+template <int PROB>
 __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
@@ -113,20 +137,24 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part) {
     __shared__ float sx[kStage], sy[kStage], sz[kStage], sr[kStage];
+    __shared__ double red[kStage];
     const int item = blockIdx.x;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
     const double R = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
-    float zx[NPT], zy[NPT], zz[NPT];
-    double acc[NPT];
+    int qq, ns, split, t0;
+    p2l_layout(q, qq, ns, split, t0);
+    const bool active = split < ns;
+    float zx[4], zy[4], zz[4];
+    double acc[4];
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int t = threadIdx.x + r * blockDim.x;
+    for (int r = 0; r < 4; ++r) {
+        const int t = t0 + r * qq;
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0f;
-        if (t < q) {
+        if (active && t < q) {
             double o0, o1, o2;
             grid_point(t, nr, nt, R, o0, o1, o2);
             zx[r] = (float)(o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
@@ -152,32 +180,42 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
             sr[idx] = rho[(int64_t)j * ptot + toff + m];
         }
         __syncthreads();
-        // FP32 sums over at most 256 points, carried in FP64 between batches
-        for (int m0 = 0; m0 < cl; m0 += 256) {
-            const int m1 = min(cl, m0 + 256);
-            float aw[NPT], al[NPT];
+        if (active) {
+            // FP32 sums over at most 256 points, carried in FP64 between runs
+            for (int m0 = split; m0 < cl; m0 += 256 * ns) {
+                const int m1 = min(cl, m0 + 256 * ns);
+                float aw[4], al[4];
 #pragma unroll
-            for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
-            for (int m = m0; m < m1; ++m) {
-                const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+                for (int r = 0; r < 4; ++r) aw[r] = al[r] = 0.0f;
+                for (int m = m0; m < m1; m += ns) {
+                    const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
-                for (int r = 0; r < NPT; ++r) {
-                    const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
-                    float w, l2;
-                    green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
-                    aw[r] += w * rr;
-                    al[r] += l2 * rr;
+                    for (int r = 0; r < 4; ++r) {
+                        const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                        float w, l2;
+                        green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                        aw[r] += w * rr;
+                        al[r] += l2 * rr;
+                    }
                 }
-            }
 #pragma unroll
-            for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+                for (int r = 0; r < 4; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+            }
         }
     }
-    const int64_t off = it_off[item];
+    __syncthreads();
+    if (active)
 #pragma unroll
-    for (int r = 0; r < NPT; ++r) {
-        const int t = threadIdx.x + r * blockDim.x;
-        if (t < q) part[off + t] = (float)acc[r];
+        for (int r = 0; r < 4; ++r) {
+            const int t = t0 + r * qq;
+            if (t < q) red[split * q + t] = acc[r];
+        }
+    __syncthreads();
+    const int64_t off = it_off[item];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) {
+        double v = 0.0;
+        for (int sp = 0; sp < ns; ++sp) v += red[sp * q + t];
+        part[off + t] = (float)v;
     }
 }
 
@@ -194,9 +232,13 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
                                                      T* __restrict__ vals, T* __restrict__ coef) {
     __shared__ double sv[kMaxGridQ];
     __shared__ double sa[kMaxGridQ];
+    __shared__ double tc[256], ts[256], tch[8 * kMaxGridNr];
     const int g = blockIdx.x;
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int i0 = g_item0[g], i1 = g_item1[g];
+    // trigonometric tables: cos, sin(2 pi j / nt) and cos(2 pi j / (8 nr))
+    for (int j = threadIdx.x; j < nt; j += blockDim.x) sincospi(2.0 * j / nt, &ts[j], &tc[j]);
+    for (int j = threadIdx.x; j < 8 * nr; j += blockDim.x) tch[j] = cospi(2.0 * j / (8.0 * nr));
     for (int t = threadIdx.x; t < q; t += blockDim.x) {
         double s = 0.0;
         for (int it = i0; it < i1; ++it) s += (double)part[it_off[it] + t];
@@ -212,25 +254,23 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
         const int k = is_sin ? m - half : m;
         const double wgt = (k == 0 || k == half) ? 1.0 / nt : 2.0 / nt;
         double s = 0.0;
+        int red = 0;
         for (int b = 0; b < nt; ++b) {
-            const int red = (k * b) % nt;
-            double sn, cs;
-            sincospi(2.0 * red / nt, &sn, &cs);
-            s += sv[a * nt + b] * (is_sin ? sn : cs);
+            s += sv[a * nt + b] * (is_sin ? ts[red] : tc[red]);
+            red += k;
+            if (red >= nt) red -= nt;
         }
         sa[idx] = wgt * s;
     }
     __syncthreads();
-    // radial transform on the positive first-kind Chebyshev nodes (parity)
+    // radial transform on the positive first-kind Chebyshev nodes (parity):
+    // T_n(x_a) = cos(2 pi n (2a+1) / (8 nr))
     for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
         const int m = idx / nr, np = idx - m * nr;
         const int k = m > half ? m - half : m;
         const int n = 2 * np + (k & 1);
         double s = 0.0;
-        for (int a = 0; a < nr; ++a) {
-            const int red = (n * (2 * a + 1)) % (8 * nr);
-            s += sa[m * nr + a] * cospi(2.0 * red / (8.0 * nr));
-        }
+        for (int a = 0; a < nr; ++a) s += sa[m * nr + a] * tch[(n * (2 * a + 1)) % (8 * nr)];
         coef[g_off[g] + idx] = (T)((n == 0 ? 1.0 : 2.0) / nr * s);
     }
 }
@@ -388,11 +428,11 @@ hipError_t tree_far<double>(hipStream_t s, const DeviceTree& d, int problem, con
                             const double* skel_off, const double* rho) {
     if (d.nitems > 0) {
         if (problem == 1)
-            hipLaunchKernelGGL((k_p2l64<1, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+            hipLaunchKernelGGL((k_p2l64<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
                                frames, skel_off, rho, d.ptot, d.part64);
         else
-            hipLaunchKernelGGL((k_p2l64<0, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+            hipLaunchKernelGGL((k_p2l64<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
                                frames, skel_off, rho, d.ptot, d.part64);
     }
@@ -407,11 +447,11 @@ hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, cons
                            const float* skel_off, const float* rho) {
     if (d.nitems > 0) {
         if (problem == 1)
-            hipLaunchKernelGGL((k_p2l32<1, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+            hipLaunchKernelGGL((k_p2l32<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
                                frames, skel_off, rho, d.ptot, d.part32);
         else
-            hipLaunchKernelGGL((k_p2l32<0, 4>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+            hipLaunchKernelGGL((k_p2l32<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
                                frames, skel_off, rho, d.ptot, d.part32);
     }

@@ -268,7 +268,7 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
                     }
                 grid_size(rho, tol_grid, nr, nt);
                 const double q = (double)nr * nt;
-                if (nr <= kMaxGridNr && q <= kMaxGridQ) {
+                if (nr <= kMaxGridNr && nt <= kMaxGridNt && q <= kMaxGridQ) {
                     const double cost_grid = ok.size() * q * pt * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
                     const double cost_direct = ok.size() * (double)mc * Kstar * p * cpair;
                     use_grid = cost_grid < cost_direct;

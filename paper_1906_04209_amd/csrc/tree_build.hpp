@@ -30,6 +30,7 @@ namespace nce {
 
 constexpr int kMaxGridQ = 1024;   // grid points per incoming grid (4 per thread x 256)
 constexpr int kMaxGridNr = 16;
+constexpr int kMaxGridNt = 256;
 constexpr int kSrcPerItem = 32;   // source patches per P2L work item
 
 struct Tree {
