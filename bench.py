@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg5", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--solve", action="store_true", help="also time FP64 and mixed solves to 1e-8")
+    ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and mixed solves to 1e-8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tol-id", type=float, default=1e-11)
     args = ap.parse_args()
@@ -131,17 +131,21 @@ def main():
                      "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }
-    if args.solve:
+    if not args.no_solve:
+        # time to a 1e-8 relative residual (FP64-verified), from x0 = 0
         for name, pr in (("fp64", nce.FP64), ("mixed", nce.MIXED)):
-            c2 = nce.Context(centers, cfg["eps"], problem=cfg["problem"], tol_id=args.tol_id, far_field=far,
-                             tol_gmres=1e-8, precision=pr)
-            r = c2.solve(want_coeffs=False)
+            ctx.set_solver(1e-8, 100, pr)
+            r = ctx.solve(want_coeffs=False, want_flux=False)
             key = "mu" if cfg["problem"] == 0 else "capture_rate"
             out[f"solve_{name}"] = {k: r[k] for k in ("iters_fp64", "iters_fp32", "outer", "rel_residual",
                                                        "t_solve_s", "converged")}
             out[f"solve_{name}"][key] = r[key]
             log(f"solve {name}: {out[f'solve_{name}']}")
-            c2.close()
+        a, b = out["solve_fp64"], out["solve_mixed"]
+        key = "mu" if cfg["problem"] == 0 else "capture_rate"
+        out["time_to_1e-8_s"] = {"fp64": a["t_solve_s"], "mixed": b["t_solve_s"],
+                                 "speedup": a["t_solve_s"] / b["t_solve_s"],
+                                 f"rel_diff_{key}": abs(a[key] - b[key]) / abs(a[key])}
     if not args.no_cpu_baseline:
         cb, rows, yref = cpu_baseline(cfg, args.tol_id, x_np, centers)
         yg = y.cpu().numpy()[rows] if args.precision == "fp64" else None

@@ -142,6 +142,13 @@ int nce_matvec_profile(nce_ctx *ctx, const double *x_dev, double *y_dev, int pre
                        double *step_ms_host);
 
 /*
+ * Change the solver settings of an existing context (tables and tree are
+ * kept): relative residual tolerance, iteration limit, NCE_FP64 or NCE_MIXED.
+ * Errors: NCE_EINVAL for values outside the ranges nce_setup accepts.
+ */
+int nce_set_solver(nce_ctx *ctx, double tol_gmres, int max_iter, int precision);
+
+/*
  * Solve the interior problem (Section 2.3): GMRES (opts.precision FP64), or
  * FP32 inner GMRES inside FP64 iterative refinement (NCE_MIXED), to
  * opts.tol_gmres, optionally from the learned warm start.

@@ -26,7 +26,7 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 
 # every symbol include/nce.h declares
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
-           "nce_matvec", "nce_matvec_profile", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
+           "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
            "nce_strerror", "nce_last_error"]
 
 
@@ -77,6 +77,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_work.argtypes = [vp, dp, dp, dp]
     lib.nce_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nce_matvec_profile.argtypes = [vp, vp, vp, ctypes.c_int, vp]
+    lib.nce_set_solver.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
     lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
     lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
     lib.nce_integral_vector.argtypes = [vp, vp]
@@ -84,7 +85,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_strerror.restype = ctypes.c_char_p
     lib.nce_last_error.argtypes = []
     lib.nce_last_error.restype = ctypes.c_char_p
-    for name in ("nce_setup", "nce_dims", "nce_frames", "nce_work", "nce_matvec", "nce_matvec_profile", "nce_solve_interior",
+    for name in ("nce_setup", "nce_dims", "nce_frames", "nce_work", "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior",
                  "nce_solve_exterior", "nce_integral_vector"):
         getattr(lib, name).restype = ctypes.c_int
     if path is None:
@@ -201,6 +202,9 @@ class Context:
         _check(self.lib, self.lib.nce_matvec_profile(self.h, _ptr(x), _ptr(y), int(precision), ms.ctypes.data))
         self._leave()
         return y, ms
+
+    def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
+        _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))
 
     def solve(self, want_coeffs: bool = True, want_flux: bool = True) -> dict:
         x = self.empty() if want_coeffs else None

@@ -595,6 +595,23 @@ int nce_matvec_profile(nce_ctx* ctx, const double* x, double* y, int precision, 
     });
 }
 
+int nce_set_solver(nce_ctx* ctx, double tol, int max_iter, int precision) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (!(tol > 0 && tol < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
+    if (max_iter < 1 || max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    return guarded([&]() -> int {
+        if (max_iter + 8 > (int)ctx->d_h.n) {
+            ctx->d_h.alloc((size_t)max_iter + 8);
+            ctx->d_partial.alloc((size_t)nce::kReduceBlocks * ((size_t)max_iter + 8));
+        }
+        ctx->opts.tol_gmres = tol;
+        ctx->opts.max_iter = max_iter;
+        ctx->opts.precision = precision;
+        return NCE_OK;
+    });
+}
+
 int nce_solve_interior(nce_ctx* ctx, double* coeffs, double* flux, double* mfpt, nce_info* info) {
     if (!ctx || !mfpt) return fail(NCE_EINVAL, "NULL argument");
     if (ctx->tab.problem != NCE_INTERIOR) return fail(NCE_ESTATE, "context was built for the exterior problem");
