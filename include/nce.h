@@ -74,7 +74,7 @@ typedef struct nce_opts {
     int max_iter;       /* GMRES iteration limit (FP64) or inner limit (mixed). Default 200 */
     int precision;      /* NCE_FP64 or NCE_MIXED for the solves. Default NCE_FP64 */
     int far_field;      /* NCE_FAR_AUTO / NCE_FAR_DIRECT / NCE_FAR_TREE. Default AUTO */
-    int warm_start;     /* 0 none; 1 learned (requires nce_load_mlp). Default 0 */
+    int warm_start;     /* reserved, must be 0 (use nce_set_warm_start). Default 0 */
     void *stream;       /* hipStream_t to run on; NULL = the library creates one */
     const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
 } nce_opts;
@@ -167,6 +167,44 @@ int nce_solve_interior(nce_ctx *ctx, double *coeffs_dev, double *patch_flux_dev,
  */
 int nce_solve_exterior(nce_ctx *ctx, double *coeffs_dev, double *patch_flux_dev,
                        double *capture_rate_host, double *I_sigma_host, nce_info *info);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start: a small FP32 multilayer perceptron (SiLU hidden layers,
+ * linear output) that maps each patch's local geometry to its coefficient
+ * vector f_i, trained on solutions this library computes. It only supplies
+ * the initial guess: x0 = gamma m with gamma fitted by one system apply, and
+ * GMRES (or the refinement loop) always runs on the true residual; the guess
+ * is rejected (info.used_fallback = 1) when it does not reduce the residual.
+ * Parameters are flattened per layer as W (row-major, out x in) then b.
+ * All *_dev arrays are FP32 device memory; `stream` is a hipStream_t (NULL =
+ * the null stream); calls that return host values synchronise it.
+ * ------------------------------------------------------------------------ */
+typedef struct nce_mlp nce_mlp;
+
+#define NCE_FEATURES 54 /* per patch: 16 nearest neighbours x (u, v, 1/r) in the patch frame
+                           (positions / (16 eps), 4 eps / distance), problem flag, 10 x area
+                           fraction, neighbour density relative to uniform within 8, 16, 32, 64 eps */
+
+/* He-initialised network n_in -> width (x hidden_layers, SiLU) -> n_out. */
+int nce_mlp_create(int n_in, int width, int hidden_layers, int n_out, uint64_t seed, nce_mlp **out);
+void nce_mlp_destroy(nce_mlp *m);
+int nce_mlp_num_params(const nce_mlp *m, int64_t *n);
+int nce_mlp_get_params(const nce_mlp *m, float *params_host);
+int nce_mlp_set_params(nce_mlp *m, const float *params_host);
+/* y (B x n_out) = network(x (B x n_in)). */
+int nce_mlp_forward(nce_mlp *m, const float *x_dev, int64_t B, float *y_dev, void *stream);
+/* Mean squared error L = sum (y - t)^2 / (B n_out) and its gradient with
+ * respect to the parameters (grad_host may be NULL; it is left on the device). */
+int nce_mlp_loss_grad(nce_mlp *m, const float *x_dev, const float *t_dev, int64_t B, double *loss_host,
+                      float *grad_host, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the loss of this batch. */
+int nce_mlp_train_step(nce_mlp *m, const float *x_dev, const float *t_dev, int64_t B, float lr, double *loss_host,
+                       void *stream);
+/* The NCE_FEATURES features of every patch of ctx (N x NCE_FEATURES FP32 device array). */
+int nce_features(const nce_ctx *ctx, float *feat_dev);
+/* Use m (n_in = NCE_FEATURES, n_out = K) as the warm start of later solves; NULL disables.
+ * The caller keeps m alive while it is set. */
+int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m);
 
 /* Integral vector I (K host doubles): I_sigma = I . sum_i f_i (eq. getI). */
 int nce_integral_vector(const nce_ctx *ctx, double *I_host);

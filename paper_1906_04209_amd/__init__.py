@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["load", "Context", "NCEError", "INTERIOR", "EXTERIOR", "FP64", "MIXED",
+__all__ = ["load", "Context", "Mlp", "NCEError", "FEATURES", "INTERIOR", "EXTERIOR", "FP64", "MIXED",
            "FAR_AUTO", "FAR_DIRECT", "FAR_TREE", "LIB_PATH", "SYMBOLS"]
 
 LIB_PATH = Path(__file__).resolve().parent / "libnce.so"
@@ -27,7 +27,10 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 # every symbol include/nce.h declares
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
-           "nce_strerror", "nce_last_error"]
+           "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
+           "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
+           "nce_mlp_train_step", "nce_features", "nce_set_warm_start"]
+FEATURES = 54
 
 
 class Opts(ctypes.Structure):
@@ -81,6 +84,22 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
     lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
     lib.nce_integral_vector.argtypes = [vp, vp]
+    lib.nce_mlp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                   ctypes.POINTER(vp)]
+    lib.nce_mlp_destroy.argtypes = [vp]
+    lib.nce_mlp_destroy.restype = None
+    lib.nce_mlp_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.nce_mlp_get_params.argtypes = [vp, vp]
+    lib.nce_mlp_set_params.argtypes = [vp, vp]
+    lib.nce_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.nce_mlp_loss_grad.argtypes = [vp, vp, vp, i64, dp, vp, vp]
+    lib.nce_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, dp, vp]
+    lib.nce_features.argtypes = [vp, vp]
+    lib.nce_set_warm_start.argtypes = [vp, vp]
+    for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
+                 "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
+                 "nce_set_warm_start"):
+        getattr(lib, name).restype = ctypes.c_int
     lib.nce_strerror.argtypes = [ctypes.c_int]
     lib.nce_strerror.restype = ctypes.c_char_p
     lib.nce_last_error.argtypes = []
@@ -99,13 +118,84 @@ def _check(lib, rc: int, allow_notconv: bool = False) -> int:
     raise NCEError(rc, lib.nce_last_error().decode() or lib.nce_strerror(rc).decode())
 
 
-def _ptr(t) -> int:
+def _ptr(t, dtype=None) -> int:
     if t is None:
         return None
     import torch
-    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+    dt = dtype or torch.float64
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dt} CUDA tensor")
     return t.data_ptr()
+
+
+class Mlp:
+    """The warm-start network (nce_mlp_*): FP32 parameters and kernels on the GPU."""
+
+    def __init__(self, n_in: int = FEATURES, width: int = 256, hidden: int = 3, n_out: int = 136, seed: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the network runs only on the GPU")
+        self.lib = load()
+        self.torch = torch
+        self.shape = (n_in, width, hidden, n_out)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.nce_mlp_create(n_in, width, hidden, n_out, seed, ctypes.byref(h)))
+        self.h = h
+        n = ctypes.c_int64()
+        _check(self.lib, self.lib.nce_mlp_num_params(h, ctypes.byref(n)))
+        self.nparam = n.value
+        self.stream = torch.cuda.Stream()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nce_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.nparam, dtype=np.float32)
+        _check(self.lib, self.lib.nce_mlp_get_params(self.h, out.ctypes.data))
+        return out
+
+    def set_params(self, theta) -> None:
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.nparam
+        _check(self.lib, self.lib.nce_mlp_set_params(self.h, th.ctypes.data))
+
+    def _run(self, fn):
+        torch = self.torch
+        self.stream.wait_stream(torch.cuda.current_stream())
+        r = fn(ctypes.c_void_p(self.stream.cuda_stream))
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return r
+
+    def forward(self, x):
+        torch = self.torch
+        y = torch.empty((x.shape[0], self.shape[3]), dtype=torch.float32, device="cuda")
+        self._run(lambda st: _check(self.lib, self.lib.nce_mlp_forward(
+            self.h, _ptr(x, torch.float32), x.shape[0], _ptr(y, torch.float32), st)))
+        return y
+
+    def loss_grad(self, x, t):
+        torch = self.torch
+        loss = ctypes.c_double()
+        g = np.empty(self.nparam, dtype=np.float32)
+        self._run(lambda st: _check(self.lib, self.lib.nce_mlp_loss_grad(
+            self.h, _ptr(x, torch.float32), _ptr(t, torch.float32), x.shape[0], ctypes.byref(loss),
+            g.ctypes.data, st)))
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float) -> float:
+        torch = self.torch
+        loss = ctypes.c_double()
+        self._run(lambda st: _check(self.lib, self.lib.nce_mlp_train_step(
+            self.h, _ptr(x, torch.float32), _ptr(t, torch.float32), x.shape[0], float(lr), ctypes.byref(loss), st)))
+        return loss.value
 
 
 class Context:
@@ -202,6 +292,17 @@ class Context:
         _check(self.lib, self.lib.nce_matvec_profile(self.h, _ptr(x), _ptr(y), int(precision), ms.ctypes.data))
         self._leave()
         return y, ms
+
+    def features(self):
+        f = self.torch.empty((self.N, FEATURES), dtype=self.torch.float32, device="cuda")
+        self._enter()
+        _check(self.lib, self.lib.nce_features(self.h, _ptr(f, self.torch.float32)))
+        self._leave()
+        return f
+
+    def set_warm_start(self, mlp: Optional["Mlp"]) -> None:
+        self._warm = mlp  # keep the network alive while it is set
+        _check(self.lib, self.lib.nce_set_warm_start(self.h, mlp.h if mlp is not None else None))
 
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
         _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))

@@ -16,8 +16,8 @@ CSRC = PKG / "csrc"
 OUT = PKG / "libnce.so"
 BUILD = PKG / "_build"
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "tree.hip"]
-CPP_SOURCES = ["precompute.cpp", "tree_build.cpp"]
+HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip", "tree.hip", "mlp.hip"]
+CPP_SOURCES = ["precompute.cpp", "tree_build.cpp", "features.cpp"]
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -15,6 +15,7 @@
 
 #include "../../include/nce.h"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "precompute.hpp"
 #include "tree.hpp"
 
@@ -96,6 +97,15 @@ struct nce_ctx {
     // solver work arrays
     DevBuf<double> d_V, d_b, d_r, d_x, d_h, d_partial, d_scal;
     int vcap = 0;  // number of Krylov vectors allocated
+    // learned warm start
+    nce::Mlp* warm = nullptr;
+    DevBuf<float> d_feat;
+    DevBuf<double> d_m, d_w;
+};
+
+struct nce_mlp {
+    nce::Mlp net;
+    nce_mlp(int a, int b, int c, int d, uint64_t e) : net(a, b, c, d, e) {}
 };
 
 namespace {
@@ -337,6 +347,50 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
     const int maxit = ctx->opts.max_iter;
     bool conv = false;
     double est = 1.0;
+    // r = residual of the current x, rel = ||r|| / ||b||
+    HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    double rel = 1.0;
+    if (ctx->warm && N > 1) {
+        // learned initial guess x0 = gamma m, gamma = argmin ||b - gamma A m||
+        const int prec = ctx->opts.precision;
+        if (!ctx->d_feat.p) {
+            std::vector<float> feat;
+            nce::patch_features(ctx->frames, N, ctx->eps, ctx->tab.problem, feat);
+            ctx->d_feat.upload(feat, s);
+        }
+        const float* m32 = ctx->warm->forward(s, ctx->d_feat.p, N);
+        if (!ctx->d_m.p) {
+            ctx->d_m.alloc(n);
+            ctx->d_w.alloc(n);
+        }
+        HIPCHK(nce::cast_f2d(s, n, m32, ctx->d_m.p));
+        matvec(ctx, ctx->d_m.p, ctx->d_w.p, prec);
+        if (prec == NCE_FP64) inf.iters_fp64++;
+        else inf.iters_fp32++;
+        const double wb = dev_dot(ctx, n, ctx->d_w.p, ctx->d_b.p);
+        const double ww = dev_dot(ctx, n, ctx->d_w.p, ctx->d_w.p);
+        const double gamma = ww > 0 ? wb / ww : 0.0;
+        if (std::isfinite(gamma) && gamma != 0.0) {
+            HIPCHK(nce::scale_copy(s, n, gamma, ctx->d_m.p, x));
+            if (prec == NCE_FP64) {
+                // r = b - gamma (A m), exact in FP64
+                HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+                HIPCHK(nce::axpby(s, n, -gamma, ctx->d_w.p, 1.0, ctx->d_r.p));
+                rel = std::sqrt(dev_dot(ctx, n, ctx->d_r.p, ctx->d_r.p)) / std::sqrt((double)N);
+            } else {
+                rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+                inf.iters_fp64++;
+            }
+        }
+        inf.rel_residual_x0 = rel;
+        if (!(rel < 0.99)) {
+            // no gain: plain start from zero
+            inf.used_fallback = 1;
+            HIPCHK(nce::fill(s, n, 0.0, x));
+            HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            rel = 1.0;
+        }
+    }
     if (N == 1) {
         // one patch: the system matrix is the identity (no scattering), x = b
         HIPCHK(hipMemcpyAsync(x, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
@@ -344,15 +398,14 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
         inf.rel_residual = 0.0;
         inf.rel_residual_x0 = 1.0;
     } else if (ctx->opts.precision == NCE_FP64) {
-        inf.rel_residual_x0 = 1.0;
-        inf.iters_fp64 = gmres(ctx, ctx->d_b.p, x, tol, maxit, NCE_FP64, conv, est);
+        if (!ctx->warm) inf.rel_residual_x0 = 1.0;
+        // GMRES on A d = r with ||r - A d|| <= tol ||b||; x += d
+        inf.iters_fp64 += gmres(ctx, ctx->d_r.p, x, tol / rel, maxit, NCE_FP64, conv, est);
         inf.rel_residual = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
         inf.outer = 1;
     } else {
         // FP64 iterative refinement: r = b - A64 x; A32 d = r by GMRES; x += d.
-        double rel = 1.0;
-        HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-        inf.rel_residual_x0 = rel;
+        if (!ctx->warm) inf.rel_residual_x0 = rel;
         const int max_outer = 12;
         conv = false;
         for (int outer = 0; outer < max_outer; ++outer) {
@@ -633,6 +686,110 @@ int nce_solve_exterior(nce_ctx* ctx, double* coeffs, double* flux, double* rate,
         if (Is_out) *Is_out = Is;
         return rc;
     });
+}
+
+int nce_mlp_create(int n_in, int width, int hidden, int n_out, uint64_t seed, nce_mlp** out) {
+    if (!out) return fail(NCE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_in < 1 || n_out < 1 || hidden < 0 || (hidden > 0 && width < 1) || hidden > 16)
+        return fail(NCE_EINVAL, "bad network shape");
+    return guarded([&]() -> int {
+        *out = new nce_mlp(n_in, width, hidden, n_out, seed);
+        return NCE_OK;
+    });
+}
+
+void nce_mlp_destroy(nce_mlp* m) { delete m; }
+
+int nce_mlp_num_params(const nce_mlp* m, int64_t* n) {
+    if (!m || !n) return fail(NCE_EINVAL, "NULL argument");
+    *n = m->net.nparam;
+    return NCE_OK;
+}
+
+int nce_mlp_get_params(const nce_mlp* m, float* h) {
+    if (!m || !h) return fail(NCE_EINVAL, "NULL argument");
+    return guarded([&]() -> int {
+        HIPCHK(hipMemcpy(h, m->net.theta, sizeof(float) * m->net.nparam, hipMemcpyDeviceToHost));
+        return NCE_OK;
+    });
+}
+
+int nce_mlp_set_params(nce_mlp* m, const float* h) {
+    if (!m || !h) return fail(NCE_EINVAL, "NULL argument");
+    for (int64_t q = 0; q < m->net.nparam; ++q)
+        if (!std::isfinite(h[q])) return fail(NCE_EINVAL, "non-finite network parameter");
+    return guarded([&]() -> int {
+        HIPCHK(hipMemcpy(m->net.theta, h, sizeof(float) * m->net.nparam, hipMemcpyHostToDevice));
+        m->net.step = 0;
+        HIPCHK(hipMemset(m->net.mom, 0, sizeof(float) * m->net.nparam));
+        HIPCHK(hipMemset(m->net.vel, 0, sizeof(float) * m->net.nparam));
+        return NCE_OK;
+    });
+}
+
+int nce_mlp_forward(nce_mlp* m, const float* x, int64_t B, float* y, void* stream) {
+    if (!m || !x || !y || B < 1) return fail(NCE_EINVAL, "bad argument");
+    return guarded([&]() -> int {
+        hipStream_t s = (hipStream_t)stream;
+        const float* out = m->net.forward(s, x, B);
+        HIPCHK(hipMemcpyAsync(y, out, sizeof(float) * B * m->net.n_out, hipMemcpyDeviceToDevice, s));
+        return NCE_OK;
+    });
+}
+
+int nce_mlp_loss_grad(nce_mlp* m, const float* x, const float* t, int64_t B, double* loss, float* grad, void* stream) {
+    if (!m || !x || !t || B < 1) return fail(NCE_EINVAL, "bad argument");
+    return guarded([&]() -> int {
+        hipStream_t s = (hipStream_t)stream;
+        m->net.loss_grad(s, x, t, B);
+        if (loss) {
+            double v = 0;
+            HIPCHK(hipMemcpyAsync(&v, m->net.lossd, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            *loss = v / ((double)B * m->net.n_out);
+        }
+        if (grad) {
+            HIPCHK(hipMemcpyAsync(grad, m->net.grad, sizeof(float) * m->net.nparam, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        return NCE_OK;
+    });
+}
+
+int nce_mlp_train_step(nce_mlp* m, const float* x, const float* t, int64_t B, float lr, double* loss, void* stream) {
+    if (!m || !x || !t || B < 1 || !(lr > 0)) return fail(NCE_EINVAL, "bad argument");
+    return guarded([&]() -> int {
+        hipStream_t s = (hipStream_t)stream;
+        m->net.loss_grad(s, x, t, B);
+        m->net.adam_step(s, lr);
+        if (loss) {
+            double v = 0;
+            HIPCHK(hipMemcpyAsync(&v, m->net.lossd, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            *loss = v / ((double)B * m->net.n_out);
+        }
+        return NCE_OK;
+    });
+}
+
+int nce_features(const nce_ctx* ctx, float* feat) {
+    if (!ctx || !feat) return fail(NCE_EINVAL, "NULL argument");
+    return guarded([&]() -> int {
+        std::vector<float> f;
+        nce::patch_features(ctx->frames, ctx->N, ctx->eps, ctx->tab.problem, f);
+        HIPCHK(hipMemcpyAsync(feat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return NCE_OK;
+    });
+}
+
+int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != ctx->K))
+        return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
+    ctx->warm = m ? &m->net : nullptr;
+    return NCE_OK;
 }
 
 int nce_integral_vector(const nce_ctx* ctx, double* I) {

@@ -1,96 +1,11 @@
-// Device kernels: block applies (T and P), direct Green's function sums, and
-// Krylov vector operations. gfx950, wave64.
+// Device kernels: direct Green's function sums and Krylov vector operations.
+// gfx950, wave64. (The block applies are in gemm.hip.)
 #include "kernels.hpp"
 #include "greens.hpp"
 
 #include <hip/hip_runtime.h>
 
 namespace nce {
-
-// ---------------------------------------------------------------------------
-// "NT" GEMM: out[i][j] = sum_k A[i][k] B[j][k] (+ add[i][j]); LDS tiles of
-// 64 x 64 outputs, 16-wide k slices, 256 threads, 4 x 4 outputs per thread.
-template <class TI, class TO, bool ADD>
-__global__ __launch_bounds__(256) void k_gemm_nt(int m, int n, int k, const TI* __restrict__ A, int lda,
-                                                 const TI* __restrict__ B, int ldb, TO* __restrict__ C,
-                                                 int ldc, const double* __restrict__ D, int ldd) {
-    __shared__ TI As[16][64 + 1];
-    __shared__ TI Bs[16][64 + 1];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-    TI acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = TI(0);
-    for (int k0 = 0; k0 < k; k0 += 16) {
-        // load 64 x 16 of A and of B: 1024 values each, 4 per thread
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int idx = threadIdx.x + 256 * r;
-            const int row = idx / 16, kk = idx % 16;
-            const int gi = i0 + row, gk = k0 + kk;
-            As[kk][row] = (gi < m && gk < k) ? A[(int64_t)gi * lda + gk] : TI(0);
-            const int gj = j0 + row;
-            Bs[kk][row] = (gj < n && gk < k) ? B[(int64_t)gj * ldb + gk] : TI(0);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            TI av[4], bv[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) av[a] = As[kk][ty + 16 * a];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) bv[b] = Bs[kk][tx + 16 * b];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int gi = i0 + ty + 16 * a;
-        if (gi >= m) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int gj = j0 + tx + 16 * b;
-            if (gj >= n) continue;
-            if (ADD)
-                C[(int64_t)gi * ldc + gj] = (TO)((double)acc[a][b] + D[(int64_t)gi * ldd + gj]);
-            else
-                C[(int64_t)gi * ldc + gj] = (TO)acc[a][b];
-        }
-    }
-}
-
-template <class T>
-hipError_t gemm_nt(hipStream_t s, int m, int n, int k, const T* A, int lda, const T* B, int ldb, T* C,
-                   int ldc, const double* D, int ldd) {
-    dim3 grid((n + 63) / 64, (m + 63) / 64);
-    if (D)
-        hipLaunchKernelGGL((k_gemm_nt<T, T, true>), grid, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, D, ldd);
-    else
-        hipLaunchKernelGGL((k_gemm_nt<T, T, false>), grid, dim3(256), 0, s, m, n, k, A, lda, B, ldb, C, ldc, D, ldd);
-    return hipGetLastError();
-}
-template hipError_t gemm_nt<double>(hipStream_t, int, int, int, const double*, int, const double*, int, double*,
-                                    int, const double*, int);
-template hipError_t gemm_nt<float>(hipStream_t, int, int, int, const float*, int, const float*, int, float*, int,
-                                   const double*, int);
-
-template <class T>
-hipError_t p_apply(hipStream_t s, int N, int K, int Kstar, const T* U, const T* P, const double* x, double* y) {
-    dim3 grid((K + 63) / 64, (N + 63) / 64);
-    hipLaunchKernelGGL((k_gemm_nt<T, double, true>), grid, dim3(256), 0, s, N, K, Kstar, U, Kstar, P, Kstar, y, K,
-                       x, K);
-    return hipGetLastError();
-}
-template hipError_t p_apply<double>(hipStream_t, int, int, int, const double*, const double*, const double*,
-                                    double*);
-template hipError_t p_apply<float>(hipStream_t, int, int, int, const float*, const float*, const double*,
-                                   double*);
 
 // ---------------------------------------------------------------------------
 // Direct all-pairs sum. One block per target patch i; each thread owns NPT of
@@ -377,6 +292,10 @@ __global__ void k_cast(int64_t n, const double* __restrict__ x, float* __restric
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         y[e] = (float)x[e];
 }
+__global__ void k_cast_up(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = (double)x[e];
+}
 __global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         x[e] = v;
@@ -397,6 +316,10 @@ hipError_t axpby(hipStream_t s, int64_t n, double a, const double* x, double b, 
 }
 hipError_t cast_d2f(hipStream_t s, int64_t n, const double* x, float* y) {
     hipLaunchKernelGGL(k_cast, ew_grid(n), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+hipError_t cast_f2d(hipStream_t s, int64_t n, const float* x, double* y) {
+    hipLaunchKernelGGL(k_cast_up, ew_grid(n), dim3(256), 0, s, n, x, y);
     return hipGetLastError();
 }
 hipError_t fill(hipStream_t s, int64_t n, double v, double* x) {

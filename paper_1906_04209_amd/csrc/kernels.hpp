@@ -18,6 +18,12 @@ template <class T>
 hipError_t gemm_nt(hipStream_t s, int m, int n, int k, const T* A, int lda, const T* B, int ldb,
                    T* C, int ldc, const double* D, int ldd);
 
+// C[i][j] (+)= alpha sum_k A[i*sai + k*sak] B[k*sbk + j*sbj] on the matrix cores
+// (accumulate != 0 adds into C).
+template <class T>
+hipError_t gemm_strided(hipStream_t s, int m, int n, int k, const T* A, int64_t sai, int64_t sak, const T* B,
+                        int64_t sbk, int64_t sbj, T* C, int64_t ldc, T alpha, int accumulate);
+
 // y[i][c] = x[i][c] + sum_q U[i][q] P[c][q]  (FP64 out, U/P in T)
 template <class T>
 hipError_t p_apply(hipStream_t s, int N, int K, int Kstar, const T* U, const T* P, const double* x,
@@ -48,6 +54,7 @@ hipError_t axpby(hipStream_t s, int64_t n, double a, const double* x, double b, 
 hipError_t combine(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* c,
                    double* x);                   // x += sum_j c_j V_j
 hipError_t cast_d2f(hipStream_t s, int64_t n, const double* x, float* y);
+hipError_t cast_f2d(hipStream_t s, int64_t n, const float* x, double* y);
 hipError_t fill(hipStream_t s, int64_t n, double v, double* x);
 // flux[i] = sum_k I[k] x[i][k]; total written to *sum (two-stage)
 hipError_t patch_flux(hipStream_t s, int N, int K, const double* I, const double* x, double* flux,

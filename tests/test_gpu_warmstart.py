@@ -1,0 +1,96 @@
+"""GPU checks of the learned warm start: the network's forward pass and
+gradient against the oracle's FP64 MLP, training, the fallback path, and the
+iterations the trained network saves on held-out layouts."""
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import layouts
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+WEIGHTS = Path(__file__).resolve().parents[1] / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def test_forward_and_gradient_vs_oracle(torch):
+    import paper_1906_04209_amd as nce
+    shape = (54, 48, 3, 136)
+    net = nce.Mlp(*shape, seed=3)
+    g = np.random.Generator(np.random.PCG64(8))
+    th = net.get_params().astype(np.float64) + 0.01 * g.standard_normal(net.nparam)
+    net.set_params(th.astype(np.float32))
+    th = th.astype(np.float32).astype(np.float64)
+    X = g.standard_normal((300, shape[0])).astype(np.float32)
+    T = g.standard_normal((300, shape[3])).astype(np.float32)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy()
+    yr, _ = omlp.forward(th, X.astype(np.float64), *shape)
+    ferr = np.max(np.abs(y - yr)) / np.max(np.abs(yr))
+    loss, gr = net.loss_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    lr_, grr = omlp.loss_and_grad(th, X.astype(np.float64), T.astype(np.float64), *shape)
+    gerr = np.max(np.abs(gr - grr)) / np.max(np.abs(grr))
+    print(f"forward rel err {ferr:.2e}, loss {loss:.6e} vs {lr_:.6e}, gradient rel err {gerr:.2e}")
+    assert ferr < 1e-5
+    assert abs(loss - lr_) < 1e-5 * lr_
+    assert gerr < 1e-4
+
+
+def test_training_reduces_loss(torch):
+    import paper_1906_04209_amd as nce
+    net = nce.Mlp(8, 32, 2, 3, seed=1)
+    g = np.random.Generator(np.random.PCG64(2))
+    X = torch.from_numpy(g.standard_normal((512, 8)).astype(np.float32)).cuda()
+    W = g.standard_normal((3, 8)).astype(np.float32)
+    T = torch.from_numpy(np.tanh(X.cpu().numpy() @ W.T)).cuda()
+    l0 = net.train_step(X, T, 1e-3)
+    for _ in range(300):
+        l1 = net.train_step(X, T, 1e-3)
+    assert l1 < 0.2 * l0
+
+
+def test_zero_network_falls_back_and_nan_rejected(torch):
+    import paper_1906_04209_amd as nce
+    net = nce.Mlp(seed=0)
+    net.set_params(np.zeros(net.nparam, np.float32))
+    bad = np.zeros(net.nparam, np.float32)
+    bad[5] = np.nan
+    with pytest.raises(nce.NCEError):
+        net.set_params(bad)
+    c = layouts.uniform_centers(10, 0.1, 1)
+    ctx = nce.Context(c, 0.1, problem=nce.EXTERIOR, tol_id=1e-12, far_field=nce.FAR_DIRECT)
+    ref = ctx.solve()
+    ctx.set_warm_start(net)
+    r = ctx.solve()
+    assert r["used_fallback"] == 1 and r["converged"]
+    assert abs(r["capture_rate"] - ref["capture_rate"]) < 1e-12 * ref["capture_rate"]
+
+
+@pytest.mark.skipif(not WEIGHTS.exists(), reason="trained weights not present")
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_trained_network_saves_iterations(torch, precision):
+    import paper_1906_04209_amd as nce
+    from paper_1906_04209_amd import warmstart
+    net = warmstart.load(WEIGHTS)
+    pr = nce.FP64 if precision == "fp64" else nce.MIXED
+    gains = []
+    for seed in (90001, 90002, 90003):  # held out: training used seeds 20000-20047
+        c = layouts.uniform_centers(1000, 0.01, seed)
+        ctx = nce.Context(c, 0.01, problem=nce.INTERIOR, tol_id=1e-11, tol_gmres=1e-8, precision=pr)
+        a = ctx.solve(want_coeffs=False)
+        ctx.set_warm_start(net)
+        b = ctx.solve(want_coeffs=False)
+        na = a["iters_fp64"] + a["iters_fp32"]
+        nb = b["iters_fp64"] + b["iters_fp32"]
+        print(f"{precision} seed {seed}: plain {na} matvecs mu {a['mu']:.12f}; warm {nb} matvecs "
+              f"(x0 residual {b['rel_residual_x0']:.3e}, fallback {b['used_fallback']}) mu {b['mu']:.12f}")
+        assert a["converged"] and b["converged"]
+        assert abs(a["mu"] - b["mu"]) < 1e-7 * a["mu"]
+        gains.append(na - nb)
+    assert np.mean(gains) > 0
