@@ -6,7 +6,7 @@ items 1-5) to a seeded random coefficient vector. Inputs are resident in HBM
 before the timed region. Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg5]
-                  [--precision fp64|mixed] [--solve] [--no-cpu-baseline]
+                  [--precision fp64|mixed] [--no-solve] [--no-warm] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -24,11 +24,15 @@ import numpy as np  # noqa: E402
 
 import layouts  # noqa: E402
 
-# Green's function pair cost in VALU lane-cycles (quarter-rate transcendentals
-# count 4), from the instruction mix of the pair evaluation; the ALU ceiling is
+# Green's function pair cost in lane-cycles: the VALU instructions of the P2L
+# inner loop (AMD assembly of this build, 4 pairs per iteration) priced at the
+# chip's issue rates -- FP64 add/mul/fma and 64-bit integer ops 1 (78.6 TFLOP/s
+# FP64 vector), 32-bit ops 0.5 (157.3 TFLOP/s FP32 vector), FP32
+# transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
-C_PAIR = {("fp64", 0): 71.2, ("fp64", 1): 58.2, ("fp32", 0): 24.5, ("fp32", 1): 18.5}
+C_PAIR = {("fp64", 0): 68.1, ("fp64", 1): 55.1, ("fp32", 0): 12.4, ("fp32", 1): 9.4}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
+WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
     "cfg5": dict(layouts.CONFIGS["cfg5"], far="tree"),
@@ -70,6 +74,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and mixed solves to 1e-8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm", action="store_true", help="skip the solves from the learned initial guess")
     ap.add_argument("--tol-id", type=float, default=1e-11)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -146,6 +151,23 @@ def main():
         out["time_to_1e-8_s"] = {"fp64": a["t_solve_s"], "mixed": b["t_solve_s"],
                                  "speedup": a["t_solve_s"] / b["t_solve_s"],
                                  f"rel_diff_{key}": abs(a[key] - b[key]) / abs(a[key])}
+        if not args.no_warm and WARM_WEIGHTS.exists():
+            # the same solves from the learned initial guess (the first one also
+            # computes the per-patch features, which is counted in its time)
+            from paper_1906_04209_amd import warmstart
+            net = warmstart.load(WARM_WEIGHTS)
+            ctx.set_warm_start(net)
+            for name, pr in (("fp64", nce.FP64), ("mixed", nce.MIXED)):
+                ctx.set_solver(1e-8, 100, pr)
+                r = ctx.solve(want_coeffs=False, want_flux=False)
+                o = {k: r[k] for k in ("iters_fp64", "iters_fp32", "outer", "rel_residual", "rel_residual_x0",
+                                       "used_fallback", "t_solve_s", "converged")}
+                o[key] = r[key]
+                o[f"rel_diff_{key}_vs_cold"] = abs(r[key] - a[key]) / abs(a[key])
+                out[f"solve_{name}_warm"] = o
+                out["time_to_1e-8_s"][f"{name}_warm"] = r["t_solve_s"]
+                log(f"solve {name} warm: {o}")
+            ctx.set_warm_start(None)
     if not args.no_cpu_baseline:
         cb, rows, yref = cpu_baseline(cfg, args.tol_id, x_np, centers)
         yg = y.cpu().numpy()[rows] if args.precision == "fp64" else None

@@ -9,6 +9,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
@@ -40,19 +41,27 @@ def _run(cmd):
     return r.stdout
 
 
+RATES = PKG / "valu_rates"   # instruction issue-cost probe (roofline pricing)
+
+
 def build(verbose: bool = False) -> Path:
     BUILD.mkdir(exist_ok=True)
     hipcc = _hipcc()
     inc = ["-I", str(CSRC), "-I", str(PKG.parent / "include")]
+    jobs = []
     objs = []
     for src in CPP_SOURCES:
         o = BUILD / (Path(src).stem + ".o")
-        _run(["g++", *GXX_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
+        jobs.append(["g++", *GXX_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
         objs.append(str(o))
     for src in HIP_SOURCES:
         o = BUILD / (Path(src).stem + ".hip.o")
-        _run([hipcc, *HIPCC_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
+        jobs.append([hipcc, *HIPCC_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
         objs.append(str(o))
+    jobs.append([hipcc, *HIPCC_FLAGS, str(CSRC / "valu_rates.hip"), "-o", str(RATES)])
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(_run, jobs))
     tmp = OUT.with_suffix(".so.tmp")
     _run([hipcc, "-shared", "--offload-arch=gfx950", "-fPIC", *objs, "-o", str(tmp), "-lgomp"])
     os.replace(tmp, OUT)
