@@ -209,6 +209,63 @@ int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m);
 /* Integral vector I (K host doubles): I_sigma = I . sum_i f_i (eq. getI). */
 int nce_integral_vector(const nce_ctx *ctx, double *I_host);
 
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent configurations (their own centres, eps and
+ * problem) in one set of launches. Not in the paper, whose solver treats one
+ * configuration at a time; each configuration's system is the one above
+ * (eq. opinteqnsdisc) and its result the scalar of Section 2.
+ *
+ * Configurations with equal (problem, eps) share tables and are applied by
+ * the same launches; each configuration's far field uses its own quadtree or
+ * direct all-pairs lists, whichever has the smaller operation count (unless
+ * opts.far_field forces one). Batch vectors (device, FP64) hold configuration
+ * b's N_b x K coefficients at the element offset nce_batch_offsets() gives.
+ */
+typedef struct nce_batch nce_batch;
+
+/*
+ * centers[b]: host array N[b] x 3 of configuration b (unit vectors, pairwise
+ * separation >= 3 eps[b]); problem[b]: NCE_INTERIOR or NCE_EXTERIOR; B >= 1.
+ * opts: shared settings (opts.problem is ignored; opts.max_iter <= 120 is the
+ * Krylov dimension of the lockstep GMRES; opts.stream as in nce_setup).
+ * Errors: NCE_EINVAL / NCE_ESEP (message names the configuration), NCE_ENOMEM,
+ * NCE_EHIP, NCE_ETABLE. Release with nce_destroy_batch.
+ */
+int nce_setup_batch(const double *const *centers_host, const int64_t *N_host, const double *eps_host,
+                    const int *problem_host, int B, const nce_opts *opts, nce_batch **out);
+void nce_destroy_batch(nce_batch *batch);
+
+/* Total batch vector length, K, and the number of (problem, eps) groups. */
+int nce_batch_dims(const nce_batch *batch, int64_t *n_total, int *K, int *ngroups);
+
+/* off_host[b] (B entries): first element of configuration b in batch vectors;
+ * far_tree_host[b] (may be NULL): 1 if its far field uses the tree, 0 direct. */
+int nce_batch_offsets(const nce_batch *batch, int64_t *off_host, int *far_tree_host);
+
+/* Operation counts of one batched apply (as nce_work). */
+int nce_batch_work(const nce_batch *batch, double *pairs_far, double *pairs_near, double *interp_fma);
+
+/* y = A x for every configuration (batch layout, device, FP64 in and out;
+ * precision NCE_FP64 or NCE_MIXED = FP32 steps). x and y must not alias. */
+int nce_batch_matvec(nce_batch *batch, const double *x_dev, double *y_dev, int precision);
+
+/* Solver settings: relative residual tolerance (per configuration), Krylov
+ * dimension (1..120), NCE_FP64 or NCE_MIXED, and whether one Arnoldi step is
+ * replayed as a captured HIP graph (1) or launched kernel by kernel (0). */
+int nce_batch_set_solver(nce_batch *batch, double tol_gmres, int max_iter, int precision, int use_graph);
+
+/*
+ * Solve every configuration from x0 = 0: lockstep GMRES over the batch
+ * (NCE_FP64), or FP32 lockstep GMRES inside FP64 iterative refinement
+ * (NCE_MIXED); a configuration stops iterating once its own FP64-verified
+ * residual meets the tolerance. result_host[b]: mu (interior, eq.
+ * mufromsigma2) or the capture rate 4 pi I_sigma (exterior) of configuration
+ * b; coeffs_dev (may be NULL): the batch solution vector; infos_host[b] (may
+ * be NULL): per configuration, with t_solve_s the whole batch's time.
+ * Returns NCE_NOTCONVERGED if any configuration missed the tolerance.
+ */
+int nce_solve_batch(nce_batch *batch, double *result_host, double *coeffs_dev, nce_info *infos_host);
+
 /* Short description of a status code. */
 const char *nce_strerror(int code);
 

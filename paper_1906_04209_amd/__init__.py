@@ -15,7 +15,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["load", "Context", "Mlp", "NCEError", "FEATURES", "INTERIOR", "EXTERIOR", "FP64", "MIXED",
+__all__ = ["load", "Context", "Batch", "Mlp", "NCEError", "FEATURES", "INTERIOR", "EXTERIOR", "FP64", "MIXED",
            "FAR_AUTO", "FAR_DIRECT", "FAR_TREE", "LIB_PATH", "SYMBOLS"]
 
 LIB_PATH = Path(__file__).resolve().parent / "libnce.so"
@@ -29,7 +29,9 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
            "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
-           "nce_mlp_train_step", "nce_features", "nce_set_warm_start"]
+           "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
+           "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
+           "nce_batch_set_solver", "nce_solve_batch"]
 FEATURES = 54
 
 
@@ -99,6 +101,18 @@ def load(path: Optional[os.PathLike] = None):
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
                  "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
                  "nce_set_warm_start"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.nce_setup_batch.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    lib.nce_destroy_batch.argtypes = [vp]
+    lib.nce_destroy_batch.restype = None
+    lib.nce_batch_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ip, ip]
+    lib.nce_batch_offsets.argtypes = [vp, vp, vp]
+    lib.nce_batch_work.argtypes = [vp, dp, dp, dp]
+    lib.nce_batch_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
+    lib.nce_batch_set_solver.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.nce_solve_batch.argtypes = [vp, vp, vp, vp]
+    for name in ("nce_setup_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
+                 "nce_batch_set_solver", "nce_solve_batch"):
         getattr(lib, name).restype = ctypes.c_int
     lib.nce_strerror.argtypes = [ctypes.c_int]
     lib.nce_strerror.restype = ctypes.c_char_p
@@ -331,3 +345,91 @@ class Context:
         out["x"] = x
         out["flux"] = f
         return out
+
+
+class Batch:
+    """Independent configurations solved together (nce_setup_batch ...
+    nce_destroy_batch). configs: sequence of (centers N_b x 3, eps_b, problem_b).
+    Batch vectors are flat float64 device tensors of length n; configuration b
+    occupies [offsets[b], offsets[b] + N_b K)."""
+
+    def __init__(self, configs, M: int = 15, tol_id: float = 1e-11, tol_grid: float = 1e-8,
+                 tol_gmres: float = 1e-10, max_iter: int = 60, precision: int = MIXED, far_field: int = FAR_AUTO,
+                 cache_dir: Optional[str] = None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the solver runs only on the GPU")
+        self.lib = load()
+        self.torch = torch
+        cs = [np.ascontiguousarray(c, dtype=np.float64) for c, _, _ in configs]
+        self.B = len(cs)
+        self.N = np.array([len(c) for c in cs], dtype=np.int64)
+        self.eps = np.array([float(e) for _, e, _ in configs], dtype=np.float64)
+        self.problem = np.array([int(p) for _, _, p in configs], dtype=np.int32)
+        ptrs = (ctypes.c_void_p * self.B)(*[c.ctypes.data for c in cs])
+        o = Opts()
+        self.lib.nce_default_opts(ctypes.byref(o))
+        o.M, o.tol_id, o.tol_grid, o.tol_gmres = M, tol_id, tol_grid, tol_gmres
+        o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        o.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        self._cache = (cache_dir or os.environ.get("NCE_CACHE") or "").encode() or None
+        o.cache_dir = self._cache
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(self.lib, self.lib.nce_setup_batch(ptrs, self.N.ctypes.data, self.eps.ctypes.data,
+                                                  self.problem.ctypes.data, self.B, ctypes.byref(o),
+                                                  ctypes.byref(h)))
+        self.h = h
+        n, K, G = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        _check(self.lib, self.lib.nce_batch_dims(h, ctypes.byref(n), ctypes.byref(K), ctypes.byref(G)))
+        self.n, self.K, self.ngroups = n.value, K.value, G.value
+        self.offsets = np.zeros(self.B, dtype=np.int64)
+        self.far_tree = np.zeros(self.B, dtype=np.int32)
+        _check(self.lib, self.lib.nce_batch_offsets(h, self.offsets.ctypes.data, self.far_tree.ctypes.data))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nce_destroy_batch(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self):
+        return self.torch.empty(self.n, dtype=self.torch.float64, device="cuda")
+
+    def part(self, v, b: int):
+        """View of configuration b's N_b x K block of a batch vector."""
+        o = int(self.offsets[b])
+        return v[o:o + int(self.N[b]) * self.K].view(int(self.N[b]), self.K)
+
+    def work(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(self.lib, self.lib.nce_batch_work(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"pairs_far": a.value, "pairs_near": b.value, "interp_fma": c.value}
+
+    def matvec(self, x, y=None, precision: int = FP64):
+        if y is None:
+            y = self.empty()
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+        _check(self.lib, self.lib.nce_batch_matvec(self.h, _ptr(x), _ptr(y), int(precision)))
+        self.torch.cuda.current_stream().wait_stream(self.stream)
+        return y
+
+    def set_solver(self, tol_gmres: float, max_iter: int, precision: int, use_graph: bool = True):
+        _check(self.lib, self.lib.nce_batch_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision),
+                                                       int(bool(use_graph))))
+
+    def solve(self, want_coeffs: bool = False) -> dict:
+        x = self.empty() if want_coeffs else None
+        res = np.zeros(self.B)
+        infos = (Info * self.B)()
+        self.stream.wait_stream(self.torch.cuda.current_stream())
+        rc = self.lib.nce_solve_batch(self.h, res.ctypes.data, _ptr(x), infos)
+        _check(self.lib, rc, allow_notconv=True)
+        self.torch.cuda.current_stream().wait_stream(self.stream)
+        return {"result": res, "info": [infos[b].asdict() for b in range(self.B)], "converged": rc == 0, "x": x}

@@ -13,102 +13,14 @@
 #include <unordered_map>
 #include <vector>
 
-#include "../../include/nce.h"
-#include "kernels.hpp"
-#include "mlp.hpp"
-#include "precompute.hpp"
-#include "tree.hpp"
+#include "ctx.hpp"
 
-namespace {
-
+namespace nce_detail {
 thread_local std::string g_err;
-
-int fail(int code, const std::string& msg) {
-    g_err = msg;
-    return code;
 }
+using namespace nce_detail;
 
-struct HipError : std::runtime_error {
-    using std::runtime_error::runtime_error;
-};
-
-#define HIPCHK(expr)                                                                               \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
-    } while (0)
-
-template <class T>
-struct DevBuf {
-    T* p = nullptr;
-    size_t n = 0;
-    void alloc(size_t count) {
-        release();
-        if (count == 0) return;
-        if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
-            p = nullptr;
-            throw std::bad_alloc();
-        }
-        n = count;
-    }
-    void upload(const std::vector<T>& v, hipStream_t s) {
-        alloc(v.size());
-        if (n) {
-            HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
-            HIPCHK(hipStreamSynchronize(s));  // the host vector may be a temporary
-        }
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        n = 0;
-    }
-    ~DevBuf() { release(); }
-};
-
-template <class T>
-std::vector<float> to_f32(const std::vector<T>& v) {
-    return std::vector<float>(v.begin(), v.end());
-}
-
-}  // namespace
-
-struct nce_ctx {
-    nce_opts opts;
-    int64_t N = 0;
-    int K = 0, Kstar = 0, p = 0;
-    int ptot = 0;                       // strengths per patch over all outgoing tables in use
-    std::vector<int> tab_off, tab_p;    // per table: first column and size (table 0 = base)
-    double eps = 0;
-    nce::PatchTables tab;
-    std::vector<double> frames;  // N x 9: c, e1, e2
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    bool use_tree = false;
-    nce::Tree tree;
-    nce::DeviceTree dtree;
-    // device tables
-    DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
-    DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
-    // matvec work arrays
-    DevBuf<double> d_rho, d_U;
-    DevBuf<float> d_rho32, d_U32, d_x32;
-    // solver work arrays
-    DevBuf<double> d_V, d_b, d_r, d_x, d_h, d_partial, d_scal;
-    int vcap = 0;  // number of Krylov vectors allocated
-    // learned warm start
-    nce::Mlp* warm = nullptr;
-    DevBuf<float> d_feat;
-    DevBuf<double> d_m, d_w;
-};
-
-struct nce_mlp {
-    nce::Mlp net;
-    nce_mlp(int a, int b, int c, int d, uint64_t e) : net(a, b, c, d, e) {}
-};
-
-namespace {
+namespace nce_detail {
 
 void build_frames(const double* c, int64_t N, std::vector<double>& fr) {
     fr.resize((size_t)N * 9);
@@ -224,7 +136,7 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     mark(5);
 }
 
-void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr) {
+void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev) {
     if (ctx->N == 1) {
         if (ev)
             for (int k = 0; k < 6; ++k) HIPCHK(hipEventRecord(ev[k], ctx->stream));
@@ -446,20 +358,139 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
     return (conv && inf.rel_residual <= tol * 1.0001) ? NCE_OK : NCE_NOTCONVERGED;
 }
 
-template <class F>
-int guarded(F&& f) {
-    try {
-        return f();
-    } catch (const HipError& e) {
-        return fail(NCE_EHIP, e.what());
-    } catch (const std::bad_alloc&) {
-        return fail(NCE_ENOMEM, "allocation failed");
-    } catch (const std::exception& e) {
-        return fail(NCE_ETABLE, e.what());
-    }
+
+int validate_opts(const nce_opts& o, double eps) {
+    if (!(eps > 0.0 && eps <= M_PI / 3.0)) return fail(NCE_EINVAL, "eps must lie in (0, pi/3]");
+    if (o.M < 0 || o.M > 30) return fail(NCE_EINVAL, "M must lie in [0, 30]");
+    if (o.problem != NCE_INTERIOR && o.problem != NCE_EXTERIOR) return fail(NCE_EINVAL, "bad problem");
+    if (!(o.tol_id > 0 && o.tol_id < 1e-3)) return fail(NCE_EINVAL, "tol_id must lie in (0, 1e-3)");
+    if (!(o.tol_grid > 0 && o.tol_grid < 1e-2)) return fail(NCE_EINVAL, "tol_grid must lie in (0, 1e-2)");
+    if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
+    if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
+    if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    if (o.far_field != NCE_FAR_AUTO && o.far_field != NCE_FAR_DIRECT && o.far_field != NCE_FAR_TREE)
+        return fail(NCE_EINVAL, "bad far_field");
+    if (o.warm_start != 0) return fail(NCE_EINVAL, "opts.warm_start is reserved (set a network with nce_set_warm_start)");
+    return NCE_OK;
 }
 
-}  // namespace
+int validate_centers(const double* centers, const std::vector<int64_t>& cfg_first, double eps) {
+    const int64_t N = cfg_first.back();
+    for (int64_t i = 0; i < N; ++i) {
+        const double* c = centers + 3 * i;
+        if (!std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2]))
+            return fail(NCE_EINVAL, "non-finite centre " + std::to_string(i));
+        double nn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        if (std::fabs(nn - 1.0) > 1e-12) return fail(NCE_EINVAL, "centre " + std::to_string(i) + " is not a unit vector");
+    }
+    for (size_t c = 0; c + 1 < cfg_first.size(); ++c) {
+        const int rc = check_separation(centers + 3 * cfg_first[c], cfg_first[c + 1] - cfg_first[c], eps);
+        if (rc != NCE_OK) {
+            if (cfg_first.size() > 2) g_err = "configuration " + std::to_string(c) + ": " + g_err;
+            return rc;
+        }
+    }
+    return NCE_OK;
+}
+
+void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& cfg_first, double eps,
+              const nce_opts& o, bool forest) {
+    const int64_t N = cfg_first.back();
+    ctx->opts = o;
+    ctx->N = N;
+    ctx->eps = eps;
+    ctx->cfg_first = cfg_first;
+    std::string dir;
+    if (o.cache_dir) dir = o.cache_dir;
+    else if (const char* e = std::getenv("NCE_CACHE")) dir = e;
+    if (!nce::load_tables(dir, o.problem, eps, o.M, o.tol_id, ctx->tab)) {
+        ctx->tab = nce::build_tables(o.problem, eps, o.M, o.tol_id);
+        nce::save_tables(dir, ctx->tab);
+    }
+    ctx->K = ctx->tab.K;
+    ctx->Kstar = ctx->tab.Kstar;
+    ctx->p = ctx->tab.p;
+    build_frames(centers, N, ctx->frames);
+    if (o.stream) {
+        ctx->stream = (hipStream_t)o.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
+    hipStream_t s = ctx->stream;
+    const size_t n = (size_t)N * ctx->K;
+    if (forest) {
+        ctx->use_tree = true;
+    } else {
+        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
+        ctx->use_tree = want_tree && N > 1;
+    }
+    // outgoing tables: the base representation, then (tree only) the
+    // recompressions for far targets, concatenated row-wise
+    std::vector<double> Tall(ctx->tab.T), soff(ctx->tab.skel_off);
+    ctx->tab_off = {0};
+    ctx->tab_p = {ctx->p};
+    if (ctx->use_tree) {
+        for (const auto& ft : ctx->tab.far) {
+            ctx->tab_off.push_back(ctx->tab_off.back() + ctx->tab_p.back());
+            ctx->tab_p.push_back(ft.p);
+            Tall.insert(Tall.end(), ft.T.begin(), ft.T.end());
+            soff.insert(soff.end(), ft.skel_off.begin(), ft.skel_off.end());
+        }
+    }
+    ctx->ptot = ctx->tab_off.back() + ctx->tab_p.back();
+    ctx->d_frames.upload(ctx->frames, s);
+    ctx->d_T.upload(Tall, s);
+    ctx->d_P.upload(ctx->tab.P, s);
+    ctx->d_I.upload(ctx->tab.I, s);
+    ctx->d_node_off.upload(ctx->tab.node_off, s);
+    ctx->d_skel_off.upload(soff, s);
+    ctx->d_T32.upload(to_f32(Tall), s);
+    ctx->d_P32.upload(to_f32(ctx->tab.P), s);
+    ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
+    ctx->d_skel_off32.upload(to_f32(soff), s);
+    ctx->d_rho.alloc((size_t)N * ctx->ptot);
+    ctx->d_U.alloc((size_t)N * ctx->Kstar);
+    ctx->d_rho32.alloc((size_t)N * ctx->ptot);
+    ctx->d_U32.alloc((size_t)N * ctx->Kstar);
+    ctx->d_x32.alloc(n);
+    ctx->d_b.alloc(n);
+    ctx->d_r.alloc(n);
+    ctx->d_x.alloc(n);
+    ctx->d_h.alloc((size_t)o.max_iter + 8);
+    ctx->d_partial.alloc((size_t)nce::kReduceBlocks * ((size_t)o.max_iter + 8));
+    ctx->d_scal.alloc(8);
+    const int ncfg = (int)cfg_first.size() - 1;
+    ctx->cfg_tree.assign(ncfg, ctx->use_tree ? 1 : 0);
+    if (ctx->use_tree && !forest) {
+        nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
+    } else if (forest) {
+        nce::start_forest(ctx->tree);
+        for (int c = 0; c < ncfg; ++c) {
+            const int64_t f0 = cfg_first[c], nc = cfg_first[c + 1] - f0;
+            bool tree = nc > 1 && o.far_field != NCE_FAR_DIRECT;
+            nce::Tree t;
+            if (tree) {
+                std::vector<double> fr(ctx->frames.begin() + 9 * f0, ctx->frames.begin() + 9 * (f0 + nc));
+                nce::build_tree(fr, nc, eps, ctx->tab, o.tol_grid, t);
+                if (o.far_field == NCE_FAR_AUTO) {
+                    // operation counts: one interpolation FMA costs about a quarter of a
+                    // Green's function pair (FP32 instruction mix of the two kernels)
+                    const double direct = (double)nc * (double)(nc - 1) * ctx->Kstar * (double)ctx->p;
+                    const double viatree = t.pairs_far + t.pairs_near + 0.25 * t.interp_fma;
+                    tree = viatree < direct;
+                }
+            }
+            ctx->cfg_tree[c] = tree ? 1 : 0;
+            if (tree) nce::append_tree(ctx->tree, t, f0);
+            else nce::append_direct(ctx->tree, f0, nc, ctx->Kstar, ctx->p);
+        }
+    }
+    if (ctx->use_tree) nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace nce_detail
 
 extern "C" {
 
@@ -486,90 +517,15 @@ int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts
     nce_default_opts(&o);
     if (opts_in) o = *opts_in;
     if (!centers || N < 1) return fail(NCE_EINVAL, "need N >= 1 centres");
-    if (!(eps > 0.0 && eps <= M_PI / 3.0)) return fail(NCE_EINVAL, "eps must lie in (0, pi/3]");
-    if (o.M < 0 || o.M > 30) return fail(NCE_EINVAL, "M must lie in [0, 30]");
-    if (o.problem != NCE_INTERIOR && o.problem != NCE_EXTERIOR) return fail(NCE_EINVAL, "bad problem");
-    if (!(o.tol_id > 0 && o.tol_id < 1e-3)) return fail(NCE_EINVAL, "tol_id must lie in (0, 1e-3)");
-    if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
-    if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
-    if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
-    if (o.warm_start != 0) return fail(NCE_EINVAL, "warm_start requires nce_load_mlp (not loaded)");
-    for (int64_t i = 0; i < N; ++i) {
-        const double* c = centers + 3 * i;
-        if (!std::isfinite(c[0]) || !std::isfinite(c[1]) || !std::isfinite(c[2]))
-            return fail(NCE_EINVAL, "non-finite centre " + std::to_string(i));
-        double nn = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-        if (std::fabs(nn - 1.0) > 1e-12) return fail(NCE_EINVAL, "centre " + std::to_string(i) + " is not a unit vector");
-    }
-    int rc = check_separation(centers, N, eps);
+    int rc = validate_opts(o, eps);
+    if (rc != NCE_OK) return rc;
+    const std::vector<int64_t> cfg_first{0, N};
+    rc = validate_centers(centers, cfg_first, eps);
     if (rc != NCE_OK) return rc;
     return guarded([&]() -> int {
         auto* ctx = new nce_ctx();
         std::unique_ptr<nce_ctx, void (*)(nce_ctx*)> guard(ctx, nce_destroy);
-        ctx->opts = o;
-        ctx->N = N;
-        ctx->eps = eps;
-        std::string dir;
-        if (o.cache_dir) dir = o.cache_dir;
-        else if (const char* e = std::getenv("NCE_CACHE")) dir = e;
-        if (!nce::load_tables(dir, o.problem, eps, o.M, o.tol_id, ctx->tab)) {
-            ctx->tab = nce::build_tables(o.problem, eps, o.M, o.tol_id);
-            nce::save_tables(dir, ctx->tab);
-        }
-        ctx->K = ctx->tab.K;
-        ctx->Kstar = ctx->tab.Kstar;
-        ctx->p = ctx->tab.p;
-        build_frames(centers, N, ctx->frames);
-        if (o.stream) {
-            ctx->stream = (hipStream_t)o.stream;
-        } else {
-            HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-            ctx->own_stream = true;
-        }
-        hipStream_t s = ctx->stream;
-        const size_t n = (size_t)N * ctx->K;
-        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
-        ctx->use_tree = want_tree && N > 1;
-        // outgoing tables: the base representation, then (tree only) the
-        // recompressions for far targets, concatenated row-wise
-        std::vector<double> Tall(ctx->tab.T), soff(ctx->tab.skel_off);
-        ctx->tab_off = {0};
-        ctx->tab_p = {ctx->p};
-        if (ctx->use_tree) {
-            for (const auto& ft : ctx->tab.far) {
-                ctx->tab_off.push_back(ctx->tab_off.back() + ctx->tab_p.back());
-                ctx->tab_p.push_back(ft.p);
-                Tall.insert(Tall.end(), ft.T.begin(), ft.T.end());
-                soff.insert(soff.end(), ft.skel_off.begin(), ft.skel_off.end());
-            }
-        }
-        ctx->ptot = ctx->tab_off.back() + ctx->tab_p.back();
-        ctx->d_frames.upload(ctx->frames, s);
-        ctx->d_T.upload(Tall, s);
-        ctx->d_P.upload(ctx->tab.P, s);
-        ctx->d_I.upload(ctx->tab.I, s);
-        ctx->d_node_off.upload(ctx->tab.node_off, s);
-        ctx->d_skel_off.upload(soff, s);
-        ctx->d_T32.upload(to_f32(Tall), s);
-        ctx->d_P32.upload(to_f32(ctx->tab.P), s);
-        ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
-        ctx->d_skel_off32.upload(to_f32(soff), s);
-        ctx->d_rho.alloc((size_t)N * ctx->ptot);
-        ctx->d_U.alloc((size_t)N * ctx->Kstar);
-        ctx->d_rho32.alloc((size_t)N * ctx->ptot);
-        ctx->d_U32.alloc((size_t)N * ctx->Kstar);
-        ctx->d_x32.alloc(n);
-        ctx->d_b.alloc(n);
-        ctx->d_r.alloc(n);
-        ctx->d_x.alloc(n);
-        ctx->d_h.alloc((size_t)o.max_iter + 8);
-        ctx->d_partial.alloc((size_t)nce::kReduceBlocks * ((size_t)o.max_iter + 8));
-        ctx->d_scal.alloc(8);
-        if (ctx->use_tree) {
-            nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
-            nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
-        }
-        HIPCHK(hipStreamSynchronize(s));
+        init_ctx(ctx, centers, cfg_first, eps, o, false);
         *out = guard.release();
         return NCE_OK;
     });

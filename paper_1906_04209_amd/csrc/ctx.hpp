@@ -1,0 +1,145 @@
+// Private to the library: the solver context and the pieces of its
+// implementation shared by the single-configuration and batched entry points.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/nce.h"
+#include "kernels.hpp"
+#include "mlp.hpp"
+#include "precompute.hpp"
+#include "tree.hpp"
+
+namespace nce_detail {
+
+extern thread_local std::string g_err;
+
+inline int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+struct HipError : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            throw HipError(std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count) {
+        release();
+        if (count == 0) return;
+        if (hipMalloc((void**)&p, count * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            throw std::bad_alloc();
+        }
+        n = count;
+    }
+    void upload(const std::vector<T>& v, hipStream_t s) {
+        alloc(v.size());
+        if (n) {
+            HIPCHK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+            HIPCHK(hipStreamSynchronize(s));  // the host vector may be a temporary
+        }
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { release(); }
+};
+
+template <class T>
+inline std::vector<float> to_f32(const std::vector<T>& v) {
+    return std::vector<float>(v.begin(), v.end());
+}
+
+
+}  // namespace nce_detail
+
+using nce_detail::DevBuf;
+
+struct nce_ctx {
+    nce_opts opts;
+    int64_t N = 0;
+    int K = 0, Kstar = 0, p = 0;
+    int ptot = 0;                       // strengths per patch over all outgoing tables in use
+    std::vector<int> tab_off, tab_p;    // per table: first column and size (table 0 = base)
+    double eps = 0;
+    nce::PatchTables tab;
+    std::vector<double> frames;  // N x 9: c, e1, e2
+    // independent configurations sharing (problem, eps): patches of
+    // configuration c are [cfg_first[c], cfg_first[c + 1]); they never interact
+    std::vector<int64_t> cfg_first;
+    std::vector<char> cfg_tree;         // per configuration: far field by the tree (1) or directly (0)
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool use_tree = false;              // tree pipeline (also used by a multi-configuration context)
+    nce::Tree tree;
+    nce::DeviceTree dtree;
+    // device tables
+    DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
+    DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
+    // matvec work arrays
+    DevBuf<double> d_rho, d_U;
+    DevBuf<float> d_rho32, d_U32, d_x32;
+    // solver work arrays
+    DevBuf<double> d_V, d_b, d_r, d_x, d_h, d_partial, d_scal;
+    int vcap = 0;  // number of Krylov vectors allocated
+    // learned warm start
+    nce::Mlp* warm = nullptr;
+    DevBuf<float> d_feat;
+    DevBuf<double> d_m, d_w;
+};
+
+struct nce_mlp {
+    nce::Mlp net;
+    nce_mlp(int a, int b, int c, int d, uint64_t e) : net(a, b, c, d, e) {}
+};
+
+namespace nce_detail {
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const HipError& e) {
+        return fail(NCE_EHIP, e.what());
+    } catch (const std::bad_alloc&) {
+        return fail(NCE_ENOMEM, "allocation failed");
+    } catch (const std::exception& e) {
+        return fail(NCE_ETABLE, e.what());
+    }
+}
+
+
+// Fills a context for the configurations [cfg_first[c], cfg_first[c + 1]) of
+// centers (all with the same eps and opts.problem). forest = false: one
+// configuration, far field chosen by opts.far_field (automatic: tree above
+// 4000 patches). forest = true: several configurations, each summed by its own
+// tree or directly (opts.far_field, or the cheaper by operation count).
+void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& cfg_first, double eps,
+              const nce_opts& o, bool forest);
+// Checks option ranges.
+int validate_opts(const nce_opts& o, double eps);
+// Checks unit centres and 3 eps separation within every configuration.
+int validate_centers(const double* centers, const std::vector<int64_t>& cfg_first, double eps);
+// y = A x (FP64 in and out; precision selects the FP64 or FP32 apply),
+// enqueued on ctx->stream; no host synchronisation.
+void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr);
+
+}  // namespace nce_detail

@@ -152,12 +152,22 @@ hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p,
                             const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
-    if (problem == 1)
-        hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, ldr, U, lptr, lsrc);
-    else
-        hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, ldr, U, lptr, lsrc);
+    // nodes per thread: 2 covers K* <= 512 without idle accumulators
+    if (Kstar <= 2 * 256) {
+        if (problem == 1)
+            hipLaunchKernelGGL((k_direct64<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+        else
+            hipLaunchKernelGGL((k_direct64<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+    } else {
+        if (problem == 1)
+            hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+        else
+            hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+    }
     return hipGetLastError();
 }
 
@@ -167,12 +177,22 @@ hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, 
                            const int64_t* lptr, const int* lsrc) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
-    if (problem == 1)
-        hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, ldr, U, lptr, lsrc);
-    else
-        hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                           rho, ldr, U, lptr, lsrc);
+    // nodes per thread: 2 covers K* <= 512 without idle accumulators
+    if (Kstar <= 2 * 256) {
+        if (problem == 1)
+            hipLaunchKernelGGL((k_direct32<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+        else
+            hipLaunchKernelGGL((k_direct32<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+    } else {
+        if (problem == 1)
+            hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+        else
+            hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
+                               rho, ldr, U, lptr, lsrc);
+    }
     return hipGetLastError();
 }
 

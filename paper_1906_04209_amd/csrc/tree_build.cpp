@@ -361,4 +361,61 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     }
 }
 
+void start_forest(Tree& t) {
+    t = Tree();
+    t.dl_ptr = {0};
+    t.l2t_ptr = {0};
+}
+
+void append_tree(Tree& dst, const Tree& src, int64_t first) {
+    const int g0 = dst.ngrid;
+    const int it0 = (int)dst.it_grid.size();
+    const int s0 = (int)dst.p2l_src.size();
+    const int64_t q0 = dst.total_q, p0 = dst.total_partial;
+    dst.nlevels = std::max(dst.nlevels, src.nlevels);
+    dst.N += src.N;
+    dst.ngrid += src.ngrid;
+    dst.g_frame.insert(dst.g_frame.end(), src.g_frame.begin(), src.g_frame.end());
+    dst.g_R.insert(dst.g_R.end(), src.g_R.begin(), src.g_R.end());
+    dst.g_nr.insert(dst.g_nr.end(), src.g_nr.begin(), src.g_nr.end());
+    dst.g_nt.insert(dst.g_nt.end(), src.g_nt.begin(), src.g_nt.end());
+    dst.g_level.insert(dst.g_level.end(), src.g_level.begin(), src.g_level.end());
+    dst.g_table.insert(dst.g_table.end(), src.g_table.begin(), src.g_table.end());
+    for (int g = 0; g < src.ngrid; ++g) {
+        dst.g_off.push_back(q0 + src.g_off[g]);
+        dst.g_item0.push_back(it0 + src.g_item0[g]);
+        dst.g_item1.push_back(it0 + src.g_item1[g]);
+    }
+    for (size_t it = 0; it < src.it_grid.size(); ++it) {
+        dst.it_grid.push_back(g0 + src.it_grid[it]);
+        dst.it_src0.push_back(s0 + src.it_src0[it]);
+        dst.it_src1.push_back(s0 + src.it_src1[it]);
+        dst.it_off.push_back(p0 + src.it_off[it]);
+    }
+    for (int j : src.p2l_src) dst.p2l_src.push_back((int)(first + j));
+    dst.total_q += src.total_q;
+    dst.total_partial += src.total_partial;
+    for (int64_t i = 0; i < src.N; ++i) {
+        dst.dl_ptr.push_back(dst.dl_ptr.back() + (src.dl_ptr[i + 1] - src.dl_ptr[i]));
+        dst.l2t_ptr.push_back(dst.l2t_ptr.back() + (src.l2t_ptr[i + 1] - src.l2t_ptr[i]));
+    }
+    for (int j : src.dl_src) dst.dl_src.push_back((int)(first + j));
+    for (int g : src.l2t_grid) dst.l2t_grid.push_back(g0 + g);
+    dst.pairs_far += src.pairs_far;
+    dst.pairs_near += src.pairs_near;
+    dst.interp_fma += src.interp_fma;
+    dst.max_q = std::max(dst.max_q, src.max_q);
+}
+
+void append_direct(Tree& dst, int64_t first, int64_t n, int Kstar, int p) {
+    dst.N += n;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) dst.dl_src.push_back((int)(first + j));
+        dst.dl_ptr.push_back(dst.dl_ptr.back() + (n - 1));
+        dst.l2t_ptr.push_back(dst.l2t_ptr.back());
+    }
+    dst.pairs_near += (double)n * (double)(n - 1) * Kstar * (double)p;
+}
+
 }  // namespace nce

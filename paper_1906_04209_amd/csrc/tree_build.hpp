@@ -67,4 +67,14 @@ void grid_size(double rho, double tol, int& nr, int& nt);
 
 void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab,
                 double tol_grid, Tree& out);
+
+// A forest: several independent configurations in one patch numbering, each
+// contributing its own tree or all-pairs direct lists; the far-field kernels
+// then run over every configuration in the same launches.
+void start_forest(Tree& t);
+// Appends the tree of a configuration whose patches are [first, first + src.N).
+void append_tree(Tree& dst, const Tree& src, int64_t first);
+// Appends a configuration of n patches starting at `first`, summed directly:
+// the direct list of each patch holds every other patch of the configuration.
+void append_direct(Tree& dst, int64_t first, int64_t n, int Kstar, int p);
 }  // namespace nce
