@@ -30,7 +30,7 @@ import layouts  # noqa: E402
 # FP64 vector), 32-bit ops 0.5 (157.3 TFLOP/s FP32 vector), FP32
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
-C_PAIR = {("fp64", 0): 68.1, ("fp64", 1): 55.1, ("fp32", 0): 12.4, ("fp32", 1): 9.4}
+C_PAIR = {("fp64", 0): 57.1, ("fp64", 1): 55.1, ("fp32", 0): 10.4, ("fp32", 1): 9.4}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
@@ -38,6 +38,7 @@ WORKLOADS = {
     "cfg5": dict(layouts.CONFIGS["cfg5"], far="tree"),
     "cfg2": dict(layouts.CONFIGS["cfg2"], far="direct"),
     "cfg3": dict(layouts.CONFIGS["cfg3"], far="tree"),
+    "cfg4": dict(problem=None, N=None, eps=None, far="auto", layout="uniform", seed=4000),
 }
 
 
@@ -65,6 +66,101 @@ def cpu_baseline(cfg, tol_id, x, centers, nrows=1):
             "seconds_per_matvec_extrapolated": per_matvec}, rows, y
 
 
+def run_batch(args):
+    """The batched workload: 256 independent configurations (interior and
+    exterior, eps 0.01 and 0.02, uneven N), applied and solved together.
+    One step = one FP32 system apply of every configuration."""
+    import torch
+    import paper_1906_04209_amd as nce
+
+    t0 = time.time()
+    mem = []
+    for b in range(256):
+        m = layouts.batch_member(b)
+        mem.append((layouts.uniform_centers(m["N"], m["eps"], m["seed"]), m["eps"], m["problem"]))
+    ntot = sum(len(c) for c, _, _ in mem)
+    log(f"layouts: 256 configurations, {ntot} patches ({time.time() - t0:.1f} s)")
+    t0 = time.time()
+    bt = nce.Batch(mem, tol_id=args.tol_id, tol_gmres=1e-8, precision=nce.MIXED, max_iter=60)
+    t_setup = time.time() - t0
+    work = bt.work()
+    log(f"batch setup {t_setup:.1f} s: groups {bt.ngroups}, tree members {int(bt.far_tree.sum())}, work {work}")
+    x = torch.from_numpy(np.concatenate([layouts.random_coeffs(len(c), bt.K, 777 + b, decay=0.1).ravel()
+                                         for b, (c, _, _) in enumerate(mem)])).cuda()
+    # x above is in member order; scatter to the batch layout
+    xb = bt.empty()
+    o = 0
+    for b, (c, _, _) in enumerate(mem):
+        n = len(c) * bt.K
+        xb[int(bt.offsets[b]):int(bt.offsets[b]) + n] = x[o:o + n]
+        o += n
+    y = bt.empty()
+    out_ms = {}
+    for name, pr in (("fp32", nce.MIXED), ("fp64", nce.FP64)):
+        for _ in range(args.warmup):
+            bt.matvec(xb, y, precision=pr)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            bt.matvec(xb, y, precision=pr)
+        torch.cuda.synchronize()
+        out_ms[name] = 1e3 * (time.perf_counter() - t1) / args.steps
+        log(f"batched apply {name}: {out_ms[name]:.2f} ms")
+    # lockstep mixed solve of all configurations to 1e-8, then FP64
+    solves = {}
+    for name, pr in (("mixed", nce.MIXED), ("fp64", nce.FP64)):
+        bt.set_solver(1e-8, 60, pr, use_graph=True)
+        r = bt.solve()
+        its = np.array([i["iters_fp32"] for i in r["info"]]), np.array([i["iters_fp64"] for i in r["info"]])
+        solves[name] = {"t_solve_s": r["info"][0]["t_solve_s"], "converged": bool(r["converged"]),
+                        "iters_fp32_max": int(its[0].max()), "iters_fp64_max": int(its[1].max()),
+                        "max_rel_residual": float(max(i["rel_residual"] for i in r["info"]))}
+        solves[name]["result"] = r["result"]
+        log(f"batched solve {name}: {solves[name]['t_solve_s']:.2f} s, converged {r['converged']}")
+    rel = np.abs(solves["mixed"]["result"] - solves["fp64"]["result"]) / np.abs(solves["fp64"]["result"])
+    # the same configurations one at a time (single contexts, mixed, same tolerance)
+    t_seq = 0.0
+    t_seq_setup = 0.0
+    seq_res = np.zeros(256)
+    nseq = len(mem) if not args.quick_sequential else 32
+    for b in range(nseq):
+        c, eps, prob = mem[b]
+        t1 = time.time()
+        ctx = nce.Context(c, eps, problem=prob, tol_id=args.tol_id, tol_gmres=1e-8, precision=nce.MIXED)
+        t_seq_setup += time.time() - t1
+        rr = ctx.solve(want_coeffs=False, want_flux=False)
+        t_seq += rr["t_solve_s"]
+        seq_res[b] = rr["mu"] if prob == nce.INTERIOR else rr["capture_rate"]
+        ctx.close()
+    t_seq *= len(mem) / nseq
+    rel_seq = np.abs(seq_res[:nseq] - solves["mixed"]["result"][:nseq]) / np.abs(seq_res[:nseq])
+    log(f"sequential single solves: {t_seq:.2f} s (scaled from {nseq}), setup {t_seq_setup:.1f} s")
+    pairs = work["pairs_far"]
+    cp = C_PAIR[("fp32", 0)]
+    for sname in ("mixed", "fp64"):
+        solves[sname].pop("result")
+    out = {
+        "metric": "batched FP32 system applies/s over 256 independent configurations (sum N = %d)" % ntot,
+        "value": 1e3 / out_ms["fp32"], "unit": "batch-apply/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": out_ms["fp32"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "cfg4", "configurations": 256, "sum_N": ntot, "eps": [0.01, 0.02],
+                   "problems": ["interior", "exterior"], "tol_id": args.tol_id,
+                   "tree_members": int(bt.far_tree.sum())},
+        "fp64_apply_ms": out_ms["fp64"], "setup_s": t_setup,
+        "solve_batched": solves,
+        "max_rel_diff_mixed_vs_fp64": float(rel.max()),
+        "solve_sequential_single_s": t_seq, "sequential_configurations_timed": nseq,
+        "max_rel_diff_batched_vs_single": float(rel_seq.max()),
+        "speedup_batched_vs_sequential": t_seq / solves["mixed"]["t_solve_s"],
+        "roofline": {"bound": "alu", "kernel": "far-field Green's sum (FP32, whole apply)",
+                     "achieved": pairs / (out_ms["fp32"] * 1e-3) / 1e9, "peak": LANE_CYCLES_PER_S / cp / 1e9,
+                     "unit": "Gpair/s", "frac": pairs / (out_ms["fp32"] * 1e-3) / (LANE_CYCLES_PER_S / cp),
+                     "traffic": None, "note": "far pairs / whole apply time (a lower bound on the P2L rate)"},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +171,8 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the FP64 and mixed solves to 1e-8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the solves from the learned initial guess")
+    ap.add_argument("--quick-sequential", action="store_true",
+                    help="batched workload: time 32 of the 256 single solves and scale")
     ap.add_argument("--tol-id", type=float, default=1e-11)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -83,6 +181,8 @@ def main():
         sys.exit(2)
 
     os.environ.setdefault("NCE_CACHE", "/tmp")
+    if args.workload == "cfg4":
+        return run_batch(args)
     import torch
     import paper_1906_04209_amd as nce
 

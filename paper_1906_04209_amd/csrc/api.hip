@@ -96,7 +96,7 @@ void ensure_krylov(nce_ctx* ctx, int nvec) {
 // stream). With ev != nullptr, events ev[0..5] bracket the five steps.
 template <class T>
 void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm, const T* noff, const T* soff,
-              T* rho, T* U, hipEvent_t* ev) {
+              T* rho, T* U, hipEvent_t* ev, const int* live) {
     const int N = (int)ctx->N, K = ctx->K, Ks = ctx->Kstar, p = ctx->p;
     hipStream_t s = ctx->stream;
     auto mark = [&](int k) {
@@ -117,13 +117,13 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     mark(1);
     if (ctx->use_tree) {
         // Step 2: far field onto incoming grids (P2L)
-        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho));
+        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho, live));
         mark(2);
         // Step 3: leaf neighbours directly at the sampling nodes (writes U)
-        HIPCHK(nce::tree_near<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U));
+        HIPCHK(nce::tree_near<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U, live));
         mark(3);
         // Step 4: interpolation of every ancestor's incoming grid (adds into U)
-        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U));
+        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U, live));
         mark(4);
     } else {
         HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U));
@@ -136,7 +136,7 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     mark(5);
 }
 
-void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev) {
+void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev, const int* live) {
     if (ctx->N == 1) {
         if (ev)
             for (int k = 0; k < 6; ++k) HIPCHK(hipEventRecord(ev[k], ctx->stream));
@@ -145,10 +145,10 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
     }
     if (precision == NCE_FP64)
         matvec_t<double>(ctx, x, y, ctx->d_T.p, ctx->d_P.p, ctx->d_node_off.p, ctx->d_skel_off.p, ctx->d_rho.p,
-                         ctx->d_U.p, ev);
+                         ctx->d_U.p, ev, live);
     else
         matvec_t<float>(ctx, x, y, ctx->d_T32.p, ctx->d_P32.p, ctx->d_node_off32.p, ctx->d_skel_off32.p,
-                        ctx->d_rho32.p, ctx->d_U32.p, ev);
+                        ctx->d_rho32.p, ctx->d_U32.p, ev, live);
 }
 
 double dev_dot(nce_ctx* ctx, int64_t n, const double* a, const double* b) {
@@ -419,11 +419,20 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     }
     hipStream_t s = ctx->stream;
     const size_t n = (size_t)N * ctx->K;
+    // far field of a single configuration: the tree or the direct all-pairs sum
+    // as opts.far_field says, or (automatic) whichever has the smaller operation
+    // count (one interpolation FMA is priced at a quarter of a Green's function
+    // pair, from the FP32 instruction mixes of the two kernels)
     if (forest) {
         ctx->use_tree = true;
+    } else if (N < 2 || o.far_field == NCE_FAR_DIRECT) {
+        ctx->use_tree = false;
     } else {
-        const bool want_tree = (o.far_field == NCE_FAR_TREE) || (o.far_field == NCE_FAR_AUTO && N > 4000);
-        ctx->use_tree = want_tree && N > 1;
+        nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
+        const double direct = (double)N * (double)(N - 1) * ctx->tab.Kstar * (double)ctx->tab.p;
+        const double viatree = ctx->tree.pairs_far + ctx->tree.pairs_near + 0.25 * ctx->tree.interp_fma;
+        ctx->use_tree = o.far_field == NCE_FAR_TREE || viatree < direct;
+        if (!ctx->use_tree) ctx->tree = nce::Tree();
     }
     // outgoing tables: the base representation, then (tree only) the
     // recompressions for far targets, concatenated row-wise
@@ -462,9 +471,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->d_scal.alloc(8);
     const int ncfg = (int)cfg_first.size() - 1;
     ctx->cfg_tree.assign(ncfg, ctx->use_tree ? 1 : 0);
-    if (ctx->use_tree && !forest) {
-        nce::build_tree(ctx->frames, N, eps, ctx->tab, o.tol_grid, ctx->tree);
-    } else if (forest) {
+    if (forest) {
         nce::start_forest(ctx->tree);
         for (int c = 0; c < ncfg; ++c) {
             const int64_t f0 = cfg_first[c], nc = cfg_first[c + 1] - f0;

@@ -232,6 +232,7 @@ struct nce_batch {
     std::vector<nce_ctx*> groups;          // one context per (problem, eps)
     std::vector<int> g_problem;
     std::vector<int64_t> g_elem;           // first vector element of each group (+ total)
+    std::vector<int> g_seg0;               // first segment of each group
     std::vector<int> seg_cfg;              // segment (internal order) -> configuration index b
     std::vector<int> cfg_seg;              // configuration b -> segment
     std::vector<int> seg_group;
@@ -262,10 +263,13 @@ struct nce_batch {
 
 namespace {
 
-// y = A x for every configuration (batch layout), enqueued on the stream
-void batch_matvec(nce_batch* bt, const double* x, double* y, int precision) {
+// y = A x for every configuration (batch layout), enqueued on the stream;
+// with live (device, per segment) the far-field work of configurations whose
+// flag is 0 is skipped.
+void batch_matvec(nce_batch* bt, const double* x, double* y, int precision, const int* live = nullptr) {
     for (size_t g = 0; g < bt->groups.size(); ++g)
-        matvec(bt->groups[g], x + bt->g_elem[g], y + bt->g_elem[g], precision);
+        matvec(bt->groups[g], x + bt->g_elem[g], y + bt->g_elem[g], precision, nullptr,
+               live ? live + bt->g_seg0[g] : nullptr);
 }
 
 void ensure_solver(nce_batch* bt, int maxit) {
@@ -323,7 +327,8 @@ void arnoldi_step(nce_batch* bt, int precision) {
     const int64_t ldv = bt->n;
     double* V = bt->d_V.p;
     hipLaunchKernelGGL(k_copy_vj, grid_for(bt->n), dim3(256), 0, s, V, ldv, bt->d_j.p, bt->n, bt->d_xin.p);
-    batch_matvec(bt, bt->d_xin.p, bt->d_w.p, precision);
+    // configurations that have converged (active = 0) skip their sums
+    batch_matvec(bt, bt->d_xin.p, bt->d_w.p, precision, bt->d_active.p);
     for (int pass = 0; pass < 2; ++pass) {
         double* h = pass == 0 ? bt->d_h1.p : bt->d_h2.p;
         hipLaunchKernelGGL(k_seg_dots, dim3(bt->nch), dim3(256), 0, s, V, ldv, bt->d_w.p, bt->d_j.p, 1,
@@ -634,6 +639,7 @@ int nce_setup_batch(const double* const* centers, const int64_t* N, const double
             bt->K = ctx->K;
             const int gidx = (int)bt->groups.size() - 1;
             bt->g_problem.push_back(og.problem);
+            bt->g_seg0.push_back((int)bt->seg_cfg.size());
             bt->g_elem.push_back(bt->g_elem.back() + ctx->N * ctx->K);
             for (int b : members) {
                 bt->cfg_seg[b] = (int)bt->seg_cfg.size();

@@ -139,7 +139,10 @@ int validate_opts(const nce_opts& o, double eps);
 // Checks unit centres and 3 eps separation within every configuration.
 int validate_centers(const double* centers, const std::vector<int64_t>& cfg_first, double eps);
 // y = A x (FP64 in and out; precision selects the FP64 or FP32 apply),
-// enqueued on ctx->stream; no host synchronisation.
-void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr);
+// enqueued on ctx->stream; no host synchronisation. live (device, may be
+// null): per configuration of a multi-configuration context, 0 skips that
+// configuration's Green's-function work (its rows of y are then unspecified).
+void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr,
+            const int* live = nullptr);
 
 }  // namespace nce_detail

@@ -79,25 +79,32 @@ __host__ __device__ __forceinline__ double rsqrt64(double x) {
 #endif
 }
 
-// G as a function of d^2 (FP64).
+// G as a function of d^2 (FP64). With r = 1/d, w = 2r and u = 1/w = d/2 =
+// d^2 r / 2, the interior logarithm is log(w^2 / (1 + w)) = -log(u^2 + u),
+// which needs no division.
 template <int PROB>
 __host__ __device__ __forceinline__ double green64(double d2) {
-    const double w = 2.0 * rsqrt64(d2);
+    const double r = rsqrt64(d2);
+    const double w = 2.0 * r;
     if (PROB == 1) return w - log64(1.0 + w);
-    return w + log64(div64(w * w, 1.0 + w));
+    const double u = 0.5 * d2 * r;
+    return w - log64(fma(u, u, u));
 }
 
 #if defined(__HIPCC__)
-// FP32: hardware reciprocal square root, reciprocal and base-2 logarithm. The
-// two parts are returned separately, G = w + sgn ln2 l2 (sgn = -1 exterior,
-// +1 interior), so the caller folds the ln 2 scale into its accumulator.
+// FP32: hardware reciprocal square root and base-2 logarithm (two
+// transcendentals per pair). The two parts are returned separately,
+// G = w - ln2 l2, so the caller folds the ln 2 scale into its accumulator:
+// exterior l2 = log2(1 + w); interior l2 = log2(u^2 + u), u = d/2 (as green64).
 template <int PROB>
 __device__ __forceinline__ void green32_parts(float d2, float& w, float& l2) {
-    w = 2.0f * __builtin_amdgcn_rsqf(d2);
+    const float r = __builtin_amdgcn_rsqf(d2);
+    w = 2.0f * r;
     if (PROB == 1) {
         l2 = __builtin_amdgcn_logf(1.0f + w);
     } else {
-        l2 = __builtin_amdgcn_logf(w * w * __builtin_amdgcn_rcpf(1.0f + w));
+        const float u = (0.5f * d2) * r;
+        l2 = __builtin_amdgcn_logf(fmaf(u, u, u));
     }
 }
 #endif

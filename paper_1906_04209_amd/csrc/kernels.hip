@@ -19,13 +19,15 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
                                                   const double* __restrict__ node_off,
                                                   const double* __restrict__ skel_off,
                                                   const double* __restrict__ rho, int ldr, double* __restrict__ U,
-                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
+                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
+                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live) {
     extern __shared__ double sm64[];
     double* sx = sm64;
     double* sy = sx + p;
     double* sz = sy + p;
     double* sr = sz + p;
     const int i = blockIdx.x;
+    if (live && !live[pt_cfg[i]]) return;
     const double* fi = frames + 9 * (int64_t)i;
     const double cix = fi[0], ciy = fi[1], ciz = fi[2];
     double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
@@ -79,13 +81,15 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
                                                   const float* __restrict__ node_off,
                                                   const float* __restrict__ skel_off,
                                                   const float* __restrict__ rho, int ldr, float* __restrict__ U,
-                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc) {
+                                                  const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
+                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live) {
     extern __shared__ float sm32[];
     float* sx = sm32;
     float* sy = sx + p;
     float* sz = sy + p;
     float* sr = sz + p;
     const int i = blockIdx.x;
+    if (live && !live[pt_cfg[i]]) return;
     const double* fi = frames + 9 * (int64_t)i;
     const double cix = fi[0], ciy = fi[1], ciz = fi[2];
     float zx[NPT], zy[NPT], zz[NPT];
@@ -104,7 +108,6 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
         }
     }
     constexpr float kLn2 = 0.69314718055994530942f;
-    constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
     // sources: every other patch, or the CSR list of patch i
     const int64_t q0 = lptr ? lptr[i] : 0, q1 = lptr ? lptr[i + 1] : N;
     for (int64_t qq = q0; qq < q1; ++qq) {
@@ -137,7 +140,7 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
         }
         // per-source-patch partial sums are short; carry the running total in FP64
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+        for (int r = 0; r < NPT; ++r) acc[r] += (double)(aw[r] - kLn2 * al[r]);
     }
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
@@ -149,24 +152,24 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
 template <>
 hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
                             const double* node_off, const double* skel_off, const double* rho, int ldr, double* U,
-                            const int64_t* lptr, const int* lsrc) {
+                            const int64_t* lptr, const int* lsrc, const int* pt_cfg, const int* live) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
         else
             hipLaunchKernelGGL((k_direct64<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
         else
             hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
     }
     return hipGetLastError();
 }
@@ -174,24 +177,24 @@ hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p,
 template <>
 hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
                            const float* node_off, const float* skel_off, const float* rho, int ldr, float* U,
-                           const int64_t* lptr, const int* lsrc) {
+                           const int64_t* lptr, const int* lsrc, const int* pt_cfg, const int* live) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
         else
             hipLaunchKernelGGL((k_direct32<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
         else
             hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
     }
     return hipGetLastError();
 }
@@ -199,7 +202,8 @@ hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, 
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
                       const T* skel_off, const T* rho, T* U) {
-    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr);
+    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr, nullptr,
+                       nullptr);
 }
 template hipError_t direct_sum<double>(hipStream_t, int, int, int, int, const double*, const double*, const double*,
                                        const double*, double*);

@@ -39,9 +39,11 @@ hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const
 
 // Same with the sources of target i restricted to lsrc[lptr[i] .. lptr[i+1]) (CSR)
 // and the strengths of patch j at rho[j * ldr .. j * ldr + p).
+// Targets i with live && !live[pt_cfg[i]] are skipped (pt_cfg, live may be null).
 template <class T>
 hipError_t list_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
-                    const T* skel_off, const T* rho, int ldr, T* U, const int64_t* lptr, const int* lsrc);
+                    const T* skel_off, const T* rho, int ldr, T* U, const int64_t* lptr, const int* lsrc,
+                    const int* pt_cfg = nullptr, const int* live = nullptr);
 
 // Krylov helpers (FP64).
 hipError_t dots(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* w,

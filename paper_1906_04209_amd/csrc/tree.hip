@@ -58,9 +58,11 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ g_nt, const int* __restrict__ g_table,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
-                                               const double* __restrict__ rho, int ptot, double* __restrict__ part) {
+                                               const double* __restrict__ rho, int ptot, double* __restrict__ part,
+                                               const int* __restrict__ it_cfg, const int* __restrict__ live) {
     __shared__ double sx[kStage], sy[kStage], sz[kStage], sr[kStage];
     const int item = blockIdx.x;
+    if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
@@ -135,10 +137,12 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ g_nt, const int* __restrict__ g_table,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
-                                               const float* __restrict__ rho, int ptot, float* __restrict__ part) {
+                                               const float* __restrict__ rho, int ptot, float* __restrict__ part,
+                                               const int* __restrict__ it_cfg, const int* __restrict__ live) {
     __shared__ float sx[kStage], sy[kStage], sz[kStage], sr[kStage];
     __shared__ double red[kStage];
     const int item = blockIdx.x;
+    if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
@@ -163,7 +167,6 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
         }
     }
     constexpr float kLn2 = 0.69314718055994530942f;
-    constexpr float sgn = (PROB == 1) ? -1.0f : 1.0f;
     const int s0 = it_src0[item];
     const int total = (it_src1[item] - s0) * pt;
     for (int c0 = 0; c0 < total; c0 += kStage) {
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                     }
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] += (double)(aw[r] + sgn * kLn2 * al[r]);
+                for (int r = 0; r < 4; ++r) acc[r] += (double)(aw[r] - kLn2 * al[r]);
             }
         }
     }
@@ -229,11 +232,13 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
                                                      const int64_t* __restrict__ g_off,
                                                      const int* __restrict__ g_item0, const int* __restrict__ g_item1,
                                                      const int64_t* __restrict__ it_off, const T* __restrict__ part,
-                                                     T* __restrict__ vals, T* __restrict__ coef) {
+                                                     T* __restrict__ vals, T* __restrict__ coef,
+                                                     const int* __restrict__ g_cfg, const int* __restrict__ live) {
     __shared__ double sv[kMaxGridQ];
     __shared__ double sa[kMaxGridQ];
     __shared__ double tc[256], ts[256], tch[8 * kMaxGridNr];
     const int g = blockIdx.x;
+    if (live && !live[g_cfg[g]]) return;
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int i0 = g_item0[g], i1 = g_item1[g];
     // trigonometric tables: cos, sin(2 pi j / nt) and cos(2 pi j / (8 nr))
@@ -285,9 +290,11 @@ __global__ __launch_bounds__(256) void k_l2t(int Kstar, const double* __restrict
                                              const int* __restrict__ l2t_grid, const double* __restrict__ g_frame,
                                              const double* __restrict__ g_R, const int* __restrict__ g_nr,
                                              const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
-                                             const T* __restrict__ coef, T* __restrict__ U) {
+                                             const T* __restrict__ coef, T* __restrict__ U,
+                                             const int* __restrict__ pt_cfg, const int* __restrict__ live) {
     __shared__ T cs[kMaxGridQ];
     const int i = blockIdx.x;
+    if (live && !live[pt_cfg[i]]) return;
     const int64_t a0 = l2t_ptr[i], a1 = l2t_ptr[i + 1];
     if (a0 == a1) return;
     const double* fi = frames + 9 * (int64_t)i;
@@ -406,6 +413,9 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
     d.dl_src = dev_copy(t.dl_src);
     d.l2t_ptr = dev_copy(t.l2t_ptr);
     d.l2t_grid = dev_copy(t.l2t_grid);
+    d.it_cfg = dev_copy(t.it_cfg);
+    d.g_cfg = dev_copy(t.g_cfg);
+    d.pt_cfg = dev_copy(t.pt_cfg);
     d.vals64 = dev_alloc<double>(t.total_q);
     d.coef64 = dev_alloc<double>(t.total_q);
     d.part64 = dev_alloc<double>(t.total_partial);
@@ -417,7 +427,8 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
 void free_tree(DeviceTree& d) {
     void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
-                    d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32};
+                    d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
+                    d.it_cfg, d.g_cfg, d.pt_cfg};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -425,69 +436,74 @@ void free_tree(DeviceTree& d) {
 
 template <>
 hipError_t tree_far<double>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
-                            const double* skel_off, const double* rho) {
+                            const double* skel_off, const double* rho, const int* live) {
+    if (!d.it_cfg) live = nullptr;
     if (d.nitems > 0) {
         if (problem == 1)
             hipLaunchKernelGGL((k_p2l64<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part64);
+                               frames, skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
         else
             hipLaunchKernelGGL((k_p2l64<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part64);
+                               frames, skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
     }
     if (d.ngrid > 0)
         hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                           d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64);
+                           d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64, d.g_cfg, live);
     return hipGetLastError();
 }
 
 template <>
 hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
-                           const float* skel_off, const float* rho) {
+                           const float* skel_off, const float* rho, const int* live) {
+    if (!d.it_cfg) live = nullptr;
     if (d.nitems > 0) {
         if (problem == 1)
             hipLaunchKernelGGL((k_p2l32<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part32);
+                               frames, skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
         else
             hipLaunchKernelGGL((k_p2l32<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                                d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part32);
+                               frames, skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
     }
     if (d.ngrid > 0)
         hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                           d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32);
+                           d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32, d.g_cfg, live);
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
-                     const T* skel_off, const T* rho, T* U) {
+                     const T* skel_off, const T* rho, T* U, const int* live) {
+    if (!d.pt_cfg) live = nullptr;
     // near field uses the base table (the first p columns of every strength row)
     return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, d.ptot, U, d.dl_ptr,
-                       d.dl_src);
+                       d.dl_src, d.pt_cfg, live);
 }
 template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
-                                      const double*, const double*, double*);
+                                      const double*, const double*, double*, const int*);
 template hipError_t tree_near<float>(hipStream_t, const DeviceTree&, int, const double*, const float*, const float*,
-                                     const float*, float*);
+                                     const float*, float*, const int*);
 
 template <>
 hipError_t tree_interp<double>(hipStream_t s, const DeviceTree& d, const double* frames, const double* node_off,
-                               double* U) {
+                               double* U, const int* live) {
     if (d.ngrid == 0) return hipSuccess;
+    if (!d.pt_cfg) live = nullptr;
     hipLaunchKernelGGL((k_l2t<double, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
-                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef64, U);
+                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef64, U, d.pt_cfg, live);
     return hipGetLastError();
 }
 
 template <>
 hipError_t tree_interp<float>(hipStream_t s, const DeviceTree& d, const double* frames, const float* node_off,
-                              float* U) {
+                              float* U, const int* live) {
     if (d.ngrid == 0) return hipSuccess;
+    if (!d.pt_cfg) live = nullptr;
     hipLaunchKernelGGL((k_l2t<float, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
-                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef32, U);
+                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef32, U, d.pt_cfg, live);
     return hipGetLastError();
 }
 

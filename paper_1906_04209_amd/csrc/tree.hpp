@@ -32,6 +32,10 @@ struct DeviceTree {
     int* dl_src = nullptr;
     int64_t* l2t_ptr = nullptr;
     int* l2t_grid = nullptr;
+    // forest: configuration of every item, grid and patch (null for one tree)
+    int* it_cfg = nullptr;
+    int* g_cfg = nullptr;
+    int* pt_cfg = nullptr;
     // work buffers (FP64 and FP32)
     double* vals64 = nullptr;
     double* coef64 = nullptr;
@@ -47,17 +51,21 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
                  hipStream_t s, DeviceTree& d);
 void free_tree(DeviceTree& d);
 
+// `live` (may be null): per configuration of a forest, 0 = skip its work in
+// this apply (its outputs are then left unspecified).
+//
 // Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per
 // grid and turned into Chebyshev-Fourier coefficients.
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
-                    const T* rho);
+                    const T* rho, const int* live = nullptr);
 // Step 3 (direct form): direct-list sums at each patch's sampling nodes; writes U.
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
-                     const T* skel_off, const T* rho, T* U);
+                     const T* skel_off, const T* rho, T* U, const int* live = nullptr);
 // Step 4: interpolate every listed incoming grid at the sampling nodes; adds into U.
 template <class T>
-hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U);
+hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U,
+                       const int* live = nullptr);
 
 }  // namespace nce

@@ -393,6 +393,10 @@ void append_tree(Tree& dst, const Tree& src, int64_t first) {
         dst.it_off.push_back(p0 + src.it_off[it]);
     }
     for (int j : src.p2l_src) dst.p2l_src.push_back((int)(first + j));
+    dst.it_cfg.insert(dst.it_cfg.end(), src.it_grid.size(), dst.ncfg);
+    dst.g_cfg.insert(dst.g_cfg.end(), (size_t)src.ngrid, dst.ncfg);
+    dst.pt_cfg.insert(dst.pt_cfg.end(), (size_t)src.N, dst.ncfg);
+    dst.ncfg += 1;
     dst.total_q += src.total_q;
     dst.total_partial += src.total_partial;
     for (int64_t i = 0; i < src.N; ++i) {
@@ -409,6 +413,8 @@ void append_tree(Tree& dst, const Tree& src, int64_t first) {
 
 void append_direct(Tree& dst, int64_t first, int64_t n, int Kstar, int p) {
     dst.N += n;
+    dst.pt_cfg.insert(dst.pt_cfg.end(), (size_t)n, dst.ncfg);
+    dst.ncfg += 1;
     for (int64_t i = 0; i < n; ++i) {
         for (int64_t j = 0; j < n; ++j)
             if (j != i) dst.dl_src.push_back((int)(first + j));

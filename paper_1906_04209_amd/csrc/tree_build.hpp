@@ -56,6 +56,9 @@ struct Tree {
     // grids to interpolate at each patch's sampling nodes, CSR over patches
     std::vector<int64_t> l2t_ptr;
     std::vector<int> l2t_grid;
+    // configuration of every item, grid and patch (forest; empty for one tree)
+    std::vector<int> it_cfg, g_cfg, pt_cfg;
+    int ncfg = 0;
     // work per matrix-vector product
     double pairs_far = 0, pairs_near = 0, interp_fma = 0;
     int max_q = 0;

@@ -25,5 +25,5 @@ int main() {
         worst_ge = std::max(worst_ge, (double)(std::fabs(nce::green64<1>(d * d) - ge) / std::fabs(ge)) / 2.220446049250313e-16);
     }
     std::printf("log64 %.2f ulp, green interior %.2f ulp, green exterior %.2f ulp\n", worst_log, worst_gi, worst_ge);
-    return (worst_log < 4 && worst_gi < 16 && worst_ge < 16) ? 0 : 1;
+    return (worst_log < 4 && worst_gi < 8 && worst_ge < 8) ? 0 : 1;
 }
