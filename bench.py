@@ -85,6 +85,9 @@ def run_batch(args):
     t_setup = time.time() - t0
     work = bt.work()
     log(f"batch setup {t_setup:.1f} s: groups {bt.ngroups}, tree members {int(bt.far_tree.sum())}, work {work}")
+    t0 = time.time()
+    tuned = {"fp64": bt.autotune(nce.FP64), "fp32": bt.autotune(nce.MIXED)}
+    log(f"autotuned shapes per group {tuned} ({time.time() - t0:.1f} s)")
     x = torch.from_numpy(np.concatenate([layouts.random_coeffs(len(c), bt.K, 777 + b, decay=0.1).ravel()
                                          for b, (c, _, _) in enumerate(mem)])).cuda()
     # x above is in member order; scatter to the batch layout
@@ -147,7 +150,7 @@ def run_batch(args):
         "config": {"workload": "cfg4", "configurations": 256, "sum_N": ntot, "eps": [0.01, 0.02],
                    "problems": ["interior", "exterior"], "tol_id": args.tol_id,
                    "tree_members": int(bt.far_tree.sum())},
-        "fp64_apply_ms": out_ms["fp64"], "setup_s": t_setup,
+        "fp64_apply_ms": out_ms["fp64"], "setup_s": t_setup, "autotuned_shapes": tuned,
         "solve_batched": solves,
         "max_rel_diff_mixed_vs_fp64": float(rel.max()),
         "solve_sequential_single_s": t_seq, "sequential_configurations_timed": nseq,
@@ -197,6 +200,8 @@ def main():
     t_setup = time.time() - t0
     work = ctx.work()
     log(f"setup {t_setup:.1f} s: K={ctx.K} K*={ctx.Kstar} p={ctx.p} levels={ctx.levels} work={work}")
+    tuned = ctx.autotune(prec) if far == nce.FAR_TREE else None
+    log(f"autotuned kernel shapes (P2L points/thread, interpolation nodes/thread): {tuned}")
     x_np = layouts.random_coeffs(cfg["N"], ctx.K, 777, decay=0.1)
     x = torch.from_numpy(x_np).cuda()
     y = ctx.empty()
@@ -231,7 +236,7 @@ def main():
                    "K": ctx.K, "Kstar": ctx.Kstar, "p": ctx.p, "levels": ctx.levels, "tol_id": args.tol_id,
                    "layout": cfg["layout"], "seed": cfg["seed"]},
         "step_ms": {"block_apply": st[0], "far": st[1], "near": st[2], "interp": st[3], "p_apply": st[4]},
-        "setup_s": t_setup,
+        "setup_s": t_setup, "autotuned_shapes": tuned,
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
                      "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},

@@ -142,6 +142,17 @@ int nce_matvec_profile(nce_ctx *ctx, const double *x_dev, double *y_dev, int pre
                        double *step_ms_host);
 
 /*
+ * Autotuner: times every valid shape of the far-field kernels on this
+ * context's own tree at the given precision -- P2L grid points per thread
+ * (4 or 8) and interpolation nodes per thread (2, 4 or 8 with 256, 128 or 64
+ * threads per patch) -- and keeps the fastest for later applies. choice_host
+ * (may be NULL): the two chosen values. Synchronises the stream; no effect on
+ * a context that sums its far field directly. Results do not depend on the
+ * shapes beyond rounding order.
+ */
+int nce_autotune(nce_ctx *ctx, int precision, int *choice_host);
+
+/*
  * Change the solver settings of an existing context (tables and tree are
  * kept): relative residual tolerance, iteration limit, NCE_FP64 or NCE_MIXED.
  * Errors: NCE_EINVAL for values outside the ranges nce_setup accepts.
@@ -265,6 +276,10 @@ int nce_batch_set_solver(nce_batch *batch, double tol_gmres, int max_iter, int p
  * Returns NCE_NOTCONVERGED if any configuration missed the tolerance.
  */
 int nce_solve_batch(nce_batch *batch, double *result_host, double *coeffs_dev, nce_info *infos_host);
+
+/* nce_autotune for every (problem, eps) group of the batch; choice_host (may
+ * be NULL): 2 x ngroups values in group order. */
+int nce_batch_autotune(nce_batch *batch, int precision, int *choice_host);
 
 /* Short description of a status code. */
 const char *nce_strerror(int code);

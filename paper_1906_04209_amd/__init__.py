@@ -31,7 +31,7 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
-           "nce_batch_set_solver", "nce_solve_batch"]
+           "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune"]
 FEATURES = 54
 
 
@@ -111,8 +111,10 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_batch_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nce_batch_set_solver.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.nce_solve_batch.argtypes = [vp, vp, vp, vp]
+    lib.nce_autotune.argtypes = [vp, ctypes.c_int, vp]
+    lib.nce_batch_autotune.argtypes = [vp, ctypes.c_int, vp]
     for name in ("nce_setup_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
-                 "nce_batch_set_solver", "nce_solve_batch"):
+                 "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     lib.nce_strerror.argtypes = [ctypes.c_int]
     lib.nce_strerror.restype = ctypes.c_char_p
@@ -321,6 +323,13 @@ class Context:
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
         _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))
 
+    def autotune(self, precision: int = FP64):
+        """Pick the fastest far-field kernel shapes on this layout; returns
+        (P2L grid points per thread, interpolation nodes per thread)."""
+        ch = np.zeros(2, dtype=np.int32)
+        _check(self.lib, self.lib.nce_autotune(self.h, int(precision), ch.ctypes.data))
+        return int(ch[0]), int(ch[1])
+
     def solve(self, want_coeffs: bool = True, want_flux: bool = True) -> dict:
         x = self.empty() if want_coeffs else None
         f = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda") if want_flux else None
@@ -423,6 +432,12 @@ class Batch:
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int, use_graph: bool = True):
         _check(self.lib, self.lib.nce_batch_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision),
                                                        int(bool(use_graph))))
+
+    def autotune(self, precision: int = MIXED):
+        """nce_batch_autotune: per group (P2L points per thread, interpolation nodes per thread)."""
+        ch = np.zeros(2 * self.ngroups, dtype=np.int32)
+        _check(self.lib, self.lib.nce_batch_autotune(self.h, int(precision), ch.ctypes.data))
+        return [(int(ch[2 * g]), int(ch[2 * g + 1])) for g in range(self.ngroups)]
 
     def solve(self, want_coeffs: bool = False) -> dict:
         x = self.empty() if want_coeffs else None

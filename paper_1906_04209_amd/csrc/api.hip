@@ -117,13 +117,15 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     mark(1);
     if (ctx->use_tree) {
         // Step 2: far field onto incoming grids (P2L)
-        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho, live));
+        const int ti = sizeof(T) == 8 ? 0 : 1;
+        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho, live,
+                                ctx->tune_p2l[ti]));
         mark(2);
         // Step 3: leaf neighbours directly at the sampling nodes (writes U)
         HIPCHK(nce::tree_near<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U, live));
         mark(3);
         // Step 4: interpolation of every ancestor's incoming grid (adds into U)
-        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U, live));
+        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
         mark(4);
     } else {
         HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U));
@@ -149,6 +151,73 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
     else
         matvec_t<float>(ctx, x, y, ctx->d_T32.p, ctx->d_P32.p, ctx->d_node_off32.p, ctx->d_skel_off32.p,
                         ctx->d_rho32.p, ctx->d_U32.p, ev, live);
+}
+
+namespace {
+
+template <class T>
+void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
+    hipStream_t s = ctx->stream;
+    const int ti = sizeof(T) == 8 ? 0 : 1;
+    const nce::DeviceTree& d = ctx->dtree;
+    // the kernels' cost does not depend on the strengths: start from zeros
+    HIPCHK(hipMemsetAsync(rho, 0, sizeof(T) * (size_t)ctx->N * ctx->ptot, s));
+    HIPCHK(hipMemsetAsync(U, 0, sizeof(T) * (size_t)ctx->N * ctx->Kstar, s));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto best_of = [&](auto&& launch) {
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(hipEventRecord(e0, s));
+            HIPCHK(launch());
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    try {
+        float tbest = 1e30f;
+        for (int r : {4, 8}) {
+            if (d.max_q > 256 * r) continue;
+            const float t = best_of([&] {
+                return nce::tree_far<T>(s, d, ctx->tab.problem, ctx->d_frames.p, soff, rho, nullptr, r);
+            });
+            if (t < tbest) {
+                tbest = t;
+                ctx->tune_p2l[ti] = r;
+            }
+        }
+        tbest = 1e30f;
+        for (int npt : {2, 4, 8}) {
+            const int threads = npt == 2 ? 256 : (npt == 4 ? 128 : 64);
+            if (threads * npt < ctx->Kstar) continue;
+            const float t = best_of([&] { return nce::tree_interp<T>(s, d, ctx->d_frames.p, noff, U, nullptr, npt); });
+            if (t < tbest) {
+                tbest = t;
+                ctx->tune_l2t[ti] = npt;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+}  // namespace
+
+void autotune(nce_ctx* ctx, int precision) {
+    if (!ctx->use_tree || ctx->dtree.ngrid == 0) return;
+    if (precision == NCE_FP64)
+        autotune_t<double>(ctx, ctx->d_skel_off.p, ctx->d_node_off.p, ctx->d_rho.p, ctx->d_U.p);
+    else
+        autotune_t<float>(ctx, ctx->d_skel_off32.p, ctx->d_node_off32.p, ctx->d_rho32.p, ctx->d_U32.p);
 }
 
 double dev_dot(nce_ctx* ctx, int64_t n, const double* a, const double* b) {
@@ -607,6 +676,20 @@ int nce_matvec_profile(nce_ctx* ctx, const double* x, double* y, int precision, 
             throw;
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
+        return NCE_OK;
+    });
+}
+
+int nce_autotune(nce_ctx* ctx, int precision, int* choice) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    return guarded([&]() -> int {
+        autotune(ctx, precision);
+        const int ti = precision == NCE_FP64 ? 0 : 1;
+        if (choice) {
+            choice[0] = ctx->tune_p2l[ti];
+            choice[1] = ctx->tune_l2t[ti];
+        }
         return NCE_OK;
     });
 }

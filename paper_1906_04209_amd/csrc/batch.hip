@@ -752,6 +752,27 @@ int nce_batch_set_solver(nce_batch* bt, double tol, int max_iter, int precision,
     });
 }
 
+int nce_batch_autotune(nce_batch* bt, int precision, int* choice) {
+    if (!bt) return fail(NCE_EINVAL, "batch is NULL");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    return guarded([&]() -> int {
+        const int ti = precision == NCE_FP64 ? 0 : 1;
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            autotune(bt->groups[g], precision);
+            if (choice) {
+                choice[2 * g] = bt->groups[g]->tune_p2l[ti];
+                choice[2 * g + 1] = bt->groups[g]->tune_l2t[ti];
+            }
+        }
+        // captured steps hold the old kernel shapes
+        if (bt->graph[ti]) {
+            (void)hipGraphExecDestroy(bt->graph[ti]);
+            bt->graph[ti] = nullptr;
+        }
+        return NCE_OK;
+    });
+}
+
 int nce_solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos) {
     if (!bt || !results) return fail(NCE_EINVAL, "NULL argument");
     return guarded([&]() -> int { return solve_batch(bt, results, coeffs, infos); });

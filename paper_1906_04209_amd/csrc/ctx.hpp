@@ -89,6 +89,10 @@ struct nce_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool use_tree = false;              // tree pipeline (also used by a multi-configuration context)
+    // kernel shapes chosen by autotune() per precision (0 FP64, 1 FP32):
+    // P2L grid points per thread and interpolation nodes per thread
+    int tune_p2l[2] = {4, 4};
+    int tune_l2t[2] = {2, 2};
     nce::Tree tree;
     nce::DeviceTree dtree;
     // device tables
@@ -144,5 +148,9 @@ int validate_centers(const double* centers, const std::vector<int64_t>& cfg_firs
 // configuration's Green's-function work (its rows of y are then unspecified).
 void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr,
             const int* live = nullptr);
+// Times every valid shape of the P2L and interpolation kernels on the
+// context's own tree at the given precision and keeps the fastest
+// (synchronises the stream; no-op without a tree).
+void autotune(nce_ctx* ctx, int precision);
 
 }  // namespace nce_detail

@@ -34,23 +34,24 @@ __device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, doub
 
 // ----------------------------------------------------------------- P2L
 // One block per work item (one grid, up to kSrcPerItem source patches). The
-// 256 threads are split into ns groups; each thread owns up to 4 grid points
-// (spaced qq = ceil(q/4) apart) and takes every ns-th staged source point, so
-// small grids still keep every lane busy. The item's source skeleton points
+// 256 threads are split into ns groups; each thread owns up to R grid points
+// (spaced qq = ceil(q/R) apart; R = 4 or 8, chosen by the autotuner) and takes
+// every ns-th staged source point, so small grids still keep every lane busy. The item's source skeleton points
 // (of the outgoing table its grid uses) and strengths are staged in LDS in
 // batches of kStage points, positions relative to the grid's cap centre. The
 // groups' partial sums are combined in LDS and written per item to `part`.
 constexpr int kStage = 1024;
 
+template <int R>
 __device__ __forceinline__ void p2l_layout(int q, int& qq, int& ns, int& split, int& t0) {
-    qq = (q + 3) / 4;
+    qq = (q + R - 1) / R;
     ns = 256 / qq;
     ns = ns < 1 ? 1 : (ns > 64 ? 64 : ns);
     split = threadIdx.x / qq;
     t0 = threadIdx.x - split * qq;
 }
 
-template <int PROB>
+template <int PROB, int R>
 __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
@@ -60,26 +61,31 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live) {
-    __shared__ double sx[kStage], sy[kStage], sz[kStage], sr[kStage];
+    // staging (4 x kStage) and, after the sums, the split partials (ns q <= 256 R)
+    __shared__ double smem[4 * kStage];
+    double* sx = smem;
+    double* sy = smem + kStage;
+    double* sz = smem + 2 * kStage;
+    double* sr = smem + 3 * kStage;
     const int item = blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
-    const double R = g_R[g];
+    const double Rg = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
-    p2l_layout(q, qq, ns, split, t0);
+    p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    double zx[4], zy[4], zz[4], acc[4];
+    double zx[R], zy[R], zz[R], acc[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int t = t0 + r * qq;
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
         if (active && t < q) {
             double o0, o1, o2;
-            grid_point(t, nr, nt, R, o0, o1, o2);
+            grid_point(t, nr, nt, Rg, o0, o1, o2);
             zx[r] = o0 * fg[0] + o1 * fg[3] + o2 * fg[6];
             zy[r] = o0 * fg[1] + o1 * fg[4] + o2 * fg[7];
             zz[r] = o0 * fg[2] + o1 * fg[5] + o2 * fg[8];
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             for (int m = split; m < cl; m += ns) {
                 const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < R; ++r) {
                     const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
                     acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
                 }
@@ -113,10 +119,10 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
         }
     }
     __syncthreads();
-    double* red = sx;  // ns * q <= 1024 partial sums
+    double* red = smem;  // ns * q <= 256 R partial sums
     if (active)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int t = t0 + r * qq;
             if (t < q) red[split * q + t] = acc[r];
         }
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     }
 }
 
-template <int PROB>
+template <int PROB, int R>
 __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
@@ -139,28 +145,33 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live) {
-    __shared__ float sx[kStage], sy[kStage], sz[kStage], sr[kStage];
-    __shared__ double red[kStage];
+    // staging (4 x kStage floats) and, after the sums, the split partials
+    // (ns q <= 256 R doubles) share one buffer
+    __shared__ double smem[2 * kStage];
+    float* sx = reinterpret_cast<float*>(smem);
+    float* sy = sx + kStage;
+    float* sz = sx + 2 * kStage;
+    float* sr = sx + 3 * kStage;
     const int item = blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
-    const double R = g_R[g];
+    const double Rg = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
-    p2l_layout(q, qq, ns, split, t0);
+    p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    float zx[4], zy[4], zz[4];
-    double acc[4];
+    float zx[R], zy[R], zz[R];
+    double acc[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int t = t0 + r * qq;
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0f;
         if (active && t < q) {
             double o0, o1, o2;
-            grid_point(t, nr, nt, R, o0, o1, o2);
+            grid_point(t, nr, nt, Rg, o0, o1, o2);
             zx[r] = (float)(o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
             zy[r] = (float)(o0 * fg[1] + o1 * fg[4] + o2 * fg[7]);
             zz[r] = (float)(o0 * fg[2] + o1 * fg[5] + o2 * fg[8]);
@@ -187,13 +198,13 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
             // FP32 sums over at most 256 points, carried in FP64 between runs
             for (int m0 = split; m0 < cl; m0 += 256 * ns) {
                 const int m1 = min(cl, m0 + 256 * ns);
-                float aw[4], al[4];
+                float aw[R], al[R];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) aw[r] = al[r] = 0.0f;
+                for (int r = 0; r < R; ++r) aw[r] = al[r] = 0.0f;
                 for (int m = m0; m < m1; m += ns) {
                     const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
+                    for (int r = 0; r < R; ++r) {
                         const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
                         float w, l2;
                         green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
@@ -202,14 +213,15 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                     }
                 }
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] += (double)(aw[r] - kLn2 * al[r]);
+                for (int r = 0; r < R; ++r) acc[r] += (double)(aw[r] - kLn2 * al[r]);
             }
         }
     }
     __syncthreads();
+    double* red = smem;
     if (active)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int t = t0 + r * qq;
             if (t < q) red[split * q + t] = acc[r];
         }
@@ -389,6 +401,7 @@ T* dev_alloc(int64_t n) {
 void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
                  hipStream_t, DeviceTree& d) {
     d.ngrid = t.ngrid;
+    d.max_q = t.max_q;
     d.ptot = tab_off.back() + tab_p.back();
     d.g_table = dev_copy(t.g_table);
     d.t_off = dev_copy(tab_off);
@@ -434,45 +447,48 @@ void free_tree(DeviceTree& d) {
     d = DeviceTree();
 }
 
-template <>
-hipError_t tree_far<double>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
-                            const double* skel_off, const double* rho, const int* live) {
-    if (!d.it_cfg) live = nullptr;
-    if (d.nitems > 0) {
-        if (problem == 1)
-            hipLaunchKernelGGL((k_p2l64<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
-        else
-            hipLaunchKernelGGL((k_p2l64<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
-    }
-    if (d.ngrid > 0)
-        hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                           d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64, d.g_cfg, live);
-    return hipGetLastError();
+template <class T, int PROB, int R>
+void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const T* skel_off, const T* rho,
+                const int* live) {
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
+    else
+        hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
 }
 
-template <>
-hipError_t tree_far<float>(hipStream_t s, const DeviceTree& d, int problem, const double* frames,
-                           const float* skel_off, const float* rho, const int* live) {
+template <class T>
+hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
+                    const T* rho, const int* live, int r_tgt) {
     if (!d.it_cfg) live = nullptr;
+    if (r_tgt != 4 && r_tgt != 8) return hipErrorInvalidValue;
+    if (d.max_q > 256 * r_tgt) return hipErrorInvalidValue;
     if (d.nitems > 0) {
-        if (problem == 1)
-            hipLaunchKernelGGL((k_p2l32<1>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
-        else
-            hipLaunchKernelGGL((k_p2l32<0>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                               d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p,
-                               frames, skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
+        if (problem == 1) {
+            if (r_tgt == 8) launch_p2l<T, 1, 8>(s, d, frames, skel_off, rho, live);
+            else launch_p2l<T, 1, 4>(s, d, frames, skel_off, rho, live);
+        } else {
+            if (r_tgt == 8) launch_p2l<T, 0, 8>(s, d, frames, skel_off, rho, live);
+            else launch_p2l<T, 0, 4>(s, d, frames, skel_off, rho, live);
+        }
     }
-    if (d.ngrid > 0)
-        hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                           d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32, d.g_cfg, live);
+    if (d.ngrid > 0) {
+        if constexpr (sizeof(T) == 8)
+            hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
+                               d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64, d.g_cfg, live);
+        else
+            hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
+                               d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32, d.g_cfg, live);
+    }
     return hipGetLastError();
 }
+template hipError_t tree_far<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
+                                     const double*, const int*, int);
+template hipError_t tree_far<float>(hipStream_t, const DeviceTree&, int, const double*, const float*, const float*,
+                                    const int*, int);
 
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
@@ -487,24 +503,31 @@ template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const
 template hipError_t tree_near<float>(hipStream_t, const DeviceTree&, int, const double*, const float*, const float*,
                                      const float*, float*, const int*);
 
-template <>
-hipError_t tree_interp<double>(hipStream_t s, const DeviceTree& d, const double* frames, const double* node_off,
-                               double* U, const int* live) {
+template <class T>
+hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U,
+                       const int* live, int npt) {
     if (d.ngrid == 0) return hipSuccess;
     if (!d.pt_cfg) live = nullptr;
-    hipLaunchKernelGGL((k_l2t<double, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
-                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef64, U, d.pt_cfg, live);
+    const T* coef;
+    if constexpr (sizeof(T) == 8) coef = d.coef64;
+    else coef = d.coef32;
+    // nodes per thread x threads per block covers K*
+    const int threads = npt == 2 ? 256 : (npt == 4 ? 128 : 64);
+    if ((npt != 2 && npt != 4 && npt != 8) || threads * npt < d.Kstar) return hipErrorInvalidValue;
+    if (npt == 2)
+        hipLaunchKernelGGL((k_l2t<T, 2>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
+    else if (npt == 4)
+        hipLaunchKernelGGL((k_l2t<T, 4>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
+    else
+        hipLaunchKernelGGL((k_l2t<T, 8>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
     return hipGetLastError();
 }
-
-template <>
-hipError_t tree_interp<float>(hipStream_t s, const DeviceTree& d, const double* frames, const float* node_off,
-                              float* U, const int* live) {
-    if (d.ngrid == 0) return hipSuccess;
-    if (!d.pt_cfg) live = nullptr;
-    hipLaunchKernelGGL((k_l2t<float, 2>), dim3((unsigned)d.N), dim3(256), 0, s, d.Kstar, frames, node_off,
-                       d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, d.coef32, U, d.pt_cfg, live);
-    return hipGetLastError();
-}
+template hipError_t tree_interp<double>(hipStream_t, const DeviceTree&, const double*, const double*, double*,
+                                        const int*, int);
+template hipError_t tree_interp<float>(hipStream_t, const DeviceTree&, const double*, const float*, float*,
+                                       const int*, int);
 
 }  // namespace nce

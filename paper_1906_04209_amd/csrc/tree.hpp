@@ -36,6 +36,7 @@ struct DeviceTree {
     int* it_cfg = nullptr;
     int* g_cfg = nullptr;
     int* pt_cfg = nullptr;
+    int max_q = 0;
     // work buffers (FP64 and FP32)
     double* vals64 = nullptr;
     double* coef64 = nullptr;
@@ -56,16 +57,18 @@ void free_tree(DeviceTree& d);
 //
 // Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per
 // grid and turned into Chebyshev-Fourier coefficients.
+// r_tgt: grid points per thread of the P2L kernel (4, or 8; needs 256 r_tgt >= max q).
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
-                    const T* rho, const int* live = nullptr);
+                    const T* rho, const int* live = nullptr, int r_tgt = 4);
 // Step 3 (direct form): direct-list sums at each patch's sampling nodes; writes U.
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
                      const T* skel_off, const T* rho, T* U, const int* live = nullptr);
 // Step 4: interpolate every listed incoming grid at the sampling nodes; adds into U.
+// npt: sampling nodes per thread (2, 4 or 8 with 256, 128 or 64 threads per patch).
 template <class T>
 hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U,
-                       const int* live = nullptr);
+                       const int* live = nullptr, int npt = 2);
 
 }  // namespace nce

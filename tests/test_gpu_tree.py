@@ -82,3 +82,26 @@ def test_tree_solve_matches_direct(torch):
     assert rd["converged"] and rt["converged"] and rm["converged"]
     assert abs(rt["mu"] - rd["mu"]) < 1e-9 * rd["mu"]
     assert abs(rm["mu"] - rd["mu"]) < 1e-9 * rd["mu"]
+
+
+def test_autotune_shapes_keep_result(torch):
+    """Every kernel shape the autotuner may pick gives the same apply up to
+    summation order."""
+    import paper_1906_04209_amd as nce
+    cfg = layouts.CONFIGS["cfg2"]
+    c = layouts.config_layout(cfg)
+    ctx = nce.Context(c, cfg["eps"], problem=cfg["problem"], tol_id=1e-11, far_field=nce.FAR_TREE)
+    x = torch.from_numpy(layouts.random_coeffs(cfg["N"], ctx.K, 5, decay=0.1)).cuda()
+    ref64 = ctx.matvec(x, precision=nce.FP64)
+    ref32 = ctx.matvec(x, precision=nce.MIXED)
+    ch64 = ctx.autotune(nce.FP64)
+    ch32 = ctx.autotune(nce.MIXED)
+    y64 = ctx.matvec(x, precision=nce.FP64)
+    y32 = ctx.matvec(x, precision=nce.MIXED)
+    d = (ref64 - x).abs().max().item()
+    e64 = (y64 - ref64).abs().max().item() / d
+    e32 = (y32 - ref32).abs().max().item() / d
+    print(f"autotune FP64 {ch64} FP32 {ch32}: change FP64 {e64:.2e} FP32 {e32:.2e}")
+    assert ch64[0] in (4, 8) and ch64[1] in (2, 4, 8) and ch32[0] in (4, 8) and ch32[1] in (2, 4, 8)
+    assert e64 < 1e-13
+    assert e32 < 1e-6
