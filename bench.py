@@ -30,7 +30,9 @@ import layouts  # noqa: E402
 # FP64 vector), 32-bit ops 0.5 (157.3 TFLOP/s FP32 vector), FP32
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
-C_PAIR = {("fp64", 0): 57.1, ("fp64", 1): 55.1, ("fp32", 0): 10.4, ("fp32", 1): 9.4}
+# Keyed by (precision, problem, P2L grid points per thread).
+C_PAIR = {("fp64", 0, 4): 56.1, ("fp64", 0, 8): 55.8, ("fp64", 1, 4): 55.1, ("fp64", 1, 8): 54.8,
+          ("fp32", 0, 4): 9.4, ("fp32", 0, 8): 9.2, ("fp32", 1, 4): 8.9, ("fp32", 1, 8): 8.7}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
@@ -139,7 +141,7 @@ def run_batch(args):
     rel_seq = np.abs(seq_res[:nseq] - solves["mixed"]["result"][:nseq]) / np.abs(seq_res[:nseq])
     log(f"sequential single solves: {t_seq:.2f} s (scaled from {nseq}), setup {t_seq_setup:.1f} s")
     pairs = work["pairs_far"]
-    cp = C_PAIR[("fp32", 0)]
+    cp = C_PAIR[("fp32", 0, 4)]
     for sname in ("mixed", "fp64"):
         solves[sname].pop("result")
     out = {
@@ -223,7 +225,7 @@ def main():
     dom = 1  # far field (direct all-pairs sum or P2L)
     pairs = work["pairs_far"]
     ptag = "fp64" if prec == nce.FP64 else "fp32"
-    cp = C_PAIR[(ptag, cfg["problem"])]
+    cp = C_PAIR[(ptag, cfg["problem"], tuned[0] if tuned else 4)]
     achieved = pairs / (st[dom] * 1e-3)
     peak = LANE_CYCLES_PER_S / cp
     out = {

@@ -79,16 +79,22 @@ __host__ __device__ __forceinline__ double rsqrt64(double x) {
 #endif
 }
 
-// G as a function of d^2 (FP64). With r = 1/d, w = 2r and u = 1/w = d/2 =
-// d^2 r / 2, the interior logarithm is log(w^2 / (1 + w)) = -log(u^2 + u),
-// which needs no division.
+// G as a function of h2 = d^2 / 4, the squared half-distance (FP64). Then
+// w = 2/d = 1/sqrt(h2) and u = 1/w = d/2 = h2 w, and the interior logarithm
+// log(w^2 / (1 + w)) = -log(u^2 + u) needs no division. The pair kernels keep
+// coordinates pre-scaled by 1/2 (exact), so h2 comes straight from them.
+template <int PROB>
+__host__ __device__ __forceinline__ double green64_half(double h2) {
+    const double w = rsqrt64(h2);
+    if (PROB == 1) return w - log64(1.0 + w);
+    const double u = h2 * w;
+    return w - log64(fma(u, u, u));
+}
+
+// G as a function of d^2 (FP64).
 template <int PROB>
 __host__ __device__ __forceinline__ double green64(double d2) {
-    const double r = rsqrt64(d2);
-    const double w = 2.0 * r;
-    if (PROB == 1) return w - log64(1.0 + w);
-    const double u = 0.5 * d2 * r;
-    return w - log64(fma(u, u, u));
+    return green64_half<PROB>(0.25 * d2);
 }
 
 #if defined(__HIPCC__)
@@ -96,14 +102,14 @@ __host__ __device__ __forceinline__ double green64(double d2) {
 // transcendentals per pair). The two parts are returned separately,
 // G = w - ln2 l2, so the caller folds the ln 2 scale into its accumulator:
 // exterior l2 = log2(1 + w); interior l2 = log2(u^2 + u), u = d/2 (as green64).
+// Argument h2 = d^2 / 4 as for green64_half.
 template <int PROB>
-__device__ __forceinline__ void green32_parts(float d2, float& w, float& l2) {
-    const float r = __builtin_amdgcn_rsqf(d2);
-    w = 2.0f * r;
+__device__ __forceinline__ void green32_parts_half(float h2, float& w, float& l2) {
+    w = __builtin_amdgcn_rsqf(h2);
     if (PROB == 1) {
         l2 = __builtin_amdgcn_logf(1.0f + w);
     } else {
-        const float u = (0.5f * d2) * r;
+        const float u = h2 * w;
         l2 = __builtin_amdgcn_logf(fmaf(u, u, u));
     }
 }

@@ -21,11 +21,7 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
                                                   const double* __restrict__ rho, int ldr, double* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
                                                   const int* __restrict__ pt_cfg, const int* __restrict__ live) {
-    extern __shared__ double sm64[];
-    double* sx = sm64;
-    double* sy = sx + p;
-    double* sz = sy + p;
-    double* sr = sz + p;
+    extern __shared__ double4 sm64[];  // p source points (x, y, z, rho), half-scaled
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
     const double* fi = frames + 9 * (int64_t)i;
@@ -37,9 +33,9 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
         acc[r] = 0.0;
         if (q < Kstar) {
             const double o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
-            zx[r] = o0 * cix + o1 * fi[3] + o2 * fi[6];
-            zy[r] = o0 * ciy + o1 * fi[4] + o2 * fi[7];
-            zz[r] = o0 * ciz + o1 * fi[5] + o2 * fi[8];
+            zx[r] = 0.5 * (o0 * cix + o1 * fi[3] + o2 * fi[6]);
+            zy[r] = 0.5 * (o0 * ciy + o1 * fi[4] + o2 * fi[7]);
+            zz[r] = 0.5 * (o0 * ciz + o1 * fi[5] + o2 * fi[8]);
         } else {
             zx[r] = zy[r] = zz[r] = 0.0;
         }
@@ -54,18 +50,20 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
         __syncthreads();
         for (int m = threadIdx.x; m < p; m += blockDim.x) {
             const double o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
-            sx[m] = dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]);
-            sy[m] = dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]);
-            sz[m] = dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]);
-            sr[m] = rho[(int64_t)j * ldr + m];
+            double4 v;
+            v.x = 0.5 * (dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]));
+            v.y = 0.5 * (dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]));
+            v.z = 0.5 * (dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]));
+            v.w = rho[(int64_t)j * ldr + m];
+            sm64[m] = v;
         }
         __syncthreads();
         for (int m = 0; m < p; ++m) {
-            const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+            const double4 a = sm64[m];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
-                acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+                const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
+                acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz) * a.w;
             }
         }
     }
@@ -83,11 +81,7 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
                                                   const float* __restrict__ rho, int ldr, float* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
                                                   const int* __restrict__ pt_cfg, const int* __restrict__ live) {
-    extern __shared__ float sm32[];
-    float* sx = sm32;
-    float* sy = sx + p;
-    float* sz = sy + p;
-    float* sr = sz + p;
+    extern __shared__ float4 sm32[];  // p source points (x, y, z, rho), half-scaled
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
     const double* fi = frames + 9 * (int64_t)i;
@@ -100,9 +94,9 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
         acc[r] = 0.0;
         if (q < Kstar) {
             const float o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
-            zx[r] = o0 * (float)cix + o1 * (float)fi[3] + o2 * (float)fi[6];
-            zy[r] = o0 * (float)ciy + o1 * (float)fi[4] + o2 * (float)fi[7];
-            zz[r] = o0 * (float)ciz + o1 * (float)fi[5] + o2 * (float)fi[8];
+            zx[r] = 0.5f * (o0 * (float)cix + o1 * (float)fi[3] + o2 * (float)fi[6]);
+            zy[r] = 0.5f * (o0 * (float)ciy + o1 * (float)fi[4] + o2 * (float)fi[7]);
+            zz[r] = 0.5f * (o0 * (float)ciz + o1 * (float)fi[5] + o2 * (float)fi[8]);
         } else {
             zx[r] = zy[r] = zz[r] = 0.0f;
         }
@@ -118,24 +112,26 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
         __syncthreads();
         for (int m = threadIdx.x; m < p; m += blockDim.x) {
             const float o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
-            sx[m] = dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]);
-            sy[m] = dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]);
-            sz[m] = dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]);
-            sr[m] = rho[(int64_t)j * ldr + m];
+            float4 v;
+            v.x = 0.5f * (dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]));
+            v.y = 0.5f * (dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]));
+            v.z = 0.5f * (dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]));
+            v.w = rho[(int64_t)j * ldr + m];
+            sm32[m] = v;
         }
         __syncthreads();
         float aw[NPT], al[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
         for (int m = 0; m < p; ++m) {
-            const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+            const float4 a = sm32[m];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                const float dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
                 float w, l2;
-                green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
-                aw[r] += w * rr;
-                al[r] += l2 * rr;
+                green32_parts_half<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                aw[r] += w * a.w;
+                al[r] += l2 * a.w;
             }
         }
         // per-source-patch partial sums are short; carry the running total in FP64

@@ -61,12 +61,10 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live) {
-    // staging (4 x kStage) and, after the sums, the split partials (ns q <= 256 R)
-    __shared__ double smem[4 * kStage];
-    double* sx = smem;
-    double* sy = smem + kStage;
-    double* sz = smem + 2 * kStage;
-    double* sr = smem + 3 * kStage;
+    // staging (kStage points of (x, y, z, rho), interleaved) and, after the
+    // sums, the split partials (ns q <= 256 R)
+    __shared__ double4 smem4[kStage];
+    double* smem = reinterpret_cast<double*>(smem4);
     const int item = blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
@@ -86,9 +84,10 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
         if (active && t < q) {
             double o0, o1, o2;
             grid_point(t, nr, nt, Rg, o0, o1, o2);
-            zx[r] = o0 * fg[0] + o1 * fg[3] + o2 * fg[6];
-            zy[r] = o0 * fg[1] + o1 * fg[4] + o2 * fg[7];
-            zz[r] = o0 * fg[2] + o1 * fg[5] + o2 * fg[8];
+            // half-scaled offsets from the cap centre
+            zx[r] = 0.5 * (o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
+            zy[r] = 0.5 * (o0 * fg[1] + o1 * fg[4] + o2 * fg[7]);
+            zz[r] = 0.5 * (o0 * fg[2] + o1 * fg[5] + o2 * fg[8]);
         }
     }
     const int s0 = it_src0[item];
@@ -101,19 +100,21 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             const int j = src[s0 + js];
             const double* fj = frames + 9 * (int64_t)j;
             const double* o = skel_off + 3 * (int64_t)(toff + m);
-            sx[idx] = (fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]);
-            sy[idx] = (fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]);
-            sz[idx] = (fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]);
-            sr[idx] = rho[(int64_t)j * ptot + toff + m];
+            double4 v;
+            v.x = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
+            v.y = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
+            v.z = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
+            v.w = rho[(int64_t)j * ptot + toff + m];
+            smem4[idx] = v;
         }
         __syncthreads();
         if (active) {
             for (int m = split; m < cl; m += ns) {
-                const double ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+                const double4 a = smem4[m];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const double dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
-                    acc[r] += green64<PROB>(dx * dx + dy * dy + dz * dz) * rr;
+                    const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
+                    acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz) * a.w;
                 }
             }
         }
@@ -145,13 +146,10 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live) {
-    // staging (4 x kStage floats) and, after the sums, the split partials
-    // (ns q <= 256 R doubles) share one buffer
-    __shared__ double smem[2 * kStage];
-    float* sx = reinterpret_cast<float*>(smem);
-    float* sy = sx + kStage;
-    float* sz = sx + 2 * kStage;
-    float* sr = sx + 3 * kStage;
+    // staging (kStage points of (x, y, z, rho), interleaved) and, after the
+    // sums, the split partials (ns q <= 256 R doubles) share one buffer
+    __shared__ float4 smem4[kStage];
+    double* smem = reinterpret_cast<double*>(smem4);
     const int item = blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
@@ -172,9 +170,10 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
         if (active && t < q) {
             double o0, o1, o2;
             grid_point(t, nr, nt, Rg, o0, o1, o2);
-            zx[r] = (float)(o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
-            zy[r] = (float)(o0 * fg[1] + o1 * fg[4] + o2 * fg[7]);
-            zz[r] = (float)(o0 * fg[2] + o1 * fg[5] + o2 * fg[8]);
+            // half-scaled offsets from the cap centre
+            zx[r] = (float)(0.5 * (o0 * fg[0] + o1 * fg[3] + o2 * fg[6]));
+            zy[r] = (float)(0.5 * (o0 * fg[1] + o1 * fg[4] + o2 * fg[7]));
+            zz[r] = (float)(0.5 * (o0 * fg[2] + o1 * fg[5] + o2 * fg[8]));
         }
     }
     constexpr float kLn2 = 0.69314718055994530942f;
@@ -188,10 +187,12 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
             const int j = src[s0 + js];
             const double* fj = frames + 9 * (int64_t)j;
             const float* o = skel_off + 3 * (int64_t)(toff + m);
-            sx[idx] = (float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]);
-            sy[idx] = (float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]);
-            sz[idx] = (float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]);
-            sr[idx] = rho[(int64_t)j * ptot + toff + m];
+            float4 v;
+            v.x = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
+            v.y = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
+            v.z = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
+            v.w = rho[(int64_t)j * ptot + toff + m];
+            smem4[idx] = v;
         }
         __syncthreads();
         if (active) {
@@ -202,14 +203,14 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) aw[r] = al[r] = 0.0f;
                 for (int m = m0; m < m1; m += ns) {
-                    const float ax = sx[m], ay = sy[m], az = sz[m], rr = sr[m];
+                    const float4 a = smem4[m];
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const float dx = zx[r] - ax, dy = zy[r] - ay, dz = zz[r] - az;
+                        const float dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
                         float w, l2;
-                        green32_parts<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
-                        aw[r] += w * rr;
-                        al[r] += l2 * rr;
+                        green32_parts_half<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                        aw[r] += w * a.w;
+                        al[r] += l2 * a.w;
                     }
                 }
 #pragma unroll
@@ -334,46 +335,82 @@ __global__ __launch_bounds__(256) void k_l2t(int Kstar, const double* __restrict
         const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
         const T cgx = (T)fg[0], cgy = (T)fg[1], cgz = (T)fg[2];
         const T invR = (T)(1.0 / g_R[g]);
+        // per node: polar coordinates about the grid's cap centre
+        T xs[NPT], ct[NPT], st[NPT], y2[NPT], t1e[NPT], t1o[NPT], val[NPT], ck[NPT], sk[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
-            const int qn = threadIdx.x + r * blockDim.x;
-            if (qn >= Kstar) continue;
             const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
             const T x1 = vx * e1x + vy * e1y + vz * e1z;
             const T x2 = vx * e2x + vy * e2y + vz * e2z;
             const T x3 = vx * cgx + vy * cgy + vz * cgz;
             const T rh = sqrt(x1 * x1 + x2 * x2);
             const T ang = atan2(rh, T(1) + x3);
-            T xs = ang * invR;
-            xs = xs > T(1) ? T(1) : xs;
-            const T ct = rh > T(0) ? x1 / rh : T(1);
-            const T st = rh > T(0) ? x2 / rh : T(0);
+            T x = ang * invR;
+            x = x > T(1) ? T(1) : x;
+            xs[r] = x;
+            ct[r] = rh > T(0) ? x1 / rh : T(1);
+            st[r] = rh > T(0) ? x2 / rh : T(0);
             // Chebyshev degrees of one parity: T_{2j}(x) = T_j(y), T_{2j+1} follow the
             // same three-term recurrence in y = T_2(x) = 2 x^2 - 1
-            const T y2 = T(2) * (T(2) * xs * xs - T(1));
-            const T t1e = T(2) * xs * xs - T(1), t1o = xs * (T(4) * xs * xs - T(3));
-            T val = T(0);
-            T ck = T(1), sk = T(0);
-            for (int k = 0; k <= half; ++k) {
-                const bool odd = k & 1;
-                const bool has_sin = (k > 0 && k < half);
-                const T* cc = cs + k * nr;
-                const T* sc = cs + (half + k) * nr;
-                T tp = odd ? xs : T(1), tc = odd ? t1o : t1e;  // degrees par, par + 2
-                T rc = cc[0] * tp, rs = has_sin ? sc[0] * tp : T(0);
-                for (int np = 1; np < nr; ++np) {
-                    rc += cc[np] * tc;
-                    if (has_sin) rs += sc[np] * tc;
-                    const T tn = y2 * tc - tp;
-                    tp = tc;
-                    tc = tn;
-                }
-                val += ck * rc + sk * rs;
-                const T cn = ck * ct - sk * st;
-                sk = sk * ct + ck * st;
-                ck = cn;
+            y2[r] = T(2) * (T(2) * x * x - T(1));
+            t1e[r] = T(2) * x * x - T(1);
+            t1o[r] = x * (T(4) * x * x - T(3));
+            val[r] = T(0);
+            ck[r] = T(1);
+            sk[r] = T(0);
+        }
+        // every coefficient read from LDS serves all NPT nodes of the thread
+        for (int k = 0; k <= half; ++k) {
+            const bool odd = k & 1;
+            const bool has_sin = (k > 0 && k < half);
+            const T* cc = cs + k * nr;
+            const T* sc = cs + (half + k) * nr;
+            T tp[NPT], tc[NPT], rc[NPT], rs[NPT];
+            const T c0 = cc[0];
+            const T s0 = has_sin ? sc[0] : T(0);
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                tp[r] = odd ? xs[r] : T(1);  // degree parity
+                tc[r] = odd ? t1o[r] : t1e[r];  // degree parity + 2
+                rc[r] = c0 * tp[r];
+                rs[r] = s0 * tp[r];
             }
-            U[(int64_t)i * Kstar + qn] += val;
+            if (has_sin) {
+                for (int np = 1; np < nr; ++np) {
+                    const T cv = cc[np], sv = sc[np];
+#pragma unroll
+                    for (int r = 0; r < NPT; ++r) {
+                        rc[r] += cv * tc[r];
+                        rs[r] += sv * tc[r];
+                        const T tn = y2[r] * tc[r] - tp[r];
+                        tp[r] = tc[r];
+                        tc[r] = tn;
+                    }
+                }
+            } else {
+                for (int np = 1; np < nr; ++np) {
+                    const T cv = cc[np];
+#pragma unroll
+                    for (int r = 0; r < NPT; ++r) {
+                        rc[r] += cv * tc[r];
+                        const T tn = y2[r] * tc[r] - tp[r];
+                        tp[r] = tc[r];
+                        tc[r] = tn;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                val[r] += ck[r] * rc[r] + sk[r] * rs[r];
+                const T cn = ck[r] * ct[r] - sk[r] * st[r];
+                sk[r] = sk[r] * ct[r] + ck[r] * st[r];
+                ck[r] = cn;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int qn = threadIdx.x + r * blockDim.x;
+            if (qn < Kstar) U[(int64_t)i * Kstar + qn] += val[r];
         }
     }
 }
