@@ -34,6 +34,10 @@ import layouts  # noqa: E402
 C_PAIR = {("fp64", 0, 4): 56.1, ("fp64", 0, 8): 55.8, ("fp64", 1, 4): 55.1, ("fp64", 1, 8): 54.8,
           ("fp32", 0, 4): 9.4, ("fp32", 0, 8): 9.2, ("fp32", 1, 4): 8.9, ("fp32", 1, 8): 8.7}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
+# HBM bytes per P2L launch at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
+# factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
+# current kernels; None where not measured.
+TRAFFIC = {("cfg5", "fp64", 8): 7.186e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
@@ -240,7 +244,8 @@ def main():
         "step_ms": {"block_apply": st[0], "far": st[1], "near": st[2], "interp": st[3], "p_apply": st[4]},
         "setup_s": t_setup, "autotuned_shapes": tuned,
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
-                     "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+                     "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
+                     "traffic": TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4)),
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }
     if not args.no_solve:
