@@ -192,9 +192,10 @@ int nce_solve_exterior(nce_ctx *ctx, double *coeffs_dev, double *patch_flux_dev,
  * ------------------------------------------------------------------------ */
 typedef struct nce_mlp nce_mlp;
 
-#define NCE_FEATURES 54 /* per patch: 16 nearest neighbours x (u, v, 1/r) in the patch frame
+#define NCE_FEATURES 56 /* per patch: 16 nearest neighbours x (u, v, 1/r) in the patch frame
                            (positions / (16 eps), 4 eps / distance), problem flag, 10 x area
-                           fraction, neighbour density relative to uniform within 8, 16, 32, 64 eps */
+                           fraction, neighbour density relative to uniform within 8, 16, 32, 64 eps,
+                           10 x (a_i / mean a - 1) and mean a (a: coarse amplitudes, see below) */
 
 /* He-initialised network n_in -> width (x hidden_layers, SiLU) -> n_out. */
 int nce_mlp_create(int n_in, int width, int hidden_layers, int n_out, uint64_t seed, nce_mlp **out);
@@ -211,11 +212,31 @@ int nce_mlp_loss_grad(nce_mlp *m, const float *x_dev, const float *t_dev, int64_
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8) on the loss of this batch. */
 int nce_mlp_train_step(nce_mlp *m, const float *x_dev, const float *t_dev, int64_t B, float lr, double *loss_host,
                        void *stream);
-/* The NCE_FEATURES features of every patch of ctx (N x NCE_FEATURES FP32 device array). */
-int nce_features(const nce_ctx *ctx, float *feat_dev);
-/* Use m (n_in = NCE_FEATURES, n_out = K) as the warm start of later solves; NULL disables.
- * The caller keeps m alive while it is set. */
-int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m);
+/* The NCE_FEATURES features of every patch of ctx (N x NCE_FEATURES FP32 device
+ * array); runs the coarse solve if it has not run yet. */
+int nce_features(nce_ctx *ctx, float *feat_dev);
+
+/*
+ * Coarse (monopole) model of the system: with f_i = a_i e_0 and every far
+ * field taken as its total charge at the patch centre, row 0 of eq.
+ * opinteqnsdisc becomes a_i + chi0 sum_{j != i} G(c_i, c_j) a_j = 1 (chi0 =
+ * total charge of e_0 in the outgoing table). Solved on the device by GMRES to
+ * 1e-6 (FP32 pair sums); once per context. a_dev: N doubles out (may be NULL);
+ * iters_host: GMRES iterations (may be NULL); chi0_host: chi0 (may be NULL).
+ * Not in the paper.
+ */
+int nce_coarse_solve(nce_ctx *ctx, double *a_dev, int *iters_host, double *chi0_host);
+
+/*
+ * Initial guess of later solves (not in the paper): use_coarse = 1 starts from
+ * x0_i = a_i e_0 (the coarse solve); with a network m (n_in = NCE_FEATURES,
+ * n_out = K) also, x0_i = a_i m_i with m_i the network's output for patch i.
+ * GMRES judges the guess: if its FP64 residual is not below 0.99 ||b||, the
+ * solve starts from zero (nce_info.used_fallback). m = NULL and use_coarse = 0
+ * disable; m without use_coarse is NCE_EINVAL. The caller keeps m alive while
+ * it is set.
+ */
+int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m, int use_coarse);
 
 /* Integral vector I (K host doubles): I_sigma = I . sum_i f_i (eq. getI). */
 int nce_integral_vector(const nce_ctx *ctx, double *I_host);

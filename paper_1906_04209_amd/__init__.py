@@ -31,8 +31,8 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
-           "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune"]
-FEATURES = 54
+           "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve"]
+FEATURES = 56
 
 
 class Opts(ctypes.Structure):
@@ -97,7 +97,9 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_mlp_loss_grad.argtypes = [vp, vp, vp, i64, dp, vp, vp]
     lib.nce_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, dp, vp]
     lib.nce_features.argtypes = [vp, vp]
-    lib.nce_set_warm_start.argtypes = [vp, vp]
+    lib.nce_set_warm_start.argtypes = [vp, vp, ctypes.c_int]
+    lib.nce_coarse_solve.argtypes = [vp, vp, ip, dp]
+    lib.nce_coarse_solve.restype = ctypes.c_int
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
                  "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
                  "nce_set_warm_start"):
@@ -316,9 +318,21 @@ class Context:
         self._leave()
         return f
 
-    def set_warm_start(self, mlp: Optional["Mlp"]) -> None:
+    def set_warm_start(self, mlp: Optional["Mlp"] = None, coarse: bool = True) -> None:
+        """Start later solves from the coarse solve (coarse=True), refined by the
+        network when one is given; set_warm_start(None, False) disables."""
         self._warm = mlp  # keep the network alive while it is set
-        _check(self.lib, self.lib.nce_set_warm_start(self.h, mlp.h if mlp is not None else None))
+        _check(self.lib, self.lib.nce_set_warm_start(self.h, mlp.h if mlp is not None else None, int(bool(coarse))))
+
+    def coarse(self, with_chi0: bool = False):
+        """(coarse amplitudes a as an N float64 device tensor, GMRES iterations
+        [, chi0])."""
+        a = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda")
+        it, chi0 = ctypes.c_int(), ctypes.c_double()
+        self._enter()
+        _check(self.lib, self.lib.nce_coarse_solve(self.h, _ptr(a), ctypes.byref(it), ctypes.byref(chi0)))
+        self._leave()
+        return (a, it.value, chi0.value) if with_chi0 else (a, it.value)
 
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
         _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))

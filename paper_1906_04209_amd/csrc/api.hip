@@ -153,6 +153,28 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
                         ctx->d_rho32.p, ctx->d_U32.p, ev, live);
 }
 
+const double* coarse_amplitudes(nce_ctx* ctx) {
+    if (ctx->coarse_iters >= 0) return ctx->d_a.p;
+    // total charge of the isolated-patch solution e_0 in the base outgoing table
+    double chi0 = 0.0;
+    for (int m = 0; m < ctx->p; ++m) chi0 += ctx->tab.T[(size_t)m * ctx->K];
+    if (!ctx->coarse)
+        ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
+    ctx->d_a.alloc((size_t)ctx->N);
+    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, ctx->d_frames.p, 1e-6, ctx->d_a.p);
+    return ctx->d_a.p;
+}
+
+std::vector<float> features_host(nce_ctx* ctx) {
+    const double* a = coarse_amplitudes(ctx);
+    std::vector<double> ah((size_t)ctx->N);
+    HIPCHK(hipMemcpyAsync(ah.data(), a, sizeof(double) * ah.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<float> f;
+    nce::patch_features(ctx->frames, ctx->N, ctx->eps, ctx->tab.problem, ah, f);
+    return f;
+}
+
 namespace {
 
 template <class T>
@@ -331,38 +353,19 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
     // r = residual of the current x, rel = ||r|| / ||b||
     HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     double rel = 1.0;
-    if (ctx->warm && N > 1) {
-        // learned initial guess x0 = gamma m, gamma = argmin ||b - gamma A m||
-        const int prec = ctx->opts.precision;
-        if (!ctx->d_feat.p) {
-            std::vector<float> feat;
-            nce::patch_features(ctx->frames, N, ctx->eps, ctx->tab.problem, feat);
-            ctx->d_feat.upload(feat, s);
+    if ((ctx->warm_coarse || ctx->warm) && N > 1) {
+        // initial guess from the monopole (coarse) solve a, refined per patch by
+        // the network's shape factors m_i: x0_i = a_i m_i (a_i e_0 without one)
+        const double* a = coarse_amplitudes(ctx);
+        const float* m32 = nullptr;
+        if (ctx->warm) {
+            if (!ctx->d_feat.p) ctx->d_feat.upload(features_host(ctx), s);
+            m32 = ctx->warm->forward(s, ctx->d_feat.p, N);
         }
-        const float* m32 = ctx->warm->forward(s, ctx->d_feat.p, N);
-        if (!ctx->d_m.p) {
-            ctx->d_m.alloc(n);
-            ctx->d_w.alloc(n);
-        }
-        HIPCHK(nce::cast_f2d(s, n, m32, ctx->d_m.p));
-        matvec(ctx, ctx->d_m.p, ctx->d_w.p, prec);
-        if (prec == NCE_FP64) inf.iters_fp64++;
-        else inf.iters_fp32++;
-        const double wb = dev_dot(ctx, n, ctx->d_w.p, ctx->d_b.p);
-        const double ww = dev_dot(ctx, n, ctx->d_w.p, ctx->d_w.p);
-        const double gamma = ww > 0 ? wb / ww : 0.0;
-        if (std::isfinite(gamma) && gamma != 0.0) {
-            HIPCHK(nce::scale_copy(s, n, gamma, ctx->d_m.p, x));
-            if (prec == NCE_FP64) {
-                // r = b - gamma (A m), exact in FP64
-                HIPCHK(hipMemcpyAsync(ctx->d_r.p, ctx->d_b.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-                HIPCHK(nce::axpby(s, n, -gamma, ctx->d_w.p, 1.0, ctx->d_r.p));
-                rel = std::sqrt(dev_dot(ctx, n, ctx->d_r.p, ctx->d_r.p)) / std::sqrt((double)N);
-            } else {
-                rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
-                inf.iters_fp64++;
-            }
-        }
+        HIPCHK(nce::rows_scale(s, N, ctx->K, a, m32, x));
+        // r = b - A x0 in FP64 (one apply)
+        rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+        inf.iters_fp64++;
         inf.rel_residual_x0 = rel;
         if (!(rel < 0.99)) {
             // no gain: plain start from zero
@@ -379,14 +382,14 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
         inf.rel_residual = 0.0;
         inf.rel_residual_x0 = 1.0;
     } else if (ctx->opts.precision == NCE_FP64) {
-        if (!ctx->warm) inf.rel_residual_x0 = 1.0;
+        if (!(ctx->warm || ctx->warm_coarse)) inf.rel_residual_x0 = 1.0;
         // GMRES on A d = r with ||r - A d|| <= tol ||b||; x += d
         inf.iters_fp64 += gmres(ctx, ctx->d_r.p, x, tol / rel, maxit, NCE_FP64, conv, est);
         inf.rel_residual = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
         inf.outer = 1;
     } else {
         // FP64 iterative refinement: r = b - A64 x; A32 d = r by GMRES; x += d.
-        if (!ctx->warm) inf.rel_residual_x0 = rel;
+        if (!(ctx->warm || ctx->warm_coarse)) inf.rel_residual_x0 = rel;
         const int max_outer = 12;
         conv = false;
         for (int outer = 0; outer < max_outer; ++outer) {
@@ -819,22 +822,35 @@ int nce_mlp_train_step(nce_mlp* m, const float* x, const float* t, int64_t B, fl
     });
 }
 
-int nce_features(const nce_ctx* ctx, float* feat) {
+int nce_features(nce_ctx* ctx, float* feat) {
     if (!ctx || !feat) return fail(NCE_EINVAL, "NULL argument");
     return guarded([&]() -> int {
-        std::vector<float> f;
-        nce::patch_features(ctx->frames, ctx->N, ctx->eps, ctx->tab.problem, f);
+        const std::vector<float> f = features_host(ctx);
         HIPCHK(hipMemcpyAsync(feat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
         return NCE_OK;
     });
 }
 
-int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m) {
+int nce_coarse_solve(nce_ctx* ctx, double* a, int* iters, double* chi0) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    return guarded([&]() -> int {
+        const double* d = coarse_amplitudes(ctx);
+        if (a) HIPCHK(hipMemcpyAsync(a, d, sizeof(double) * ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+        if (iters) *iters = ctx->coarse_iters;
+        if (chi0) *chi0 = ctx->coarse->chi0;
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        return NCE_OK;
+    });
+}
+
+int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != ctx->K))
         return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
+    if (m && !use_coarse) return fail(NCE_EINVAL, "the network refines the coarse solve: use_coarse must be 1");
     ctx->warm = m ? &m->net : nullptr;
+    ctx->warm_coarse = use_coarse != 0;
     return NCE_OK;
 }
 

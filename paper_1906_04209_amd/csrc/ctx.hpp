@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/nce.h"
+#include "coarse.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "precompute.hpp"
@@ -104,10 +105,14 @@ struct nce_ctx {
     // solver work arrays
     DevBuf<double> d_V, d_b, d_r, d_x, d_h, d_partial, d_scal;
     int vcap = 0;  // number of Krylov vectors allocated
-    // learned warm start
+    // initial guess: monopole (coarse) solve, optionally refined per patch by
+    // the learned network (x0_i = a_i m_i)
+    bool warm_coarse = false;
     nce::Mlp* warm = nullptr;
+    std::unique_ptr<nce::CoarseSolver> coarse;
+    DevBuf<double> d_a;                 // coarse amplitudes a_i (valid when coarse_iters >= 0)
+    int coarse_iters = -1;
     DevBuf<float> d_feat;
-    DevBuf<double> d_m, d_w;
 };
 
 struct nce_mlp {
@@ -148,6 +153,10 @@ int validate_centers(const double* centers, const std::vector<int64_t>& cfg_firs
 // configuration's Green's-function work (its rows of y are then unspecified).
 void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t* ev = nullptr,
             const int* live = nullptr);
+// Coarse amplitudes a (device, N) of the context's layout, solved once and kept.
+const double* coarse_amplitudes(nce_ctx* ctx);
+// Host copy of the network features (kFeatureDim per patch).
+std::vector<float> features_host(nce_ctx* ctx);
 // Times every valid shape of the P2L and interpolation kernels on the
 // context's own tree at the given precision and keeps the fastest
 // (synchronises the stream; no-op without a tree).

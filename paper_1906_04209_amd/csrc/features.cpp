@@ -7,15 +7,19 @@
 
 namespace nce {
 
-constexpr int kFeatureDimHost = 54;
+constexpr int kFeatureDimHost = 56;
 
 static inline double geod(const double* a, const double* b) {
     double c0 = a[1] * b[2] - a[2] * b[1], c1 = a[2] * b[0] - a[0] * b[2], c2 = a[0] * b[1] - a[1] * b[0];
     return std::atan2(std::sqrt(c0 * c0 + c1 * c1 + c2 * c2), a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
 }
 
-void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem, std::vector<float>& out) {
+void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem,
+                    const std::vector<double>& a, std::vector<float>& out) {
     out.assign((size_t)N * kFeatureDimHost, 0.0f);
+    double amean = 0.0;
+    for (int64_t i = 0; i < N; ++i) amean += a[i];
+    amean /= (double)N;
     const double radii[4] = {8 * eps, 16 * eps, 32 * eps, 64 * eps};
     const double area = N * std::sin(0.5 * eps) * std::sin(0.5 * eps);  // patch area fraction (Section 10)
     const double h = std::max(2.0 * std::sin(std::min(32.0 * eps, 1.5)), 1e-3);  // chord of 64 eps (cell size)
@@ -71,6 +75,8 @@ void patch_features(const std::vector<double>& frames, int64_t N, double eps, in
             const double expect = std::max((N - 1) * 0.5 * (1.0 - std::cos(R)), 1e-12);
             o[50 + q] = (float)(cnt / expect);
         }
+        o[54] = (float)(10.0 * (a[i] / amean - 1.0));
+        o[55] = (float)amean;
     }
 }
 

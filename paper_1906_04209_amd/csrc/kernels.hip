@@ -316,6 +316,16 @@ __global__ void k_cast_up(int64_t n, const float* __restrict__ x, double* __rest
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         y[e] = (double)x[e];
 }
+__global__ void k_rows_scale(int64_t N, int K, const double* __restrict__ a, const float* __restrict__ m,
+                             double* __restrict__ x) {
+    const int64_t n = N * K;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / K;
+        const int k = (int)(e - i * K);
+        x[e] = m ? a[i] * (double)m[e] : (k == 0 ? a[i] : 0.0);
+    }
+}
+
 __global__ void k_fill(int64_t n, double v, double* __restrict__ x) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         x[e] = v;
@@ -342,6 +352,14 @@ hipError_t cast_f2d(hipStream_t s, int64_t n, const float* x, double* y) {
     hipLaunchKernelGGL(k_cast_up, ew_grid(n), dim3(256), 0, s, n, x, y);
     return hipGetLastError();
 }
+hipError_t rows_scale(hipStream_t s, int64_t N, int K, const double* a, const float* m, double* x) {
+    const int64_t n = N * K;
+    const int64_t b = (n + 255) / 256;
+    hipLaunchKernelGGL(k_rows_scale, dim3((unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192)), dim3(256), 0, s, N, K, a, m,
+                       x);
+    return hipGetLastError();
+}
+
 hipError_t fill(hipStream_t s, int64_t n, double v, double* x) {
     hipLaunchKernelGGL(k_fill, ew_grid(n), dim3(256), 0, s, n, v, x);
     return hipGetLastError();

@@ -40,9 +40,12 @@ struct Mlp {
 
 // Per-patch input features of the warm-start network (host): the 16 nearest
 // neighbours' positions in the patch frame (scaled by 1/eps) and inverse
-// distances, the problem flag, the area fraction, and the neighbour density
-// relative to uniform within 8, 16, 32 and 64 eps. frames: N x 9 (c, e1, e2).
-constexpr int kFeatureDim = 54;
-void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem, std::vector<float>& out);
+// distances, the problem flag, the area fraction, the neighbour density
+// relative to uniform within 8, 16, 32 and 64 eps, and the patch's coarse
+// amplitude relative to the layout mean with that mean itself.
+// frames: N x 9 (c, e1, e2); a: the N coarse amplitudes.
+constexpr int kFeatureDim = 56;
+void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem,
+                    const std::vector<double>& a, std::vector<float>& out);
 
 }  // namespace nce

@@ -1,12 +1,14 @@
 """Learned warm start: training data from the library's own solves, GPU
 training of the network with the library's kernels, and weights I/O.
 
-Data: for seeded layouts shaped like the small workloads (N=10 patches of
-radius 0.1 and N=1000 of radius 0.01, uniform, area fraction 0.025, both
-problems), the FP64 solution f_i of every patch is the target, divided by
-the layout's mean f_i[0] (the network predicts the shape; the solver fits the
-overall scale by one system apply). Inputs are the NCE_FEATURES per-patch
-features computed by the library.
+The initial guess of a solve is x0_i = a_i m_i: a_i is the patch's amplitude
+from the coarse (monopole) solve, which carries the long-range coupling of
+the whole layout, and m_i (K coefficients) is the network's prediction of the
+patch's own solution shape from its neighbourhood and a_i. Training data: for
+seeded layouts shaped like the small workloads (N=10 patches of radius 0.1,
+N=1000 of radius 0.01, uniform, area fraction 0.025, both problems), inputs
+are the NCE_FEATURES per-patch features and targets the FP64 solutions f_i
+divided by a_i.
 
     python -m paper_1906_04209_amd.warmstart --out paper_1906_04209_amd/weights/warmstart.npz
 """
@@ -34,12 +36,12 @@ SHAPE = (FEATURES, 256, 3, 136)
 
 
 def layout_samples(centers, eps, problem, tol_id=1e-11):
-    """(features, normalised targets, solve info) of one layout."""
+    """(features, targets f_i / a_i, solve info) of one layout."""
     ctx = Context(centers, eps, problem=problem, tol_id=tol_id, tol_gmres=1e-10, far_field=FAR_AUTO)
     r = ctx.solve()
-    x = r["x"]
-    scale = x[:, 0].mean()
-    t = (x / scale).float()
+    a, _ = ctx.coarse()
+    a = a.clamp(min=0.05 * float(a.mean()))
+    t = (r["x"] / a[:, None]).float()
     f = ctx.features()
     ctx.close()
     return f, t, r
@@ -66,18 +68,45 @@ def generate(n_small: int, n_large: int, base_seed: int = 0, log=print):
     return torch.cat(F), torch.cat(T)
 
 
+def _last_layer(shape):
+    """Offsets of the last layer's W (n_out x width) and b in the flat parameters."""
+    n_in, width, hidden, n_out = shape
+    dims = [n_in] + [width] * hidden + [n_out]
+    off = 0
+    for l in range(len(dims) - 1):
+        w0 = off
+        off += dims[l] * dims[l + 1]
+        b0 = off
+        off += dims[l + 1]
+    return w0, b0, dims[-2], dims[-1]
+
+
 def train(F, T, steps: int = 4000, batch: int = 2048, lr: float = 1e-3, seed: int = 0, log=print) -> Mlp:
+    """Fit the network to the corrections T - e_0 of the coarse start, scaled to
+    unit RMS so that the loss resolves them; the scale and the e_0 offset are
+    then folded into the last layer, so the network's output is T itself."""
     import torch
     net = Mlp(*SHAPE, seed=seed)
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
+    C = T.clone()
+    C[:, 0] -= 1.0
+    S = float(1.0 / torch.sqrt((C.double() ** 2).mean()))
+    C = (C * S).contiguous()
+    log(f"  train: correction RMS {1.0 / S:.3e}")
     n = F.shape[0]
     for it in range(steps):
         idx = torch.randint(0, n, (min(batch, n),), device="cuda", generator=g)
         lr_t = lr * (0.5 * (1 + np.cos(np.pi * it / steps)))  # cosine decay
-        loss = net.train_step(F[idx].contiguous(), T[idx].contiguous(), lr_t)
+        loss = net.train_step(F[idx].contiguous(), C[idx].contiguous(), lr_t)
         if it % 500 == 0 or it == steps - 1:
-            log(f"  train: step {it} loss {loss:.3e}")
+            log(f"  train: step {it} loss {loss:.3e} (relative to the correction RMS)")
+    th = net.get_params().astype(np.float64)
+    w0, b0, n_prev, n_out = _last_layer(net.shape)
+    th[w0:w0 + n_prev * n_out] /= S
+    th[b0:b0 + n_out] /= S
+    th[b0] += 1.0
+    net.set_params(th.astype(np.float32))
     return net
 
 
@@ -98,8 +127,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=str(WEIGHTS))
     ap.add_argument("--small", type=int, default=200)
-    ap.add_argument("--large", type=int, default=48)
-    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--large", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=6000)
     args = ap.parse_args()
     os.environ.setdefault("NCE_CACHE", "/tmp")
     t0 = time.time()

@@ -43,3 +43,18 @@ def test_silu_derivative():
     z = np.linspace(-6, 6, 101)
     h = 1e-6
     assert np.allclose(mlp.dsilu(z), (mlp.silu(z + h) - mlp.silu(z - h)) / (2 * h), atol=1e-9)
+
+
+def test_warmstart_last_layer_offsets_match_layout():
+    """The offsets the training code uses to fold the output scale into the last
+    layer are those of the documented parameter layout (per layer W then b)."""
+    from paper_1906_04209_amd import warmstart
+    shape = (7, 5, 3, 4)
+    n = mlp.n_params(*shape)
+    th = np.arange(n, dtype=np.float64)
+    layers = mlp.unflatten(th, *shape)
+    W, b = layers[-1]
+    w0, b0, n_prev, n_out = warmstart._last_layer(shape)
+    assert (n_prev, n_out) == (5, 4)
+    assert np.array_equal(th[w0:w0 + n_prev * n_out].reshape(n_out, n_prev), W)
+    assert np.array_equal(th[b0:b0 + n_out], b)
