@@ -89,7 +89,7 @@ def run_batch(args):
     t0 = time.time()
     bt = nce.Batch(mem, tol_id=args.tol_id, tol_gmres=1e-8, precision=nce.MIXED, max_iter=60)
     t_setup = time.time() - t0
-    work = bt.work()
+    work = bt.work(nce.MIXED)
     log(f"batch setup {t_setup:.1f} s: groups {bt.ngroups}, tree members {int(bt.far_tree.sum())}, work {work}")
     t0 = time.time()
     tuned = {"fp64": bt.autotune(nce.FP64), "fp32": bt.autotune(nce.MIXED)}
@@ -204,7 +204,7 @@ def main():
     t0 = time.time()
     ctx = nce.Context(centers, cfg["eps"], problem=cfg["problem"], tol_id=args.tol_id, far_field=far)
     t_setup = time.time() - t0
-    work = ctx.work()
+    work = ctx.work(prec)
     log(f"setup {t_setup:.1f} s: K={ctx.K} K*={ctx.Kstar} p={ctx.p} levels={ctx.levels} work={work}")
     tuned = ctx.autotune(prec) if far == nce.FAR_TREE else None
     log(f"autotuned kernel shapes (P2L points/thread, interpolation nodes/thread): {tuned}")

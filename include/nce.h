@@ -61,7 +61,7 @@ typedef struct nce_ctx nce_ctx;
 #define NCE_MIXED 1  /* FP32 Green's sums and block applies inside FP64 iterative refinement */
 
 /* far-field method */
-#define NCE_FAR_AUTO 0    /* direct for small N, tree otherwise */
+#define NCE_FAR_AUTO 0    /* the tree or the direct sum, whichever has the smaller operation count */
 #define NCE_FAR_DIRECT 1  /* all pairs of patches summed directly */
 #define NCE_FAR_TREE 2    /* hierarchical cube-sphere quadtree (Section 7.2, Section 8 step 2) */
 
@@ -77,6 +77,10 @@ typedef struct nce_opts {
     int warm_start;     /* reserved, must be 0 (use nce_set_warm_start). Default 0 */
     void *stream;       /* hipStream_t to run on; NULL = the library creates one */
     const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
+    double tol_grid_fp32; /* grid tolerance of the FP32 applies (mixed solves): a second, coarser
+                             set of incoming grids when it differs from tol_grid; 0 = tol_grid.
+                             Default 1e-6 (below the FP32 inner solve's 1e-5 target; the FP64
+                             residuals always use tol_grid) */
 } nce_opts;
 
 typedef struct nce_info {
@@ -115,10 +119,11 @@ int nce_dims(const nce_ctx *ctx, int *K, int *Kstar, int *p, int *levels);
 /* Patch frames, N x 9 host doubles per patch: c (3), e1 (3), e2 (3). */
 int nce_frames(const nce_ctx *ctx, double *frames_host);
 
-/* Work counts of one matrix-vector product: Green's function pair evaluations
+/* Work counts of one matrix-vector product at the given precision (NCE_FP64
+ * or NCE_MIXED, whose grids may be coarser): Green's function pair evaluations
  * of the far field (P2L or direct), of the near field, and interpolation
  * multiply-adds (tree L2T). Any pointer may be NULL. */
-int nce_work(const nce_ctx *ctx, double *pairs_far, double *pairs_near, double *interp_fma);
+int nce_work(const nce_ctx *ctx, int precision, double *pairs_far, double *pairs_near, double *interp_fma);
 
 /*
  * One application of the system matrix (eq. sysmatapply):
@@ -274,8 +279,8 @@ int nce_batch_dims(const nce_batch *batch, int64_t *n_total, int *K, int *ngroup
  * far_tree_host[b] (may be NULL): 1 if its far field uses the tree, 0 direct. */
 int nce_batch_offsets(const nce_batch *batch, int64_t *off_host, int *far_tree_host);
 
-/* Operation counts of one batched apply (as nce_work). */
-int nce_batch_work(const nce_batch *batch, double *pairs_far, double *pairs_near, double *interp_fma);
+/* Operation counts of one batched apply at the given precision (as nce_work). */
+int nce_batch_work(const nce_batch *batch, int precision, double *pairs_far, double *pairs_near, double *interp_fma);
 
 /* y = A x for every configuration (batch layout, device, FP64 in and out;
  * precision NCE_FP64 or NCE_MIXED = FP32 steps). x and y must not alias. */

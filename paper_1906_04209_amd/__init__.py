@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("tol_grid", ctypes.c_double), ("tol_gmres", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p)]
+                ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -79,7 +79,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_destroy.restype = None
     lib.nce_dims.argtypes = [vp, ip, ip, ip, ip]
     lib.nce_frames.argtypes = [vp, vp]
-    lib.nce_work.argtypes = [vp, dp, dp, dp]
+    lib.nce_work.argtypes = [vp, ctypes.c_int, dp, dp, dp]
     lib.nce_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nce_matvec_profile.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.nce_set_solver.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.c_int]
@@ -109,7 +109,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_destroy_batch.restype = None
     lib.nce_batch_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ip, ip]
     lib.nce_batch_offsets.argtypes = [vp, vp, vp]
-    lib.nce_batch_work.argtypes = [vp, dp, dp, dp]
+    lib.nce_batch_work.argtypes = [vp, ctypes.c_int, dp, dp, dp]
     lib.nce_batch_matvec.argtypes = [vp, vp, vp, ctypes.c_int]
     lib.nce_batch_set_solver.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.nce_solve_batch.argtypes = [vp, vp, vp, vp]
@@ -222,7 +222,7 @@ class Context:
     def __init__(self, centers: np.ndarray, eps: float, problem: int = INTERIOR, M: int = 15,
                  tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
                  max_iter: int = 100, precision: int = FP64, far_field: int = FAR_AUTO,
-                 cache_dir: Optional[str] = None, stream=None):
+                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -232,6 +232,8 @@ class Context:
         o = Opts()
         self.lib.nce_default_opts(ctypes.byref(o))
         o.problem, o.M, o.tol_id, o.tol_grid, o.tol_gmres = problem, M, tol_id, tol_grid, tol_gmres
+        if tol_grid_fp32 is not None:
+            o.tol_grid_fp32 = tol_grid_fp32
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         # the library works on its own (non-default) stream; calls below order
         # it against the caller's current stream in both directions
@@ -277,9 +279,10 @@ class Context:
         _check(self.lib, self.lib.nce_integral_vector(self.h, out.ctypes.data))
         return out
 
-    def work(self):
+    def work(self, precision: int = FP64):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _check(self.lib, self.lib.nce_work(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        _check(self.lib, self.lib.nce_work(self.h, int(precision), ctypes.byref(a), ctypes.byref(b),
+                                           ctypes.byref(c)))
         return {"pairs_far": a.value, "pairs_near": b.value, "interp_fma": c.value}
 
     def empty(self):
@@ -378,7 +381,7 @@ class Batch:
 
     def __init__(self, configs, M: int = 15, tol_id: float = 1e-11, tol_grid: float = 1e-8,
                  tol_gmres: float = 1e-10, max_iter: int = 60, precision: int = MIXED, far_field: int = FAR_AUTO,
-                 cache_dir: Optional[str] = None, stream=None):
+                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -393,6 +396,8 @@ class Batch:
         o = Opts()
         self.lib.nce_default_opts(ctypes.byref(o))
         o.M, o.tol_id, o.tol_grid, o.tol_gmres = M, tol_id, tol_grid, tol_gmres
+        if tol_grid_fp32 is not None:
+            o.tol_grid_fp32 = tol_grid_fp32
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         self.stream = stream if stream is not None else torch.cuda.Stream()
         o.stream = ctypes.c_void_p(self.stream.cuda_stream)
@@ -430,9 +435,10 @@ class Batch:
         o = int(self.offsets[b])
         return v[o:o + int(self.N[b]) * self.K].view(int(self.N[b]), self.K)
 
-    def work(self):
+    def work(self, precision: int = FP64):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _check(self.lib, self.lib.nce_batch_work(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        _check(self.lib, self.lib.nce_batch_work(self.h, int(precision), ctypes.byref(a), ctypes.byref(b),
+                                                 ctypes.byref(c)))
         return {"pairs_far": a.value, "pairs_near": b.value, "interp_fma": c.value}
 
     def matvec(self, x, y=None, precision: int = FP64):

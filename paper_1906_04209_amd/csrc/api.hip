@@ -116,16 +116,16 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     HIPCHK(nce::gemm_nt<T>(s, N, pt, K, xin, K, Tm, K, rho, pt, nullptr, 0));
     mark(1);
     if (ctx->use_tree) {
-        // Step 2: far field onto incoming grids (P2L)
         const int ti = sizeof(T) == 8 ? 0 : 1;
-        HIPCHK(nce::tree_far<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, soff, rho, live,
-                                ctx->tune_p2l[ti]));
+        const nce::DeviceTree& dt = (ti == 1 && ctx->has_tree32) ? ctx->dtree32 : ctx->dtree;
+        // Step 2: far field onto incoming grids (P2L)
+        HIPCHK(nce::tree_far<T>(s, dt, ctx->tab.problem, ctx->d_frames.p, soff, rho, live, ctx->tune_p2l[ti]));
         mark(2);
         // Step 3: leaf neighbours directly at the sampling nodes (writes U)
-        HIPCHK(nce::tree_near<T>(s, ctx->dtree, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U, live));
+        HIPCHK(nce::tree_near<T>(s, dt, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U, live));
         mark(3);
         // Step 4: interpolation of every ancestor's incoming grid (adds into U)
-        HIPCHK(nce::tree_interp<T>(s, ctx->dtree, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
+        HIPCHK(nce::tree_interp<T>(s, dt, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
         mark(4);
     } else {
         HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U));
@@ -181,7 +181,7 @@ template <class T>
 void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
     hipStream_t s = ctx->stream;
     const int ti = sizeof(T) == 8 ? 0 : 1;
-    const nce::DeviceTree& d = ctx->dtree;
+    const nce::DeviceTree& d = (ti == 1 && ctx->has_tree32) ? ctx->dtree32 : ctx->dtree;
     // the kernels' cost does not depend on the strengths: start from zeros
     HIPCHK(hipMemsetAsync(rho, 0, sizeof(T) * (size_t)ctx->N * ctx->ptot, s));
     HIPCHK(hipMemsetAsync(U, 0, sizeof(T) * (size_t)ctx->N * ctx->Kstar, s));
@@ -235,7 +235,8 @@ void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
 }  // namespace
 
 void autotune(nce_ctx* ctx, int precision) {
-    if (!ctx->use_tree || ctx->dtree.ngrid == 0) return;
+    if (!ctx->use_tree) return;
+    if ((precision == NCE_FP64 || !ctx->has_tree32) ? ctx->dtree.ngrid == 0 : ctx->dtree32.ngrid == 0) return;
     if (precision == NCE_FP64)
         autotune_t<double>(ctx, ctx->d_skel_off.p, ctx->d_node_off.p, ctx->d_rho.p, ctx->d_U.p);
     else
@@ -437,6 +438,8 @@ int validate_opts(const nce_opts& o, double eps) {
     if (o.problem != NCE_INTERIOR && o.problem != NCE_EXTERIOR) return fail(NCE_EINVAL, "bad problem");
     if (!(o.tol_id > 0 && o.tol_id < 1e-3)) return fail(NCE_EINVAL, "tol_id must lie in (0, 1e-3)");
     if (!(o.tol_grid > 0 && o.tol_grid < 1e-2)) return fail(NCE_EINVAL, "tol_grid must lie in (0, 1e-2)");
+    if (!(o.tol_grid_fp32 == 0.0 || (o.tol_grid_fp32 > 0 && o.tol_grid_fp32 < 1e-2)))
+        return fail(NCE_EINVAL, "tol_grid_fp32 must be 0 or lie in (0, 1e-2)");
     if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
     if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
     if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
@@ -543,14 +546,18 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->d_scal.alloc(8);
     const int ncfg = (int)cfg_first.size() - 1;
     ctx->cfg_tree.assign(ncfg, ctx->use_tree ? 1 : 0);
+    const double tol32 = o.tol_grid_fp32 > 0 ? o.tol_grid_fp32 : o.tol_grid;
+    ctx->has_tree32 = ctx->use_tree && tol32 != o.tol_grid;
     if (forest) {
         nce::start_forest(ctx->tree);
+        if (ctx->has_tree32) nce::start_forest(ctx->tree32);
         for (int c = 0; c < ncfg; ++c) {
             const int64_t f0 = cfg_first[c], nc = cfg_first[c + 1] - f0;
             bool tree = nc > 1 && o.far_field != NCE_FAR_DIRECT;
             nce::Tree t;
+            std::vector<double> fr;
             if (tree) {
-                std::vector<double> fr(ctx->frames.begin() + 9 * f0, ctx->frames.begin() + 9 * (f0 + nc));
+                fr.assign(ctx->frames.begin() + 9 * f0, ctx->frames.begin() + 9 * (f0 + nc));
                 nce::build_tree(fr, nc, eps, ctx->tab, o.tol_grid, t);
                 if (o.far_field == NCE_FAR_AUTO) {
                     // operation counts: one interpolation FMA costs about a quarter of a
@@ -563,9 +570,22 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
             ctx->cfg_tree[c] = tree ? 1 : 0;
             if (tree) nce::append_tree(ctx->tree, t, f0);
             else nce::append_direct(ctx->tree, f0, nc, ctx->Kstar, ctx->p);
+            if (ctx->has_tree32) {
+                if (tree) {
+                    nce::Tree t32;
+                    nce::build_tree(fr, nc, eps, ctx->tab, tol32, t32);
+                    nce::append_tree(ctx->tree32, t32, f0);
+                } else {
+                    nce::append_direct(ctx->tree32, f0, nc, ctx->Kstar, ctx->p);
+                }
+            }
         }
+    } else if (ctx->has_tree32) {
+        nce::build_tree(ctx->frames, N, eps, ctx->tab, tol32, ctx->tree32);
     }
     if (ctx->use_tree) nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
+    if (ctx->has_tree32)
+        nce::upload_tree(ctx->tree32, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree32);
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -586,6 +606,7 @@ void nce_default_opts(nce_opts* o) {
     o->warm_start = 0;
     o->stream = nullptr;
     o->cache_dir = nullptr;
+    o->tol_grid_fp32 = 1e-6;
 }
 
 int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {
@@ -614,6 +635,7 @@ void nce_destroy(nce_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     nce::free_tree(ctx->dtree);
+    nce::free_tree(ctx->dtree32);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -633,13 +655,15 @@ int nce_frames(const nce_ctx* ctx, double* fr) {
     return NCE_OK;
 }
 
-int nce_work(const nce_ctx* ctx, double* far, double* near, double* interp) {
+int nce_work(const nce_ctx* ctx, int precision, double* far, double* near, double* interp) {
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
     double f = 0, nr = 0, it = 0;
     if (ctx->use_tree) {
-        f = ctx->tree.pairs_far;
-        nr = ctx->tree.pairs_near;
-        it = ctx->tree.interp_fma;
+        const nce::Tree& t = (precision == NCE_MIXED && ctx->has_tree32) ? ctx->tree32 : ctx->tree;
+        f = t.pairs_far;
+        nr = t.pairs_near;
+        it = t.interp_fma;
     } else {
         f = (double)ctx->N * (double)(ctx->N - 1) * ctx->Kstar * (double)ctx->p;
     }

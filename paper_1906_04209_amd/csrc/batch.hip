@@ -710,13 +710,15 @@ int nce_batch_offsets(const nce_batch* bt, int64_t* off, int* far_tree) {
     return NCE_OK;
 }
 
-int nce_batch_work(const nce_batch* bt, double* far, double* near, double* interp) {
+int nce_batch_work(const nce_batch* bt, int precision, double* far, double* near, double* interp) {
     if (!bt) return fail(NCE_EINVAL, "batch is NULL");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
     double f = 0, nr = 0, it = 0;
     for (const nce_ctx* g : bt->groups) {
-        f += g->tree.pairs_far;
-        nr += g->tree.pairs_near;
-        it += g->tree.interp_fma;
+        const nce::Tree& t = (precision == NCE_MIXED && g->has_tree32) ? g->tree32 : g->tree;
+        f += t.pairs_far;
+        nr += t.pairs_near;
+        it += t.interp_fma;
     }
     if (far) *far = f;
     if (near) *near = nr;

@@ -96,6 +96,10 @@ struct nce_ctx {
     int tune_l2t[2] = {2, 2};
     nce::Tree tree;
     nce::DeviceTree dtree;
+    // grids of the FP32 applies at opts.tol_grid_fp32 (when it differs from tol_grid)
+    bool has_tree32 = false;
+    nce::Tree tree32;
+    nce::DeviceTree dtree32;
     // device tables
     DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
     DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
