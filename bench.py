@@ -52,7 +52,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, tol_id, x, centers, nrows=1):
+def cpu_baseline(cfg, tol_id, x, centers, nrows=3):
     """Time the oracle's dense compressed matvec on `nrows` sampled target
     patches (plain C loop over all N source patches, all host cores) and scale
     to one full matvec."""
