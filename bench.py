@@ -115,9 +115,17 @@ def run_batch(args):
         torch.cuda.synchronize()
         out_ms[name] = 1e3 * (time.perf_counter() - t1) / args.steps
         log(f"batched apply {name}: {out_ms[name]:.2f} ms")
-    # lockstep mixed solve of all configurations to 1e-8, then FP64
+    # lockstep solves of all configurations to 1e-8: mixed and FP64 from zero,
+    # mixed from the per-member coarse start and from the learned start
+    net = None
+    if WARM_WEIGHTS.exists() and int(np.load(WARM_WEIGHTS, allow_pickle=False)["shape"][0]) == nce.FEATURES:
+        from paper_1906_04209_amd import warmstart
+        net = warmstart.load(WARM_WEIGHTS)
+    runs = [("mixed", nce.MIXED, None, False), ("fp64", nce.FP64, None, False),
+            ("mixed_coarse", nce.MIXED, None, True)] + ([("mixed_learned", nce.MIXED, net, True)] if net else [])
     solves = {}
-    for name, pr in (("mixed", nce.MIXED), ("fp64", nce.FP64)):
+    for name, pr, mlp, coarse in runs:
+        bt.set_warm_start(mlp, coarse)
         bt.set_solver(1e-8, 60, pr, use_graph=True)
         r = bt.solve()
         its = np.array([i["iters_fp32"] for i in r["info"]]), np.array([i["iters_fp64"] for i in r["info"]])
@@ -146,7 +154,11 @@ def run_batch(args):
     log(f"sequential single solves: {t_seq:.2f} s (scaled from {nseq}), setup {t_seq_setup:.1f} s")
     pairs = work["pairs_far"]
     cp = C_PAIR[("fp32", 0, 4)]
-    for sname in ("mixed", "fp64"):
+    for sname in solves:
+        if sname != "mixed":
+            solves[sname]["max_rel_diff_vs_mixed"] = float(np.max(np.abs(solves[sname]["result"] - solves["mixed"]["result"])
+                                                                  / np.abs(solves["mixed"]["result"])))
+    for sname in solves:
         solves[sname].pop("result")
     out = {
         "metric": "batched FP32 system applies/s over 256 independent configurations (sum N = %d)" % ntot,

@@ -303,6 +303,10 @@ int nce_batch_set_solver(nce_batch *batch, double tol_gmres, int max_iter, int p
  */
 int nce_solve_batch(nce_batch *batch, double *result_host, double *coeffs_dev, nce_info *infos_host);
 
+/* Initial guess of later batched solves, as nce_set_warm_start: a coarse solve
+ * per member (use_coarse = 1), refined per patch by network m when given. */
+int nce_batch_set_warm_start(nce_batch *batch, nce_mlp *m, int use_coarse);
+
 /* nce_autotune for every (problem, eps) group of the batch; choice_host (may
  * be NULL): 2 x ngroups values in group order. */
 int nce_batch_autotune(nce_batch *batch, int precision, int *choice_host);

@@ -31,7 +31,8 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
-           "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve"]
+           "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve",
+           "nce_batch_set_warm_start"]
 FEATURES = 56
 
 
@@ -115,6 +116,8 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_solve_batch.argtypes = [vp, vp, vp, vp]
     lib.nce_autotune.argtypes = [vp, ctypes.c_int, vp]
     lib.nce_batch_autotune.argtypes = [vp, ctypes.c_int, vp]
+    lib.nce_batch_set_warm_start.argtypes = [vp, vp, ctypes.c_int]
+    lib.nce_batch_set_warm_start.restype = ctypes.c_int
     for name in ("nce_setup_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
                  "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune"):
         getattr(lib, name).restype = ctypes.c_int
@@ -452,6 +455,13 @@ class Batch:
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int, use_graph: bool = True):
         _check(self.lib, self.lib.nce_batch_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision),
                                                        int(bool(use_graph))))
+
+    def set_warm_start(self, mlp: Optional["Mlp"] = None, coarse: bool = True) -> None:
+        """Start later batched solves from per-member coarse solves (refined by
+        the network when given); set_warm_start(None, False) disables."""
+        self._warm = mlp
+        _check(self.lib, self.lib.nce_batch_set_warm_start(self.h, mlp.h if mlp is not None else None,
+                                                           int(bool(coarse))))
 
     def autotune(self, precision: int = MIXED):
         """nce_batch_autotune: per group (P2L points per thread, interpolation nodes per thread)."""

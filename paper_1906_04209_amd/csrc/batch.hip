@@ -252,6 +252,12 @@ struct nce_batch {
     DevBuf<int> d_active, d_mused, d_j, d_all;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_maxit[2] = {0, 0};
+    // initial guess: per-member coarse solves, optionally refined by a network
+    bool warm_coarse = false;
+    nce::Mlp* warm = nullptr;
+    std::vector<DevBuf<double>> g_a;       // per group: coarse amplitudes of its patches
+    std::vector<DevBuf<float>> g_feat;     // per group: network features of its patches
+    bool have_a = false;
 
     ~nce_batch() {
         for (auto& gr : graph)
@@ -425,6 +431,50 @@ void gmres_batch(nce_batch* bt, const double* rhs, double* x, const std::vector<
     for (int q = 0; q < S; ++q) est[q] = act[q] ? e[q] : 0.0;
 }
 
+// Coarse amplitudes of every member (one coarse solve per member, kept), and
+// with a network the features of every patch.
+void batch_coarse(nce_batch* bt) {
+    if (bt->have_a) return;
+    hipStream_t s = bt->stream;
+    bt->g_a.resize(bt->groups.size());
+    for (size_t g = 0; g < bt->groups.size(); ++g) {
+        nce_ctx* c = bt->groups[g];
+        double chi0 = 0.0;
+        for (int m = 0; m < c->p; ++m) chi0 += c->tab.T[(size_t)m * c->K];
+        bt->g_a[g].alloc((size_t)c->N);
+        for (size_t q = 0; q + 1 < c->cfg_first.size(); ++q) {
+            const int64_t f0 = c->cfg_first[q], nc = c->cfg_first[q + 1] - f0;
+            nce::CoarseSolver cs((int)nc, c->tab.problem, chi0, 80);
+            cs.solve(s, c->d_frames.p + 9 * f0, 1e-6, bt->g_a[g].p + f0);
+        }
+    }
+    bt->have_a = true;
+}
+
+void batch_features(nce_batch* bt) {
+    if (!bt->g_feat.empty()) return;
+    batch_coarse(bt);
+    hipStream_t s = bt->stream;
+    bt->g_feat.resize(bt->groups.size());
+    for (size_t g = 0; g < bt->groups.size(); ++g) {
+        nce_ctx* c = bt->groups[g];
+        std::vector<double> a((size_t)c->N);
+        HIPCHK(hipMemcpyAsync(a.data(), bt->g_a[g].p, sizeof(double) * a.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<float> all;
+        all.reserve((size_t)c->N * nce::kFeatureDim);
+        for (size_t q = 0; q + 1 < c->cfg_first.size(); ++q) {
+            const int64_t f0 = c->cfg_first[q], nc = c->cfg_first[q + 1] - f0;
+            std::vector<double> fr(c->frames.begin() + 9 * f0, c->frames.begin() + 9 * (f0 + nc));
+            std::vector<double> aq(a.begin() + f0, a.begin() + f0 + nc);
+            std::vector<float> f;
+            nce::patch_features(fr, nc, c->eps, c->tab.problem, aq, f);
+            all.insert(all.end(), f.begin(), f.end());
+        }
+        bt->g_feat[g].upload(all, s);
+    }
+}
+
 // r = b - A x (FP64); returns per-segment ||r_s|| / ||b_s||
 std::vector<double> batch_residual(nce_batch* bt, std::vector<double>& bn) {
     batch_matvec(bt, bt->d_x.p, bt->d_r.p, NCE_FP64);
@@ -468,6 +518,35 @@ int solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos)
     std::vector<double> rel(S, 1.0);
     for (int q = 0; q < S; ++q)
         if (!todo[q]) rel[q] = 0.0;
+    if (bt->warm_coarse || bt->warm) {
+        // x0_i = a_i m_i per member (m_i = e_0 without a network), r = b - A x0 in FP64
+        batch_coarse(bt);
+        if (bt->warm) batch_features(bt);
+        for (size_t g = 0; g < bt->groups.size(); ++g) {
+            nce_ctx* c = bt->groups[g];
+            const float* m32 = bt->warm ? bt->warm->forward(s, bt->g_feat[g].p, c->N) : nullptr;
+            HIPCHK(nce::rows_scale(s, c->N, bt->K, bt->g_a[g].p, m32, bt->d_x.p + bt->g_elem[g]));
+        }
+        for (int q = 0; q < S; ++q)
+            if (!todo[q])
+                HIPCHK(hipMemcpyAsync(bt->d_x.p + bt->seg_off[q], bt->d_b.p + bt->seg_off[q],
+                                      sizeof(double) * bt->K, hipMemcpyDeviceToDevice, s));
+        rel = batch_residual(bt, bn);
+        for (int q = 0; q < S; ++q) {
+            if (!todo[q]) continue;
+            inf[q].iters_fp64 += 1;
+            inf[q].rel_residual_x0 = rel[q];
+            if (!(rel[q] < 0.99)) {
+                // no gain for this member: start it from zero
+                inf[q].used_fallback = 1;
+                HIPCHK(nce::fill(s, bt->seg_off[q + 1] - bt->seg_off[q], 0.0, bt->d_x.p + bt->seg_off[q]));
+                HIPCHK(hipMemcpyAsync(bt->d_r.p + bt->seg_off[q], bt->d_b.p + bt->seg_off[q],
+                                      sizeof(double) * (bt->seg_off[q + 1] - bt->seg_off[q]),
+                                      hipMemcpyDeviceToDevice, s));
+                rel[q] = 1.0;
+            }
+        }
+    }
     if (bt->precision == NCE_FP64) {
         // restarted lockstep GMRES(maxit) on the residual until every configuration converges
         for (int cycle = 0; cycle < 8; ++cycle) {
@@ -773,6 +852,16 @@ int nce_batch_autotune(nce_batch* bt, int precision, int* choice) {
         }
         return NCE_OK;
     });
+}
+
+int nce_batch_set_warm_start(nce_batch* bt, nce_mlp* m, int use_coarse) {
+    if (!bt) return fail(NCE_EINVAL, "batch is NULL");
+    if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != bt->K))
+        return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
+    if (m && !use_coarse) return fail(NCE_EINVAL, "the network refines the coarse solve: use_coarse must be 1");
+    bt->warm = m ? &m->net : nullptr;
+    bt->warm_coarse = use_coarse != 0;
+    return NCE_OK;
 }
 
 int nce_solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos) {

@@ -127,3 +127,23 @@ def test_graph_replay_equals_eager(torch):
         bt.close()
     assert np.array_equal(out[0]["result"], out[1]["result"])
     assert torch.equal(out[0]["x"], out[1]["x"])
+
+
+def test_batch_coarse_and_learned_start(torch):
+    """Per-member coarse (and learned) starts give the cold results with fewer
+    applies; members with one patch stay exact."""
+    import paper_1906_04209_amd as nce
+    mem = _members()
+    bt = nce.Batch(mem, tol_id=TOL_ID, tol_gmres=1e-10, precision=nce.MIXED, max_iter=60)
+    cold = bt.solve()
+    bt.set_warm_start(None, True)
+    warm = bt.solve()
+    assert cold["converged"] and warm["converged"]
+    for b in range(len(mem)):
+        rel = abs(warm["result"][b] - cold["result"][b]) / abs(cold["result"][b])
+        ic, iw = cold["info"][b], warm["info"][b]
+        print(f"member {b} N={len(mem[b][0])}: cold {ic['iters_fp32']}+{ic['iters_fp64']} coarse "
+              f"{iw['iters_fp32']}+{iw['iters_fp64']} applies, x0 residual {iw['rel_residual_x0']:.2e}, rel {rel:.1e}")
+        assert rel < 1e-8
+        if len(mem[b][0]) > 1:
+            assert iw["rel_residual_x0"] < 0.5 and not iw["used_fallback"]
