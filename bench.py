@@ -124,8 +124,13 @@ def run_batch(args):
     runs = [("mixed", nce.MIXED, None, False), ("fp64", nce.FP64, None, False),
             ("mixed_coarse", nce.MIXED, None, True)] + ([("mixed_learned", nce.MIXED, net, True)] if net else [])
     solves = {}
+    prep = {}
     for name, pr, mlp, coarse in runs:
+        t1 = time.perf_counter()
         bt.set_warm_start(mlp, coarse)
+        torch.cuda.synchronize()
+        if coarse:
+            prep[name] = time.perf_counter() - t1
         bt.set_solver(1e-8, 60, pr, use_graph=True)
         r = bt.solve()
         its = np.array([i["iters_fp32"] for i in r["info"]]), np.array([i["iters_fp64"] for i in r["info"]])
@@ -169,7 +174,7 @@ def run_batch(args):
                    "problems": ["interior", "exterior"], "tol_id": args.tol_id,
                    "tree_members": int(bt.far_tree.sum())},
         "fp64_apply_ms": out_ms["fp64"], "setup_s": t_setup, "autotuned_shapes": tuned,
-        "solve_batched": solves,
+        "solve_batched": solves, "start_preprocessing_s": prep,
         "max_rel_diff_mixed_vs_fp64": float(rel.max()),
         "solve_sequential_single_s": t_seq, "sequential_configurations_timed": nseq,
         "max_rel_diff_batched_vs_single": float(rel_seq.max()),
@@ -274,8 +279,14 @@ def main():
                 log("stored network weights do not match the current features; learned start skipped")
         starts = [("", None, False), ("_coarse", None, True)] + ([("_learned", net, True)] if net else [])
         times = {}
+        prep = {}
         for sfx, mlp, coarse in starts:
+            # per-layout preprocessing of the start (coarse solve, network features)
+            t1 = time.perf_counter()
             ctx.set_warm_start(mlp, coarse)
+            torch.cuda.synchronize()
+            if sfx:
+                prep[sfx[1:]] = time.perf_counter() - t1
             for name, pr in (("fp64", nce.FP64), ("mixed", nce.MIXED)):
                 ctx.set_solver(1e-8, 100, pr)
                 r = ctx.solve(want_coeffs=False, want_flux=False)
@@ -293,6 +304,7 @@ def main():
         best = "mixed_learned" if "mixed_learned" in times else "mixed_coarse"
         out["time_to_1e-8_s"] = dict(times, speedup_mixed_vs_fp64=times["fp64"] / times["mixed"],
                                      **{f"speedup_{best}_vs_fp64": times["fp64"] / times[best]})
+        out["start_preprocessing_s"] = prep
     if not args.no_cpu_baseline:
         cb, rows, yref = cpu_baseline(cfg, args.tol_id, x_np, centers)
         yg = y.cpu().numpy()[rows] if args.precision == "fp64" else None

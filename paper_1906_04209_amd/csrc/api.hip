@@ -161,7 +161,7 @@ const double* coarse_amplitudes(nce_ctx* ctx) {
     if (!ctx->coarse)
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
     ctx->d_a.alloc((size_t)ctx->N);
-    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, ctx->d_frames.p, 1e-6, ctx->d_a.p);
+    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, (int)ctx->N, ctx->d_frames.p, 1e-6, ctx->d_a.p);
     return ctx->d_a.p;
 }
 
@@ -364,9 +364,24 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
             m32 = ctx->warm->forward(s, ctx->d_feat.p, N);
         }
         HIPCHK(nce::rows_scale(s, N, ctx->K, a, m32, x));
-        // r = b - A x0 in FP64 (one apply)
-        rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
-        inf.iters_fp64++;
+        if (ctx->opts.precision == NCE_MIXED) {
+            // r0 with the FP32 apply first: when the guess is good enough for one
+            // refinement step to reach the tolerance (r0 <= tol / 1e-5, the FP32
+            // solve's floor) r0 is recomputed in FP64; otherwise the refinement
+            // starts from this estimate and verifies in FP64 after its first step
+            matvec(ctx, x, ctx->d_r.p, NCE_MIXED);
+            HIPCHK(nce::axpby(s, n, 1.0, ctx->d_b.p, -1.0, ctx->d_r.p));
+            rel = std::sqrt(dev_dot(ctx, n, ctx->d_r.p, ctx->d_r.p) / dev_dot(ctx, n, ctx->d_b.p, ctx->d_b.p));
+            inf.iters_fp32++;
+            if (rel <= tol / 1e-5) {
+                rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+                inf.iters_fp64++;
+            }
+        } else {
+            // r = b - A x0 in FP64 (one apply)
+            rel = residual(ctx, ctx->d_b.p, x, ctx->d_r.p);
+            inf.iters_fp64++;
+        }
         inf.rel_residual_x0 = rel;
         if (!(rel < 0.99)) {
             // no gain: plain start from zero
@@ -873,9 +888,14 @@ int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
     if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != ctx->K))
         return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
     if (m && !use_coarse) return fail(NCE_EINVAL, "the network refines the coarse solve: use_coarse must be 1");
-    ctx->warm = m ? &m->net : nullptr;
-    ctx->warm_coarse = use_coarse != 0;
-    return NCE_OK;
+    return guarded([&]() -> int {
+        ctx->warm = m ? &m->net : nullptr;
+        ctx->warm_coarse = use_coarse != 0;
+        // per-layout preprocessing now, not inside the next solve
+        if (ctx->warm_coarse && ctx->N > 1) coarse_amplitudes(ctx);
+        if (ctx->warm && ctx->N > 1 && !ctx->d_feat.p) ctx->d_feat.upload(features_host(ctx), ctx->stream);
+        return NCE_OK;
+    });
 }
 
 int nce_integral_vector(const nce_ctx* ctx, double* I) {

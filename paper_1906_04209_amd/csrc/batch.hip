@@ -442,10 +442,14 @@ void batch_coarse(nce_batch* bt) {
         double chi0 = 0.0;
         for (int m = 0; m < c->p; ++m) chi0 += c->tab.T[(size_t)m * c->K];
         bt->g_a[g].alloc((size_t)c->N);
+        int64_t nmax = 1;
+        for (size_t q = 0; q + 1 < c->cfg_first.size(); ++q)
+            nmax = std::max<int64_t>(nmax, c->cfg_first[q + 1] - c->cfg_first[q]);
+        // one solver for the group, reused by every member
+        nce::CoarseSolver cs((int)nmax, c->tab.problem, chi0, 80);
         for (size_t q = 0; q + 1 < c->cfg_first.size(); ++q) {
             const int64_t f0 = c->cfg_first[q], nc = c->cfg_first[q + 1] - f0;
-            nce::CoarseSolver cs((int)nc, c->tab.problem, chi0, 80);
-            cs.solve(s, c->d_frames.p + 9 * f0, 1e-6, bt->g_a[g].p + f0);
+            cs.solve(s, (int)nc, c->d_frames.p + 9 * f0, 1e-6, bt->g_a[g].p + f0);
         }
     }
     bt->have_a = true;
@@ -531,10 +535,48 @@ int solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos)
             if (!todo[q])
                 HIPCHK(hipMemcpyAsync(bt->d_x.p + bt->seg_off[q], bt->d_b.p + bt->seg_off[q],
                                       sizeof(double) * bt->K, hipMemcpyDeviceToDevice, s));
-        rel = batch_residual(bt, bn);
+        if (bt->precision == NCE_MIXED) {
+            // FP32 r0 for every member; FP64 r0 only for the members whose guess
+            // allows one refinement step to reach the tolerance (as the single
+            // solve), with the other members' far fields masked off
+            batch_matvec(bt, bt->d_x.p, bt->d_r.p, NCE_MIXED);
+            hipLaunchKernelGGL(k_sub_from, grid_for(bt->n), dim3(256), 0, s, bt->n, bt->d_b.p, bt->d_r.p);
+            HIPCHK(hipGetLastError());
+            const std::vector<double> rn = seg_norm2(bt, bt->d_r.p);
+            std::vector<int> exact(S, 0);
+            int nexact = 0;
+            for (int q = 0; q < S; ++q) {
+                rel[q] = todo[q] ? std::sqrt(rn[q]) / bn[q] : 0.0;
+                if (todo[q]) inf[q].iters_fp32 += 1;
+                if (todo[q] && rel[q] <= bt->tol / 1e-5) {
+                    exact[q] = 1;
+                    ++nexact;
+                }
+            }
+            if (nexact) {
+                HIPCHK(hipMemcpyAsync(bt->d_active.p, exact.data(), sizeof(int) * S, hipMemcpyHostToDevice, s));
+                batch_matvec(bt, bt->d_x.p, bt->d_w.p, NCE_FP64, bt->d_active.p);
+                hipLaunchKernelGGL(k_sub_from, grid_for(bt->n), dim3(256), 0, s, bt->n, bt->d_b.p, bt->d_w.p);
+                HIPCHK(hipGetLastError());
+                for (int q = 0; q < S; ++q)
+                    if (exact[q])
+                        HIPCHK(hipMemcpyAsync(bt->d_r.p + bt->seg_off[q], bt->d_w.p + bt->seg_off[q],
+                                              sizeof(double) * (bt->seg_off[q + 1] - bt->seg_off[q]),
+                                              hipMemcpyDeviceToDevice, s));
+                const std::vector<double> rn64 = seg_norm2(bt, bt->d_r.p);
+                for (int q = 0; q < S; ++q)
+                    if (exact[q]) {
+                        rel[q] = std::sqrt(rn64[q]) / bn[q];
+                        inf[q].iters_fp64 += 1;
+                    }
+            }
+        } else {
+            rel = batch_residual(bt, bn);
+            for (int q = 0; q < S; ++q)
+                if (todo[q]) inf[q].iters_fp64 += 1;
+        }
         for (int q = 0; q < S; ++q) {
             if (!todo[q]) continue;
-            inf[q].iters_fp64 += 1;
             inf[q].rel_residual_x0 = rel[q];
             if (!(rel[q] < 0.99)) {
                 // no gain for this member: start it from zero
@@ -859,9 +901,14 @@ int nce_batch_set_warm_start(nce_batch* bt, nce_mlp* m, int use_coarse) {
     if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != bt->K))
         return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
     if (m && !use_coarse) return fail(NCE_EINVAL, "the network refines the coarse solve: use_coarse must be 1");
-    bt->warm = m ? &m->net : nullptr;
-    bt->warm_coarse = use_coarse != 0;
-    return NCE_OK;
+    return guarded([&]() -> int {
+        bt->warm = m ? &m->net : nullptr;
+        bt->warm_coarse = use_coarse != 0;
+        // per-layout preprocessing now, not inside the next solve
+        if (bt->warm_coarse) batch_coarse(bt);
+        if (bt->warm) batch_features(bt);
+        return NCE_OK;
+    });
 }
 
 int nce_solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos) {

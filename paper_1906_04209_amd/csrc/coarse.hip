@@ -111,14 +111,20 @@ __global__ void k_coarse_finish(int N, int nsplit, const double* __restrict__ pa
 
 }  // namespace
 
+// source splits for a layout of n centres: enough for >= 2048 blocks, each
+// split at least one tile
+static int splits_for(int n) {
+    const int ntb = (n + 256 * kTgt - 1) / (256 * kTgt);
+    return std::max(1, std::min((n + kTile - 1) / kTile, (2048 + ntb - 1) / ntb));
+}
+
 CoarseSolver::CoarseSolver(int N_, int problem_, double chi0_, int maxit_)
     : N(N_), problem(problem_), chi0(chi0_), maxit(maxit_) {
-    const int ntb = (N + 256 * kTgt - 1) / (256 * kTgt);
-    // enough source splits for >= 2048 blocks, each split at least one tile
-    nsplit = std::max(1, std::min((N + kTile - 1) / kTile, (2048 + ntb - 1) / ntb));
-    chunk = (N + nsplit - 1) / nsplit;
+    // partial sums for any layout of n <= N centres
+    size_t maxpart = 1;
+    for (int n = 1; n <= N; ++n) maxpart = std::max(maxpart, (size_t)splits_for(n) * n);
     chk(hipMalloc((void**)&src, sizeof(float4) * (size_t)N), "hipMalloc");
-    chk(hipMalloc((void**)&part, sizeof(double) * (size_t)N * nsplit), "hipMalloc");
+    chk(hipMalloc((void**)&part, sizeof(double) * maxpart), "hipMalloc");
     chk(hipMalloc((void**)&V, sizeof(double) * (size_t)N * (maxit + 1)), "hipMalloc");
     chk(hipMalloc((void**)&h, sizeof(double) * (size_t)(maxit + 2)), "hipMalloc");
     chk(hipMalloc((void**)&rpart, sizeof(double) * (size_t)kReduceBlocks * (maxit + 2)), "hipMalloc");
@@ -130,23 +136,26 @@ CoarseSolver::~CoarseSolver() {
         if (p) (void)hipFree(p);
 }
 
-void CoarseSolver::apply(hipStream_t s, const double* frames, const double* a, double* y) {
-    hipLaunchKernelGGL(k_coarse_src, dim3((N + 255) / 256), dim3(256), 0, s, N, frames, a, src);
-    const dim3 grid((N + 256 * kTgt - 1) / (256 * kTgt), nsplit);
+void CoarseSolver::apply(hipStream_t s, int n, const double* frames, const double* a, double* y) {
+    if (n < 1 || n > N) throw std::runtime_error("coarse apply: layout larger than the solver");
+    const int nsplit = splits_for(n), chunk = (n + nsplit - 1) / nsplit;
+    hipLaunchKernelGGL(k_coarse_src, dim3((n + 255) / 256), dim3(256), 0, s, n, frames, a, src);
+    const dim3 grid((n + 256 * kTgt - 1) / (256 * kTgt), nsplit);
     if (problem == 1)
-        hipLaunchKernelGGL(k_coarse_sum<1>, grid, dim3(256), 0, s, N, src, chunk, part);
+        hipLaunchKernelGGL(k_coarse_sum<1>, grid, dim3(256), 0, s, n, src, chunk, part);
     else
-        hipLaunchKernelGGL(k_coarse_sum<0>, grid, dim3(256), 0, s, N, src, chunk, part);
-    hipLaunchKernelGGL(k_coarse_finish, dim3((N + 255) / 256), dim3(256), 0, s, N, nsplit, part, a, chi0, y);
+        hipLaunchKernelGGL(k_coarse_sum<0>, grid, dim3(256), 0, s, n, src, chunk, part);
+    hipLaunchKernelGGL(k_coarse_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, nsplit, part, a, chi0, y);
     chk(hipGetLastError(), "coarse apply");
 }
 
-int CoarseSolver::solve(hipStream_t s, const double* frames, double tol, double* a) {
+int CoarseSolver::solve(hipStream_t s, int nn, const double* frames, double tol, double* a) {
     // GMRES (CGS2, Givens on the host) for C a = 1 from a = 0
-    const int64_t n = N;
-    std::vector<double> one((size_t)N, 1.0);
+    if (nn < 1 || nn > N) throw std::runtime_error("coarse solve: layout larger than the solver");
+    const int64_t n = nn;
+    std::vector<double> one((size_t)n, 1.0);
     chk(hipMemcpyAsync(V, one.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "copy");
-    const double bnorm = std::sqrt((double)N);
+    const double bnorm = std::sqrt((double)n);
     chk(scale_copy(s, n, 1.0 / bnorm, V, V), "scale");
     chk(fill(s, n, 0.0, a), "fill");
     std::vector<double> H((size_t)(maxit + 1) * maxit, 0.0), cs(maxit), sn(maxit), g(maxit + 1, 0.0);
@@ -155,7 +164,7 @@ int CoarseSolver::solve(hipStream_t s, const double* frames, double tol, double*
     int k = 0;
     for (k = 0; k < maxit; ++k) {
         double* w = V + (int64_t)(k + 1) * n;
-        apply(s, frames, V + (int64_t)k * n, w);
+        apply(s, nn, frames, V + (int64_t)k * n, w);
         for (int pass = 0; pass < 2; ++pass) {
             chk(dots(s, n, k + 1, V, n, w, rpart, h), "dots");
             chk(axpys(s, n, k + 1, V, n, h, w), "axpys");

@@ -9,10 +9,9 @@
 namespace nce {
 
 struct CoarseSolver {
-    int N, problem;
+    int N, problem;          // N: the largest layout the solver takes
     double chi0;
     int maxit;
-    int nsplit = 1, chunk = 0;
     float4* src = nullptr;
     double* part = nullptr;
     double* V = nullptr;
@@ -24,10 +23,11 @@ struct CoarseSolver {
     ~CoarseSolver();
     CoarseSolver(const CoarseSolver&) = delete;
     CoarseSolver& operator=(const CoarseSolver&) = delete;
-    // y = C a (device vectors of N doubles); frames: N x 9 device (c, e1, e2)
-    void apply(hipStream_t s, const double* frames, const double* a, double* y);
+    // y = C a for a layout of n <= N centres (device vectors of n doubles);
+    // frames: n x 9 device (c, e1, e2)
+    void apply(hipStream_t s, int n, const double* frames, const double* a, double* y);
     // a = C^{-1} 1 to relative residual tol (GMRES); returns the iterations used
-    int solve(hipStream_t s, const double* frames, double tol, double* a);
+    int solve(hipStream_t s, int n, const double* frames, double tol, double* a);
 };
 
 }  // namespace nce
