@@ -203,8 +203,8 @@ void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
     };
     try {
         float tbest = 1e30f;
-        for (int r : {4, 8}) {
-            if (d.max_q > 256 * r) continue;
+        for (int r : {4, 8, 0}) {
+            if (d.max_q > 256 * (r == 4 ? 4 : 8)) continue;
             const float t = best_of([&] {
                 return nce::tree_far<T>(s, d, ctx->tab.problem, ctx->d_frames.p, soff, rho, nullptr, r);
             });

@@ -32,6 +32,27 @@ __device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, doub
     o2 = s * sb;
 }
 
+// Half-scaled grid points of every grid, relative to its cap centre, in the
+// global frame (FP64 and FP32 copies); one block per grid, once per tree.
+__global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_nr, const int* __restrict__ g_nt,
+                                                     const double* __restrict__ g_R, const double* __restrict__ g_frame,
+                                                     const int64_t* __restrict__ g_off, double* __restrict__ out64,
+                                                     float* __restrict__ out32) {
+    const int g = blockIdx.x;
+    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const double* fg = g_frame + 9 * (int64_t)g;
+    for (int t = threadIdx.x; t < q; t += blockDim.x) {
+        double o0, o1, o2;
+        grid_point(t, nr, nt, g_R[g], o0, o1, o2);
+        const int64_t e = 3 * (g_off[g] + t);
+        for (int c = 0; c < 3; ++c) {
+            const double v = 0.5 * (o0 * fg[c] + o1 * fg[3 + c] + o2 * fg[6 + c]);
+            out64[e + c] = v;
+            out32[e + c] = (float)v;
+        }
+    }
+}
+
 // ----------------------------------------------------------------- P2L
 // One block per work item (one grid, up to kSrcPerItem source patches). The
 // 256 threads are split into ns groups; each thread owns up to R grid points
@@ -60,17 +81,18 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
-                                               const int* __restrict__ it_cfg, const int* __restrict__ live) {
+                                               const int* __restrict__ it_cfg, const int* __restrict__ live,
+                                               const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
+                                               const int* __restrict__ it_list) {
     // staging (kStage points of (x, y, z, rho), interleaved) and, after the
     // sums, the split partials (ns q <= 256 R)
     __shared__ double4 smem4[kStage];
     double* smem = reinterpret_cast<double*>(smem4);
-    const int item = blockIdx.x;
+    const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
-    const double Rg = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -82,12 +104,11 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
         if (active && t < q) {
-            double o0, o1, o2;
-            grid_point(t, nr, nt, Rg, o0, o1, o2);
-            // half-scaled offsets from the cap centre
-            zx[r] = 0.5 * (o0 * fg[0] + o1 * fg[3] + o2 * fg[6]);
-            zy[r] = 0.5 * (o0 * fg[1] + o1 * fg[4] + o2 * fg[7]);
-            zz[r] = 0.5 * (o0 * fg[2] + o1 * fg[5] + o2 * fg[8]);
+            // half-scaled offsets from the cap centre, precomputed per tree
+            const double* z = gpt + 3 * (g_off[g] + t);
+            zx[r] = z[0];
+            zy[r] = z[1];
+            zz[r] = z[2];
         }
     }
     const int s0 = it_src0[item];
@@ -145,17 +166,18 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part,
-                                               const int* __restrict__ it_cfg, const int* __restrict__ live) {
+                                               const int* __restrict__ it_cfg, const int* __restrict__ live,
+                                               const int64_t* __restrict__ g_off, const float* __restrict__ gpt,
+                                               const int* __restrict__ it_list) {
     // staging (kStage points of (x, y, z, rho), interleaved) and, after the
     // sums, the split partials (ns q <= 256 R doubles) share one buffer
     __shared__ float4 smem4[kStage];
     double* smem = reinterpret_cast<double*>(smem4);
-    const int item = blockIdx.x;
+    const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
-    const double Rg = g_R[g];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -168,12 +190,11 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0f;
         if (active && t < q) {
-            double o0, o1, o2;
-            grid_point(t, nr, nt, Rg, o0, o1, o2);
-            // half-scaled offsets from the cap centre
-            zx[r] = (float)(0.5 * (o0 * fg[0] + o1 * fg[3] + o2 * fg[6]));
-            zy[r] = (float)(0.5 * (o0 * fg[1] + o1 * fg[4] + o2 * fg[7]));
-            zz[r] = (float)(0.5 * (o0 * fg[2] + o1 * fg[5] + o2 * fg[8]));
+            // half-scaled offsets from the cap centre, precomputed per tree
+            const float* z = gpt + 3 * (g_off[g] + t);
+            zx[r] = z[0];
+            zy[r] = z[1];
+            zz[r] = z[2];
         }
     }
     constexpr float kLn2 = 0.69314718055994530942f;
@@ -436,7 +457,7 @@ T* dev_alloc(int64_t n) {
 }  // namespace
 
 void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
-                 hipStream_t, DeviceTree& d) {
+                 hipStream_t s, DeviceTree& d) {
     d.ngrid = t.ngrid;
     d.max_q = t.max_q;
     d.ptot = tab_off.back() + tab_p.back();
@@ -472,13 +493,39 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
     d.vals32 = dev_alloc<float>(t.total_q);
     d.coef32 = dev_alloc<float>(t.total_q);
     d.part32 = dev_alloc<float>(t.total_partial);
+    {
+        // busy (target, source split) slots of a block, as p2l_layout arranges them:
+        // ns = 256 / ceil(q / R) splits of q targets over 256 R slots
+        std::vector<int> l4, l8;
+        for (int it = 0; it < (int)t.it_grid.size(); ++it) {
+            const int q = t.g_nr[t.it_grid[it]] * t.g_nt[t.it_grid[it]];
+            auto use = [&](int R) {
+                const int qq = (q + R - 1) / R;
+                const int ns = std::min(64, std::max(1, 256 / std::max(qq, 1)));
+                return (double)std::min(ns * q, 256 * R) / (256.0 * R);
+            };
+            if (q <= 1024 && use(4) >= use(8)) l4.push_back(it);
+            else l8.push_back(it);
+        }
+        d.n_items4 = (int)l4.size();
+        d.items4 = dev_copy(l4);
+        d.items8 = dev_copy(l8);
+    }
+    d.gpt64 = dev_alloc<double>(3 * t.total_q);
+    d.gpt32 = dev_alloc<float>(3 * t.total_q);
+    if (d.ngrid > 0) {
+        hipLaunchKernelGGL(k_grid_points, dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_R, d.g_frame, d.g_off,
+                           d.gpt64, d.gpt32);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            throw std::runtime_error("grid point setup failed");
+    }
 }
 
 void free_tree(DeviceTree& d) {
     void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
-                    d.it_cfg, d.g_cfg, d.pt_cfg};
+                    d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -486,31 +533,41 @@ void free_tree(DeviceTree& d) {
 
 template <class T, int PROB, int R>
 void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const T* skel_off, const T* rho,
-                const int* live) {
+                const int* live, int nblocks, const int* it_list) {
+    if (nblocks <= 0) return;
     if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+        hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
-                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live);
+                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live, d.g_off, d.gpt64, it_list);
     else
-        hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+        hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
-                           skel_off, rho, d.ptot, d.part32, d.it_cfg, live);
+                           skel_off, rho, d.ptot, d.part32, d.it_cfg, live, d.g_off, d.gpt32, it_list);
+}
+
+template <class T, int PROB>
+void launch_p2l_shape(hipStream_t s, const DeviceTree& d, const double* frames, const T* skel_off, const T* rho,
+                      const int* live, int r_tgt) {
+    if (r_tgt == 8) {
+        launch_p2l<T, PROB, 8>(s, d, frames, skel_off, rho, live, d.nitems, nullptr);
+    } else if (r_tgt == 4) {
+        launch_p2l<T, PROB, 4>(s, d, frames, skel_off, rho, live, d.nitems, nullptr);
+    } else {
+        // per item: the shape that keeps more (target, source split) slots busy
+        launch_p2l<T, PROB, 4>(s, d, frames, skel_off, rho, live, d.n_items4, d.items4);
+        launch_p2l<T, PROB, 8>(s, d, frames, skel_off, rho, live, d.nitems - d.n_items4, d.items8);
+    }
 }
 
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
                     const T* rho, const int* live, int r_tgt) {
     if (!d.it_cfg) live = nullptr;
-    if (r_tgt != 4 && r_tgt != 8) return hipErrorInvalidValue;
-    if (d.max_q > 256 * r_tgt) return hipErrorInvalidValue;
+    if (r_tgt != 4 && r_tgt != 8 && r_tgt != 0) return hipErrorInvalidValue;
+    if (d.max_q > 256 * (r_tgt == 4 ? 4 : 8)) return hipErrorInvalidValue;
     if (d.nitems > 0) {
-        if (problem == 1) {
-            if (r_tgt == 8) launch_p2l<T, 1, 8>(s, d, frames, skel_off, rho, live);
-            else launch_p2l<T, 1, 4>(s, d, frames, skel_off, rho, live);
-        } else {
-            if (r_tgt == 8) launch_p2l<T, 0, 8>(s, d, frames, skel_off, rho, live);
-            else launch_p2l<T, 0, 4>(s, d, frames, skel_off, rho, live);
-        }
+        if (problem == 1) launch_p2l_shape<T, 1>(s, d, frames, skel_off, rho, live, r_tgt);
+        else launch_p2l_shape<T, 0>(s, d, frames, skel_off, rho, live, r_tgt);
     }
     if (d.ngrid > 0) {
         if constexpr (sizeof(T) == 8)

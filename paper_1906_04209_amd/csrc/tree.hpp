@@ -37,6 +37,13 @@ struct DeviceTree {
     int* g_cfg = nullptr;
     int* pt_cfg = nullptr;
     int max_q = 0;
+    // half-scaled grid points relative to each cap centre (3 per point, Σq points)
+    double* gpt64 = nullptr;
+    float* gpt32 = nullptr;
+    // items whose grids keep more lanes busy with 4 (resp. 8) grid points per thread
+    int n_items4 = 0;
+    int* items4 = nullptr;
+    int* items8 = nullptr;
     // work buffers (FP64 and FP32)
     double* vals64 = nullptr;
     double* coef64 = nullptr;
@@ -57,7 +64,8 @@ void free_tree(DeviceTree& d);
 //
 // Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per
 // grid and turned into Chebyshev-Fourier coefficients.
-// r_tgt: grid points per thread of the P2L kernel (4, or 8; needs 256 r_tgt >= max q).
+// r_tgt: grid points per thread of the P2L kernel: 4 (needs max q <= 1024), 8,
+// or 0 = per item, whichever keeps more lanes busy for its grid.
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
                     const T* rho, const int* live = nullptr, int r_tgt = 4);
