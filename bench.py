@@ -31,7 +31,7 @@ import layouts  # noqa: E402
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
 # Keyed by (precision, problem, P2L grid points per thread).
-C_PAIR = {("fp64", 0, 4): 56.1, ("fp64", 0, 8): 55.8, ("fp64", 1, 4): 55.1, ("fp64", 1, 8): 54.8,
+C_PAIR = {("fp64", 0, 4): 41.6, ("fp64", 0, 8): 41.3, ("fp64", 1, 4): 40.6, ("fp64", 1, 8): 40.3,
           ("fp32", 0, 4): 9.4, ("fp32", 0, 8): 9.2, ("fp32", 1, 4): 8.9, ("fp32", 1, 8): 8.7}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes per P2L launch at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the

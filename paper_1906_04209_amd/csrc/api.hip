@@ -128,7 +128,8 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         HIPCHK(nce::tree_interp<T>(s, dt, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
         mark(4);
     } else {
-        HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U));
+        HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U,
+                                  ctx->d_logtab.p));
         mark(2);
         mark(3);
         mark(4);
@@ -548,6 +549,11 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->d_P32.upload(to_f32(ctx->tab.P), s);
     ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
     ctx->d_skel_off32.upload(to_f32(soff), s);
+    {
+        std::vector<nce::LogEntry> lt(nce::kLogTab);
+        nce::build_log_table(lt.data());
+        ctx->d_logtab.upload(lt, s);
+    }
     ctx->d_rho.alloc((size_t)N * ctx->ptot);
     ctx->d_U.alloc((size_t)N * ctx->Kstar);
     ctx->d_rho32.alloc((size_t)N * ctx->ptot);

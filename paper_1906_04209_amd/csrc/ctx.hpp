@@ -110,6 +110,7 @@ struct nce_ctx {
     // device tables
     DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
     DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
+    DevBuf<nce::LogEntry> d_logtab;     // FP64 logarithm table of the direct sums
     // matvec work arrays
     DevBuf<double> d_rho, d_U;
     DevBuf<float> d_rho32, d_U32, d_x32;

@@ -4,71 +4,70 @@
 //   exterior  2/d - log(2/d) - log(1 + d/2) = w - log(1 + w)
 //   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
 //
-// The FP64 logarithm is a short table-free routine: x = m 2^e with m in
-// [sqrt(1/2), sqrt(2)), log m = 2 atanh(u), u = (m - 1)/(m + 1), |u| <= 0.1716,
-// summed as the odd series 2u (1 + u^2/3 + ... + u^20/21) (truncation below
-// 2^-53 relative), and e ln 2 added with a two-part ln 2. It is valid for
-// positive normal arguments, which is all the kernels pass (w >= 1). The
-// quotient and the reciprocal use the hardware reciprocal with Newton steps.
-// Host builds of these functions exist only for the CPU accuracy test.
+// FP64 logarithm (log64t): x = m 2^e with m in [1, 2); the top 7 mantissa bits
+// pick a table entry (r_k, -log r_k) with r_k the FP32-rounded reciprocal of
+// the bin centre, so u = m r_k - 1 (one fma, |u| < 2^-7.9) and
+// log x = e ln 2 - log r_k + log(1 + u), the last by its degree-7 series
+// (truncation below 1e-20). The table holds -log r_k as a double plus a float
+// correction, computed on the host in extended precision; kernels stage it in
+// LDS (2 KiB). Valid for positive normal arguments, which is all the kernels
+// pass. Host builds of these functions serve the CPU accuracy test.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 namespace nce {
 
-__host__ __device__ __forceinline__ double rcp64(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    double r = __builtin_amdgcn_rcp(x);
-#else
-    double r = (double)(1.0f / (float)x);  // same starting accuracy class as the hardware estimate
-#endif
-    // two Newton steps: r (2 - x r)
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    return r;
-}
+struct alignas(16) LogEntry {
+    double t_hi;  // -log r_k, leading part
+    float t_lo;   // -log r_k, correction
+    float r;      // r_k
+};
+constexpr int kLogBits = 7;
+constexpr int kLogTab = 1 << kLogBits;
 
-// a / b to about one ulp (reciprocal, then one residual correction)
-__host__ __device__ __forceinline__ double div64(double a, double b) {
-    const double r = rcp64(b);
-    const double q = a * r;
-    return fma(fma(-b, q, a), r, q);
-}
-
-__host__ __device__ __forceinline__ double log64(double x) {
-    int e;
-#if defined(__HIP_DEVICE_COMPILE__)
-    double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1)
-    e = __builtin_amdgcn_frexp_exp(x);
-#else
-    double m = std::frexp(x, &e);
-#endif
-    if (m < 0.70710678118654752440) {
-        m *= 2.0;
-        e -= 1;
+// Host: fills the kLogTab entries (extended-precision logarithms).
+inline void build_log_table(LogEntry* tab) {
+    for (int k = 0; k < kLogTab; ++k) {
+        const long double c = 1.0L + (k + 0.5L) / kLogTab;
+        const float r = (float)(1.0L / c);
+        const long double t = -std::log((long double)r);
+        tab[k].t_hi = (double)t;
+        tab[k].t_lo = (float)(t - (long double)tab[k].t_hi);
+        tab[k].r = r;
     }
-    const double u = div64(m - 1.0, m + 1.0);
-    const double s = u * u;
-    double p = 1.0 / 21.0;
-    p = fma(p, s, 1.0 / 19.0);
-    p = fma(p, s, 1.0 / 17.0);
-    p = fma(p, s, 1.0 / 15.0);
-    p = fma(p, s, 1.0 / 13.0);
-    p = fma(p, s, 1.0 / 11.0);
-    p = fma(p, s, 1.0 / 9.0);
-    p = fma(p, s, 1.0 / 7.0);
-    p = fma(p, s, 1.0 / 5.0);
-    p = fma(p, s, 1.0 / 3.0);
-    const double lm = fma(2.0 * u * s, p, 2.0 * u);  // 2u + 2u s P(s)
+}
+
+__host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __restrict__ tab) {
+    int e;
+    double m;
+#if defined(__HIP_DEVICE_COMPILE__)
+    m = 2.0 * __builtin_amdgcn_frexp_mant(x);  // [1, 2)
+    e = __builtin_amdgcn_frexp_exp(x) - 1;
+    const unsigned hi = (unsigned)__double2hiint(m);
+#else
+    m = 2.0 * std::frexp(x, &e);
+    e -= 1;
+    unsigned long long bits;
+    std::memcpy(&bits, &m, sizeof bits);
+    const unsigned hi = (unsigned)(bits >> 32);
+#endif
+    const LogEntry L = tab[(hi >> (20 - kLogBits)) & (kLogTab - 1)];
+    const double u = fma(m, (double)L.r, -1.0);
+    double q = 1.0 / 7.0;
+    q = fma(q, u, -1.0 / 6.0);
+    q = fma(q, u, 1.0 / 5.0);
+    q = fma(q, u, -1.0 / 4.0);
+    q = fma(q, u, 1.0 / 3.0);
+    q = fma(q, u, -0.5);
+    const double lp = fma(q * u, u, u);  // log(1 + u)
     const double de = (double)e;
     // ln 2 = hi + lo with hi exact to 2^-32 so that e * hi is exact for |e| < 2^21
     const double ln2_hi = 6.93147180369123816490e-01;
     const double ln2_lo = 1.90821492927058770002e-10;
-    return fma(de, ln2_hi, fma(de, ln2_lo, lm));
+    return fma(de, ln2_hi, L.t_hi) + (fma(de, ln2_lo, (double)L.t_lo) + lp);
 }
 
 __host__ __device__ __forceinline__ double rsqrt64(double x) {
@@ -84,17 +83,17 @@ __host__ __device__ __forceinline__ double rsqrt64(double x) {
 // log(w^2 / (1 + w)) = -log(u^2 + u) needs no division. The pair kernels keep
 // coordinates pre-scaled by 1/2 (exact), so h2 comes straight from them.
 template <int PROB>
-__host__ __device__ __forceinline__ double green64_half(double h2) {
+__host__ __device__ __forceinline__ double green64_half(double h2, const LogEntry* __restrict__ tab) {
     const double w = rsqrt64(h2);
-    if (PROB == 1) return w - log64(1.0 + w);
+    if (PROB == 1) return w - log64t(1.0 + w, tab);
     const double u = h2 * w;
-    return w - log64(fma(u, u, u));
+    return w - log64t(fma(u, u, u), tab);
 }
 
 // G as a function of d^2 (FP64).
 template <int PROB>
-__host__ __device__ __forceinline__ double green64(double d2) {
-    return green64_half<PROB>(0.25 * d2);
+__host__ __device__ __forceinline__ double green64(double d2, const LogEntry* __restrict__ tab) {
+    return green64_half<PROB>(0.25 * d2, tab);
 }
 
 #if defined(__HIPCC__)

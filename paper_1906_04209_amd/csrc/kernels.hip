@@ -20,10 +20,13 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
                                                   const double* __restrict__ skel_off,
                                                   const double* __restrict__ rho, int ldr, double* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
-                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live) {
+                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live,
+                                                  const LogEntry* __restrict__ logtab) {
     extern __shared__ double4 sm64[];  // p source points (x, y, z, rho), half-scaled
+    __shared__ LogEntry ltab[kLogTab];
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
+    for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
     const double* fi = frames + 9 * (int64_t)i;
     const double cix = fi[0], ciy = fi[1], ciz = fi[2];
     double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
                 const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
-                acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz) * a.w;
+                acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz, ltab) * a.w;
             }
         }
     }
@@ -80,7 +83,8 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
                                                   const float* __restrict__ skel_off,
                                                   const float* __restrict__ rho, int ldr, float* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
-                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live) {
+                                                  const int* __restrict__ pt_cfg, const int* __restrict__ live,
+                                                  const LogEntry* __restrict__ logtab) {
     extern __shared__ float4 sm32[];  // p source points (x, y, z, rho), half-scaled
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
@@ -148,24 +152,25 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
 template <>
 hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
                             const double* node_off, const double* skel_off, const double* rho, int ldr, double* U,
-                            const int64_t* lptr, const int* lsrc, const int* pt_cfg, const int* live) {
+                            const int64_t* lptr, const int* lsrc, const LogEntry* logtab, const int* pt_cfg,
+                            const int* live) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
         else
             hipLaunchKernelGGL((k_direct64<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
         else
             hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
     }
     return hipGetLastError();
 }
@@ -173,38 +178,39 @@ hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p,
 template <>
 hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
                            const float* node_off, const float* skel_off, const float* rho, int ldr, float* U,
-                           const int64_t* lptr, const int* lsrc, const int* pt_cfg, const int* live) {
+                           const int64_t* lptr, const int* lsrc, const LogEntry* logtab, const int* pt_cfg,
+                           const int* live) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
         else
             hipLaunchKernelGGL((k_direct32<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
         else
             hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
     }
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
-                      const T* skel_off, const T* rho, T* U) {
-    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr, nullptr,
-                       nullptr);
+                      const T* skel_off, const T* rho, T* U, const LogEntry* logtab) {
+    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr, logtab,
+                       nullptr, nullptr);
 }
 template hipError_t direct_sum<double>(hipStream_t, int, int, int, int, const double*, const double*, const double*,
-                                       const double*, double*);
+                                       const double*, double*, const LogEntry*);
 template hipError_t direct_sum<float>(hipStream_t, int, int, int, int, const double*, const float*, const float*,
-                                      const float*, float*);
+                                      const float*, float*, const LogEntry*);
 
 // ---------------------------------------------------------------------------
 // Krylov vector operations (FP64). Reductions are two-stage and deterministic:

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "greens.hpp"
+
 namespace nce {
 
 // Green's function of the unit sphere on the surface, as a function of
@@ -33,9 +35,10 @@ hipError_t p_apply(hipStream_t s, int N, int K, int Kstar, const T* U, const T* 
 // U[i][q] = sum_{j != i} sum_m G(|z_iq - s_jm|) rho[j][m]
 // frames: N x 9 FP64 (c, e1, e2); node_off: Kstar x 3, skel_off: p x 3 local
 // offsets in T precision; rho: N x p in T.
+// logtab: the FP64 logarithm's table (device, kLogTab entries; unused by FP32).
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                      const T* node_off, const T* skel_off, const T* rho, T* U);
+                      const T* node_off, const T* skel_off, const T* rho, T* U, const LogEntry* logtab);
 
 // Same with the sources of target i restricted to lsrc[lptr[i] .. lptr[i+1]) (CSR)
 // and the strengths of patch j at rho[j * ldr .. j * ldr + p).
@@ -43,7 +46,7 @@ hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const
 template <class T>
 hipError_t list_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
                     const T* skel_off, const T* rho, int ldr, T* U, const int64_t* lptr, const int* lsrc,
-                    const int* pt_cfg = nullptr, const int* live = nullptr);
+                    const LogEntry* logtab, const int* pt_cfg = nullptr, const int* live = nullptr);
 
 // Krylov helpers (FP64).
 hipError_t dots(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* w,

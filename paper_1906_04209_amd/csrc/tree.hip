@@ -83,13 +83,15 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
-                                               const int* __restrict__ it_list) {
+                                               const int* __restrict__ it_list, const LogEntry* __restrict__ logtab) {
     // staging (kStage points of (x, y, z, rho), interleaved) and, after the
     // sums, the split partials (ns q <= 256 R)
     __shared__ double4 smem4[kStage];
+    __shared__ LogEntry ltab[kLogTab];
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
+    for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
-                    acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz) * a.w;
+                    acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz, ltab) * a.w;
                 }
             }
         }
@@ -511,6 +513,11 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
         d.items4 = dev_copy(l4);
         d.items8 = dev_copy(l8);
     }
+    {
+        std::vector<LogEntry> lt(kLogTab);
+        build_log_table(lt.data());
+        d.logtab = dev_copy(lt);
+    }
     d.gpt64 = dev_alloc<double>(3 * t.total_q);
     d.gpt32 = dev_alloc<float>(3 * t.total_q);
     if (d.ngrid > 0) {
@@ -525,7 +532,7 @@ void free_tree(DeviceTree& d) {
     void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
-                    d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8};
+                    d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -538,7 +545,7 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
     if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
-                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live, d.g_off, d.gpt64, it_list);
+                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live, d.g_off, d.gpt64, it_list, d.logtab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
@@ -590,7 +597,7 @@ hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const doub
     if (!d.pt_cfg) live = nullptr;
     // near field uses the base table (the first p columns of every strength row)
     return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, d.ptot, U, d.dl_ptr,
-                       d.dl_src, d.pt_cfg, live);
+                       d.dl_src, d.logtab, d.pt_cfg, live);
 }
 template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
                                       const double*, const double*, double*, const int*);

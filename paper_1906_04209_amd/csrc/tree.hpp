@@ -4,6 +4,7 @@
 
 #include <vector>
 
+#include "greens.hpp"
 #include "tree_build.hpp"
 
 namespace nce {
@@ -41,6 +42,7 @@ struct DeviceTree {
     double* gpt64 = nullptr;
     float* gpt32 = nullptr;
     // items whose grids keep more lanes busy with 4 (resp. 8) grid points per thread
+    LogEntry* logtab = nullptr;  // FP64 logarithm table (kLogTab entries)
     int n_items4 = 0;
     int* items4 = nullptr;
     int* items8 = nullptr;
