@@ -81,6 +81,8 @@ typedef struct nce_opts {
                              set of incoming grids when it differs from tol_grid; 0 = tol_grid.
                              Default 1e-6 (below the FP32 inner solve's 1e-5 target; the FP64
                              residuals always use tol_grid) */
+    double tol_id_fp32;   /* ID tolerance of the outgoing representation used by the FP32 applies
+                             (mixed solves); 0 = tol_id. Default 1e-8 */
 } nce_opts;
 
 typedef struct nce_info {

@@ -41,7 +41,8 @@ class Opts(ctypes.Structure):
                 ("tol_grid", ctypes.c_double), ("tol_gmres", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double)]
+                ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double),
+                ("tol_id_fp32", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -225,7 +226,8 @@ class Context:
     def __init__(self, centers: np.ndarray, eps: float, problem: int = INTERIOR, M: int = 15,
                  tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
                  max_iter: int = 100, precision: int = FP64, far_field: int = FAR_AUTO,
-                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None):
+                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
+                 tol_id_fp32: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -237,6 +239,8 @@ class Context:
         o.problem, o.M, o.tol_id, o.tol_grid, o.tol_gmres = problem, M, tol_id, tol_grid, tol_gmres
         if tol_grid_fp32 is not None:
             o.tol_grid_fp32 = tol_grid_fp32
+        if tol_id_fp32 is not None:
+            o.tol_id_fp32 = tol_id_fp32
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         # the library works on its own (non-default) stream; calls below order
         # it against the caller's current stream in both directions
@@ -384,7 +388,8 @@ class Batch:
 
     def __init__(self, configs, M: int = 15, tol_id: float = 1e-11, tol_grid: float = 1e-8,
                  tol_gmres: float = 1e-10, max_iter: int = 60, precision: int = MIXED, far_field: int = FAR_AUTO,
-                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None):
+                 cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
+                 tol_id_fp32: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -401,6 +406,8 @@ class Batch:
         o.M, o.tol_id, o.tol_grid, o.tol_gmres = M, tol_id, tol_grid, tol_gmres
         if tol_grid_fp32 is not None:
             o.tol_grid_fp32 = tol_grid_fp32
+        if tol_id_fp32 is not None:
+            o.tol_id_fp32 = tol_id_fp32
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         self.stream = stream if stream is not None else torch.cuda.Stream()
         o.stream = ctypes.c_void_p(self.stream.cuda_stream)

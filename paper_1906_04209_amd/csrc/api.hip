@@ -96,8 +96,8 @@ void ensure_krylov(nce_ctx* ctx, int nvec) {
 // stream). With ev != nullptr, events ev[0..5] bracket the five steps.
 template <class T>
 void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm, const T* noff, const T* soff,
-              T* rho, T* U, hipEvent_t* ev, const int* live) {
-    const int N = (int)ctx->N, K = ctx->K, Ks = ctx->Kstar, p = ctx->p;
+              T* rho, T* U, hipEvent_t* ev, const int* live, int p, int pt) {
+    const int N = (int)ctx->N, K = ctx->K, Ks = ctx->Kstar;
     hipStream_t s = ctx->stream;
     auto mark = [&](int k) {
         if (ev) HIPCHK(hipEventRecord(ev[k], s));
@@ -112,7 +112,6 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
     }
     // Step 1: rho_i = T f_i for every patch and every outgoing table in use
     // (one GEMM with the shared, concatenated T)
-    const int pt = ctx->ptot;
     HIPCHK(nce::gemm_nt<T>(s, N, pt, K, xin, K, Tm, K, rho, pt, nullptr, 0));
     mark(1);
     if (ctx->use_tree) {
@@ -148,10 +147,10 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
     }
     if (precision == NCE_FP64)
         matvec_t<double>(ctx, x, y, ctx->d_T.p, ctx->d_P.p, ctx->d_node_off.p, ctx->d_skel_off.p, ctx->d_rho.p,
-                         ctx->d_U.p, ev, live);
+                         ctx->d_U.p, ev, live, ctx->p, ctx->ptot);
     else
         matvec_t<float>(ctx, x, y, ctx->d_T32.p, ctx->d_P32.p, ctx->d_node_off32.p, ctx->d_skel_off32.p,
-                        ctx->d_rho32.p, ctx->d_U32.p, ev, live);
+                        ctx->d_rho32.p, ctx->d_U32.p, ev, live, ctx->p32, ctx->ptot32);
 }
 
 const double* coarse_amplitudes(nce_ctx* ctx) {
@@ -184,7 +183,7 @@ void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
     const int ti = sizeof(T) == 8 ? 0 : 1;
     const nce::DeviceTree& d = (ti == 1 && ctx->has_tree32) ? ctx->dtree32 : ctx->dtree;
     // the kernels' cost does not depend on the strengths: start from zeros
-    HIPCHK(hipMemsetAsync(rho, 0, sizeof(T) * (size_t)ctx->N * ctx->ptot, s));
+    HIPCHK(hipMemsetAsync(rho, 0, sizeof(T) * (size_t)ctx->N * (ti == 0 ? ctx->ptot : ctx->ptot32), s));
     HIPCHK(hipMemsetAsync(U, 0, sizeof(T) * (size_t)ctx->N * ctx->Kstar, s));
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -456,6 +455,8 @@ int validate_opts(const nce_opts& o, double eps) {
     if (!(o.tol_grid > 0 && o.tol_grid < 1e-2)) return fail(NCE_EINVAL, "tol_grid must lie in (0, 1e-2)");
     if (!(o.tol_grid_fp32 == 0.0 || (o.tol_grid_fp32 > 0 && o.tol_grid_fp32 < 1e-2)))
         return fail(NCE_EINVAL, "tol_grid_fp32 must be 0 or lie in (0, 1e-2)");
+    if (!(o.tol_id_fp32 == 0.0 || (o.tol_id_fp32 > 0 && o.tol_id_fp32 < 1e-3)))
+        return fail(NCE_EINVAL, "tol_id_fp32 must be 0 or lie in (0, 1e-3)");
     if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
     if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
     if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
@@ -501,6 +502,15 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->K = ctx->tab.K;
     ctx->Kstar = ctx->tab.Kstar;
     ctx->p = ctx->tab.p;
+    // the FP32 applies may use a coarser outgoing representation
+    const double tid32 = o.tol_id_fp32 > 0 ? o.tol_id_fp32 : o.tol_id;
+    ctx->has_tab32 = tid32 != o.tol_id;
+    if (ctx->has_tab32 && !nce::load_tables(dir, o.problem, eps, o.M, tid32, ctx->tab32)) {
+        ctx->tab32 = nce::build_tables(o.problem, eps, o.M, tid32);
+        nce::save_tables(dir, ctx->tab32);
+    }
+    const nce::PatchTables& t32 = ctx->has_tab32 ? ctx->tab32 : ctx->tab;
+    ctx->p32 = t32.p;
     build_frames(centers, N, ctx->frames);
     if (o.stream) {
         ctx->stream = (hipStream_t)o.stream;
@@ -539,16 +549,28 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
         }
     }
     ctx->ptot = ctx->tab_off.back() + ctx->tab_p.back();
+    std::vector<double> Tall32(t32.T), soff32(t32.skel_off);
+    ctx->tab_off32 = {0};
+    ctx->tab_p32 = {ctx->p32};
+    if (ctx->use_tree) {
+        for (const auto& ft : t32.far) {
+            ctx->tab_off32.push_back(ctx->tab_off32.back() + ctx->tab_p32.back());
+            ctx->tab_p32.push_back(ft.p);
+            Tall32.insert(Tall32.end(), ft.T.begin(), ft.T.end());
+            soff32.insert(soff32.end(), ft.skel_off.begin(), ft.skel_off.end());
+        }
+    }
+    ctx->ptot32 = ctx->tab_off32.back() + ctx->tab_p32.back();
     ctx->d_frames.upload(ctx->frames, s);
     ctx->d_T.upload(Tall, s);
     ctx->d_P.upload(ctx->tab.P, s);
     ctx->d_I.upload(ctx->tab.I, s);
     ctx->d_node_off.upload(ctx->tab.node_off, s);
     ctx->d_skel_off.upload(soff, s);
-    ctx->d_T32.upload(to_f32(Tall), s);
+    ctx->d_T32.upload(to_f32(Tall32), s);
     ctx->d_P32.upload(to_f32(ctx->tab.P), s);
     ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
-    ctx->d_skel_off32.upload(to_f32(soff), s);
+    ctx->d_skel_off32.upload(to_f32(soff32), s);
     {
         std::vector<nce::LogEntry> lt(nce::kLogTab);
         nce::build_log_table(lt.data());
@@ -556,7 +578,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     }
     ctx->d_rho.alloc((size_t)N * ctx->ptot);
     ctx->d_U.alloc((size_t)N * ctx->Kstar);
-    ctx->d_rho32.alloc((size_t)N * ctx->ptot);
+    ctx->d_rho32.alloc((size_t)N * ctx->ptot32);
     ctx->d_U32.alloc((size_t)N * ctx->Kstar);
     ctx->d_x32.alloc(n);
     ctx->d_b.alloc(n);
@@ -568,7 +590,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     const int ncfg = (int)cfg_first.size() - 1;
     ctx->cfg_tree.assign(ncfg, ctx->use_tree ? 1 : 0);
     const double tol32 = o.tol_grid_fp32 > 0 ? o.tol_grid_fp32 : o.tol_grid;
-    ctx->has_tree32 = ctx->use_tree && tol32 != o.tol_grid;
+    ctx->has_tree32 = ctx->use_tree && (tol32 != o.tol_grid || ctx->has_tab32);
     if (forest) {
         nce::start_forest(ctx->tree);
         if (ctx->has_tree32) nce::start_forest(ctx->tree32);
@@ -593,20 +615,20 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
             else nce::append_direct(ctx->tree, f0, nc, ctx->Kstar, ctx->p);
             if (ctx->has_tree32) {
                 if (tree) {
-                    nce::Tree t32;
-                    nce::build_tree(fr, nc, eps, ctx->tab, tol32, t32);
-                    nce::append_tree(ctx->tree32, t32, f0);
+                    nce::Tree tr32;
+                    nce::build_tree(fr, nc, eps, t32, tol32, tr32);
+                    nce::append_tree(ctx->tree32, tr32, f0);
                 } else {
-                    nce::append_direct(ctx->tree32, f0, nc, ctx->Kstar, ctx->p);
+                    nce::append_direct(ctx->tree32, f0, nc, ctx->Kstar, ctx->p32);
                 }
             }
         }
     } else if (ctx->has_tree32) {
-        nce::build_tree(ctx->frames, N, eps, ctx->tab, tol32, ctx->tree32);
+        nce::build_tree(ctx->frames, N, eps, t32, tol32, ctx->tree32);
     }
     if (ctx->use_tree) nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
     if (ctx->has_tree32)
-        nce::upload_tree(ctx->tree32, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree32);
+        nce::upload_tree(ctx->tree32, ctx->Kstar, ctx->p32, ctx->tab_off32, ctx->tab_p32, s, ctx->dtree32);
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -628,6 +650,7 @@ void nce_default_opts(nce_opts* o) {
     o->stream = nullptr;
     o->cache_dir = nullptr;
     o->tol_grid_fp32 = 1e-6;
+    o->tol_id_fp32 = 1e-8;
 }
 
 int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {
@@ -686,7 +709,7 @@ int nce_work(const nce_ctx* ctx, int precision, double* far, double* near, doubl
         nr = t.pairs_near;
         it = t.interp_fma;
     } else {
-        f = (double)ctx->N * (double)(ctx->N - 1) * ctx->Kstar * (double)ctx->p;
+        f = (double)ctx->N * (double)(ctx->N - 1) * ctx->Kstar * (double)(precision == NCE_MIXED ? ctx->p32 : ctx->p);
     }
     if (far) *far = f;
     if (near) *near = nr;

@@ -87,6 +87,11 @@ struct nce_ctx {
     int K = 0, Kstar = 0, p = 0;
     int ptot = 0;                       // strengths per patch over all outgoing tables in use
     std::vector<int> tab_off, tab_p;    // per table: first column and size (table 0 = base)
+    // outgoing tables of the FP32 applies (opts.tol_id_fp32; the same as above when equal to tol_id)
+    bool has_tab32 = false;
+    nce::PatchTables tab32;
+    int p32 = 0, ptot32 = 0;
+    std::vector<int> tab_off32, tab_p32;
     double eps = 0;
     nce::PatchTables tab;
     std::vector<double> frames;  // N x 9: c, e1, e2
