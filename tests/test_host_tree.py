@@ -55,3 +55,28 @@ def test_cube_corner_and_edges(exe, tmp_path):
         if all(np.arccos(np.clip(c[i] @ c[k], -1, 1)) >= 0.031 for k in keep):
             keep.append(i)
     print(_run(exe, tmp_path, c[keep], 0.01))
+
+
+@pytest.fixture(scope="module")
+def forest_exe(tmp_path_factory):
+    d = tmp_path_factory.mktemp("forest")
+    out = d / "forest_check"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", str(CSRC), str(ROOT / "tests" / "host" / "forest_check.cpp"),
+                           str(CSRC / "tree_build.cpp"), "-o", str(out)])
+    return out
+
+
+def test_forest_coverage(forest_exe, tmp_path):
+    """Several configurations in one numbering (trees and direct lists, one of a
+    single patch): pairs only within a configuration, each exactly once."""
+    eps = 0.02
+    cfgs = [layouts.uniform_centers(n, eps, 70 + k) for k, n in enumerate([150, 1, 60, 400, 2, 33, 250])]
+    f = tmp_path / "forest.txt"
+    with open(f, "w") as fh:
+        fh.write(f"{len(cfgs)}\n")
+        for c in cfgs:
+            fh.write(f"{len(c)}\n")
+            np.savetxt(fh, c, fmt="%.17g")
+    r = subprocess.run([str(forest_exe), str(f), repr(eps), "1e-8"], capture_output=True, text=True)
+    print(r.stdout)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout + r.stderr
