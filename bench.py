@@ -37,7 +37,7 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes per P2L launch at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels; None where not measured.
-TRAFFIC = {("cfg5", "fp64", 8): 9.112e9}
+TRAFFIC = {("cfg5", "fp64", 8): 9.112e9, ("cfg5", "fp32", 4): 4.828e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
