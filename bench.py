@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--tol-id", type=float, default=1e-11)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); nothing in this build uses a second GPU.",
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path.",
               file=sys.stderr)
         sys.exit(2)
 

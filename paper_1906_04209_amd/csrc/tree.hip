@@ -317,28 +317,105 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
 }
 
 // ------------------------------------------------------------------ L2T
-// One block per patch; for every grid in the patch's list, stage the grid's
-// coefficients in LDS and evaluate the expansion at the patch's K* nodes in
-// the grid's geodesic polar coordinates; add into U.
+// One block per patch: evaluate every grid of the patch's list at the patch's
+// K* nodes, in the grid's geodesic polar coordinates (r / R, theta), and add
+// the total into U once. The expansion of a grid is
+//     sum_k [cos k theta C_k(r) + sin k theta S_k(r)],
+// C_k, S_k Chebyshev series over the degrees of the parity of k. Per grid, a
+// thread forms the Chebyshev values of its nodes once per parity and reuses
+// them for every angular row of that parity; cos k theta and sin k theta
+// advance by rotation through 2 theta. Coefficients are staged in LDS through
+// a double buffer filled from registers loaded one grid ahead, so the next
+// grid's global loads are in flight while the current one is summed and
+// each grid costs one barrier.
+template <class T, int NPT, int NR>
+__device__ __forceinline__ void l2t_sum(const T* __restrict__ cs, int half, const T (&xs)[NPT],
+                                        const T (&ct)[NPT], const T (&st)[NPT], T (&val)[NPT]) {
+    T c2[NPT], s2[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) {
+        c2[r] = ct[r] * ct[r] - st[r] * st[r];
+        s2[r] = T(2) * ct[r] * st[r];
+    }
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        // tb[r][n] = T_{2n+par}(x): T_{m+2} = 2 T_2 T_m - T_{m-2}, T_2 = 2 x^2 - 1
+        T tb[NPT][NR], ck[NPT], sk[NPT];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const T x = xs[r], y = T(2) * x * x - T(1), ty = T(2) * y;
+            tb[r][0] = par ? x : T(1);
+            if (NR > 1) tb[r][1] = par ? x * (ty - T(1)) : y;
+#pragma unroll
+            for (int n = 2; n < NR; ++n) tb[r][n] = ty * tb[r][n - 1] - tb[r][n - 2];
+            ck[r] = par ? ct[r] : T(1);
+            sk[r] = par ? st[r] : T(0);
+        }
+        for (int k = par; k <= half; k += 2) {
+            const T* cc = cs + k * NR;
+            T rc[NPT];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) rc[r] = cc[0] * tb[r][0];
+#pragma unroll
+            for (int n = 1; n < NR; ++n) {
+                const T cv = cc[n];
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) rc[r] += cv * tb[r][n];
+            }
+            if (k > 0 && k < half) {
+                const T* sc = cs + (half + k) * NR;
+                T rs[NPT];
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) rs[r] = sc[0] * tb[r][0];
+#pragma unroll
+                for (int n = 1; n < NR; ++n) {
+                    const T sv = sc[n];
+#pragma unroll
+                    for (int r = 0; r < NPT; ++r) rs[r] += sv * tb[r][n];
+                }
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r] + sk[r] * rs[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r];
+            }
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                const T cn = ck[r] * c2[r] - sk[r] * s2[r];
+                sk[r] = sk[r] * c2[r] + ck[r] * s2[r];
+                ck[r] = cn;
+            }
+        }
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T rsqrt_t(T v) {
+    if constexpr (sizeof(T) == 8) return rsqrt64(v);
+    else return rsqrtf(v);
+}
+
 template <class T, int NPT>
-__global__ __launch_bounds__(256) void k_l2t(int Kstar, const double* __restrict__ frames,
-                                             const T* __restrict__ node_off, const int64_t* __restrict__ l2t_ptr,
-                                             const int* __restrict__ l2t_grid, const double* __restrict__ g_frame,
-                                             const double* __restrict__ g_R, const int* __restrict__ g_nr,
-                                             const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
-                                             const T* __restrict__ coef, T* __restrict__ U,
-                                             const int* __restrict__ pt_cfg, const int* __restrict__ live) {
-    __shared__ T cs[kMaxGridQ];
+__global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __restrict__ frames,
+                                                    const T* __restrict__ node_off, const int64_t* __restrict__ l2t_ptr,
+                                                    const int* __restrict__ l2t_grid, const double* __restrict__ g_frame,
+                                                    const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                                    const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
+                                                    const T* __restrict__ coef, T* __restrict__ U,
+                                                    const int* __restrict__ pt_cfg, const int* __restrict__ live) {
+    constexpr int kThreads = 512 / NPT;
+    constexpr int kPre = (kMaxGridQ + kThreads - 1) / kThreads;  // coefficients per thread per grid
+    __shared__ T cs[2][kMaxGridQ];
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
     const int64_t a0 = l2t_ptr[i], a1 = l2t_ptr[i + 1];
     if (a0 == a1) return;
     const double* fi = frames + 9 * (int64_t)i;
-    T ox[NPT], oy[NPT], oz[NPT];
+    T ox[NPT], oy[NPT], oz[NPT], val[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
-        const int q = threadIdx.x + r * blockDim.x;
-        ox[r] = oy[r] = oz[r] = T(0);
+        const int q = threadIdx.x + r * kThreads;
+        ox[r] = oy[r] = oz[r] = val[r] = T(0);
         if (q < Kstar) {
             const T o0 = node_off[3 * q], o1 = node_off[3 * q + 1], o2 = node_off[3 * q + 2];
             ox[r] = o0 * (T)fi[0] + o1 * (T)fi[3] + o2 * (T)fi[6];
@@ -346,95 +423,82 @@ __global__ __launch_bounds__(256) void k_l2t(int Kstar, const double* __restrict
             oz[r] = o0 * (T)fi[2] + o1 * (T)fi[5] + o2 * (T)fi[8];
         }
     }
+    // coefficients of the next grid, loaded into registers ahead of use
+    T pre[kPre];
+    auto fetch = [&](int g) {
+        const int q = g_nr[g] * g_nt[g];
+        const T* src = coef + g_off[g];
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) {
+            const int t = threadIdx.x + j * kThreads;
+            pre[j] = t < q ? src[t] : T(0);
+        }
+    };
+    int gn = l2t_grid[a0];
+    fetch(gn);
+    int buf = 0;
     for (int64_t aa = a0; aa < a1; ++aa) {
-        const int g = l2t_grid[aa];
-        const int nr = g_nr[g], nt = g_nt[g], q = nr * nt, half = nt / 2;
+        const int g = gn;
+#pragma unroll
+        for (int j = 0; j < kPre; ++j) cs[buf][threadIdx.x + j * kThreads] = pre[j];
+        __syncthreads();
+        if (aa + 1 < a1) {
+            gn = l2t_grid[aa + 1];
+            fetch(gn);
+        }
+        const int nr = g_nr[g], half = g_nt[g] / 2;
         const double* fg = g_frame + 9 * (int64_t)g;
-        __syncthreads();
-        for (int t = threadIdx.x; t < q; t += blockDim.x) cs[t] = coef[g_off[g] + t];
-        __syncthreads();
         const T dcx = (T)(fi[0] - fg[0]), dcy = (T)(fi[1] - fg[1]), dcz = (T)(fi[2] - fg[2]);
         const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
         const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
         const T cgx = (T)fg[0], cgy = (T)fg[1], cgz = (T)fg[2];
         const T invR = (T)(1.0 / g_R[g]);
-        // per node: polar coordinates about the grid's cap centre
-        T xs[NPT], ct[NPT], st[NPT], y2[NPT], t1e[NPT], t1o[NPT], val[NPT], ck[NPT], sk[NPT];
+        // polar coordinates of every node about the grid's cap centre
+        T xs[NPT], ct[NPT], st[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
             const T x1 = vx * e1x + vy * e1y + vz * e1z;
             const T x2 = vx * e2x + vy * e2y + vz * e2z;
             const T x3 = vx * cgx + vy * cgy + vz * cgz;
-            const T rh = sqrt(x1 * x1 + x2 * x2);
-            const T ang = atan2(rh, T(1) + x3);
-            T x = ang * invR;
-            x = x > T(1) ? T(1) : x;
-            xs[r] = x;
-            ct[r] = rh > T(0) ? x1 / rh : T(1);
-            st[r] = rh > T(0) ? x2 / rh : T(0);
-            // Chebyshev degrees of one parity: T_{2j}(x) = T_j(y), T_{2j+1} follow the
-            // same three-term recurrence in y = T_2(x) = 2 x^2 - 1
-            y2[r] = T(2) * (T(2) * x * x - T(1));
-            t1e[r] = T(2) * x * x - T(1);
-            t1o[r] = x * (T(4) * x * x - T(3));
-            val[r] = T(0);
-            ck[r] = T(1);
-            sk[r] = T(0);
+            const T s = x1 * x1 + x2 * x2;
+            const bool off_axis = s > T(0);
+            const T w = rsqrt_t<T>(off_axis ? s : T(1));
+            const T rh = off_axis ? s * w : T(0);
+            ct[r] = off_axis ? x1 * w : T(1);
+            st[r] = off_axis ? x2 * w : T(0);
+            const T x = atan2(rh, T(1) + x3) * invR;
+            xs[r] = x > T(1) ? T(1) : x;
         }
-        // every coefficient read from LDS serves all NPT nodes of the thread
-        for (int k = 0; k <= half; ++k) {
-            const bool odd = k & 1;
-            const bool has_sin = (k > 0 && k < half);
-            const T* cc = cs + k * nr;
-            const T* sc = cs + (half + k) * nr;
-            T tp[NPT], tc[NPT], rc[NPT], rs[NPT];
-            const T c0 = cc[0];
-            const T s0 = has_sin ? sc[0] : T(0);
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                tp[r] = odd ? xs[r] : T(1);  // degree parity
-                tc[r] = odd ? t1o[r] : t1e[r];  // degree parity + 2
-                rc[r] = c0 * tp[r];
-                rs[r] = s0 * tp[r];
-            }
-            if (has_sin) {
-                for (int np = 1; np < nr; ++np) {
-                    const T cv = cc[np], sv = sc[np];
-#pragma unroll
-                    for (int r = 0; r < NPT; ++r) {
-                        rc[r] += cv * tc[r];
-                        rs[r] += sv * tc[r];
-                        const T tn = y2[r] * tc[r] - tp[r];
-                        tp[r] = tc[r];
-                        tc[r] = tn;
-                    }
-                }
-            } else {
-                for (int np = 1; np < nr; ++np) {
-                    const T cv = cc[np];
-#pragma unroll
-                    for (int r = 0; r < NPT; ++r) {
-                        rc[r] += cv * tc[r];
-                        const T tn = y2[r] * tc[r] - tp[r];
-                        tp[r] = tc[r];
-                        tc[r] = tn;
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) {
-                val[r] += ck[r] * rc[r] + sk[r] * rs[r];
-                const T cn = ck[r] * ct[r] - sk[r] * st[r];
-                sk[r] = sk[r] * ct[r] + ck[r] * st[r];
-                ck[r] = cn;
-            }
+        const T* c = cs[buf];
+        static_assert(kMaxGridNr == 16, "one case per radial order");
+        switch (nr) {
+#define NCE_L2T_CASE(n) \
+    case n: l2t_sum<T, NPT, n>(c, half, xs, ct, st, val); break;
+            NCE_L2T_CASE(1) NCE_L2T_CASE(2) NCE_L2T_CASE(3) NCE_L2T_CASE(4)
+            NCE_L2T_CASE(5) NCE_L2T_CASE(6) NCE_L2T_CASE(7) NCE_L2T_CASE(8)
+#undef NCE_L2T_CASE
+            // long radial series (grids tighter than about 1e-9): one node at a
+            // time, so the Chebyshev values of all NPT nodes need not be live
+#define NCE_L2T_CASE(n)                                                       \
+    case n:                                                                   \
+        for (int r = 0; r < NPT; ++r) {                                       \
+            T x1[1] = {xs[r]}, c1[1] = {ct[r]}, s1[1] = {st[r]}, v1[1] = {val[r]}; \
+            l2t_sum<T, 1, n>(c, half, x1, c1, s1, v1);                        \
+            val[r] = v1[0];                                                   \
+        }                                                                     \
+        break;
+            NCE_L2T_CASE(9) NCE_L2T_CASE(10) NCE_L2T_CASE(11) NCE_L2T_CASE(12)
+            NCE_L2T_CASE(13) NCE_L2T_CASE(14) NCE_L2T_CASE(15) NCE_L2T_CASE(16)
+#undef NCE_L2T_CASE
+            default: break;
         }
+        buf ^= 1;
+    }
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            const int qn = threadIdx.x + r * blockDim.x;
-            if (qn < Kstar) U[(int64_t)i * Kstar + qn] += val[r];
-        }
+    for (int r = 0; r < NPT; ++r) {
+        const int qn = threadIdx.x + r * kThreads;
+        if (qn < Kstar) U[(int64_t)i * Kstar + qn] += val[r];
     }
 }
 
