@@ -25,7 +25,7 @@ import numpy as np  # noqa: E402
 import layouts  # noqa: E402
 
 # Green's function pair cost in lane-cycles: the VALU instructions of the P2L
-# inner loop (AMD assembly of this build, 4 pairs per iteration) priced at the
+# inner loop (AMD assembly of the compiled library, 4 pairs per iteration) priced at the
 # chip's issue rates -- FP64 add/mul/fma and 64-bit integer ops 1 (78.6 TFLOP/s
 # FP64 vector), 32-bit ops 0.5 (157.3 TFLOP/s FP32 vector), FP32
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
@@ -37,7 +37,7 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes per P2L launch at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels; None where not measured.
-TRAFFIC = {("cfg5", "fp64", 8): 9.112e9, ("cfg5", "fp32", 4): 4.828e9}
+TRAFFIC = {("cfg5", "fp64", 8): 9.112e9, ("cfg5", "fp32", 4): 4.380e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
@@ -200,6 +200,10 @@ def main():
     ap.add_argument("--quick-sequential", action="store_true",
                     help="batched workload: time 32 of the 256 single solves and scale")
     ap.add_argument("--tol-id", type=float, default=1e-11)
+    ap.add_argument("--tol-grid-fp32", type=float, default=None,
+                    help="grid tolerance of the FP32 applies (library default when omitted)")
+    ap.add_argument("--tol-id-fp32", type=float, default=None,
+                    help="outgoing-table tolerance of the FP32 applies (library default when omitted)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path.",
@@ -219,7 +223,8 @@ def main():
     far = nce.FAR_TREE if cfg["far"] == "tree" else nce.FAR_DIRECT
     prec = nce.FP64 if args.precision == "fp64" else nce.MIXED
     t0 = time.time()
-    ctx = nce.Context(centers, cfg["eps"], problem=cfg["problem"], tol_id=args.tol_id, far_field=far)
+    ctx = nce.Context(centers, cfg["eps"], problem=cfg["problem"], tol_id=args.tol_id, far_field=far,
+                      tol_grid_fp32=args.tol_grid_fp32, tol_id_fp32=args.tol_id_fp32)
     t_setup = time.time() - t0
     work = ctx.work(prec)
     log(f"setup {t_setup:.1f} s: K={ctx.K} K*={ctx.Kstar} p={ctx.p} levels={ctx.levels} work={work}")
@@ -257,12 +262,15 @@ def main():
         "config": {"workload": args.workload, "N": cfg["N"], "eps": cfg["eps"],
                    "problem": "interior" if cfg["problem"] == 0 else "exterior", "far_field": cfg["far"],
                    "K": ctx.K, "Kstar": ctx.Kstar, "p": ctx.p, "levels": ctx.levels, "tol_id": args.tol_id,
-                   "layout": cfg["layout"], "seed": cfg["seed"]},
+                   "layout": cfg["layout"], "seed": cfg["seed"],
+                   **({"tol_grid_fp32": args.tol_grid_fp32} if args.tol_grid_fp32 is not None else {}),
+                   **({"tol_id_fp32": args.tol_id_fp32} if args.tol_id_fp32 is not None else {})},
         "step_ms": {"block_apply": st[0], "far": st[1], "near": st[2], "interp": st[3], "p_apply": st[4]},
         "setup_s": t_setup, "autotuned_shapes": tuned,
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
                      "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
-                     "traffic": TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4)),
+                     "traffic": (TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4))
+                                 if args.tol_grid_fp32 is None and args.tol_id_fp32 is None else None),
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }
     if not args.no_solve:

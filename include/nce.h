@@ -79,10 +79,12 @@ typedef struct nce_opts {
     const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
     double tol_grid_fp32; /* grid tolerance of the FP32 applies (mixed solves): a second, coarser
                              set of incoming grids when it differs from tol_grid; 0 = tol_grid.
-                             Default 1e-6 (below the FP32 inner solve's 1e-5 target; the FP64
+                             Default 1e-5 (measured grid errors are about 0.04 of the tolerance,
+                             an order below the FP32 inner solve's 1e-5 target; the FP64
                              residuals always use tol_grid) */
     double tol_id_fp32;   /* ID tolerance of the outgoing representation used by the FP32 applies
-                             (mixed solves); 0 = tol_id. Default 1e-8 */
+                             (mixed solves); 0 = tol_id. Default 1e-7 (an order below the inner
+                             target; the FP64 residuals always use tol_id) */
 } nce_opts;
 
 typedef struct nce_info {

@@ -649,8 +649,8 @@ void nce_default_opts(nce_opts* o) {
     o->warm_start = 0;
     o->stream = nullptr;
     o->cache_dir = nullptr;
-    o->tol_grid_fp32 = 1e-6;
-    o->tol_id_fp32 = 1e-8;
+    o->tol_grid_fp32 = 1e-5;
+    o->tol_id_fp32 = 1e-7;
 }
 
 int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {
