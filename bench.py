@@ -31,13 +31,15 @@ import layouts  # noqa: E402
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
 # Keyed by (precision, problem, P2L grid points per thread).
-C_PAIR = {("fp64", 0, 4): 41.6, ("fp64", 0, 8): 41.3, ("fp64", 1, 4): 40.6, ("fp64", 1, 8): 40.3,
-          ("fp32", 0, 4): 9.4, ("fp32", 0, 8): 9.2, ("fp32", 1, 4): 8.9, ("fp32", 1, 8): 8.7}
+C_PAIR = {("fp64", 0, 4): 34.1, ("fp64", 0, 8): 34.1, ("fp64", 1, 4): 33.1, ("fp64", 1, 8): 33.1,
+          ("fp32", 0, 4): 9.1, ("fp32", 0, 8): 9.1, ("fp32", 1, 4): 8.6, ("fp32", 1, 8): 8.6}
+# shape 0: R = 4 or 8 per item by its grid size; both price the same
+C_PAIR.update({(p, b, 0): C_PAIR[(p, b, 4)] for p in ("fp64", "fp32") for b in (0, 1)})
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
-# HBM bytes per P2L launch at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
+# HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
-# current kernels; None where not measured.
-TRAFFIC = {("cfg5", "fp64", 8): 9.112e9, ("cfg5", "fp32", 4): 4.380e9}
+# current kernels. The bytes depend on the work items, not on the thread shape.
+TRAFFIC = {("cfg5", "fp64"): 8.642e9, ("cfg5", "fp32"): 4.085e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
@@ -269,7 +271,7 @@ def main():
         "setup_s": t_setup, "autotuned_shapes": tuned,
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
                      "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
-                     "traffic": (TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4))
+                     "traffic": (TRAFFIC.get((args.workload, ptag))
                                  if args.tol_grid_fp32 is None and args.tol_id_fp32 is None else None),
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }

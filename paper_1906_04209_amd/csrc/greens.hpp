@@ -4,13 +4,14 @@
 //   exterior  2/d - log(2/d) - log(1 + d/2) = w - log(1 + w)
 //   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
 //
-// FP64 logarithm (log64t): x = m 2^e with m in [1, 2); the top 7 mantissa bits
-// pick a table entry (r_k, -log r_k) with r_k the FP32-rounded reciprocal of
-// the bin centre, so u = m r_k - 1 (one fma, |u| < 2^-7.9) and
-// log x = e ln 2 - log r_k + log(1 + u), the last by its degree-7 series
-// (truncation below 1e-20). The table holds -log r_k as a double plus a float
-// correction, computed on the host in extended precision; kernels stage it in
-// LDS (2 KiB). Valid for positive normal arguments, which is all the kernels
+// FP64 logarithm (log64t): x = m 2^e with m in [1/2, 1); the top 7 bits of
+// the mantissa pick a table entry (2 r_k, -log(2 r_k)) with r_k the FP32-
+// rounded reciprocal of the bin centre of 2m, so u = m (2 r_k) - 1 (one fma,
+// |u| < 2^-7.9) and log x = e ln 2 - log(2 r_k) + log(1 + u), the last by its
+// degree-6 series (truncation below 2e-18 absolute). The table holds
+// -log(2 r_k) as a double pair, computed on the host in extended precision,
+// and 2 r_k as a double, so the kernels need no conversions; they stage it in
+// LDS (4 KiB). Valid for positive normal arguments, which is all the kernels
 // pass. Host builds of these functions serve the CPU accuracy test.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -20,10 +21,11 @@
 
 namespace nce {
 
-struct alignas(16) LogEntry {
-    double t_hi;  // -log r_k, leading part
-    float t_lo;   // -log r_k, correction
-    float r;      // r_k
+struct alignas(32) LogEntry {
+    double t_hi;  // -log(2 r_k), leading part
+    double t_lo;  // -log(2 r_k), correction
+    double r2;    // 2 r_k
+    double pad;
 };
 constexpr int kLogBits = 7;
 constexpr int kLogTab = 1 << kLogBits;
@@ -33,10 +35,11 @@ inline void build_log_table(LogEntry* tab) {
     for (int k = 0; k < kLogTab; ++k) {
         const long double c = 1.0L + (k + 0.5L) / kLogTab;
         const float r = (float)(1.0L / c);
-        const long double t = -std::log((long double)r);
+        const long double t = -std::log(2.0L * (long double)r);
         tab[k].t_hi = (double)t;
-        tab[k].t_lo = (float)(t - (long double)tab[k].t_hi);
-        tab[k].r = r;
+        tab[k].t_lo = (double)(t - (long double)tab[k].t_hi);
+        tab[k].r2 = 2.0 * (double)r;
+        tab[k].pad = 0.0;
     }
 }
 
@@ -44,20 +47,19 @@ __host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __re
     int e;
     double m;
 #if defined(__HIP_DEVICE_COMPILE__)
-    m = 2.0 * __builtin_amdgcn_frexp_mant(x);  // [1, 2)
-    e = __builtin_amdgcn_frexp_exp(x) - 1;
+    m = __builtin_amdgcn_frexp_mant(x);  // [1/2, 1)
+    e = __builtin_amdgcn_frexp_exp(x);
     const unsigned hi = (unsigned)__double2hiint(m);
 #else
-    m = 2.0 * std::frexp(x, &e);
-    e -= 1;
+    m = std::frexp(x, &e);
     unsigned long long bits;
     std::memcpy(&bits, &m, sizeof bits);
     const unsigned hi = (unsigned)(bits >> 32);
 #endif
-    const LogEntry L = tab[(hi >> (20 - kLogBits)) & (kLogTab - 1)];
-    const double u = fma(m, (double)L.r, -1.0);
-    double q = 1.0 / 7.0;
-    q = fma(q, u, -1.0 / 6.0);
+    // m and 2m share their mantissa bits: bin k of 2m in [1, 2)
+    const LogEntry& L = tab[(hi >> (20 - kLogBits)) & (kLogTab - 1)];
+    const double u = fma(m, L.r2, -1.0);
+    double q = -1.0 / 6.0;
     q = fma(q, u, 1.0 / 5.0);
     q = fma(q, u, -1.0 / 4.0);
     q = fma(q, u, 1.0 / 3.0);
@@ -67,12 +69,17 @@ __host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __re
     // ln 2 = hi + lo with hi exact to 2^-32 so that e * hi is exact for |e| < 2^21
     const double ln2_hi = 6.93147180369123816490e-01;
     const double ln2_lo = 1.90821492927058770002e-10;
-    return fma(de, ln2_hi, L.t_hi) + (fma(de, ln2_lo, (double)L.t_lo) + lp);
+    return fma(de, ln2_hi, L.t_hi) + (fma(de, ln2_lo, L.t_lo) + lp);
 }
 
+// 1/sqrt(x) for positive normal x: the hardware estimate and one
+// second-order correction y (1 + e/2 + 3e^2/8), e = 1 - x y^2 (no checks for
+// zero, infinity or denormals, which no kernel passes).
 __host__ __device__ __forceinline__ double rsqrt64(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return rsqrt(x);
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
 #else
     return 1.0 / std::sqrt(x);
 #endif

@@ -54,21 +54,31 @@ __global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_n
 }
 
 // ----------------------------------------------------------------- P2L
-// One block per work item (one grid, up to kSrcPerItem source patches). The
+// One block per work item (one grid and a run of its source patches). The
 // 256 threads are split into ns groups; each thread owns up to R grid points
 // (spaced qq = ceil(q/R) apart; R = 4 or 8, chosen by the autotuner) and takes
-// every ns-th staged source point, so small grids still keep every lane busy. The item's source skeleton points
-// (of the outgoing table its grid uses) and strengths are staged in LDS in
-// batches of kStage points, positions relative to the grid's cap centre. The
-// groups' partial sums are combined in LDS and written per item to `part`.
+// every ns-th staged source point, so small grids still keep every lane busy.
+// The item's source skeleton points (of the outgoing table its grid uses) and
+// strengths are staged in LDS in batches of kStage points, positions relative
+// to the grid's cap centre; every batch is padded with ns points of zero
+// strength so that all groups run the same number of iterations (loop control
+// on the scalar unit). The groups' partial sums are combined in LDS and
+// written per item to `part`.
 constexpr int kStage = 1024;
+constexpr int kStagePad = 64;  // >= the largest ns
+
+// floor(a / b) for 0 <= a < 2^21, 1 <= b < 2^12, by one reciprocal: the
+// quotient's fractional part is at least 0.5 / b away from the next integer,
+// far more than the reciprocal's error
+__device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
 template <int R>
 __device__ __forceinline__ void p2l_layout(int q, int& qq, int& ns, int& split, int& t0) {
     qq = (q + R - 1) / R;
-    ns = 256 / qq;
-    ns = ns < 1 ? 1 : (ns > 64 ? 64 : ns);
-    split = threadIdx.x / qq;
+    const float inv = __builtin_amdgcn_rcpf((float)qq);
+    ns = div_small(256, inv);
+    ns = ns < 1 ? 1 : (ns > kStagePad ? kStagePad : ns);
+    split = div_small((int)threadIdx.x, inv);
     t0 = threadIdx.x - split * qq;
 }
 
@@ -86,7 +96,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_list, const LogEntry* __restrict__ logtab) {
     // staging (kStage points of (x, y, z, rho), interleaved) and, after the
     // sums, the split partials (ns q <= 256 R)
-    __shared__ double4 smem4[kStage];
+    __shared__ double4 smem4[kStage + kStagePad];
     __shared__ LogEntry ltab[kLogTab];
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
@@ -115,25 +125,31 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     }
     const int s0 = it_src0[item];
     const int total = (it_src1[item] - s0) * pt;
+    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStage) {
         const int cl = min(kStage, total - c0);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cl; idx += blockDim.x) {
-            const int e = c0 + idx, js = e / pt, m = e - js * pt;
-            const int j = src[s0 + js];
-            const double* fj = frames + 9 * (int64_t)j;
-            const double* o = skel_off + 3 * (int64_t)(toff + m);
-            double4 v;
-            v.x = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
-            v.y = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
-            v.z = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
-            v.w = rho[(int64_t)j * ptot + toff + m];
+        for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
+            double4 v = make_double4(8.0, 8.0, 8.0, 0.0);  // padding: far away, zero strength
+            if (idx < cl) {
+                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
+                const int j = src[s0 + js];
+                const double* fj = frames + 9 * (int64_t)j;
+                const double* o = skel_off + 3 * (int64_t)(toff + m);
+                v.x = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
+                v.y = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
+                v.z = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
+                v.w = rho[(int64_t)j * ptot + toff + m];
+            }
             smem4[idx] = v;
         }
         __syncthreads();
+        // the same trip count for every group: points cl .. cl + ns - 1 are padding
+        const int nit = (cl + ns - 1) / ns;
         if (active) {
-            for (int m = split; m < cl; m += ns) {
-                const double4 a = smem4[m];
+            const double4* a_ptr = smem4 + split;
+            for (int it = 0; it < nit; ++it, a_ptr += ns) {
+                const double4 a = *a_ptr;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
@@ -173,7 +189,7 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_list) {
     // staging (kStage points of (x, y, z, rho), interleaved) and, after the
     // sums, the split partials (ns q <= 256 R doubles) share one buffer
-    __shared__ float4 smem4[kStage];
+    __shared__ float4 smem4[kStage + kStagePad];
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
@@ -202,31 +218,37 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
     constexpr float kLn2 = 0.69314718055994530942f;
     const int s0 = it_src0[item];
     const int total = (it_src1[item] - s0) * pt;
+    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStage) {
         const int cl = min(kStage, total - c0);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < cl; idx += blockDim.x) {
-            const int e = c0 + idx, js = e / pt, m = e - js * pt;
-            const int j = src[s0 + js];
-            const double* fj = frames + 9 * (int64_t)j;
-            const float* o = skel_off + 3 * (int64_t)(toff + m);
-            float4 v;
-            v.x = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
-            v.y = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
-            v.z = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
-            v.w = rho[(int64_t)j * ptot + toff + m];
+        for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
+            float4 v = make_float4(8.0f, 8.0f, 8.0f, 0.0f);  // padding: far away, zero strength
+            if (idx < cl) {
+                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
+                const int j = src[s0 + js];
+                const double* fj = frames + 9 * (int64_t)j;
+                const float* o = skel_off + 3 * (int64_t)(toff + m);
+                v.x = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
+                v.y = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
+                v.z = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
+                v.w = rho[(int64_t)j * ptot + toff + m];
+            }
             smem4[idx] = v;
         }
         __syncthreads();
+        // the same trip count for every group: points cl .. cl + ns - 1 are padding
+        const int nit = (cl + ns - 1) / ns;
         if (active) {
             // FP32 sums over at most 256 points, carried in FP64 between runs
-            for (int m0 = split; m0 < cl; m0 += 256 * ns) {
-                const int m1 = min(cl, m0 + 256 * ns);
+            const float4* a_ptr = smem4 + split;
+            for (int i0 = 0; i0 < nit; i0 += 256) {
+                const int i1 = min(nit, i0 + 256);
                 float aw[R], al[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) aw[r] = al[r] = 0.0f;
-                for (int m = m0; m < m1; m += ns) {
-                    const float4 a = smem4[m];
+                for (int it = i0; it < i1; ++it, a_ptr += ns) {
+                    const float4 a = *a_ptr;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const float dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;

@@ -329,8 +329,13 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         qoff += q;
         out.g_item0[g] = (int)out.it_grid.size();
         const std::vector<int>& s = grid_src[g];
-        for (size_t a = 0; a < s.size(); a += kSrcPerItem) {
-            const size_t e = std::min(s.size(), a + kSrcPerItem);
+        const int pg = out.g_table[g] == 0 ? p : tab.far[out.g_table[g] - 1].p;
+        // at least kSrcPerItem sources per item, more where the grid and its
+        // outgoing table are small, so that every item carries about
+        // kItemPairs pair evaluations or more
+        const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + (size_t)q * pg - 1) / ((size_t)q * pg));
+        for (size_t a = 0; a < s.size(); a += spi) {
+            const size_t e = std::min(s.size(), a + spi);
             out.it_grid.push_back(g);
             out.it_src0.push_back((int)(out.p2l_src.size() + a));
             out.it_src1.push_back((int)(out.p2l_src.size() + e));
@@ -339,7 +344,6 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         }
         out.p2l_src.insert(out.p2l_src.end(), s.begin(), s.end());
         out.g_item1[g] = (int)out.it_grid.size();
-        const int pg = out.g_table[g] == 0 ? p : tab.far[out.g_table[g] - 1].p;
         out.pairs_far += (double)s.size() * q * pg;
     }
     out.total_q = qoff;

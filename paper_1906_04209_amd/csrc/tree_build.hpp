@@ -31,7 +31,8 @@ namespace nce {
 constexpr int kMaxGridQ = 1024;   // grid points per incoming grid (4 per thread x 256)
 constexpr int kMaxGridNr = 16;
 constexpr int kMaxGridNt = 256;
-constexpr int kSrcPerItem = 32;   // source patches per P2L work item
+constexpr int kSrcPerItem = 32;   // source patches per P2L work item (at least)
+constexpr size_t kItemPairs = size_t(1) << 18;  // pair evaluations per P2L work item (at least)
 
 struct Tree {
     int nlevels = 0;
