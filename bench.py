@@ -31,15 +31,15 @@ import layouts  # noqa: E402
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
 # Keyed by (precision, problem, P2L grid points per thread).
-C_PAIR = {("fp64", 0, 4): 34.1, ("fp64", 0, 8): 34.1, ("fp64", 1, 4): 33.1, ("fp64", 1, 8): 33.1,
-          ("fp32", 0, 4): 9.1, ("fp32", 0, 8): 9.1, ("fp32", 1, 4): 8.6, ("fp32", 1, 8): 8.6}
-# shape 0: R = 4 or 8 per item by its grid size; both price the same
-C_PAIR.update({(p, b, 0): C_PAIR[(p, b, 4)] for p in ("fp64", "fp32") for b in (0, 1)})
+C_PAIR = {("fp64", 0, 4): 31.3, ("fp64", 0, 8): 31.1, ("fp64", 1, 4): 30.3, ("fp64", 1, 8): 30.1,
+          ("fp32", 0, 4): 8.25, ("fp32", 0, 8): 8.1, ("fp32", 1, 4): 7.75, ("fp32", 1, 8): 7.6}
+# shape 0 runs R = 4 and R = 8 launches; priced at the cheaper of the two (the higher ceiling)
+C_PAIR.update({(p, b, 0): min(C_PAIR[(p, b, 4)], C_PAIR[(p, b, 8)]) for p in ("fp64", "fp32") for b in (0, 1)})
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels. The bytes depend on the work items, not on the thread shape.
-TRAFFIC = {("cfg5", "fp64"): 8.642e9, ("cfg5", "fp32"): 4.085e9}
+TRAFFIC = {}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {

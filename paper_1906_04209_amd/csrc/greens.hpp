@@ -5,14 +5,16 @@
 //   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
 //
 // FP64 logarithm (log64t): x = m 2^e with m in [1/2, 1); the top 7 bits of
-// the mantissa pick a table entry (2 r_k, -log(2 r_k)) with r_k the FP32-
-// rounded reciprocal of the bin centre of 2m, so u = m (2 r_k) - 1 (one fma,
-// |u| < 2^-7.9) and log x = e ln 2 - log(2 r_k) + log(1 + u), the last by its
-// degree-6 series (truncation below 2e-18 absolute). The table holds
-// -log(2 r_k) as a double pair, computed on the host in extended precision,
-// and 2 r_k as a double, so the kernels need no conversions; they stage it in
-// LDS (4 KiB). Valid for positive normal arguments, which is all the kernels
-// pass. Host builds of these functions serve the CPU accuracy test.
+// the mantissa pick a table entry (2 r_k, -log(2 r_k)) and u = m (2 r_k) - 1
+// (one fma, |u| < 2^-7.9), so log x = e ln 2 - log(2 r_k) + log(1 + u), the
+// last by its degree-6 series (truncation below 3e-18 absolute). r_k is an
+// FP32 number within 2^-14 of the reciprocal of the bin centre of 2m, chosen
+// (the accurate-tables idea of Gal's method) so that -log(2 r_k) lies within
+// about 2^-62 of a double: one double then carries it, and an entry is 16
+// bytes read by one LDS instruction. The table is built on the host in
+// extended precision; kernels stage it in LDS (2 KiB). Valid for positive
+// normal arguments, which is all the kernels pass. Host builds of these
+// functions serve the CPU accuracy test.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,25 +23,34 @@
 
 namespace nce {
 
-struct alignas(32) LogEntry {
-    double t_hi;  // -log(2 r_k), leading part
-    double t_lo;  // -log(2 r_k), correction
-    double r2;    // 2 r_k
-    double pad;
+struct alignas(16) LogEntry {
+    double t;   // -log(2 r_k), within about 2^-62 relative of the exact value
+    double r2;  // 2 r_k
 };
 constexpr int kLogBits = 7;
 constexpr int kLogTab = 1 << kLogBits;
 
-// Host: fills the kLogTab entries (extended-precision logarithms).
+// Host: fills the kLogTab entries. For each bin, among the FP32 numbers within
+// 2^-14 of 1 / (bin centre), takes the one whose -log(2 r) is closest (in
+// extended precision) to its own double rounding.
 inline void build_log_table(LogEntry* tab) {
     for (int k = 0; k < kLogTab; ++k) {
         const long double c = 1.0L + (k + 0.5L) / kLogTab;
-        const float r = (float)(1.0L / c);
-        const long double t = -std::log(2.0L * (long double)r);
-        tab[k].t_hi = (double)t;
-        tab[k].t_lo = (double)(t - (long double)tab[k].t_hi);
-        tab[k].r2 = 2.0 * (double)r;
-        tab[k].pad = 0.0;
+        const float r0 = (float)(1.0L / c);
+        float best = r0;
+        long double best_err = 1.0L;
+        float r = r0;
+        for (int j = 0; j < 512; ++j) r = std::nextafter(r, 0.0f);
+        for (int j = -512; j <= 512; ++j, r = std::nextafter(r, 2.0f)) {
+            const long double t = -std::log(2.0L * (long double)r);
+            const long double err = std::fabs(t - (long double)(double)t) / std::fabs(t);
+            if (err < best_err) {
+                best_err = err;
+                best = r;
+            }
+        }
+        tab[k].t = (double)(-std::log(2.0L * (long double)best));
+        tab[k].r2 = 2.0 * (double)best;
     }
 }
 
@@ -69,7 +80,7 @@ __host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __re
     // ln 2 = hi + lo with hi exact to 2^-32 so that e * hi is exact for |e| < 2^21
     const double ln2_hi = 6.93147180369123816490e-01;
     const double ln2_lo = 1.90821492927058770002e-10;
-    return fma(de, ln2_hi, L.t_hi) + (fma(de, ln2_lo, L.t_lo) + lp);
+    return fma(de, ln2_hi, L.t) + fma(de, ln2_lo, lp);
 }
 
 // 1/sqrt(x) for positive normal x: the hardware estimate and one

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_n
 // on the scalar unit). The groups' partial sums are combined in LDS and
 // written per item to `part`.
 constexpr int kStage = 1024;
+constexpr int kStage64 = 768;  // FP64: 40 bytes per staged point
 constexpr int kStagePad = 64;  // >= the largest ns
 
 // floor(a / b) for 0 <= a < 2^21, 1 <= b < 2^12, by one reciprocal: the
@@ -94,9 +95,11 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
                                                const int* __restrict__ it_list, const LogEntry* __restrict__ logtab) {
-    // staging (kStage points of (x, y, z, rho), interleaved) and, after the
-    // sums, the split partials (ns q <= 256 R)
-    __shared__ double4 smem4[kStage + kStagePad];
+    // staging (kStage64 points: (-2 a, |a|^2) with a the half-scaled offset
+    // from the cap centre, and the strengths) and, after the sums, the split
+    // partials (ns q <= 256 R)
+    __shared__ double4 smem4[kStage64 + kStagePad];
+    __shared__ double srho[kStage64 + kStagePad];
     __shared__ LogEntry ltab[kLogTab];
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    double zx[R], zy[R], zz[R], acc[R];
+    double zx[R], zy[R], zz[R], z2[R], acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int t = t0 + r * qq;
@@ -122,38 +125,48 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             zy[r] = z[1];
             zz[r] = z[2];
         }
+        z2[r] = zx[r] * zx[r] + zy[r] * zy[r] + zz[r] * zz[r];
     }
     const int s0 = it_src0[item];
     const int total = (it_src1[item] - s0) * pt;
     const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
-    for (int c0 = 0; c0 < total; c0 += kStage) {
-        const int cl = min(kStage, total - c0);
+    for (int c0 = 0; c0 < total; c0 += kStage64) {
+        const int cl = min(kStage64, total - c0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
-            double4 v = make_double4(8.0, 8.0, 8.0, 0.0);  // padding: far away, zero strength
+            double ax = 8.0, ay = 8.0, az = 8.0, w = 0.0;  // padding: far away, zero strength
             if (idx < cl) {
                 const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
                 const int j = src[s0 + js];
                 const double* fj = frames + 9 * (int64_t)j;
                 const double* o = skel_off + 3 * (int64_t)(toff + m);
-                v.x = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
-                v.y = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
-                v.z = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
-                v.w = rho[(int64_t)j * ptot + toff + m];
+                ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
+                ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
+                az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
+                w = rho[(int64_t)j * ptot + toff + m];
             }
-            smem4[idx] = v;
+            // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a: grid points lie within the cap
+            // and sources at least a cap radius beyond it, so the cancellation
+            // costs at most a factor 5 in relative rounding
+            smem4[idx] = make_double4(-2.0 * ax, -2.0 * ay, -2.0 * az, ax * ax + ay * ay + az * az);
+            srho[idx] = w;
         }
         __syncthreads();
         // the same trip count for every group: points cl .. cl + ns - 1 are padding
         const int nit = (cl + ns - 1) / ns;
         if (active) {
             const double4* a_ptr = smem4 + split;
-            for (int it = 0; it < nit; ++it, a_ptr += ns) {
+            const double* w_ptr = srho + split;
+            // two points per pass: the second reads are in flight while the
+            // first point is summed
+#pragma unroll 2
+            for (int it = 0; it < nit; ++it, a_ptr += ns, w_ptr += ns) {
                 const double4 a = *a_ptr;
+                const double w = *w_ptr;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const double dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
-                    acc[r] += green64_half<PROB>(dx * dx + dy * dy + dz * dz, ltab) * a.w;
+                    const double h2 = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
+                    acc[r] += green64_half<PROB>(h2, ltab) * w;
                 }
             }
         }
@@ -187,9 +200,11 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const float* __restrict__ gpt,
                                                const int* __restrict__ it_list) {
-    // staging (kStage points of (x, y, z, rho), interleaved) and, after the
-    // sums, the split partials (ns q <= 256 R doubles) share one buffer
+    // staging (kStage points: (-2 a, |a|^2) with a the half-scaled offset from
+    // the cap centre, and the strengths) and, after the sums, the split
+    // partials (ns q <= 256 R doubles, in smem4)
     __shared__ float4 smem4[kStage + kStagePad];
+    __shared__ float srho[kStage + kStagePad];
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
@@ -200,7 +215,7 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    float zx[R], zy[R], zz[R];
+    float zx[R], zy[R], zz[R], z2[R];
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -214,6 +229,7 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
             zy[r] = z[1];
             zz[r] = z[2];
         }
+        z2[r] = zx[r] * zx[r] + zy[r] * zy[r] + zz[r] * zz[r];
     }
     constexpr float kLn2 = 0.69314718055994530942f;
     const int s0 = it_src0[item];
@@ -223,18 +239,21 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
         const int cl = min(kStage, total - c0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
-            float4 v = make_float4(8.0f, 8.0f, 8.0f, 0.0f);  // padding: far away, zero strength
+            float ax = 8.0f, ay = 8.0f, az = 8.0f, w = 0.0f;  // padding: far away, zero strength
             if (idx < cl) {
                 const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
                 const int j = src[s0 + js];
                 const double* fj = frames + 9 * (int64_t)j;
                 const float* o = skel_off + 3 * (int64_t)(toff + m);
-                v.x = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
-                v.y = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
-                v.z = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
-                v.w = rho[(int64_t)j * ptot + toff + m];
+                ax = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
+                ay = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
+                az = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
+                w = rho[(int64_t)j * ptot + toff + m];
             }
-            smem4[idx] = v;
+            // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a (cancellation at most a factor 5,
+            // as in the FP64 kernel)
+            smem4[idx] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
+            srho[idx] = w;
         }
         __syncthreads();
         // the same trip count for every group: points cl .. cl + ns - 1 are padding
@@ -242,20 +261,22 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
         if (active) {
             // FP32 sums over at most 256 points, carried in FP64 between runs
             const float4* a_ptr = smem4 + split;
+            const float* w_ptr = srho + split;
             for (int i0 = 0; i0 < nit; i0 += 256) {
                 const int i1 = min(nit, i0 + 256);
                 float aw[R], al[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) aw[r] = al[r] = 0.0f;
-                for (int it = i0; it < i1; ++it, a_ptr += ns) {
+                for (int it = i0; it < i1; ++it, a_ptr += ns, w_ptr += ns) {
                     const float4 a = *a_ptr;
+                    const float sw = *w_ptr;
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        const float dx = zx[r] - a.x, dy = zy[r] - a.y, dz = zz[r] - a.z;
+                        const float h2 = fmaf(zx[r], a.x, fmaf(zy[r], a.y, fmaf(zz[r], a.z, a.w))) + z2[r];
                         float w, l2;
-                        green32_parts_half<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
-                        aw[r] += w * a.w;
-                        al[r] += l2 * a.w;
+                        green32_parts_half<PROB>(h2, w, l2);
+                        aw[r] += w * sw;
+                        al[r] += l2 * sw;
                     }
                 }
 #pragma unroll
