@@ -311,9 +311,16 @@ def main():
         for k in list(out):
             if k.startswith("solve_") and k != "solve_fp64":
                 out[k][f"rel_diff_{key}_vs_fp64"] = abs(out[k][key] - ref) / abs(ref)
-        best = "mixed_learned" if "mixed_learned" in times else "mixed_coarse"
-        out["time_to_1e-8_s"] = dict(times, speedup_mixed_vs_fp64=times["fp64"] / times["mixed"],
-                                     **{f"speedup_{best}_vs_fp64": times["fp64"] / times[best]})
+        # a start's per-layout preprocessing is part of its time to solution:
+        # the coarse solve for both starts, the features and network as well
+        # for the learned one
+        pre = {"": 0.0, "_coarse": prep.get("coarse", 0.0),
+               "_learned": prep.get("coarse", 0.0) + prep.get("learned", 0.0)}
+        total = {k: v + pre["_" + k.split("_", 1)[1] if "_" in k else ""] for k, v in times.items()}
+        best = min((k for k in total if k.startswith("mixed")), key=lambda k: total[k])
+        out["time_to_1e-8_s"] = dict(total, speedup_mixed_vs_fp64=total["fp64"] / total["mixed"],
+                                     best=best, **{"speedup_best_vs_fp64": total["fp64"] / total[best]})
+        out["solve_only_s"] = times
         out["start_preprocessing_s"] = prep
     if not args.no_cpu_baseline:
         cb, rows, yref = cpu_baseline(cfg, args.tol_id, x_np, centers)

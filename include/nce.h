@@ -85,6 +85,10 @@ typedef struct nce_opts {
     double tol_id_fp32;   /* ID tolerance of the outgoing representation used by the FP32 applies
                              (mixed solves); 0 = tol_id. Default 1e-7 (an order below the inner
                              target; the FP64 residuals always use tol_id) */
+    double tol_coarse;    /* relative residual to which the coarse (monopole) solve of the initial
+                             guess is taken (nce_set_warm_start, nce_coarse_solve); in (0, 0.1).
+                             Default 1e-5 (the guess's own residual is set by the monopole
+                             model, near 5e-4 at N = 1e5; tighter solves do not improve it) */
 } nce_opts;
 
 typedef struct nce_info {

@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double),
-                ("tol_id_fp32", ctypes.c_double)]
+                ("tol_id_fp32", ctypes.c_double), ("tol_coarse", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -227,7 +227,7 @@ class Context:
                  tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
                  max_iter: int = 100, precision: int = FP64, far_field: int = FAR_AUTO,
                  cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
-                 tol_id_fp32: Optional[float] = None):
+                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -241,6 +241,8 @@ class Context:
             o.tol_grid_fp32 = tol_grid_fp32
         if tol_id_fp32 is not None:
             o.tol_id_fp32 = tol_id_fp32
+        if tol_coarse is not None:
+            o.tol_coarse = tol_coarse
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         # the library works on its own (non-default) stream; calls below order
         # it against the caller's current stream in both directions
@@ -389,7 +391,7 @@ class Batch:
     def __init__(self, configs, M: int = 15, tol_id: float = 1e-11, tol_grid: float = 1e-8,
                  tol_gmres: float = 1e-10, max_iter: int = 60, precision: int = MIXED, far_field: int = FAR_AUTO,
                  cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
-                 tol_id_fp32: Optional[float] = None):
+                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -408,6 +410,8 @@ class Batch:
             o.tol_grid_fp32 = tol_grid_fp32
         if tol_id_fp32 is not None:
             o.tol_id_fp32 = tol_id_fp32
+        if tol_coarse is not None:
+            o.tol_coarse = tol_coarse
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         self.stream = stream if stream is not None else torch.cuda.Stream()
         o.stream = ctypes.c_void_p(self.stream.cuda_stream)

@@ -161,7 +161,7 @@ const double* coarse_amplitudes(nce_ctx* ctx) {
     if (!ctx->coarse)
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
     ctx->d_a.alloc((size_t)ctx->N);
-    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, (int)ctx->N, ctx->d_frames.p, 1e-6, ctx->d_a.p);
+    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, (int)ctx->N, ctx->d_frames.p, ctx->opts.tol_coarse, ctx->d_a.p);
     return ctx->d_a.p;
 }
 
@@ -457,6 +457,7 @@ int validate_opts(const nce_opts& o, double eps) {
         return fail(NCE_EINVAL, "tol_grid_fp32 must be 0 or lie in (0, 1e-2)");
     if (!(o.tol_id_fp32 == 0.0 || (o.tol_id_fp32 > 0 && o.tol_id_fp32 < 1e-3)))
         return fail(NCE_EINVAL, "tol_id_fp32 must be 0 or lie in (0, 1e-3)");
+    if (!(o.tol_coarse > 0 && o.tol_coarse < 0.1)) return fail(NCE_EINVAL, "tol_coarse must lie in (0, 0.1)");
     if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
     if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
     if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
@@ -651,6 +652,7 @@ void nce_default_opts(nce_opts* o) {
     o->cache_dir = nullptr;
     o->tol_grid_fp32 = 1e-5;
     o->tol_id_fp32 = 1e-7;
+    o->tol_coarse = 1e-5;
 }
 
 int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {

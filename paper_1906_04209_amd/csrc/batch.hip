@@ -449,7 +449,7 @@ void batch_coarse(nce_batch* bt) {
         nce::CoarseSolver cs((int)nmax, c->tab.problem, chi0, 80);
         for (size_t q = 0; q + 1 < c->cfg_first.size(); ++q) {
             const int64_t f0 = c->cfg_first[q], nc = c->cfg_first[q + 1] - f0;
-            cs.solve(s, (int)nc, c->d_frames.p + 9 * f0, 1e-6, bt->g_a[g].p + f0);
+            cs.solve(s, (int)nc, c->d_frames.p + 9 * f0, c->opts.tol_coarse, bt->g_a[g].p + f0);
         }
     }
     bt->have_a = true;

@@ -50,7 +50,7 @@ def test_coarse_solve_satisfies_its_equations(torch):
     from oracle import greens
     for prob, N, eps, seed in ((nce.INTERIOR, 300, 0.02, 3), (nce.EXTERIOR, 700, 0.01, 4)):
         c = layouts.uniform_centers(N, eps, seed)
-        ctx = nce.Context(c, eps, problem=prob, tol_id=1e-11)
+        ctx = nce.Context(c, eps, problem=prob, tol_id=1e-11, tol_coarse=1e-6)
         a, iters, chi0 = ctx.coarse(with_chi0=True)
         a = a.cpu().numpy()
         d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=-1)

@@ -80,3 +80,69 @@ def test_forest_coverage(forest_exe, tmp_path):
     r = subprocess.run([str(forest_exe), str(f), repr(eps), "1e-8"], capture_output=True, text=True)
     print(r.stdout)
     assert r.returncode == 0 and r.stdout.startswith("OK"), r.stdout + r.stderr
+
+
+@pytest.fixture(scope="module")
+def features_exe(tmp_path_factory):
+    d = tmp_path_factory.mktemp("features")
+    out = d / "features_check"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", str(ROOT / "tests" / "host" / "features_check.cpp"),
+                           str(CSRC / "features.cpp"), "-o", str(out)])
+    return out
+
+
+def _frames(c):
+    """Orthonormal tangent frames (c, e1, e2) per centre."""
+    a = np.where(np.abs(c[:, 2:3]) > 1 / np.sqrt(2), [[1.0, 0.0, 0.0]], [[0.0, 0.0, 1.0]])
+    e1 = a - np.sum(a * c, axis=1, keepdims=True) * c
+    e1 /= np.linalg.norm(e1, axis=1, keepdims=True)
+    e2 = np.cross(c, e1)
+    return np.concatenate([c, e1, e2], axis=1)
+
+
+def _features_brute(fr, eps, problem, a):
+    """The feature definition written out by brute force over all pairs."""
+    N = len(fr)
+    c = fr[:, :3]
+    cr = np.linalg.norm(np.cross(c[:, None, :], c[None, :, :]), axis=-1)
+    geo = np.arctan2(cr, c @ c.T)
+    np.fill_diagonal(geo, np.inf)
+    out = np.zeros((N, 56))
+    area = N * np.sin(0.5 * eps) ** 2
+    for i in range(N):
+        nb = np.argsort(geo[i], kind="stable")[:16]
+        d = c[nb] - c[i]
+        out[i, 0:48:3] = (d @ fr[i, 3:6]) / eps / 16.0
+        out[i, 1:48:3] = (d @ fr[i, 6:9]) / eps / 16.0
+        out[i, 2:48:3] = 4.0 / (geo[i, nb] / eps)
+        out[i, 48] = problem
+        out[i, 49] = 10.0 * area
+        for q, R in enumerate((8 * eps, 16 * eps, 32 * eps, 64 * eps)):
+            R = min(R, np.pi)
+            out[i, 50 + q] = np.sum(geo[i] <= R) / max((N - 1) * 0.5 * (1 - np.cos(R)), 1e-12)
+        out[i, 54] = 10.0 * (a[i] / a.mean() - 1.0)
+        out[i, 55] = a.mean()
+    return out
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered"])
+def test_features_match_brute_force(features_exe, tmp_path, kind):
+    """Grid-accelerated neighbour features equal the all-pairs definition."""
+    eps, prob = 0.01, 1
+    if kind == "uniform":
+        c = layouts.uniform_centers(500, eps, 31)
+    else:
+        c = layouts.vmf_centers(500, eps, 32)
+    fr = _frames(c)
+    a = 1.0 + 0.1 * np.random.default_rng(5).standard_normal(len(c))
+    f = tmp_path / "in.txt"
+    with open(f, "w") as fh:
+        fh.write(f"{len(c)} {eps!r} {prob}\n")
+        np.savetxt(fh, fr, fmt="%.17g")
+        np.savetxt(fh, a, fmt="%.17g")
+    r = subprocess.run([str(features_exe), str(f)], capture_output=True, text=True, check=True)
+    got = np.loadtxt(r.stdout.splitlines())
+    ref = _features_brute(fr, eps, prob, a)
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    print(f"{kind}: N={len(c)} max rel err {err.max():.2e}")
+    assert err.max() < 1e-5
