@@ -39,7 +39,7 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels. The bytes depend on the work items, not on the thread shape.
-TRAFFIC = {}
+TRAFFIC = {("cfg5", "fp64"): 8.595e9, ("cfg5", "fp32"): 4.966e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
