@@ -275,6 +275,21 @@ def main():
                                  if args.tol_grid_fp32 is None and args.tol_id_fp32 is None else None),
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }
+    out["median_ms_per_step_events"] = float(np.median([m.sum() for m in steps_ms]))
+    if prec == nce.FP64 and far == nce.FAR_TREE:
+        # the FP32 apply of the mixed solves, timed after the FP64 line (same
+        # vector, its own autotuned shapes), not part of the timed region above
+        tuned32 = ctx.autotune(nce.MIXED)
+        for _ in range(max(args.warmup, 1)):
+            ctx.matvec_profile(x, y, nce.MIXED)
+        ms32 = [ctx.matvec_profile(x, y, nce.MIXED)[1] for _ in range(max(args.steps, 3))]
+        st32 = np.mean(np.array(ms32), axis=0)
+        out["fp32_apply"] = {"ms_per_step": float(st32.sum()), "matvec_per_s": 1e3 / float(st32.sum()),
+                             "median_ms": float(np.median([m.sum() for m in ms32])),
+                             "step_ms": {"block_apply": st32[0], "far": st32[1], "near": st32[2],
+                                         "interp": st32[3], "p_apply": st32[4]},
+                             "autotuned_shapes": tuned32, "work": ctx.work(nce.MIXED)}
+        log(f"FP32 apply: {st32.sum():.2f} ms {np.round(st32, 3).tolist()}")
     if not args.no_solve:
         # time to a 1e-8 relative residual (FP64-verified): from x0 = 0, from the
         # coarse (monopole) solve, and from the coarse solve refined by the

@@ -74,19 +74,36 @@ __global__ __launch_bounds__(256) void k_coarse_sum(int N, const float4* __restr
         float aw[kTgt], al[kTgt];
 #pragma unroll
         for (int r = 0; r < kTgt; ++r) aw[r] = al[r] = 0.0f;
-        for (int k = 0; k < tl; ++k) {
-            const float4 s = tile[k];
+        // only a tile that holds some of this block's targets can meet a
+        // target itself; every other tile skips the check
+        const bool overlap = t0 < i0 + 256 * kTgt && i0 < t0 + tl;
+        if (overlap) {
+            for (int k = 0; k < tl; ++k) {
+                const float4 s = tile[k];
 #pragma unroll
-            for (int r = 0; r < kTgt; ++r) {
-                const float dx = tx[r] - s.x, dy = ty[r] - s.y, dz = tz[r] - s.z;
-                const float h2 = dx * dx + dy * dy + dz * dz;
-                // the target itself (h2 = 0) contributes nothing
-                const bool self = !(h2 > 0.0f);
-                float w, l2;
-                green32_parts_half<PROB>(self ? 1.0f : h2, w, l2);
-                const float q = self ? 0.0f : s.w;
-                aw[r] += w * q;
-                al[r] += l2 * q;
+                for (int r = 0; r < kTgt; ++r) {
+                    const float dx = tx[r] - s.x, dy = ty[r] - s.y, dz = tz[r] - s.z;
+                    const float h2 = dx * dx + dy * dy + dz * dz;
+                    // the target itself (h2 = 0) contributes nothing
+                    const bool self = !(h2 > 0.0f);
+                    float w, l2;
+                    green32_parts_half<PROB>(self ? 1.0f : h2, w, l2);
+                    const float q = self ? 0.0f : s.w;
+                    aw[r] += w * q;
+                    al[r] += l2 * q;
+                }
+            }
+        } else {
+            for (int k = 0; k < tl; ++k) {
+                const float4 s = tile[k];
+#pragma unroll
+                for (int r = 0; r < kTgt; ++r) {
+                    const float dx = tx[r] - s.x, dy = ty[r] - s.y, dz = tz[r] - s.z;
+                    float w, l2;
+                    green32_parts_half<PROB>(dx * dx + dy * dy + dz * dz, w, l2);
+                    aw[r] += w * s.w;
+                    al[r] += l2 * s.w;
+                }
             }
         }
 #pragma unroll
