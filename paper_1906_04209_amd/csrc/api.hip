@@ -277,8 +277,12 @@ int gmres(nce_ctx* ctx, const double* rhs, double* x, double tol, int maxit, int
         double* w = V + (int64_t)(k + 1) * n;
         matvec(ctx, V + (int64_t)k * n, w, precision);
         used++;
-        // classical Gram-Schmidt, twice
-        for (int pass = 0; pass < 2; ++pass) {
+        // classical Gram-Schmidt on FP64 vectors: twice for the FP64 solves;
+        // once for the FP32 inner solves of the mixed form, whose 1e-5 target
+        // is far above the orthogonality lost in one FP64 pass
+        const int passes = precision == NCE_MIXED ? 1 : 2;
+        std::fill(h2.begin(), h2.end(), 0.0);
+        for (int pass = 0; pass < passes; ++pass) {
             HIPCHK(nce::dots(s, n, k + 1, V, n, w, ctx->d_partial.p, ctx->d_h.p));
             HIPCHK(nce::axpys(s, n, k + 1, V, n, ctx->d_h.p, w));
             HIPCHK(hipMemcpyAsync(pass == 0 ? h.data() : h2.data(), ctx->d_h.p, sizeof(double) * (k + 1),

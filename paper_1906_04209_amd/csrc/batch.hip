@@ -122,7 +122,8 @@ __global__ void k_copy_vj(const double* __restrict__ V, int64_t ldv, const int* 
 }
 
 // One Givens step per active configuration s at Krylov index j = *jdev.
-// Column of the Hessenberg matrix: h1 + h2 (the two Gram-Schmidt passes),
+// Column of the Hessenberg matrix: h1 + h2 (the two Gram-Schmidt passes; h2
+// null after a single pass),
 // subdiagonal sqrt(nrm2). Rotations cs/sn (nseg x maxit), triangular factor R
 // (nseg x maxit x maxit), right-hand side g (nseg x (maxit + 1)).
 __global__ void k_givens(int nseg, const int* __restrict__ jdev, const double* __restrict__ h1,
@@ -138,7 +139,8 @@ __global__ void k_givens(int nseg, const int* __restrict__ jdev, const double* _
     double* css = cs + (int64_t)s * maxit;
     double* sns = sn + (int64_t)s * maxit;
     double* gs = g + (int64_t)s * (maxit + 1);
-    for (int v = 0; v <= j; ++v) Rs[(int64_t)v * maxit + j] = h1[(int64_t)s * ldh + v] + h2[(int64_t)s * ldh + v];
+    for (int v = 0; v <= j; ++v)
+        Rs[(int64_t)v * maxit + j] = h1[(int64_t)s * ldh + v] + (h2 ? h2[(int64_t)s * ldh + v] : 0.0);
     const double hk1 = sqrt(fmax(nrm2[(int64_t)s * ldh], 0.0));
     for (int v = 0; v < j; ++v) {
         const double a = Rs[(int64_t)v * maxit + j], b = Rs[(int64_t)(v + 1) * maxit + j];
@@ -335,7 +337,11 @@ void arnoldi_step(nce_batch* bt, int precision) {
     hipLaunchKernelGGL(k_copy_vj, grid_for(bt->n), dim3(256), 0, s, V, ldv, bt->d_j.p, bt->n, bt->d_xin.p);
     // configurations that have converged (active = 0) skip their sums
     batch_matvec(bt, bt->d_xin.p, bt->d_w.p, precision, bt->d_active.p);
-    for (int pass = 0; pass < 2; ++pass) {
+    // classical Gram-Schmidt twice for FP64, once for the FP32 inner solves of
+    // the mixed form (their 1e-5 target is far above the orthogonality lost in
+    // one pass over FP64 vectors)
+    const int passes = precision == NCE_MIXED ? 1 : 2;
+    for (int pass = 0; pass < passes; ++pass) {
         double* h = pass == 0 ? bt->d_h1.p : bt->d_h2.p;
         hipLaunchKernelGGL(k_seg_dots, dim3(bt->nch), dim3(256), 0, s, V, ldv, bt->d_w.p, bt->d_j.p, 1,
                            bt->d_ch_e0.p, bt->d_ch_seg.p, bt->d_active.p, bt->d_partial.p, ldp);
@@ -348,7 +354,8 @@ void arnoldi_step(nce_batch* bt, int precision) {
                        (const int*)nullptr, 1, bt->d_ch_e0.p, bt->d_ch_seg.p, bt->d_active.p, bt->d_partial.p, ldp);
     hipLaunchKernelGGL(k_seg_reduce, dim3(bt->B), dim3(128), 0, s, bt->d_partial.p, ldp, bt->d_seg_ch.p,
                        (const int*)nullptr, 1, bt->d_active.p, bt->d_nrm.p, ldp);
-    hipLaunchKernelGGL(k_givens, dim3((bt->B + 63) / 64), dim3(64), 0, s, bt->B, bt->d_j.p, bt->d_h1.p, bt->d_h2.p,
+    hipLaunchKernelGGL(k_givens, dim3((bt->B + 63) / 64), dim3(64), 0, s, bt->B, bt->d_j.p, bt->d_h1.p,
+                       passes == 2 ? (const double*)bt->d_h2.p : (const double*)nullptr,
                        ldp, bt->d_nrm.p, bt->d_beta.p, bt->d_tol.p, bt->maxit, bt->d_active.p, bt->d_R.p,
                        bt->d_cs.p, bt->d_sn.p, bt->d_g.p, bt->d_mused.p, bt->d_est.p, bt->d_invh.p);
     hipLaunchKernelGGL(k_seg_scale, dim3(bt->nch), dim3(256), 0, s, bt->d_w.p, bt->d_invh.p, bt->d_ch_e0.p,

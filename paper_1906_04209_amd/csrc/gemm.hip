@@ -62,13 +62,17 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int m, int n, int k, const T*
             for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
     const int lr = lane % 16, lk = lane / 16;
     for (int k0 = 0; k0 < k; k0 += 16) {
+        // consecutive threads walk the operand's contiguous index (k when the
+        // k stride is 1, the row or column otherwise) so that loads coalesce
+        const bool a_k = sak == 1, b_k = sbk == 1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int idx = threadIdx.x + 256 * r;  // 0..1023
-            const int row = idx % 64, kk = idx / 64;
-            const int gi = i0 + row, gk = k0 + kk, gj = j0 + row;
-            As[kk][row] = (gi < m && gk < k) ? A[gi * sai + gk * sak] : T(0);
-            Bs[kk][row] = (gj < n && gk < k) ? B[gk * sbk + gj * sbj] : T(0);
+            const int ra = a_k ? idx / 16 : idx % 64, ka = a_k ? idx % 16 : idx / 64;
+            const int cb = b_k ? idx / 16 : idx % 64, kb = b_k ? idx % 16 : idx / 64;
+            const int gi = i0 + ra, gka = k0 + ka, gj = j0 + cb, gkb = k0 + kb;
+            As[ka][ra] = (gi < m && gka < k) ? A[gi * sai + gka * sak] : T(0);
+            Bs[kb][cb] = (gj < n && gkb < k) ? B[gkb * sbk + gj * sbj] : T(0);
         }
         __syncthreads();
 #pragma unroll
