@@ -245,9 +245,11 @@ int nce_coarse_solve(nce_ctx *ctx, double *a_dev, int *iters_host, double *chi0_
  * x0_i = a_i e_0 (the coarse solve); with a network m (n_in = NCE_FEATURES,
  * n_out = K) also, x0_i = a_i m_i with m_i the network's output for patch i.
  * GMRES judges the guess: if its FP64 residual is not below 0.99 ||b||, the
- * solve starts from zero (nce_info.used_fallback). m = NULL and use_coarse = 0
- * disable; m without use_coarse is NCE_EINVAL. The caller keeps m alive while
- * it is set.
+ * solve starts from zero (nce_info.used_fallback). The per-layout work (the
+ * coarse solve, and the network's features, computed on host threads while
+ * the coarse solve runs) is done here, not in the next solve. m = NULL and
+ * use_coarse = 0 disable and drop that work, so a later call redoes it; m
+ * without use_coarse is NCE_EINVAL. The caller keeps m alive while it is set.
  */
 int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m, int use_coarse);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <future>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -926,9 +927,32 @@ int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
     return guarded([&]() -> int {
         ctx->warm = m ? &m->net : nullptr;
         ctx->warm_coarse = use_coarse != 0;
+        if (!m && !use_coarse) {
+            // disabled: drop the per-layout data, so a later start recomputes it
+            ctx->d_feat.release();
+            ctx->d_a.release();
+            ctx->coarse_iters = -1;
+            return NCE_OK;
+        }
         // per-layout preprocessing now, not inside the next solve
-        if (ctx->warm_coarse && ctx->N > 1) coarse_amplitudes(ctx);
-        if (ctx->warm && ctx->N > 1 && !ctx->d_feat.p) ctx->d_feat.upload(features_host(ctx), ctx->stream);
+        if (ctx->warm && ctx->N > 1 && !ctx->d_feat.p) {
+            // the neighbour features on host threads while the coarse solve runs
+            // on the device; the amplitude features follow from its result
+            std::vector<float> feat;
+            auto geometry = std::async(std::launch::async, [&] {
+                nce::patch_features_geometry(ctx->frames, ctx->N, ctx->eps, ctx->tab.problem, feat);
+            });
+            coarse_amplitudes(ctx);
+            geometry.get();
+            std::vector<double> ah((size_t)ctx->N);
+            HIPCHK(hipMemcpyAsync(ah.data(), ctx->d_a.p, sizeof(double) * ah.size(), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            nce::patch_features_amplitudes(ah, ctx->N, feat);
+            ctx->d_feat.upload(feat, ctx->stream);
+        } else if (ctx->warm_coarse && ctx->N > 1) {
+            coarse_amplitudes(ctx);
+        }
         return NCE_OK;
     });
 }

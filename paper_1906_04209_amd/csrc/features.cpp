@@ -21,12 +21,9 @@ static inline double geod(const double* a, const double* b) {
 // come from a uniform grid of cubic cells over [-1, 1]^3 (cell side = chord of
 // 64 eps), searched in growing cubes until the 16th neighbour and the largest
 // radius lie inside the searched ball.
-void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem,
-                    const std::vector<double>& a, std::vector<float>& out) {
+void patch_features_geometry(const std::vector<double>& frames, int64_t N, double eps, int problem,
+                             std::vector<float>& out) {
     out.assign((size_t)N * kFeatureDimHost, 0.0f);
-    double amean = 0.0;
-    for (int64_t i = 0; i < N; ++i) amean += a[i];
-    amean /= (double)N;
     const double radii[4] = {8 * eps, 16 * eps, 32 * eps, 64 * eps};
     double chord2[4];
     for (int q = 0; q < 4; ++q) {
@@ -107,10 +104,25 @@ void patch_features(const std::vector<double>& frames, int64_t N, double eps, in
                 const double expect = std::max((N - 1) * 0.5 * (1.0 - std::cos(R)), 1e-12);
                 o[50 + q] = (float)(cnt[q] / expect);
             }
-            o[54] = (float)(10.0 * (a[i] / amean - 1.0));
-            o[55] = (float)amean;
         }
     }
+}
+
+void patch_features_amplitudes(const std::vector<double>& a, int64_t N, std::vector<float>& out) {
+    double amean = 0.0;
+    for (int64_t i = 0; i < N; ++i) amean += a[i];
+    amean /= (double)N;
+    for (int64_t i = 0; i < N; ++i) {
+        float* o = &out[(size_t)i * kFeatureDimHost];
+        o[54] = (float)(10.0 * (a[i] / amean - 1.0));
+        o[55] = (float)amean;
+    }
+}
+
+void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem,
+                    const std::vector<double>& a, std::vector<float>& out) {
+    patch_features_geometry(frames, N, eps, problem, out);
+    patch_features_amplitudes(a, N, out);
 }
 
 }  // namespace nce

@@ -47,5 +47,11 @@ struct Mlp {
 constexpr int kFeatureDim = 56;
 void patch_features(const std::vector<double>& frames, int64_t N, double eps, int problem,
                     const std::vector<double>& a, std::vector<float>& out);
+// The same in two parts: everything but the amplitude features (sizes out),
+// then the two amplitude features, so that the first part can run on the host
+// while the coarse solve runs on the device.
+void patch_features_geometry(const std::vector<double>& frames, int64_t N, double eps, int problem,
+                             std::vector<float>& out);
+void patch_features_amplitudes(const std::vector<double>& a, int64_t N, std::vector<float>& out);
 
 }  // namespace nce
