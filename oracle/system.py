@@ -229,3 +229,26 @@ def solve_gmres(lay: Layout, tol: float = 1e-12, maxiter: int = 300, incoming=No
     out = scalars(lay.tab, x)
     out.update(x=x, iters=it, hist=hist)
     return out
+
+
+def patch_residual(lay: Layout, op, x: np.ndarray, i: int, t: np.ndarray, theta: np.ndarray) -> np.ndarray:
+    """v - 1 at points (t, theta) of patch i, v = sum_j S_j[sigma_j] the
+    single-layer potential of the densities sigma_j = B x_j (Sections 3 and 6):
+    the self term is the patch's data sum_k x_ik Z_k (what the one-patch solve
+    reproduces on its own patch), the other patches' terms come from the fine
+    quadrature of their densities. Zero up to the truncation of the incoming
+    fields to degree M when x solves the system; the paper's L2 residual error
+    on a patch (eq. patcherrl2, Sections 9.3 and 10.2) is its root mean square."""
+    tab = lay.tab
+    self_part = np.zeros(len(t))
+    for k, (n, m) in enumerate(zernike.modes(tab.M)):
+        self_part += x[i, k] * zernike.basis(n, m, t / tab.eps, theta)
+    X = patch_points(lay.c[i:i + 1], lay.e1[i:i + 1], lay.e2[i:i + 1], t, theta)[0]
+    Xf = patch_points(lay.c, lay.e1, lay.e2, op.fine_t, op.fine_theta)
+    sw = (x @ op.B.T) * op.w[None, :]
+    far = np.zeros(len(t))
+    for j in range(lay.N):
+        if j != i:
+            far += green_block(X, Xf[j], tab.problem) @ sw[j]
+    return self_part + far - 1.0
+

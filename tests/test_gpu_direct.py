@@ -104,3 +104,37 @@ def test_single_patch_and_pair(torch):
     r2 = nce.Context(c2, 0.05, problem=nce.EXTERIOR, tol_id=TOL_ID).solve()
     f = r2["flux"].cpu().numpy()
     assert abs(f[0] - f[1]) < 1e-14 * abs(f[0])
+
+
+@pytest.fixture(scope="module")
+def cfg1_onepatch():
+    """The oracle's exterior one-patch solution and tables at eps = 0.1 (CPU)."""
+    from oracle import tables
+    from oracle.greens import EXTERIOR
+    tab, op, _ = tables.compute(EXTERIOR, 0.1, 15, 1e-12)
+    return tab, op
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_cfg1_dirichlet_condition(torch, cfg1_onepatch, mixed):
+    """The GPU solution satisfies u = 1 on every patch (the physical condition
+    behind the system) at random points off the discretization grids: the
+    oracle evaluates the single-layer potential of the library's densities
+    there (self term from the patch data, the rest by fine quadrature)."""
+    import paper_1906_04209_amd as nce
+    from oracle import system
+    tab, op = cfg1_onepatch
+    cfg = layouts.CONFIGS["cfg1"]
+    c = layouts.config_layout(cfg)
+    ctx = _ctx(cfg, precision=nce.MIXED if mixed else nce.FP64)
+    r = ctx.solve()
+    x = r["x"].cpu().numpy().reshape(len(c), ctx.K)
+    lay = system.Layout(c, tab)
+    g = np.random.default_rng(11)
+    worst = 0.0
+    for i in range(len(c)):
+        t = cfg["eps"] * np.sqrt(g.random(20))
+        th = 2 * np.pi * g.random(20)
+        worst = max(worst, float(np.max(np.abs(system.patch_residual(lay, op, x, i, t, th)))))
+    print(f"cfg1 {'mixed' if mixed else 'fp64'}: max |u - 1| on the patches {worst:.2e}")
+    assert worst < 1e-9

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import layouts
-from oracle import onepatch, system, tables
+from oracle import greens, onepatch, system, tables
 from oracle.greens import EXTERIOR, INTERIOR
 
 
@@ -17,6 +17,17 @@ def tab_e():
 @pytest.fixture(scope="module")
 def tab_i():
     return tables.get(INTERIOR, 0.1, 15, 1e-12)
+
+
+_FULL = {}
+
+
+def _full(problem):
+    """(Tables, OnePatch) at eps = 0.1, computed once per module."""
+    if problem not in _FULL:
+        tab, op, _ = tables.compute(problem, 0.1, 15, 1e-12)
+        _FULL[problem] = (tab, op)
+    return _FULL[problem]
 
 
 def test_single_patch(tab_i, tab_e):
@@ -104,3 +115,68 @@ def test_fibonacci_table2_plausibility():
         c = layouts.fibonacci_centers(N, variant)
         r = system.solve_dense(system.Layout(c, tab))
         assert abs(r["mu"] - 0.62771752) < 0.002 * 0.62771752, r["mu"]
+
+
+@pytest.mark.slow
+def test_interior_flux_identity():
+    """Divergence theorem for the interior problem (Section 2.3): v = sum_i
+    S_i[sigma_i] has the same normal derivative, -I_sigma, at every point of
+    the reflecting surface (Lemma intsigma), so vbar = (v - 1) / (3 D) +
+    (1 - |x|^2) / 6 with D = -I_sigma has zero flux there and the whole escape
+    flux through the patches is the ball's volume 4 pi / 3. The derivative is
+    taken numerically from the off-surface Green's function on interior points
+    and compared with I_sigma from the integral vector I. This holds for any
+    densities (it checks G_I's Neumann property and I as the integral of
+    sigma); that the densities solve the system is checked on the patches by
+    test_dirichlet_condition_on_patches."""
+    tab, res = _full(INTERIOR)
+    c = layouts.uniform_centers(4, 0.1, 41)
+    lay = system.Layout(c, tab)
+    r = system.solve_dense(lay)
+    Is = r["I_sigma"]
+    Xf = system.patch_points(lay.c, lay.e1, lay.e2, res.fine_t, res.fine_theta)   # (N, n_f, 3)
+    sw = (r["x"] @ res.B.T) * res.w[None, :]                                      # sigma_j dS
+
+    def v(y):
+        return sum(float(np.sum(greens.g_offsurface(y[None, :], Xf[j], INTERIOR) * sw[j])) for j in range(lay.N))
+
+    g = np.random.default_rng(7)
+    checked = 0
+    while checked < 6:
+        x = g.standard_normal(3)
+        x /= np.linalg.norm(x)
+        if np.min(np.arccos(np.clip(lay.c @ x, -1, 1))) < 0.4:   # stay clear of the patches (eps = 0.1)
+            continue
+        h = 1e-5
+        # one-sided second-order difference along the outward normal
+        dvdn = (3 * v(x) - 4 * v((1 - h) * x) + v((1 - 2 * h) * x)) / (2 * h)
+        assert abs(dvdn + Is) < 1e-7 * abs(Is), (dvdn, -Is)
+        checked += 1
+    # with D = -I_sigma the flux of vbar through the patches: (1/(3D)) * (-D |Gamma_R|) - |Gamma_A|/3 = -4 pi/3
+    area_a = lay.N * 2 * math.pi * (1 - math.cos(0.1))
+    D = -Is
+    flux_a = (1.0 / (3.0 * D)) * (-D * (4 * math.pi - area_a)) - area_a / 3.0
+    assert abs(flux_a + 4 * math.pi / 3) < 1e-12
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("problem", [INTERIOR, EXTERIOR])
+def test_dirichlet_condition_on_patches(problem):
+    """v = 1 on every patch (the absorbing condition, Sections 2.2 and 2.3) at
+    random points off the discretization grids, for the solved densities; a
+    relative change of 1e-6 in one patch's leading coefficient breaks it by
+    that much."""
+    tab, res = _full(problem)
+    eps = 0.1
+    for N, seed in ((4, 41), (8, 42)):
+        lay = system.Layout(layouts.uniform_centers(N, eps, seed), tab)
+        x = system.solve_dense(lay)["x"]
+        g = np.random.default_rng(3)
+        for i in range(N):
+            t = eps * np.sqrt(g.random(30))
+            th = 2 * np.pi * g.random(30)
+            assert np.max(np.abs(system.patch_residual(lay, res, x, i, t, th))) < 1e-11
+        xp = x.copy()
+        xp[0, 0] *= 1 + 1e-6
+        assert np.max(np.abs(system.patch_residual(lay, res, xp, 0, t, th))) > 5e-7
+
