@@ -244,11 +244,10 @@ def patch_residual(lay: Layout, op, x: np.ndarray, i: int, t: np.ndarray, theta:
     for k, (n, m) in enumerate(zernike.modes(tab.M)):
         self_part += x[i, k] * zernike.basis(n, m, t / tab.eps, theta)
     X = patch_points(lay.c[i:i + 1], lay.e1[i:i + 1], lay.e2[i:i + 1], t, theta)[0]
-    Xf = patch_points(lay.c, lay.e1, lay.e2, op.fine_t, op.fine_theta)
-    sw = (x @ op.B.T) * op.w[None, :]
     far = np.zeros(len(t))
     for j in range(lay.N):
         if j != i:
-            far += green_block(X, Xf[j], tab.problem) @ sw[j]
+            Xf = patch_points(lay.c[j:j + 1], lay.e1[j:j + 1], lay.e2[j:j + 1], op.fine_t, op.fine_theta)[0]
+            far += green_block(X, Xf, tab.problem) @ ((op.B @ x[j]) * op.w)
     return self_part + far - 1.0
 

@@ -105,3 +105,40 @@ def test_autotune_shapes_keep_result(torch):
     assert ch64[0] in (4, 8) and ch64[1] in (2, 4, 8) and ch32[0] in (4, 8) and ch32[1] in (2, 4, 8)
     assert e64 < 1e-13
     assert e32 < 1e-6
+
+
+@pytest.fixture(scope="module")
+def cfg2_onepatch():
+    """The oracle's interior one-patch solution and tables at eps = 0.01 (CPU)."""
+    from oracle import tables
+    cfg = layouts.CONFIGS["cfg2"]
+    tab, op, _ = tables.compute(cfg["problem"], cfg["eps"], 15, 1e-12)
+    return tab, op
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg2_tree_solution_dirichlet_condition(torch, cfg2_onepatch, precision):
+    """The tree-accelerated solve of the N = 1000 interior workload satisfies
+    u = 1 on its patches at random off-grid points (single-layer potential of
+    the library's densities evaluated by the oracle: the patch's own data plus
+    every other patch by fine quadrature), to the tree and ID tolerances."""
+    import paper_1906_04209_amd as nce
+    from oracle import system
+    cfg = layouts.CONFIGS["cfg2"]
+    c = layouts.config_layout(cfg)
+    tab, op = cfg2_onepatch
+    pr = nce.FP64 if precision == "fp64" else nce.MIXED
+    ctx = nce.Context(c, cfg["eps"], problem=cfg["problem"], tol_id=1e-11, far_field=nce.FAR_TREE,
+                      tol_gmres=1e-10, precision=pr)
+    r = ctx.solve()
+    assert r["converged"]
+    x = r["x"].cpu().numpy().reshape(len(c), ctx.K)
+    lay = system.Layout(c, tab)
+    g = np.random.default_rng(12)
+    worst = 0.0
+    for i in g.choice(len(c), 2, replace=False):
+        t = cfg["eps"] * np.sqrt(g.random(8))
+        th = 2 * np.pi * g.random(8)
+        worst = max(worst, float(np.max(np.abs(system.patch_residual(lay, op, x, int(i), t, th)))))
+    print(f"cfg2 tree {precision}: max |u - 1| on 2 random patches {worst:.2e}")
+    assert worst < 1e-8
