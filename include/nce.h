@@ -89,6 +89,12 @@ typedef struct nce_opts {
                              guess is taken (nce_set_warm_start, nce_coarse_solve); in (0, 0.1).
                              Default 1e-5 (the guess's own residual is set by the monopole
                              model, near 5e-4 at N = 1e5; tighter solves do not improve it) */
+    int deflation;        /* 1: the FP32 inner solves of the mixed form are right-preconditioned by
+                             coarse-space deflation (not in the paper): the 16 polynomials of degree
+                             <= 3 in the patch centres, in every patch's first coefficient, with the
+                             coarse (monopole) model of the system on them; built at the first mixed
+                             solve of a context with N >= 64. 0: off. The FP64 solves are never
+                             preconditioned. Default 1 */
 } nce_opts;
 
 typedef struct nce_info {
@@ -239,6 +245,20 @@ int nce_features(nce_ctx *ctx, float *feat_dev);
  * Not in the paper.
  */
 int nce_coarse_solve(nce_ctx *ctx, double *a_dev, int *iters_host, double *chi0_host);
+
+/*
+ * The coarse-space deflation of the mixed solves (opts.deflation; not in the
+ * paper): *k (<= 16) independent basis columns, the orthonormalized harmonic
+ * polynomials of degree <= 3 in the patch centres, and T = I + chi0 Z^T G Z,
+ * the coarse model of the system on them (G(c_i, c_j) between centres, i != j;
+ * chi0 as for nce_coarse_solve). T_host: k*k host doubles, row-major (room for
+ * 256 suffices), may be NULL. Builds the deflation if the context has not yet;
+ * k = 0 for N < 64, where none is used.
+ */
+int nce_deflation_matrix(nce_ctx *ctx, int *k, double *T_host);
+
+/* Turns the deflation of later mixed solves on (1) or off (0), as opts.deflation. */
+int nce_set_deflation(nce_ctx *ctx, int on);
 
 /*
  * Initial guess of later solves (not in the paper): use_coarse = 1 starts from

@@ -32,7 +32,7 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
            "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve",
-           "nce_batch_set_warm_start"]
+           "nce_batch_set_warm_start", "nce_deflation_matrix", "nce_set_deflation"]
 FEATURES = 56
 
 
@@ -42,7 +42,7 @@ class Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
                 ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double),
-                ("tol_id_fp32", ctypes.c_double), ("tol_coarse", ctypes.c_double)]
+                ("tol_id_fp32", ctypes.c_double), ("tol_coarse", ctypes.c_double), ("deflation", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -102,6 +102,10 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_set_warm_start.argtypes = [vp, vp, ctypes.c_int]
     lib.nce_coarse_solve.argtypes = [vp, vp, ip, dp]
     lib.nce_coarse_solve.restype = ctypes.c_int
+    lib.nce_deflation_matrix.argtypes = [vp, ip, dp]
+    lib.nce_deflation_matrix.restype = ctypes.c_int
+    lib.nce_set_deflation.argtypes = [vp, ctypes.c_int]
+    lib.nce_set_deflation.restype = ctypes.c_int
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
                  "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
                  "nce_set_warm_start"):
@@ -227,7 +231,8 @@ class Context:
                  tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
                  max_iter: int = 100, precision: int = FP64, far_field: int = FAR_AUTO,
                  cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
-                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None):
+                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None,
+                 deflation: Optional[bool] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -243,6 +248,8 @@ class Context:
             o.tol_id_fp32 = tol_id_fp32
         if tol_coarse is not None:
             o.tol_coarse = tol_coarse
+        if deflation is not None:
+            o.deflation = int(bool(deflation))
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         # the library works on its own (non-default) stream; calls below order
         # it against the caller's current stream in both directions
@@ -346,6 +353,19 @@ class Context:
         self._leave()
         return (a, it.value, chi0.value) if with_chi0 else (a, it.value)
 
+    def set_deflation(self, on: bool) -> None:
+        _check(self.lib, self.lib.nce_set_deflation(self.h, int(bool(on))))
+
+    def deflation_matrix(self):
+        """(k, T): the coarse operator of the mixed solves' deflation on its k
+        basis columns (k x k numpy array; k = 0 for N < 64)."""
+        k = ctypes.c_int()
+        T = np.zeros(256)
+        self._enter()
+        _check(self.lib, self.lib.nce_deflation_matrix(self.h, ctypes.byref(k), T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        self._leave()
+        return k.value, T[:k.value * k.value].reshape(k.value, k.value)
+
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
         _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))
 
@@ -391,7 +411,8 @@ class Batch:
     def __init__(self, configs, M: int = 15, tol_id: float = 1e-11, tol_grid: float = 1e-8,
                  tol_gmres: float = 1e-10, max_iter: int = 60, precision: int = MIXED, far_field: int = FAR_AUTO,
                  cache_dir: Optional[str] = None, stream=None, tol_grid_fp32: Optional[float] = None,
-                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None):
+                 tol_id_fp32: Optional[float] = None, tol_coarse: Optional[float] = None,
+                 deflation: Optional[bool] = None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no HIP device: the solver runs only on the GPU")
@@ -412,6 +433,8 @@ class Batch:
             o.tol_id_fp32 = tol_id_fp32
         if tol_coarse is not None:
             o.tol_coarse = tol_coarse
+        if deflation is not None:
+            o.deflation = int(bool(deflation))
         o.max_iter, o.precision, o.far_field = max_iter, precision, far_field
         self.stream = stream if stream is not None else torch.cuda.Stream()
         o.stream = ctypes.c_void_p(self.stream.cuda_stream)

@@ -17,8 +17,8 @@ CSRC = PKG / "csrc"
 OUT = PKG / "libnce.so"
 BUILD = PKG / "_build"
 
-HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip", "batch.hip", "tree.hip", "mlp.hip", "coarse.hip"]
-CPP_SOURCES = ["precompute.cpp", "tree_build.cpp", "features.cpp"]
+HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip", "batch.hip", "tree.hip", "mlp.hip", "coarse.hip", "deflate.hip"]
+CPP_SOURCES = ["precompute.cpp", "tree_build.cpp", "features.cpp", "deflate_basis.cpp"]
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

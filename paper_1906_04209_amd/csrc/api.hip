@@ -154,11 +154,25 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
                         ctx->d_rho32.p, ctx->d_U32.p, ev, live, ctx->p32, ctx->ptot32);
 }
 
-const double* coarse_amplitudes(nce_ctx* ctx) {
-    if (ctx->coarse_iters >= 0) return ctx->d_a.p;
-    // total charge of the isolated-patch solution e_0 in the base outgoing table
+// total charge of the isolated-patch solution e_0 in the base outgoing table
+double coarse_chi0(const nce_ctx* ctx) {
     double chi0 = 0.0;
     for (int m = 0; m < ctx->p; ++m) chi0 += ctx->tab.T[(size_t)m * ctx->K];
+    return chi0;
+}
+
+// Builds the coarse-space deflation of the mixed inner solves (N >= 64).
+void ensure_deflation(nce_ctx* ctx) {
+    if (ctx->defl || ctx->N < 64) return;
+    auto d = std::make_unique<nce::Deflation>();
+    d->build(ctx->stream, (int)ctx->N, ctx->K, ctx->tab.problem, coarse_chi0(ctx), ctx->frames, ctx->d_frames.p);
+    ctx->d_dtmp.alloc((size_t)ctx->N * ctx->K);
+    ctx->defl = std::move(d);
+}
+
+const double* coarse_amplitudes(nce_ctx* ctx) {
+    if (ctx->coarse_iters >= 0) return ctx->d_a.p;
+    const double chi0 = coarse_chi0(ctx);
     if (!ctx->coarse)
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
     ctx->d_a.alloc((size_t)ctx->N);
@@ -261,6 +275,7 @@ int gmres(nce_ctx* ctx, const double* rhs, double* x, double tol, int maxit, int
     hipStream_t s = ctx->stream;
     ensure_krylov(ctx, maxit + 1);
     double* V = ctx->d_V.p;
+    const bool defl = precision == NCE_MIXED && ctx->opts.deflation && ctx->defl;
     const double bnorm = std::sqrt(dev_dot(ctx, n, rhs, rhs));
     converged = false;
     est_rel = 1.0;
@@ -276,7 +291,13 @@ int gmres(nce_ctx* ctx, const double* rhs, double* x, double tol, int maxit, int
     int k = 0, used = 0;
     for (k = 0; k < maxit; ++k) {
         double* w = V + (int64_t)(k + 1) * n;
-        matvec(ctx, V + (int64_t)k * n, w, precision);
+        if (defl) {
+            // right preconditioning: w = A M^{-1} v_k
+            HIPCHK(ctx->defl->apply(s, V + (int64_t)k * n, ctx->d_dtmp.p));
+            matvec(ctx, ctx->d_dtmp.p, w, precision);
+        } else {
+            matvec(ctx, V + (int64_t)k * n, w, precision);
+        }
         used++;
         // classical Gram-Schmidt on FP64 vectors: twice for the FP64 solves;
         // once for the FP32 inner solves of the mixed form, whose 1e-5 target
@@ -327,7 +348,15 @@ int gmres(nce_ctx* ctx, const double* rhs, double* x, double tol, int maxit, int
         y[i] = acc / H[(size_t)i * maxit + i];
     }
     HIPCHK(hipMemcpyAsync(ctx->d_h.p, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, s));
-    HIPCHK(nce::combine(s, n, m, V, n, ctx->d_h.p, x));
+    if (defl) {
+        // x += M^{-1} (V y)
+        HIPCHK(nce::fill(s, n, 0.0, ctx->d_dtmp.p));
+        HIPCHK(nce::combine(s, n, m, V, n, ctx->d_h.p, ctx->d_dtmp.p));
+        HIPCHK(ctx->defl->apply(s, ctx->d_dtmp.p, ctx->d_dtmp.p));
+        HIPCHK(nce::axpby(s, n, 1.0, ctx->d_dtmp.p, 1.0, x));
+    } else {
+        HIPCHK(nce::combine(s, n, m, V, n, ctx->d_h.p, x));
+    }
     return used;
 }
 
@@ -346,6 +375,8 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
     const int64_t N = ctx->N, n = N * (int64_t)ctx->K;
     hipStream_t s = ctx->stream;
     nce_info inf{};
+    // coarse-space deflation of the inner solves, once per context (inside the timed solve)
+    if (ctx->opts.precision == NCE_MIXED && ctx->opts.deflation) ensure_deflation(ctx);
     // b = P 1 = e_0 on every patch
     std::vector<double> hb((size_t)n, 0.0);
     for (int64_t i = 0; i < N; ++i) hb[(size_t)i * ctx->K] = 1.0;
@@ -463,6 +494,7 @@ int validate_opts(const nce_opts& o, double eps) {
     if (!(o.tol_id_fp32 == 0.0 || (o.tol_id_fp32 > 0 && o.tol_id_fp32 < 1e-3)))
         return fail(NCE_EINVAL, "tol_id_fp32 must be 0 or lie in (0, 1e-3)");
     if (!(o.tol_coarse > 0 && o.tol_coarse < 0.1)) return fail(NCE_EINVAL, "tol_coarse must lie in (0, 0.1)");
+    if (o.deflation != 0 && o.deflation != 1) return fail(NCE_EINVAL, "deflation must be 0 or 1");
     if (!(o.tol_gmres > 0 && o.tol_gmres < 1)) return fail(NCE_EINVAL, "tol_gmres must lie in (0, 1)");
     if (o.max_iter < 1 || o.max_iter > 2000) return fail(NCE_EINVAL, "max_iter must lie in [1, 2000]");
     if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
@@ -658,6 +690,7 @@ void nce_default_opts(nce_opts* o) {
     o->tol_grid_fp32 = 1e-5;
     o->tol_id_fp32 = 1e-7;
     o->tol_coarse = 1e-5;
+    o->deflation = 1;
 }
 
 int nce_setup(const double* centers, int64_t N, double eps, const nce_opts* opts_in, nce_ctx** out) {
@@ -903,6 +936,23 @@ int nce_features(nce_ctx* ctx, float* feat) {
         const std::vector<float> f = features_host(ctx);
         HIPCHK(hipMemcpyAsync(feat, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
+        return NCE_OK;
+    });
+}
+
+int nce_set_deflation(nce_ctx* ctx, int on) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (on != 0 && on != 1) return fail(NCE_EINVAL, "on must be 0 or 1");
+    ctx->opts.deflation = on;
+    return NCE_OK;
+}
+
+int nce_deflation_matrix(nce_ctx* ctx, int* k, double* T_host) {
+    if (!ctx || !k) return fail(NCE_EINVAL, "ctx and k must not be NULL");
+    return guarded([&]() -> int {
+        ensure_deflation(ctx);
+        *k = ctx->defl ? ctx->defl->k : 0;
+        if (T_host && ctx->defl) std::copy(ctx->defl->T.begin(), ctx->defl->T.end(), T_host);
         return NCE_OK;
     });
 }

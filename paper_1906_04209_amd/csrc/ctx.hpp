@@ -11,6 +11,7 @@
 
 #include "../../include/nce.h"
 #include "coarse.hpp"
+#include "deflate.hpp"
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "precompute.hpp"
@@ -130,6 +131,9 @@ struct nce_ctx {
     DevBuf<double> d_a;                 // coarse amplitudes a_i (valid when coarse_iters >= 0)
     int coarse_iters = -1;
     DevBuf<float> d_feat;
+    // coarse-space deflation of the FP32 inner solves (built at the first mixed solve)
+    std::unique_ptr<nce::Deflation> defl;
+    DevBuf<double> d_dtmp;
 };
 
 struct nce_mlp {

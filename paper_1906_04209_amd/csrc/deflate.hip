@@ -1,0 +1,246 @@
+// Coarse-space deflation of the FP32 inner solves: basis, coarse operator on
+// it, and the preconditioner apply (see deflate.hpp).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "deflate.hpp"
+#include "greens.hpp"
+#include "kernels.hpp"
+
+namespace nce {
+
+namespace {
+
+constexpr int kMTile = 256;   // source centres per LDS tile
+constexpr int kDotBlocks = 256;
+
+void chk(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// pos[j] = c_j / 2; zf[j] = Z_j in FP32
+__global__ void k_defl_src(int N, const double* __restrict__ frames, const double* __restrict__ Z,
+                           float4* __restrict__ pos, float* __restrict__ zf) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const double* f = frames + 9 * (int64_t)j;
+    pos[j] = make_float4((float)(0.5 * f[0]), (float)(0.5 * f[1]), (float)(0.5 * f[2]), 0.0f);
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) zf[(int64_t)j * kDefl + q] = (float)Z[(int64_t)j * kDefl + q];
+}
+
+// partial[split][i][q] = sum over this split's sources j != i of G(c_i, c_j) Z_j[q]
+template <int PROB>
+__global__ __launch_bounds__(256) void k_coarse_multi(int N, const float4* __restrict__ pos,
+                                                      const float* __restrict__ zf, int chunk,
+                                                      double* __restrict__ partial) {
+    __shared__ float4 tp[kMTile];
+    __shared__ float4 tz[kMTile][kDefl / 4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float4 ci = pos[i < N ? i : N - 1];
+    double acc[kDefl];
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) acc[q] = 0.0;
+    const int j0 = blockIdx.y * chunk, j1 = min(N, j0 + chunk);
+    constexpr float kLn2 = 0.69314718055994530942f;
+    const float4* z4 = reinterpret_cast<const float4*>(zf);
+    for (int t0 = j0; t0 < j1; t0 += kMTile) {
+        const int tl = min(kMTile, j1 - t0);
+        __syncthreads();
+        for (int k = threadIdx.x; k < tl; k += blockDim.x) {
+            tp[k] = pos[t0 + k];
+#pragma unroll
+            for (int qq = 0; qq < kDefl / 4; ++qq) tz[k][qq] = z4[(int64_t)(t0 + k) * (kDefl / 4) + qq];
+        }
+        __syncthreads();
+        float a[kDefl];
+#pragma unroll
+        for (int q = 0; q < kDefl; ++q) a[q] = 0.0f;
+        for (int k = 0; k < tl; ++k) {
+            const float4 s = tp[k];
+            const float dx = ci.x - s.x, dy = ci.y - s.y, dz = ci.z - s.z;
+            const float h2 = dx * dx + dy * dy + dz * dz;
+            // the target itself (h2 = 0) contributes nothing
+            const bool self = !(h2 > 0.0f);
+            float w, l2;
+            green32_parts_half<PROB>(self ? 1.0f : h2, w, l2);
+            const float g = self ? 0.0f : w - kLn2 * l2;
+#pragma unroll
+            for (int qq = 0; qq < kDefl / 4; ++qq) {
+                const float4 z = tz[k][qq];
+                a[4 * qq] += g * z.x;
+                a[4 * qq + 1] += g * z.y;
+                a[4 * qq + 2] += g * z.z;
+                a[4 * qq + 3] += g * z.w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kDefl; ++q) acc[q] += (double)a[q];
+    }
+    if (i < N)
+#pragma unroll
+        for (int q = 0; q < kDefl; ++q) partial[((int64_t)blockIdx.y * N + i) * kDefl + q] = acc[q];
+}
+
+__global__ void k_sum_splits(int64_t n, int nsplit, const double* __restrict__ partial, double* __restrict__ S) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    double v = 0.0;
+    for (int k = 0; k < nsplit; ++k) v += partial[(int64_t)k * n + e];
+    S[e] = v;
+}
+
+// partial[b][q] = sum over this block's patches i of Z[i][q] v[i][0]
+__global__ __launch_bounds__(256) void k_defl_dots(int N, int K, const double* __restrict__ Z,
+                                                   const double* __restrict__ v, double* __restrict__ partial) {
+    __shared__ double red[kDefl][256];
+    double acc[kDefl];
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) acc[q] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const double x = v[(int64_t)i * K];
+#pragma unroll
+        for (int q = 0; q < kDefl; ++q) acc[q] += Z[(int64_t)i * kDefl + q] * x;
+    }
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < kDefl; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDefl) partial[blockIdx.x * kDefl + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// out[i][0] += sum_q Z[i][q] c[q], c = Minv (sum_b partial[b]) (every block
+// forms c itself, in a fixed order)
+__global__ __launch_bounds__(256) void k_defl_update(int N, int K, const double* __restrict__ Z,
+                                                     const double* __restrict__ Minv, const double* __restrict__ partial,
+                                                     int nb, double* __restrict__ out) {
+    __shared__ double zt[kDefl], c[kDefl];
+    if (threadIdx.x < kDefl) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[b * kDefl + threadIdx.x];
+        zt[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDefl) {
+        double s = 0.0;
+        for (int r = 0; r < kDefl; ++r) s += Minv[threadIdx.x * kDefl + r] * zt[r];
+        c[threadIdx.x] = s;
+    }
+    __syncthreads();
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kDefl; ++q) s += Z[(int64_t)i * kDefl + q] * c[q];
+        out[(int64_t)i * K] += s;
+    }
+}
+
+}  // namespace
+
+void coarse_multi(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S) {
+    const int ntb = (N + 255) / 256;
+    const int nsplit = std::max(1, std::min((N + kMTile - 1) / kMTile, (2048 + ntb - 1) / ntb));
+    const int chunk = (N + nsplit - 1) / nsplit;
+    float4* pos = nullptr;
+    float* zf = nullptr;
+    double* partial = nullptr;
+    chk(hipMalloc((void**)&pos, sizeof(float4) * (size_t)N), "hipMalloc");
+    chk(hipMalloc((void**)&zf, sizeof(float) * (size_t)N * kDefl), "hipMalloc");
+    chk(hipMalloc((void**)&partial, sizeof(double) * (size_t)nsplit * N * kDefl), "hipMalloc");
+    hipLaunchKernelGGL(k_defl_src, dim3(ntb), dim3(256), 0, s, N, frames_dev, Z, pos, zf);
+    if (problem == 1)
+        hipLaunchKernelGGL(k_coarse_multi<1>, dim3(ntb, nsplit), dim3(256), 0, s, N, pos, zf, chunk, partial);
+    else
+        hipLaunchKernelGGL(k_coarse_multi<0>, dim3(ntb, nsplit), dim3(256), 0, s, N, pos, zf, chunk, partial);
+    const int64_t n = (int64_t)N * kDefl;
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsplit, partial, S);
+    chk(hipGetLastError(), "coarse_multi");
+    chk(hipStreamSynchronize(s), "sync");
+    (void)hipFree(pos);
+    (void)hipFree(zf);
+    (void)hipFree(partial);
+}
+
+Deflation::~Deflation() {
+    for (void* p : {(void*)Z, (void*)Minv, (void*)partial})
+        if (p) (void)hipFree(p);
+}
+
+void Deflation::build(hipStream_t s, int N_, int K_, int problem, double chi0, const std::vector<double>& frames,
+                      const double* frames_dev) {
+    N = N_;
+    K = K_;
+    std::vector<double> Zh;
+    k = deflation_basis(frames, N, Zh);
+    chk(hipMalloc((void**)&Z, sizeof(double) * Zh.size()), "hipMalloc");
+    chk(hipMalloc((void**)&Minv, sizeof(double) * kDefl * kDefl), "hipMalloc");
+    chk(hipMalloc((void**)&partial, sizeof(double) * kDotBlocks * kDefl), "hipMalloc");
+    chk(hipMemcpyAsync(Z, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, s), "copy");
+    double* Sd = nullptr;
+    chk(hipMalloc((void**)&Sd, sizeof(double) * Zh.size()), "hipMalloc");
+    coarse_multi(s, problem, N, frames_dev, Z, Sd);
+    std::vector<double> Sh(Zh.size());
+    chk(hipMemcpy(Sh.data(), Sd, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost), "copy");
+    (void)hipFree(Sd);
+    // T = Z^T (I + chi0 G) Z on the k independent columns (Z^T Z = I)
+    std::vector<double> T;
+    deflation_gram(Zh, Sh, N, k, T);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) T[(size_t)a * k + b] = (a == b ? 1.0 : 0.0) + chi0 * T[(size_t)a * k + b];
+    this->T = T;
+    // T^{-1} by Gauss-Jordan elimination with partial pivoting
+    std::vector<double> inv((size_t)k * k, 0.0);
+    for (int a = 0; a < k; ++a) inv[(size_t)a * k + a] = 1.0;
+    for (int col = 0; col < k; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < k; ++r)
+            if (std::fabs(T[(size_t)r * k + col]) > std::fabs(T[(size_t)piv * k + col])) piv = r;
+        if (!(std::fabs(T[(size_t)piv * k + col]) > 0.0)) throw std::runtime_error("singular coarse deflation matrix");
+        for (int c = 0; c < k; ++c) {
+            std::swap(T[(size_t)col * k + c], T[(size_t)piv * k + c]);
+            std::swap(inv[(size_t)col * k + c], inv[(size_t)piv * k + c]);
+        }
+        const double d = T[(size_t)col * k + col];
+        for (int c = 0; c < k; ++c) {
+            T[(size_t)col * k + c] /= d;
+            inv[(size_t)col * k + c] /= d;
+        }
+        for (int r = 0; r < k; ++r)
+            if (r != col) {
+                const double f = T[(size_t)r * k + col];
+                for (int c = 0; c < k; ++c) {
+                    T[(size_t)r * k + c] -= f * T[(size_t)col * k + c];
+                    inv[(size_t)r * k + c] -= f * inv[(size_t)col * k + c];
+                }
+            }
+    }
+    std::vector<double> M((size_t)kDefl * kDefl, 0.0);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) M[(size_t)a * kDefl + b] = inv[(size_t)a * k + b] - (a == b ? 1.0 : 0.0);
+    chk(hipMemcpyAsync(Minv, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, s), "copy");
+    chk(hipStreamSynchronize(s), "sync");
+}
+
+hipError_t Deflation::apply(hipStream_t s, const double* in, double* out) const {
+    if (out != in) {
+        const hipError_t e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)N * K, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    const int nb = std::max(1, std::min(kDotBlocks, (N + 255) / 256));
+    hipLaunchKernelGGL(k_defl_dots, dim3(nb), dim3(256), 0, s, N, K, Z, in, partial);
+    const int nu = std::max(1, std::min(1024, (N + 255) / 256));
+    hipLaunchKernelGGL(k_defl_update, dim3(nu), dim3(256), 0, s, N, K, Z, Minv, partial, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace nce

@@ -44,10 +44,10 @@ def test_default_opts():
     o = nce.Opts()
     lib.nce_default_opts(ctypes.byref(o))
     assert (o.M, o.tol_id, o.tol_grid, o.tol_gmres, o.precision) == (15, 1e-11, 1e-8, 1e-10, 0)
-    assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse) == (1e-5, 1e-7, 1e-5)
+    assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse, o.deflation) == (1e-5, 1e-7, 1e-5, 1)
 
 
-@pytest.mark.parametrize("case", ["nonunit", "nan", "eps0", "epsbig", "badM", "badprob", "badcoarse", "badgrid32"])
+@pytest.mark.parametrize("case", ["nonunit", "nan", "eps0", "epsbig", "badM", "badprob", "badcoarse", "badgrid32", "baddefl"])
 def test_invalid_arguments(case):
     c = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
     eps, kw = 0.1, {}
@@ -67,6 +67,8 @@ def test_invalid_arguments(case):
         kw = {"tol_coarse": 0.5}
     elif case == "badgrid32":
         kw = {"tol_grid_fp32": 0.5}
+    elif case == "baddefl":
+        kw = {"deflation": 2}
     rc, msg, h = _setup(c, eps, **kw)
     assert rc == -1 and not h.value and msg
 
