@@ -31,15 +31,17 @@ import layouts  # noqa: E402
 # transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
 # 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
 # Keyed by (precision, problem, P2L grid points per thread).
-C_PAIR = {("fp64", 0, 4): 31.3, ("fp64", 0, 8): 31.1, ("fp64", 1, 4): 30.3, ("fp64", 1, 8): 30.1,
+C_PAIR = {("fp64", 0, 4): 28.25, ("fp64", 0, 8): 28.1, ("fp64", 1, 4): 27.25, ("fp64", 1, 8): 27.1,
           ("fp32", 0, 4): 8.25, ("fp32", 0, 8): 8.1, ("fp32", 1, 4): 7.75, ("fp32", 1, 8): 7.6}
 # shape 0 runs R = 4 and R = 8 launches; priced at the cheaper of the two (the higher ceiling)
 C_PAIR.update({(p, b, 0): min(C_PAIR[(p, b, 4)], C_PAIR[(p, b, 8)]) for p in ("fp64", "fp32") for b in (0, 1)})
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
-# current kernels. The bytes depend on the work items, not on the thread shape.
-TRAFFIC = {("cfg5", "fp64"): 8.595e9, ("cfg5", "fp32"): 4.966e9}
+# current kernels, per thread shape (4 or 8 grid points per thread, 0 = per-item
+# class: two launches over item lists, which read more through L2 misses).
+TRAFFIC = {("cfg5", "fp64", 4): 8.572e9, ("cfg5", "fp64", 8): 8.575e9, ("cfg5", "fp64", 0): 9.026e9,
+           ("cfg5", "fp32", 4): 4.969e9, ("cfg5", "fp32", 8): 4.589e9, ("cfg5", "fp32", 0): 4.969e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
@@ -271,7 +273,7 @@ def main():
         "setup_s": t_setup, "autotuned_shapes": tuned,
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
                      "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
-                     "traffic": (TRAFFIC.get((args.workload, ptag))
+                     "traffic": (TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4))
                                  if args.tol_grid_fp32 is None and args.tol_id_fp32 is None else None),
                      "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
     }

@@ -4,17 +4,19 @@
 //   exterior  2/d - log(2/d) - log(1 + d/2) = w - log(1 + w)
 //   interior  2/d + log(2/d) - log(1 + d/2) = w + log(w^2 / (1 + w))
 //
-// FP64 logarithm (log64t): x = m 2^e with m in [1/2, 1); the top 7 bits of
-// the mantissa pick a table entry (2 r_k, -log(2 r_k)) and u = m (2 r_k) - 1
-// (one fma, |u| < 2^-7.9), so log x = e ln 2 - log(2 r_k) + log(1 + u), the
-// last by its degree-6 series (truncation below 3e-18 absolute). r_k is an
-// FP32 number within 2^-14 of the reciprocal of the bin centre of 2m, chosen
-// (the accurate-tables idea of Gal's method) so that -log(2 r_k) lies within
-// about 2^-62 of a double: one double then carries it, and an entry is 16
-// bytes read by one LDS instruction. The table is built on the host in
-// extended precision; kernels stage it in LDS (2 KiB). Valid for positive
-// normal arguments, which is all the kernels pass. Host builds of these
-// functions serve the CPU accuracy test.
+// FP64 logarithm (log64t): x = m 2^e with m in [1/2, 1); the top 10 bits of
+// the mantissa pick a table entry (r_k, -log(2 r_k)) and v = m r_k - 1/2 =
+// u / 2 with u = 2 m r_k - 1 (one fma, |u| < 2^-10.8), so log x = e ln 2 -
+// log(2 r_k) + log(1 + u), the last by its degree-4 series (truncation below
+// 2^-56 absolute), written in v as 2 (v - v^2 (1 - 4v/3 + 2v^2)) so that no
+// fma needs two constants outside the inline set. r_k is an FP32 number
+// within 2^-15 of the reciprocal of the bin centre of 2m, chosen (the
+// accurate-tables idea of Gal's method) so that -log(2 r_k) lies within about
+// 2^-62 of a double: one double then carries it, and an entry is 16 bytes
+// read by one LDS instruction. The table is built on the host in extended
+// precision; kernels stage it in LDS (16 KiB). Valid for positive normal
+// arguments, which is all the kernels pass. Host builds of these functions
+// serve the CPU accuracy test.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -24,14 +26,14 @@
 namespace nce {
 
 struct alignas(16) LogEntry {
-    double t;   // -log(2 r_k), within about 2^-62 relative of the exact value
-    double r2;  // 2 r_k
+    double t;  // -log(2 r_k), within about 2^-62 relative of the exact value
+    double r;  // r_k
 };
-constexpr int kLogBits = 7;
+constexpr int kLogBits = 10;
 constexpr int kLogTab = 1 << kLogBits;
 
 // Host: fills the kLogTab entries. For each bin, among the FP32 numbers within
-// 2^-14 of 1 / (bin centre), takes the one whose -log(2 r) is closest (in
+// 2^-15 of 1 / (bin centre), takes the one whose -log(2 r) is closest (in
 // extended precision) to its own double rounding.
 inline void build_log_table(LogEntry* tab) {
     for (int k = 0; k < kLogTab; ++k) {
@@ -50,11 +52,16 @@ inline void build_log_table(LogEntry* tab) {
             }
         }
         tab[k].t = (double)(-std::log(2.0L * (long double)best));
-        tab[k].r2 = 2.0 * (double)best;
+        tab[k].r = (double)best;
     }
 }
 
-__host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __restrict__ tab) {
+// log x split as e ln 2 + t + 2 h: t = -log(2 r_k) from the table,
+// 2 h = log(1 + u); de = e as a double.
+struct LogParts {
+    double t, h, de;
+};
+__host__ __device__ __forceinline__ LogParts log64t_parts(double x, const LogEntry* __restrict__ tab) {
     int e;
     double m;
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -69,18 +76,18 @@ __host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __re
 #endif
     // m and 2m share their mantissa bits: bin k of 2m in [1, 2)
     const LogEntry& L = tab[(hi >> (20 - kLogBits)) & (kLogTab - 1)];
-    const double u = fma(m, L.r2, -1.0);
-    double q = -1.0 / 6.0;
-    q = fma(q, u, 1.0 / 5.0);
-    q = fma(q, u, -1.0 / 4.0);
-    q = fma(q, u, 1.0 / 3.0);
-    q = fma(q, u, -0.5);
-    const double lp = fma(q * u, u, u);  // log(1 + u)
-    const double de = (double)e;
-    // ln 2 = hi + lo with hi exact to 2^-32 so that e * hi is exact for |e| < 2^21
-    const double ln2_hi = 6.93147180369123816490e-01;
-    const double ln2_lo = 1.90821492927058770002e-10;
-    return fma(de, ln2_hi, L.t) + fma(de, ln2_lo, lp);
+    const double v = fma(m, L.r, -0.5);                         // u / 2, exact scaling
+    const double q = fma(fma(v, 2.0, -4.0 / 3.0), v, 1.0);      // 1 - 4v/3 + 2v^2
+    return {L.t, fma(-v * q, v, v), (double)e};
+}
+
+// ln 2 = hi + lo with hi exact to 2^-32 so that e * hi is exact for |e| < 2^21
+constexpr double kLn2Hi = 6.93147180369123816490e-01;
+constexpr double kLn2Lo = 1.90821492927058770002e-10;
+
+__host__ __device__ __forceinline__ double log64t(double x, const LogEntry* __restrict__ tab) {
+    const LogParts p = log64t_parts(x, tab);
+    return fma(p.de, kLn2Hi, p.t) + fma(p.de, kLn2Lo, 2.0 * p.h);
 }
 
 // 1/sqrt(x) for positive normal x: the hardware estimate and one
@@ -106,6 +113,26 @@ __host__ __device__ __forceinline__ double green64_half(double h2, const LogEntr
     if (PROB == 1) return w - log64t(1.0 + w, tab);
     const double u = h2 * w;
     return w - log64t(fma(u, u, u), tab);
+}
+
+// G = g - e ln 2 (FP64) with e the binary exponent of the logarithm's
+// argument, returned separately (de) so that a sum over many pairs can carry
+// sum rho e apart from sum rho g and apply ln 2 once at the end: per pair this
+// saves the conversion of e ln 2 into the logarithm.
+template <int PROB>
+__host__ __device__ __forceinline__ double green64_half_split(double h2, const LogEntry* __restrict__ tab,
+                                                              double& de) {
+    const double w = rsqrt64(h2);
+    double x;
+    if (PROB == 1) {
+        x = 1.0 + w;
+    } else {
+        const double u = h2 * w;
+        x = fma(u, u, u);
+    }
+    const LogParts p = log64t_parts(x, tab);
+    de = p.de;
+    return fma(-2.0, p.h, w - p.t);
 }
 
 // G as a function of d^2 (FP64).

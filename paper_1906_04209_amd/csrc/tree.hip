@@ -112,11 +112,12 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    double zx[R], zy[R], zz[R], z2[R], acc[R];
+    // acc: sum of rho (G + e ln 2), ace: sum of rho e (e the logarithm's binary exponent)
+    double zx[R], zy[R], zz[R], z2[R], acc[R], ace[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int t = t0 + r * qq;
-        acc[r] = 0.0;
+        acc[r] = ace[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
         if (active && t < q) {
             // half-scaled offsets from the cap centre, precomputed per tree
@@ -166,7 +167,10 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double h2 = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
-                    acc[r] += green64_half<PROB>(h2, ltab) * w;
+                    double de;
+                    const double gs = green64_half_split<PROB>(h2, ltab, de);
+                    acc[r] = fma(gs, w, acc[r]);
+                    ace[r] = fma(de, w, ace[r]);
                 }
             }
         }
@@ -177,7 +181,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int t = t0 + r * qq;
-            if (t < q) red[split * q + t] = acc[r];
+            if (t < q) red[split * q + t] = fma(-kLn2Hi, ace[r], fma(-kLn2Lo, ace[r], acc[r]));
         }
     __syncthreads();
     const int64_t off = it_off[item];
