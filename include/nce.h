@@ -337,6 +337,12 @@ int nce_solve_batch(nce_batch *batch, double *result_host, double *coeffs_dev, n
  * per member (use_coarse = 1), refined per patch by network m when given. */
 int nce_batch_set_warm_start(nce_batch *batch, nce_mlp *m, int use_coarse);
 
+/* Turns the coarse-space deflation of the batch's mixed inner solves on (1)
+ * or off (0) (opts.deflation at setup; not in the paper): per member, as
+ * nce_set_deflation, for members of at least 64 patches. Turning it on for a
+ * mixed batch builds every member's deflation data now. */
+int nce_batch_set_deflation(nce_batch *batch, int on);
+
 /* nce_autotune for every (problem, eps) group of the batch; choice_host (may
  * be NULL): 2 x ngroups values in group order. */
 int nce_batch_autotune(nce_batch *batch, int precision, int *choice_host);

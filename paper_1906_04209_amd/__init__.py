@@ -32,7 +32,7 @@ SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_fram
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
            "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve",
-           "nce_batch_set_warm_start", "nce_deflation_matrix", "nce_set_deflation"]
+           "nce_batch_set_warm_start", "nce_deflation_matrix", "nce_set_deflation", "nce_batch_set_deflation"]
 FEATURES = 56
 
 
@@ -106,6 +106,8 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_deflation_matrix.restype = ctypes.c_int
     lib.nce_set_deflation.argtypes = [vp, ctypes.c_int]
     lib.nce_set_deflation.restype = ctypes.c_int
+    lib.nce_batch_set_deflation.argtypes = [vp, ctypes.c_int]
+    lib.nce_batch_set_deflation.restype = ctypes.c_int
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
                  "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
                  "nce_set_warm_start"):
@@ -496,6 +498,10 @@ class Batch:
         self._warm = mlp
         _check(self.lib, self.lib.nce_batch_set_warm_start(self.h, mlp.h if mlp is not None else None,
                                                            int(bool(coarse))))
+
+    def set_deflation(self, on: bool) -> None:
+        """nce_batch_set_deflation: deflation of the mixed inner solves per member."""
+        _check(self.lib, self.lib.nce_batch_set_deflation(self.h, int(bool(on))))
 
     def autotune(self, precision: int = MIXED):
         """nce_batch_autotune: per group (P2L points per thread, interpolation nodes per thread)."""

@@ -163,7 +163,7 @@ double coarse_chi0(const nce_ctx* ctx) {
 
 // Builds the coarse-space deflation of the mixed inner solves (N >= 64).
 void ensure_deflation(nce_ctx* ctx) {
-    if (ctx->defl || ctx->N < 64) return;
+    if (ctx->defl || ctx->N < nce::kDeflMinN) return;
     auto d = std::make_unique<nce::Deflation>();
     d->build(ctx->stream, (int)ctx->N, ctx->K, ctx->tab.problem, coarse_chi0(ctx), ctx->frames, ctx->d_frames.p);
     ctx->d_dtmp.alloc((size_t)ctx->N * ctx->K);

@@ -260,6 +260,12 @@ struct nce_batch {
     std::vector<DevBuf<double>> g_a;       // per group: coarse amplitudes of its patches
     std::vector<DevBuf<float>> g_feat;     // per group: network features of its patches
     bool have_a = false;
+    // coarse-space deflation of the FP32 inner solves, per member (segment order)
+    bool deflation = true;
+    bool have_defl = false;
+    DevBuf<double> d_dZ, d_dM, d_dd, d_dtmp;  // npatch x 16, S x 16 x 16, S x 16, n
+    DevBuf<int64_t> d_pseg;                   // S + 1 patch offsets
+    DevBuf<int> d_patch_seg;                  // patch -> segment
 
     ~nce_batch() {
         for (auto& gr : graph)
@@ -278,6 +284,76 @@ void batch_matvec(nce_batch* bt, const double* x, double* y, int precision, cons
     for (size_t g = 0; g < bt->groups.size(); ++g)
         matvec(bt->groups[g], x + bt->g_elem[g], y + bt->g_elem[g], precision, nullptr,
                live ? live + bt->g_seg0[g] : nullptr);
+}
+
+bool deflated(const nce_batch* bt, int precision) {
+    return precision == NCE_MIXED && bt->deflation && bt->have_defl;
+}
+
+// Deflation data of every member (built once): bases on host threads over
+// all members, one upload, the members' coarse products enqueued back to back
+// on shared scratch, one download, then T^{-1} - I per member on the host.
+void ensure_batch_deflation(nce_batch* bt) {
+    if (bt->have_defl) return;
+    hipStream_t s = bt->stream;
+    const int S = bt->B;
+    const int64_t npatch = bt->n / bt->K;
+    std::vector<int64_t> pseg(S + 1);
+    std::vector<int> pcfg((size_t)npatch), Nq(S), kq(S);
+    std::vector<const double*> frh(S);
+    std::vector<double> chi0(S, 0.0);
+    int nmax = 1;
+    for (int q = 0; q <= S; ++q) pseg[q] = bt->seg_off[q] / bt->K;
+    for (int q = 0; q < S; ++q) {
+        for (int64_t i = pseg[q]; i < pseg[q + 1]; ++i) pcfg[(size_t)i] = q;
+        const int g = bt->seg_group[q];
+        nce_ctx* c = bt->groups[g];
+        const int member = q - bt->g_seg0[g];
+        const int64_t f0 = c->cfg_first[member], nc = c->cfg_first[member + 1] - f0;
+        if (nc != pseg[q + 1] - pseg[q]) throw std::runtime_error("batch layout mismatch");
+        Nq[q] = (int)nc;
+        frh[q] = c->frames.data() + 9 * f0;
+        for (int m = 0; m < c->p; ++m) chi0[q] += c->tab.T[(size_t)m * c->K];
+        if (nc >= nce::kDeflMinN) nmax = std::max(nmax, (int)nc);
+    }
+    std::vector<double> Zall((size_t)npatch * nce::kDefl, 0.0), Mall((size_t)S * nce::kDefl * nce::kDefl, 0.0);
+    nce::deflation_bases(S, frh.data(), Nq.data(), pseg.data(), nce::kDeflMinN, Zall.data(), kq.data());
+    bt->d_dZ.upload(Zall, s);
+    DevBuf<double> dS;
+    dS.alloc(Zall.size());
+    {
+        nce::CoarseMultiWs ws;
+        ws.reserve(nmax);
+        for (int q = 0; q < S; ++q) {
+            if (kq[q] == 0) continue;
+            const int g = bt->seg_group[q];
+            nce_ctx* c = bt->groups[g];
+            const int64_t f0 = c->cfg_first[q - bt->g_seg0[g]];
+            nce::coarse_multi_enqueue(s, c->tab.problem, Nq[q], c->d_frames.p + 9 * f0,
+                                      bt->d_dZ.p + pseg[q] * nce::kDefl, dS.p + pseg[q] * nce::kDefl, ws);
+        }
+        std::vector<double> Sall(Zall.size());
+        HIPCHK(hipMemcpyAsync(Sall.data(), dS.p, sizeof(double) * Sall.size(), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));  // before the scratch is released
+        const int bad = nce::deflation_inverses(S, Nq.data(), pseg.data(), kq.data(), chi0.data(), Zall.data(),
+                                                Sall.data(), Mall.data());
+        if (bad >= 0) throw std::runtime_error("singular coarse deflation matrix");
+    }
+    bt->d_dM.upload(Mall, s);
+    bt->d_pseg.upload(pseg, s);
+    bt->d_patch_seg.upload(pcfg, s);
+    bt->d_dd.alloc((size_t)S * nce::kDefl);
+    bt->d_dtmp.alloc((size_t)bt->n);
+    HIPCHK(hipStreamSynchronize(s));
+    bt->have_defl = true;
+}
+
+void drop_graphs(nce_batch* bt) {
+    for (auto& gr : bt->graph)
+        if (gr) {
+            (void)hipGraphExecDestroy(gr);
+            gr = nullptr;
+        }
 }
 
 void ensure_solver(nce_batch* bt, int maxit) {
@@ -335,6 +411,10 @@ void arnoldi_step(nce_batch* bt, int precision) {
     const int64_t ldv = bt->n;
     double* V = bt->d_V.p;
     hipLaunchKernelGGL(k_copy_vj, grid_for(bt->n), dim3(256), 0, s, V, ldv, bt->d_j.p, bt->n, bt->d_xin.p);
+    // deflated inner solves iterate on A M^{-1}
+    if (deflated(bt, precision))
+        HIPCHK(nce::deflation_apply_batched(s, bt->B, bt->n / bt->K, bt->K, bt->d_pseg.p, bt->d_patch_seg.p,
+                                            bt->d_dZ.p, bt->d_dM.p, bt->d_active.p, bt->d_dd.p, bt->d_xin.p));
     // configurations that have converged (active = 0) skip their sums
     batch_matvec(bt, bt->d_xin.p, bt->d_w.p, precision, bt->d_active.p);
     // classical Gram-Schmidt twice for FP64, once for the FP32 inner solves of
@@ -428,8 +508,18 @@ void gmres_batch(nce_batch* bt, const double* rhs, double* x, const std::vector<
     }
     hipLaunchKernelGGL(k_backsolve, dim3((S + 63) / 64), dim3(64), 0, s, S, bt->d_R.p, bt->d_g.p, maxit,
                        bt->d_mused.p, bt->d_y.p);
-    hipLaunchKernelGGL(k_seg_combine, dim3(bt->nch), dim3(256), 0, s, bt->d_V.p, (int64_t)bt->n, bt->d_y.p, maxit,
-                       bt->d_mused.p, bt->d_ch_e0.p, bt->d_ch_seg.p, x);
+    if (deflated(bt, precision)) {
+        // x += M^{-1} (V y)
+        HIPCHK(nce::fill(s, bt->n, 0.0, bt->d_dtmp.p));
+        hipLaunchKernelGGL(k_seg_combine, dim3(bt->nch), dim3(256), 0, s, bt->d_V.p, (int64_t)bt->n, bt->d_y.p,
+                           maxit, bt->d_mused.p, bt->d_ch_e0.p, bt->d_ch_seg.p, bt->d_dtmp.p);
+        HIPCHK(nce::deflation_apply_batched(s, bt->B, bt->n / bt->K, bt->K, bt->d_pseg.p, bt->d_patch_seg.p,
+                                            bt->d_dZ.p, bt->d_dM.p, nullptr, bt->d_dd.p, bt->d_dtmp.p));
+        HIPCHK(nce::axpby(s, bt->n, 1.0, bt->d_dtmp.p, 1.0, x));
+    } else {
+        hipLaunchKernelGGL(k_seg_combine, dim3(bt->nch), dim3(256), 0, s, bt->d_V.p, (int64_t)bt->n, bt->d_y.p,
+                           maxit, bt->d_mused.p, bt->d_ch_e0.p, bt->d_ch_seg.p, x);
+    }
     HIPCHK(hipGetLastError());
     std::vector<double> e(S);
     HIPCHK(hipMemcpyAsync(steps.data(), bt->d_mused.p, sizeof(int) * S, hipMemcpyDeviceToHost, s));
@@ -500,6 +590,7 @@ std::vector<double> batch_residual(nce_batch* bt, std::vector<double>& bn) {
 int solve_batch(nce_batch* bt, double* results, double* coeffs, nce_info* infos) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = bt->stream;
+    if (bt->precision == NCE_MIXED && bt->deflation) ensure_batch_deflation(bt);
     const int S = bt->B;
     const int64_t npatch = bt->n / bt->K;
     hipLaunchKernelGGL(k_init_rhs, grid_for(bt->n), dim3(256), 0, s, npatch, bt->K, bt->d_b.p, bt->d_x.p);
@@ -800,6 +891,7 @@ int nce_setup_batch(const double* const* centers, const int64_t* N, const double
         bt->d_flux.alloc(bt->n / bt->K);
         bt->tol = o.tol_gmres;
         bt->precision = o.precision;
+        bt->deflation = o.deflation != 0;
         ensure_solver(bt, o.max_iter);
         HIPCHK(hipStreamSynchronize(bt->stream));
         *out = guard.release();
@@ -914,6 +1006,17 @@ int nce_batch_set_warm_start(nce_batch* bt, nce_mlp* m, int use_coarse) {
         // per-layout preprocessing now, not inside the next solve
         if (bt->warm_coarse) batch_coarse(bt);
         if (bt->warm) batch_features(bt);
+        return NCE_OK;
+    });
+}
+
+int nce_batch_set_deflation(nce_batch* bt, int on) {
+    if (!bt) return fail(NCE_EINVAL, "batch is NULL");
+    if (on != 0 && on != 1) return fail(NCE_EINVAL, "on must be 0 or 1");
+    return guarded([&]() -> int {
+        if (bt->deflation != (on == 1)) drop_graphs(bt);  // the captured step differs
+        bt->deflation = on == 1;
+        if (bt->deflation && bt->precision == NCE_MIXED) ensure_batch_deflation(bt);
         return NCE_OK;
     });
 }

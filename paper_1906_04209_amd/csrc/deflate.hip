@@ -145,30 +145,115 @@ __global__ __launch_bounds__(256) void k_defl_update(int N, int K, const double*
     }
 }
 
+// Batched form, one block per configuration c (patches [pseg[c], pseg[c + 1])):
+// d[c] = M_c Z_c^T v[:, 0]; inactive configurations get d[c] = 0.
+__global__ __launch_bounds__(256) void k_bdefl_dots(int K, const int64_t* __restrict__ pseg,
+                                                    const double* __restrict__ Z, const double* __restrict__ M,
+                                                    const int* __restrict__ active, const double* __restrict__ v,
+                                                    double* __restrict__ d) {
+    __shared__ double red[kDefl][256];
+    __shared__ double c[kDefl];
+    const int cf = blockIdx.x;
+    const bool on = !active || active[cf];
+    const int64_t p0 = pseg[cf], p1 = pseg[cf + 1];
+    double acc[kDefl];
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) acc[q] = 0.0;
+    if (on)
+        for (int64_t i = p0 + threadIdx.x; i < p1; i += blockDim.x) {
+            const double x = v[i * K];
+#pragma unroll
+            for (int q = 0; q < kDefl; ++q) acc[q] += Z[i * kDefl + q] * x;
+        }
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < kDefl; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kDefl) c[threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < kDefl) {
+        const double* Mc = M + (int64_t)cf * kDefl * kDefl + threadIdx.x * kDefl;
+        double s = 0.0;
+        for (int r = 0; r < kDefl; ++r) s += Mc[r] * c[r];
+        d[(int64_t)cf * kDefl + threadIdx.x] = on ? s : 0.0;
+    }
+}
+
+// v[i][0] += sum_q Z[i][q] d[cfg(i)][q] for every patch i
+__global__ __launch_bounds__(256) void k_bdefl_update(int64_t npatch, int K, const int* __restrict__ patch_cfg,
+                                                      const double* __restrict__ Z, const double* __restrict__ d,
+                                                      double* __restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npatch) return;
+    const double* dc = d + (int64_t)patch_cfg[i] * kDefl;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q) s += Z[i * kDefl + q] * dc[q];
+    v[i * K] += s;
+}
+
 }  // namespace
 
-void coarse_multi(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S) {
+CoarseMultiWs::~CoarseMultiWs() {
+    for (void* p : {(void*)pos, (void*)zf, (void*)partial})
+        if (p) (void)hipFree(p);
+}
+
+namespace {
+int coarse_splits(int N) {
     const int ntb = (N + 255) / 256;
-    const int nsplit = std::max(1, std::min((N + kMTile - 1) / kMTile, (2048 + ntb - 1) / ntb));
+    return std::max(1, std::min((N + kMTile - 1) / kMTile, (2048 + ntb - 1) / ntb));
+}
+}  // namespace
+
+void CoarseMultiWs::reserve(int N) {
+    const size_t np = (size_t)N, npart = (size_t)coarse_splits(N) * N * kDefl;
+    if (np > cap_n) {
+        if (pos) (void)hipFree(pos);
+        if (zf) (void)hipFree(zf);
+        pos = nullptr;
+        zf = nullptr;
+        cap_n = 0;
+        chk(hipMalloc((void**)&pos, sizeof(float4) * np), "hipMalloc");
+        chk(hipMalloc((void**)&zf, sizeof(float) * np * kDefl), "hipMalloc");
+        cap_n = np;
+    }
+    if (npart > cap_part) {
+        if (partial) (void)hipFree(partial);
+        partial = nullptr;
+        cap_part = 0;
+        chk(hipMalloc((void**)&partial, sizeof(double) * npart), "hipMalloc");
+        cap_part = npart;
+    }
+}
+
+void coarse_multi_enqueue(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S,
+                          CoarseMultiWs& ws) {
+    const int ntb = (N + 255) / 256;
+    const int nsplit = coarse_splits(N);
     const int chunk = (N + nsplit - 1) / nsplit;
-    float4* pos = nullptr;
-    float* zf = nullptr;
-    double* partial = nullptr;
-    chk(hipMalloc((void**)&pos, sizeof(float4) * (size_t)N), "hipMalloc");
-    chk(hipMalloc((void**)&zf, sizeof(float) * (size_t)N * kDefl), "hipMalloc");
-    chk(hipMalloc((void**)&partial, sizeof(double) * (size_t)nsplit * N * kDefl), "hipMalloc");
-    hipLaunchKernelGGL(k_defl_src, dim3(ntb), dim3(256), 0, s, N, frames_dev, Z, pos, zf);
+    if ((size_t)N > ws.cap_n || (size_t)nsplit * N * kDefl > ws.cap_part)
+        throw std::runtime_error("coarse_multi workspace too small");
+    hipLaunchKernelGGL(k_defl_src, dim3(ntb), dim3(256), 0, s, N, frames_dev, Z, ws.pos, ws.zf);
     if (problem == 1)
-        hipLaunchKernelGGL(k_coarse_multi<1>, dim3(ntb, nsplit), dim3(256), 0, s, N, pos, zf, chunk, partial);
+        hipLaunchKernelGGL(k_coarse_multi<1>, dim3(ntb, nsplit), dim3(256), 0, s, N, ws.pos, ws.zf, chunk, ws.partial);
     else
-        hipLaunchKernelGGL(k_coarse_multi<0>, dim3(ntb, nsplit), dim3(256), 0, s, N, pos, zf, chunk, partial);
+        hipLaunchKernelGGL(k_coarse_multi<0>, dim3(ntb, nsplit), dim3(256), 0, s, N, ws.pos, ws.zf, chunk, ws.partial);
     const int64_t n = (int64_t)N * kDefl;
-    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsplit, partial, S);
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, nsplit, ws.partial, S);
     chk(hipGetLastError(), "coarse_multi");
+}
+
+void coarse_multi(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S) {
+    CoarseMultiWs ws;
+    ws.reserve(N);
+    coarse_multi_enqueue(s, problem, N, frames_dev, Z, S, ws);
     chk(hipStreamSynchronize(s), "sync");
-    (void)hipFree(pos);
-    (void)hipFree(zf);
-    (void)hipFree(partial);
 }
 
 Deflation::~Deflation() {
@@ -176,57 +261,53 @@ Deflation::~Deflation() {
         if (p) (void)hipFree(p);
 }
 
+int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::vector<double>& frames,
+                     const double* frames_dev, std::vector<double>& Zh, std::vector<double>& M,
+                     std::vector<double>* Tout) {
+    M.assign((size_t)kDefl * kDefl, 0.0);
+    if (N < kDeflMinN) {
+        Zh.assign((size_t)N * kDefl, 0.0);
+        if (Tout) Tout->clear();
+        return 0;
+    }
+    const int k = deflation_basis(frames, N, Zh);
+    double* Zd = nullptr;
+    double* Sd = nullptr;
+    chk(hipMalloc((void**)&Zd, sizeof(double) * Zh.size()), "hipMalloc");
+    if (hipMalloc((void**)&Sd, sizeof(double) * Zh.size()) != hipSuccess) {
+        (void)hipFree(Zd);
+        throw std::runtime_error("hipMalloc failed");
+    }
+    std::vector<double> Sh(Zh.size());
+    try {
+        chk(hipMemcpyAsync(Zd, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, s), "copy");
+        coarse_multi(s, problem, N, frames_dev, Zd, Sd);
+        chk(hipMemcpy(Sh.data(), Sd, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost), "copy");
+    } catch (...) {
+        (void)hipFree(Zd);
+        (void)hipFree(Sd);
+        throw;
+    }
+    (void)hipFree(Zd);
+    (void)hipFree(Sd);
+    // T = Z^T (I + chi0 G) Z on the k independent columns (Z^T Z = I)
+    std::vector<double> T;
+    deflation_coarse_matrix(Zh, Sh, N, k, chi0, T);
+    if (Tout) *Tout = T;
+    if (!deflation_invert(T, k, M)) throw std::runtime_error("singular coarse deflation matrix");
+    return k;
+}
+
 void Deflation::build(hipStream_t s, int N_, int K_, int problem, double chi0, const std::vector<double>& frames,
                       const double* frames_dev) {
     N = N_;
     K = K_;
-    std::vector<double> Zh;
-    k = deflation_basis(frames, N, Zh);
+    std::vector<double> Zh, M;
+    k = deflation_member(s, N, problem, chi0, frames, frames_dev, Zh, M, &T);
     chk(hipMalloc((void**)&Z, sizeof(double) * Zh.size()), "hipMalloc");
     chk(hipMalloc((void**)&Minv, sizeof(double) * kDefl * kDefl), "hipMalloc");
     chk(hipMalloc((void**)&partial, sizeof(double) * kDotBlocks * kDefl), "hipMalloc");
     chk(hipMemcpyAsync(Z, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, s), "copy");
-    double* Sd = nullptr;
-    chk(hipMalloc((void**)&Sd, sizeof(double) * Zh.size()), "hipMalloc");
-    coarse_multi(s, problem, N, frames_dev, Z, Sd);
-    std::vector<double> Sh(Zh.size());
-    chk(hipMemcpy(Sh.data(), Sd, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost), "copy");
-    (void)hipFree(Sd);
-    // T = Z^T (I + chi0 G) Z on the k independent columns (Z^T Z = I)
-    std::vector<double> T;
-    deflation_gram(Zh, Sh, N, k, T);
-    for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) T[(size_t)a * k + b] = (a == b ? 1.0 : 0.0) + chi0 * T[(size_t)a * k + b];
-    this->T = T;
-    // T^{-1} by Gauss-Jordan elimination with partial pivoting
-    std::vector<double> inv((size_t)k * k, 0.0);
-    for (int a = 0; a < k; ++a) inv[(size_t)a * k + a] = 1.0;
-    for (int col = 0; col < k; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < k; ++r)
-            if (std::fabs(T[(size_t)r * k + col]) > std::fabs(T[(size_t)piv * k + col])) piv = r;
-        if (!(std::fabs(T[(size_t)piv * k + col]) > 0.0)) throw std::runtime_error("singular coarse deflation matrix");
-        for (int c = 0; c < k; ++c) {
-            std::swap(T[(size_t)col * k + c], T[(size_t)piv * k + c]);
-            std::swap(inv[(size_t)col * k + c], inv[(size_t)piv * k + c]);
-        }
-        const double d = T[(size_t)col * k + col];
-        for (int c = 0; c < k; ++c) {
-            T[(size_t)col * k + c] /= d;
-            inv[(size_t)col * k + c] /= d;
-        }
-        for (int r = 0; r < k; ++r)
-            if (r != col) {
-                const double f = T[(size_t)r * k + col];
-                for (int c = 0; c < k; ++c) {
-                    T[(size_t)r * k + c] -= f * T[(size_t)col * k + c];
-                    inv[(size_t)r * k + c] -= f * inv[(size_t)col * k + c];
-                }
-            }
-    }
-    std::vector<double> M((size_t)kDefl * kDefl, 0.0);
-    for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) M[(size_t)a * kDefl + b] = inv[(size_t)a * k + b] - (a == b ? 1.0 : 0.0);
     chk(hipMemcpyAsync(Minv, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, s), "copy");
     chk(hipStreamSynchronize(s), "sync");
 }
@@ -240,6 +321,16 @@ hipError_t Deflation::apply(hipStream_t s, const double* in, double* out) const 
     hipLaunchKernelGGL(k_defl_dots, dim3(nb), dim3(256), 0, s, N, K, Z, in, partial);
     const int nu = std::max(1, std::min(1024, (N + 255) / 256));
     hipLaunchKernelGGL(k_defl_update, dim3(nu), dim3(256), 0, s, N, K, Z, Minv, partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t deflation_apply_batched(hipStream_t s, int ncfg, int64_t npatch, int K, const int64_t* pseg,
+                                   const int* patch_cfg, const double* Z, const double* M, const int* active,
+                                   double* d, double* v) {
+    if (ncfg <= 0 || npatch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bdefl_dots, dim3(ncfg), dim3(256), 0, s, K, pseg, Z, M, active, v, d);
+    hipLaunchKernelGGL(k_bdefl_update, dim3((unsigned)((npatch + 255) / 256)), dim3(256), 0, s, npatch, K, patch_cfg,
+                       Z, d, v);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ namespace nce {
 
 constexpr int kDefl = 16;  // basis columns (padded with zeros when the layout gives fewer); equals
                            // the count of deflate_basis.cpp
+constexpr int kDeflMinN = 64;  // configurations with fewer patches are not deflated
 
 struct Deflation {
     int N = 0, K = 0, k = 0;         // k = independent basis columns (<= kDefl)
@@ -45,6 +46,23 @@ struct Deflation {
     hipError_t apply(hipStream_t s, const double* in, double* out) const;
 };
 
+// One configuration's deflation data on the host: Z (N x kDefl, zero beyond
+// the k independent columns) and M = T^{-1} - I (kDefl x kDefl, zero beyond
+// k); T (k x k) into *T when given. Returns k; N < kDeflMinN gives k = 0 and
+// zero Z and M (the apply is then the identity).
+int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::vector<double>& frames,
+                     const double* frames_dev, std::vector<double>& Z, std::vector<double>& M,
+                     std::vector<double>* T);
+
+// M^{-1} for ncfg configurations stored one after another (configuration c =
+// patches [pseg[c], pseg[c + 1]), patch_cfg[i] = c; Z: npatch x kDefl, M: ncfg
+// x kDefl x kDefl, d: ncfg x kDefl scratch; all device), in place on v (npatch
+// x K, e_0 coefficients changed). Configurations with active[c] = 0 (active
+// may be null) are left unchanged. Two launches, no allocation.
+hipError_t deflation_apply_batched(hipStream_t s, int ncfg, int64_t npatch, int K, const int64_t* pseg,
+                                   const int* patch_cfg, const double* Z, const double* M, const int* active,
+                                   double* d, double* v);
+
 // Host: orthonormal basis (modified Gram-Schmidt, twice) of the monomials of
 // degree <= 3 in the centres c_i = frames[9 i .. 9 i + 2]; returns the number
 // of independent columns and fills Z (N x kDefl, zero beyond them).
@@ -55,6 +73,39 @@ void deflation_gram(const std::vector<double>& Z, const std::vector<double>& S, 
 
 // S_i = sum_{j != i} G(c_i, c_j) Z_j for the kDefl columns at once (FP32 pair
 // sums, FP64 accumulation); Z, S: N x kDefl row-major device arrays.
+// Synchronous, with its own scratch.
 void coarse_multi(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S);
+
+// Device scratch of coarse_multi_enqueue, reusable across configurations in
+// stream order; reserve(N) before enqueueing configurations of up to N patches.
+struct CoarseMultiWs {
+    float4* pos = nullptr;
+    float* zf = nullptr;
+    double* partial = nullptr;
+    size_t cap_n = 0, cap_part = 0;
+    CoarseMultiWs() = default;
+    CoarseMultiWs(const CoarseMultiWs&) = delete;
+    CoarseMultiWs& operator=(const CoarseMultiWs&) = delete;
+    ~CoarseMultiWs();
+    void reserve(int N);
+};
+// As coarse_multi, only enqueued (no allocation, no synchronization).
+void coarse_multi_enqueue(hipStream_t s, int problem, int N, const double* frames_dev, const double* Z, double* S,
+                          CoarseMultiWs& ws);
+
+// Host (deflate_basis.cpp): T = I + chi0 Z^T S on the k independent columns;
+// M = T^{-1} - I padded to kDefl x kDefl (false if T is singular).
+void deflation_coarse_matrix(const std::vector<double>& Z, const std::vector<double>& S, int N, int k, double chi0,
+                             std::vector<double>& T);
+bool deflation_invert(std::vector<double> T, int k, std::vector<double>& M);
+// Host, in parallel over configurations: the bases of ncfg configurations
+// (frames fr[c], N[c] patches, rows at Zall + kDefl off[c]; N[c] < nmin gives
+// k[c] = 0 and zero rows), and M_c = T_c^{-1} - I of each from its coarse
+// products Sall (same layout) into Mall (ncfg x kDefl x kDefl); the latter
+// returns a configuration whose T is singular, or -1.
+void deflation_bases(int ncfg, const double* const* fr, const int* N, const int64_t* off, int nmin, double* Zall,
+                     int* k);
+int deflation_inverses(int ncfg, const int* N, const int64_t* off, const int* k, const double* chi0,
+                       const double* Zall, const double* Sall, double* Mall);
 
 }  // namespace nce

@@ -623,10 +623,14 @@ static FarTable compress_outgoing(int problem, double D, double tol_id, const st
     for (int a = 0; a < p; ++a)
         for (int k = 0; k < K; ++k) out.T[(size_t)a * K + k] = wB[(size_t)piv[a] * K + k];
     const int nrest = nf - p;
+    // per-thread partial sums, added in thread order afterwards (the same
+    // result for a given thread count, whatever the scheduling)
+    std::vector<std::vector<double>> Tparts((size_t)omp_get_max_threads());
 #pragma omp parallel
     {
         std::vector<double> z(p);
-        std::vector<double> Tloc((size_t)p * K, 0.0);
+        std::vector<double>& Tloc = Tparts[(size_t)omp_get_thread_num()];
+        Tloc.assign((size_t)p * K, 0.0);
 #pragma omp for schedule(static)
         for (int j = 0; j < nrest; ++j) {
             const int col = p + j;
@@ -642,9 +646,9 @@ static FarTable compress_outgoing(int problem, double D, double tol_id, const st
                 for (int k = 0; k < K; ++k) tr[k] += za * wb[k];
             }
         }
-#pragma omp critical(nce_tred)
-        for (size_t q = 0; q < Tloc.size(); ++q) out.T[q] += Tloc[q];
     }
+    for (const std::vector<double>& Tloc : Tparts)
+        for (size_t q = 0; q < Tloc.size(); ++q) out.T[q] += Tloc[q];
     out.skel_t.resize(p);
     out.skel_theta.resize(p);
     out.skel_off.resize((size_t)3 * p);

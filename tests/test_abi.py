@@ -73,6 +73,16 @@ def test_invalid_arguments(case):
     assert rc == -1 and not h.value and msg
 
 
+def test_null_handles_rejected():
+    """Entry points on a NULL context or batch fail with NCE_EINVAL and a
+    message, before any device work."""
+    lib = nce.load()
+    for fn, args in [(lib.nce_set_deflation, (None, 1)), (lib.nce_batch_set_deflation, (None, 1)),
+                     (lib.nce_batch_set_warm_start, (None, None, 1))]:
+        assert fn(*args) == -1
+        assert lib.nce_last_error()
+
+
 def test_separation_rule():
     # centres 2.9 eps apart in arclength violate the 3 eps rule (Section 3)
     eps = 0.05

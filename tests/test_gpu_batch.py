@@ -147,3 +147,42 @@ def test_batch_coarse_and_learned_start(torch):
         assert rel < 1e-8
         if len(mem[b][0]) > 1:
             assert iw["rel_residual_x0"] < 0.5 and not iw["used_fallback"]
+
+
+def test_batch_deflation(torch):
+    """The per-member deflation of the mixed inner solves changes how many FP32
+    steps a member takes, not what it converges to: the results with and
+    without it agree with each other and with deflated single solves; members
+    below 64 patches and with one patch are left undeflated; toggling it
+    rebuilds the captured step, and a repeated solve is bit-identical."""
+    import paper_1906_04209_amd as nce
+    spec = [(1500, 0.01, 0), (800, 0.01, 0), (40, 0.01, 0), (1200, 0.02, 1), (1, 0.01, 0), (600, 0.02, 1)]
+    mem = [(layouts.uniform_centers(N, eps, 900 + k), eps, prob) for k, (N, eps, prob) in enumerate(spec)]
+    bt = nce.Batch(mem, tol_id=1e-10, tol_gmres=1e-10, precision=nce.MIXED, max_iter=60)
+    on = bt.solve()
+    bt.set_deflation(False)
+    off = bt.solve()
+    bt.set_deflation(True)
+    again = bt.solve()
+    assert on["converged"] and off["converged"] and again["converged"]
+    assert np.array_equal(again["result"], on["result"])
+    n_on = n_off = 0
+    for b, (c, eps, prob) in enumerate(mem):
+        i_on, i_off = on["info"][b], off["info"][b]
+        rel = abs(on["result"][b] - off["result"][b]) / abs(off["result"][b])
+        ctx = nce.Context(c, eps, problem=prob, tol_id=1e-10, tol_gmres=1e-10, precision=nce.MIXED)
+        s = ctx.solve(want_coeffs=False, want_flux=False)
+        ref = s["mu"] if prob == nce.INTERIOR else s["capture_rate"]
+        rel_single = abs(on["result"][b] - ref) / abs(ref)
+        print(f"member {b} N={len(c)}: FP32 steps deflated {i_on['iters_fp32']} plain {i_off['iters_fp32']}; "
+              f"on vs off {rel:.1e}, vs single deflated solve {rel_single:.1e} (single {s['iters_fp32']} steps)")
+        assert i_on["rel_residual"] <= 1e-10 * 1.0001 and i_off["rel_residual"] <= 1e-10 * 1.0001
+        assert rel < 1e-8 and rel_single < 1e-8
+        if len(c) < 64:
+            assert i_on["iters_fp32"] == i_off["iters_fp32"]
+        else:
+            n_on += i_on["iters_fp32"]
+            n_off += i_off["iters_fp32"]
+        ctx.close()
+    assert n_on < n_off
+    bt.close()

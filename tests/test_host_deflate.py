@@ -2,6 +2,7 @@
 with g++, no GPU): orthonormal columns spanning the polynomials of degree <= 3
 on the patch centres, equal to the modified Gram-Schmidt result written out
 here in numpy."""
+import os
 import subprocess
 from pathlib import Path
 
@@ -54,6 +55,11 @@ def test_deflation_basis(exe, tmp_path, kind):
         fh.write(f"{len(c)}\n")
         np.savetxt(fh, fr, fmt="%.17g")
     out = subprocess.run([str(exe), str(f)], capture_output=True, text=True, check=True).stdout.splitlines()
+    # bit-identical whatever the thread count (fixed-order reductions)
+    for nt in ("1", "3"):
+        env = dict(os.environ, OMP_NUM_THREADS=nt)
+        assert subprocess.run([str(exe), str(f)], capture_output=True, text=True, check=True,
+                              env=env).stdout.splitlines() == out
     k = int(out[0])
     Z = np.loadtxt(out[1:])
     assert k == 16
