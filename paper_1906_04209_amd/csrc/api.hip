@@ -378,9 +378,8 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
     // coarse-space deflation of the inner solves, once per context (inside the timed solve)
     if (ctx->opts.precision == NCE_MIXED && ctx->opts.deflation) ensure_deflation(ctx);
     // b = P 1 = e_0 on every patch
-    std::vector<double> hb((size_t)n, 0.0);
-    for (int64_t i = 0; i < N; ++i) hb[(size_t)i * ctx->K] = 1.0;
-    ctx->d_b.upload(hb, s);
+    if (ctx->d_b.n < (size_t)n) ctx->d_b.alloc((size_t)n);
+    HIPCHK(nce::unit_rhs(s, N, ctx->K, ctx->d_b.p));
     double* x = ctx->d_x.p;
     HIPCHK(nce::fill(s, n, 0.0, x));
     const double tol = ctx->opts.tol_gmres;

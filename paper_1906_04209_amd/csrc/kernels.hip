@@ -371,6 +371,17 @@ hipError_t fill(hipStream_t s, int64_t n, double v, double* x) {
     return hipGetLastError();
 }
 
+__global__ void k_unit_rhs(int64_t n, int K, double* __restrict__ b) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        b[e] = e % K == 0 ? 1.0 : 0.0;
+}
+
+hipError_t unit_rhs(hipStream_t s, int64_t N, int K, double* b) {
+    const int64_t n = N * K;
+    hipLaunchKernelGGL(k_unit_rhs, ew_grid(n), dim3(256), 0, s, n, K, b);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_flux(int N, int K, const double* __restrict__ I, const double* __restrict__ x,
                                               double* __restrict__ flux, double* __restrict__ partial) {
     __shared__ double red[4];

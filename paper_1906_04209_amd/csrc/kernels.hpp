@@ -61,6 +61,8 @@ hipError_t combine(hipStream_t s, int64_t n, int nv, const double* V, int64_t ld
 hipError_t cast_d2f(hipStream_t s, int64_t n, const double* x, float* y);
 hipError_t cast_f2d(hipStream_t s, int64_t n, const float* x, double* y);
 hipError_t fill(hipStream_t s, int64_t n, double v, double* x);
+// b = e_0 on each of N patches (the right-hand side P 1), N x K
+hipError_t unit_rhs(hipStream_t s, int64_t N, int K, double* b);
 // x[i][k] = a[i] m[i][k] (m: N x K FP32), or a[i] [k == 0] when m is null
 hipError_t rows_scale(hipStream_t s, int64_t N, int K, const double* a, const float* m, double* x);
 // flux[i] = sum_k I[k] x[i][k]; total written to *sum (two-stage)
