@@ -93,8 +93,9 @@ typedef struct nce_opts {
                              coarse-space deflation (not in the paper): the 16 polynomials of degree
                              <= 3 in the patch centres, in every patch's first coefficient, with the
                              coarse (monopole) model of the system on them; built at the first mixed
-                             solve of a context with N >= 64. 0: off. The FP64 solves are never
-                             preconditioned. Default 1 */
+                             solve or coarse solve of a context with N >= 64, and it also
+                             preconditions the coarse solve of the initial guess. 0: off. The FP64
+                             solves are never preconditioned. Default 1 */
 } nce_opts;
 
 typedef struct nce_info {

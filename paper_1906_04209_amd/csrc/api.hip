@@ -161,7 +161,8 @@ double coarse_chi0(const nce_ctx* ctx) {
     return chi0;
 }
 
-// Builds the coarse-space deflation of the mixed inner solves (N >= 64).
+// Builds the coarse-space deflation of the mixed inner solves and the coarse
+// solve (N >= 64).
 void ensure_deflation(nce_ctx* ctx) {
     if (ctx->defl || ctx->N < nce::kDeflMinN) return;
     auto d = std::make_unique<nce::Deflation>();
@@ -176,7 +177,11 @@ const double* coarse_amplitudes(nce_ctx* ctx) {
     if (!ctx->coarse)
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
     ctx->d_a.alloc((size_t)ctx->N);
-    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, (int)ctx->N, ctx->d_frames.p, ctx->opts.tol_coarse, ctx->d_a.p);
+    // the deflation's smooth modes are the coarse model's own slow ones: it
+    // preconditions this solve as well
+    if (ctx->opts.deflation) ensure_deflation(ctx);
+    ctx->coarse_iters = ctx->coarse->solve(ctx->stream, (int)ctx->N, ctx->d_frames.p, ctx->opts.tol_coarse, ctx->d_a.p,
+                                           ctx->opts.deflation ? ctx->defl.get() : nullptr);
     return ctx->d_a.p;
 }
 

@@ -146,10 +146,11 @@ CoarseSolver::CoarseSolver(int N_, int problem_, double chi0_, int maxit_)
     chk(hipMalloc((void**)&h, sizeof(double) * (size_t)(maxit + 2)), "hipMalloc");
     chk(hipMalloc((void**)&rpart, sizeof(double) * (size_t)kReduceBlocks * (maxit + 2)), "hipMalloc");
     chk(hipMalloc((void**)&scal, sizeof(double) * 8), "hipMalloc");
+    chk(hipMalloc((void**)&tmp, sizeof(double) * (size_t)N), "hipMalloc");
 }
 
 CoarseSolver::~CoarseSolver() {
-    for (void* p : {(void*)src, (void*)part, (void*)V, (void*)h, (void*)rpart, (void*)scal})
+    for (void* p : {(void*)src, (void*)part, (void*)V, (void*)h, (void*)rpart, (void*)scal, (void*)tmp})
         if (p) (void)hipFree(p);
 }
 
@@ -166,9 +167,11 @@ void CoarseSolver::apply(hipStream_t s, int n, const double* frames, const doubl
     chk(hipGetLastError(), "coarse apply");
 }
 
-int CoarseSolver::solve(hipStream_t s, int nn, const double* frames, double tol, double* a) {
-    // GMRES (CGS2, Givens on the host) for C a = 1 from a = 0
+int CoarseSolver::solve(hipStream_t s, int nn, const double* frames, double tol, double* a, const Deflation* defl) {
+    // GMRES (CGS2, Givens on the host) for C a = 1 from a = 0; with defl on
+    // C M^{-1}, a = M^{-1} V y at the end
     if (nn < 1 || nn > N) throw std::runtime_error("coarse solve: layout larger than the solver");
+    if (defl && defl->N != nn) throw std::runtime_error("coarse solve: deflation of another layout");
     const int64_t n = nn;
     std::vector<double> one((size_t)n, 1.0);
     chk(hipMemcpyAsync(V, one.data(), sizeof(double) * n, hipMemcpyHostToDevice, s), "copy");
@@ -181,7 +184,12 @@ int CoarseSolver::solve(hipStream_t s, int nn, const double* frames, double tol,
     int k = 0;
     for (k = 0; k < maxit; ++k) {
         double* w = V + (int64_t)(k + 1) * n;
-        apply(s, nn, frames, V + (int64_t)k * n, w);
+        if (defl) {
+            chk(defl->apply_stride(s, V + (int64_t)k * n, tmp, 1), "deflation");
+            apply(s, nn, frames, tmp, w);
+        } else {
+            apply(s, nn, frames, V + (int64_t)k * n, w);
+        }
         for (int pass = 0; pass < 2; ++pass) {
             chk(dots(s, n, k + 1, V, n, w, rpart, h), "dots");
             chk(axpys(s, n, k + 1, V, n, h, w), "axpys");
@@ -224,6 +232,7 @@ int CoarseSolver::solve(hipStream_t s, int nn, const double* frames, double tol,
     }
     chk(hipMemcpyAsync(h, y.data(), sizeof(double) * m, hipMemcpyHostToDevice, s), "copy");
     chk(combine(s, n, m, V, n, h, a), "combine");
+    if (defl) chk(defl->apply_stride(s, a, a, 1), "deflation");
     chk(hipStreamSynchronize(s), "sync");
     return m;
 }

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "deflate.hpp"
+
 namespace nce {
 
 struct CoarseSolver {
@@ -18,6 +20,7 @@ struct CoarseSolver {
     double* h = nullptr;
     double* rpart = nullptr;
     double* scal = nullptr;
+    double* tmp = nullptr;   // N doubles: the preconditioned Krylov vector
 
     CoarseSolver(int N, int problem, double chi0, int maxit);
     ~CoarseSolver();
@@ -26,8 +29,10 @@ struct CoarseSolver {
     // y = C a for a layout of n <= N centres (device vectors of n doubles);
     // frames: n x 9 device (c, e1, e2)
     void apply(hipStream_t s, int n, const double* frames, const double* a, double* y);
-    // a = C^{-1} 1 to relative residual tol (GMRES); returns the iterations used
-    int solve(hipStream_t s, int n, const double* frames, double tol, double* a);
+    // a = C^{-1} 1 to relative residual tol (GMRES); returns the iterations
+    // used. With defl (built for this layout, n patches) GMRES runs on
+    // C M^{-1} with the deflation's M^{-1} acting on the amplitudes.
+    int solve(hipStream_t s, int n, const double* frames, double tol, double* a, const Deflation* defl = nullptr);
 };
 
 }  // namespace nce

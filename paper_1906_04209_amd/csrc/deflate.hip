@@ -312,15 +312,15 @@ void Deflation::build(hipStream_t s, int N_, int K_, int problem, double chi0, c
     chk(hipStreamSynchronize(s), "sync");
 }
 
-hipError_t Deflation::apply(hipStream_t s, const double* in, double* out) const {
+hipError_t Deflation::apply_stride(hipStream_t s, const double* in, double* out, int stride) const {
     if (out != in) {
-        const hipError_t e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)N * K, hipMemcpyDeviceToDevice, s);
+        const hipError_t e = hipMemcpyAsync(out, in, sizeof(double) * (size_t)N * stride, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
     const int nb = std::max(1, std::min(kDotBlocks, (N + 255) / 256));
-    hipLaunchKernelGGL(k_defl_dots, dim3(nb), dim3(256), 0, s, N, K, Z, in, partial);
+    hipLaunchKernelGGL(k_defl_dots, dim3(nb), dim3(256), 0, s, N, stride, Z, in, partial);
     const int nu = std::max(1, std::min(1024, (N + 255) / 256));
-    hipLaunchKernelGGL(k_defl_update, dim3(nu), dim3(256), 0, s, N, K, Z, Minv, partial, nb, out);
+    hipLaunchKernelGGL(k_defl_update, dim3(nu), dim3(256), 0, s, N, stride, Z, Minv, partial, nb, out);
     return hipGetLastError();
 }
 

@@ -43,7 +43,10 @@ struct Deflation {
     void build(hipStream_t s, int N, int K, int problem, double chi0, const std::vector<double>& frames,
                const double* frames_dev);
     // out = M^{-1} in for N x K vectors (out may equal in).
-    hipError_t apply(hipStream_t s, const double* in, double* out) const;
+    hipError_t apply(hipStream_t s, const double* in, double* out) const { return apply_stride(s, in, out, K); }
+    // the same for N x stride vectors (stride 1: one value per patch, as the
+    // coarse model's amplitudes)
+    hipError_t apply_stride(hipStream_t s, const double* in, double* out, int stride) const;
 };
 
 // One configuration's deflation data on the host: Z (N x kDefl, zero beyond
