@@ -40,7 +40,8 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels, per thread shape (4 or 8 grid points per thread, 0 = per-item
 # class: two launches over item lists, which read more through L2 misses).
-TRAFFIC = {("cfg5", "fp64", 4): 8.572e9, ("cfg5", "fp64", 8): 8.575e9, ("cfg5", "fp64", 0): 9.026e9}
+TRAFFIC = {("cfg5", "fp64", 4): 8.572e9, ("cfg5", "fp64", 8): 8.575e9, ("cfg5", "fp64", 0): 9.026e9,
+           ("cfg5", "fp32", 4): 5.002e9, ("cfg5", "fp32", 8): 4.554e9, ("cfg5", "fp32", 0): 5.021e9}
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
