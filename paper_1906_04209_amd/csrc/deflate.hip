@@ -124,12 +124,21 @@ __global__ __launch_bounds__(256) void k_defl_dots(int N, int K, const double* _
 __global__ __launch_bounds__(256) void k_defl_update(int N, int K, const double* __restrict__ Z,
                                                      const double* __restrict__ Minv, const double* __restrict__ partial,
                                                      int nb, double* __restrict__ out) {
+    __shared__ double red[kDefl][256];
     __shared__ double zt[kDefl], c[kDefl];
-    if (threadIdx.x < kDefl) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += partial[b * kDefl + threadIdx.x];
-        zt[threadIdx.x] = s;
+    // sum of the nb <= 256 block partials: one row per thread, then a tree in
+    // LDS (the same order in every block)
+#pragma unroll
+    for (int q = 0; q < kDefl; ++q)
+        red[q][threadIdx.x] = (int)threadIdx.x < nb ? partial[threadIdx.x * kDefl + q] : 0.0;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int q = 0; q < kDefl; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        __syncthreads();
     }
+    if (threadIdx.x < kDefl) zt[threadIdx.x] = red[threadIdx.x][0];
     __syncthreads();
     if (threadIdx.x < kDefl) {
         double s = 0.0;
