@@ -47,11 +47,14 @@ def test_default_opts():
     assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse, o.deflation) == (1e-4, 1e-6, 1e-5, 1)
 
 
-@pytest.mark.parametrize("case", ["nonunit", "nan", "eps0", "epsbig", "badM", "badprob", "badcoarse", "badgrid32", "baddefl"])
+@pytest.mark.parametrize("case", ["empty", "nonunit", "nan", "eps0", "epsbig", "badM", "badprob", "badcoarse",
+                                  "badgrid32", "baddefl"])
 def test_invalid_arguments(case):
     c = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
     eps, kw = 0.1, {}
-    if case == "nonunit":
+    if case == "empty":
+        c = np.zeros((0, 3))
+    elif case == "nonunit":
         c = c * 1.001
     elif case == "nan":
         c[1, 0] = np.nan
@@ -74,13 +77,20 @@ def test_invalid_arguments(case):
 
 
 def test_null_handles_rejected():
-    """Entry points on a NULL context or batch fail with NCE_EINVAL and a
-    message, before any device work."""
+    """Entry points on a NULL context or batch, and a batch of no
+    configurations, fail with NCE_EINVAL and a message, before any device
+    work."""
     lib = nce.load()
+    h = ctypes.c_void_p()
+    mu = ctypes.c_double()
     for fn, args in [(lib.nce_set_deflation, (None, 1)), (lib.nce_batch_set_deflation, (None, 1)),
-                     (lib.nce_batch_set_warm_start, (None, None, 1))]:
-        assert fn(*args) == -1
+                     (lib.nce_batch_set_warm_start, (None, None, 1)), (lib.nce_matvec, (None, None, None, 0)),
+                     (lib.nce_solve_interior, (None, None, None, ctypes.byref(mu), None)),
+                     (lib.nce_solve_batch, (None, None, None, None)), (lib.nce_batch_matvec, (None, None, None, 0)),
+                     (lib.nce_setup_batch, (None, None, None, None, 0, None, ctypes.byref(h)))]:
+        assert fn(*args) == -1, fn.__name__
         assert lib.nce_last_error()
+    assert not h.value
 
 
 def test_separation_rule():
