@@ -303,7 +303,12 @@ int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::
     std::vector<double> T;
     deflation_coarse_matrix(Zh, Sh, N, k, chi0, T);
     if (Tout) *Tout = T;
-    if (!deflation_invert(T, k, M)) throw std::runtime_error("singular coarse deflation matrix");
+    // a singular T (not met in practice) leaves the configuration undeflated:
+    // M = 0 makes M^{-1} the identity
+    if (!deflation_invert(T, k, M)) {
+        M.assign((size_t)kDefl * kDefl, 0.0);
+        return 0;
+    }
     return k;
 }
 

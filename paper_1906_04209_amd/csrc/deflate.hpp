@@ -51,8 +51,8 @@ struct Deflation {
 
 // One configuration's deflation data on the host: Z (N x kDefl, zero beyond
 // the k independent columns) and M = T^{-1} - I (kDefl x kDefl, zero beyond
-// k); T (k x k) into *T when given. Returns k; N < kDeflMinN gives k = 0 and
-// zero Z and M (the apply is then the identity).
+// k); T (k x k) into *T when given. Returns k; N < kDeflMinN (zero Z and M)
+// or a singular T (zero M) give 0, and the apply is then the identity.
 int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::vector<double>& frames,
                      const double* frames_dev, std::vector<double>& Z, std::vector<double>& M,
                      std::vector<double>* T);
@@ -105,7 +105,8 @@ bool deflation_invert(std::vector<double> T, int k, std::vector<double>& M);
 // (frames fr[c], N[c] patches, rows at Zall + kDefl off[c]; N[c] < nmin gives
 // k[c] = 0 and zero rows), and M_c = T_c^{-1} - I of each from its coarse
 // products Sall (same layout) into Mall (ncfg x kDefl x kDefl); the latter
-// returns a configuration whose T is singular, or -1.
+// leaves configurations with a singular T undeflated (M = 0) and returns
+// their count.
 void deflation_bases(int ncfg, const double* const* fr, const int* N, const int64_t* off, int nmin, double* Zall,
                      int* k);
 int deflation_inverses(int ncfg, const int* N, const int64_t* off, const int* k, const double* chi0,

@@ -166,11 +166,12 @@ void deflation_bases(int ncfg, const double* const* fr, const int* N, const int6
 }
 
 // M_c = T_c^{-1} - I of many configurations (Zall, Sall as for
-// deflation_bases; Mall: ncfg x 16 x 16, zero where k[c] = 0). Returns the
-// index of a configuration with a singular T, or -1.
+// deflation_bases; Mall: ncfg x 16 x 16, zero where k[c] = 0 or where T_c is
+// singular, which leaves that configuration undeflated). Returns how many
+// configurations had a singular T.
 int deflation_inverses(int ncfg, const int* N, const int64_t* off, const int* k, const double* chi0,
                        const double* Zall, const double* Sall, double* Mall) {
-    int bad = -1;
+    int bad = 0;
 #pragma omp parallel for schedule(dynamic)
     for (int c = 0; c < ncfg; ++c) {
         double* Mc = Mall + (size_t)c * kDeflHost * kDeflHost;
@@ -181,8 +182,8 @@ int deflation_inverses(int ncfg, const int* N, const int64_t* off, const int* k,
         std::vector<double> T, M;
         deflation_coarse_matrix(Z, S, N[c], k[c], chi0[c], T);
         if (!deflation_invert(T, k[c], M)) {
-#pragma omp critical(nce_defl_bad)
-            bad = c;
+#pragma omp atomic
+            ++bad;
             continue;
         }
         std::copy(M.begin(), M.end(), Mc);
