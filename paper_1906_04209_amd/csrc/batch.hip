@@ -254,6 +254,7 @@ struct nce_batch {
     DevBuf<int> d_active, d_mused, d_j, d_all;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int graph_maxit[2] = {0, 0};
+    bool graph_defl[2] = {false, false};   // whether the captured step applies the deflation
     // initial guess: per-member coarse solves, optionally refined by a network
     bool warm_coarse = false;
     nce::Mlp* warm = nullptr;
@@ -481,6 +482,11 @@ void gmres_batch(nce_batch* bt, const double* rhs, double* x, const std::vector<
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, bt->d_j.p);
     HIPCHK(hipGetLastError());
     const int gi = precision == NCE_FP64 ? 0 : 1;
+    // the captured step and the final combination must agree on the deflation
+    if (bt->graph[gi] && bt->graph_defl[gi] != deflated(bt, precision)) {
+        (void)hipGraphExecDestroy(bt->graph[gi]);
+        bt->graph[gi] = nullptr;
+    }
     if (bt->use_graph && !bt->graph[gi]) {
         hipGraph_t gr = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -497,6 +503,7 @@ void gmres_batch(nce_batch* bt, const double* rhs, double* x, const std::vector<
         (void)hipGraphDestroy(gr);
         HIPCHK(e);
         bt->graph[gi] = ex;
+        bt->graph_defl[gi] = deflated(bt, precision);
     }
     std::vector<int> a(S);
     for (int j = 0; j < maxit; ++j) {
