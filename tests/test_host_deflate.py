@@ -71,3 +71,43 @@ def test_deflation_basis(exe, tmp_path, kind):
     # the same columns as Gram-Schmidt on the harmonic polynomials in this order
     Q = mgs(harmonic_polys(c))
     assert np.max(np.abs(Z - Q)) < 1e-10
+
+
+@pytest.fixture(scope="module")
+def inv_exe(tmp_path_factory):
+    out = tmp_path_factory.mktemp("inv") / "invert_check"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", str(ROOT / "tests" / "host" / "invert_check.cpp"),
+                           str(CSRC / "deflate_basis.cpp"), "-o", str(out)])
+    return out
+
+
+def _invert(exe, tmp_path, T):
+    f = tmp_path / "T.txt"
+    with open(f, "w") as fh:
+        fh.write(f"{len(T)}\n")
+        np.savetxt(fh, T, fmt="%.17g")
+    out = subprocess.run([str(exe), str(f)], capture_output=True, text=True, check=True).stdout.splitlines()
+    return out[0], (np.loadtxt(out[1:]) if out[0] == "ok" else None)
+
+
+@pytest.mark.parametrize("k", [16, 7, 1])
+def test_deflation_inverse_matches_numpy(inv_exe, tmp_path, k):
+    """M = T^-1 - I on the first k rows and columns, zero padding beyond, for a
+    nonsymmetric T whose pivots need row exchanges (zero leading diagonal)."""
+    g = np.random.Generator(np.random.PCG64(70 + k))
+    T = np.eye(k) + 0.3 * g.standard_normal((k, k))
+    if k > 1:
+        T[0, 0] = 0.0
+    status, M = _invert(inv_exe, tmp_path, T)
+    assert status == "ok"
+    ref = np.zeros((16, 16))
+    ref[:k, :k] = np.linalg.inv(T) - np.eye(k)
+    assert np.max(np.abs(M - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_deflation_inverse_singular(inv_exe, tmp_path):
+    """A singular T is reported (the library then leaves the layout undeflated)."""
+    T = np.eye(5)
+    T[3] = T[1]
+    status, _ = _invert(inv_exe, tmp_path, T)
+    assert status == "singular"
