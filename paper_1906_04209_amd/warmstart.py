@@ -6,7 +6,8 @@ from the coarse (monopole) solve, which carries the long-range coupling of
 the whole layout, and m_i (K coefficients) is the network's prediction of the
 patch's own solution shape from its neighbourhood and a_i. Training data: for
 seeded layouts shaped like the small workloads (N=10 patches of radius 0.1,
-N=1000 of radius 0.01, uniform, area fraction 0.025, both problems), inputs
+N=1000 of radius 0.01, uniform, area fraction 0.025, both problems; optionally
+N=10,000 of radius 0.003 at the same area fraction), inputs
 are the NCE_FEATURES per-patch features and targets the FP64 solutions f_i
 divided by a_i.
 
@@ -47,7 +48,7 @@ def layout_samples(centers, eps, problem, tol_id=1e-11):
     return f, t, r
 
 
-def generate(n_small: int, n_large: int, base_seed: int = 0, log=print):
+def generate(n_small: int, n_large: int, base_seed: int = 0, log=print, n_xl: int = 0):
     import torch
     F, T = [], []
     t0 = time.time()
@@ -65,6 +66,15 @@ def generate(n_small: int, n_large: int, base_seed: int = 0, log=print):
         T.append(t)
         if s % 10 == 0:
             log(f"  data: layout {s + 1}/{n_large} iters {r['iters_fp64']} ({time.time() - t0:.0f} s)")
+    for s in range(n_xl):
+        # larger layouts at the same area fraction: the long-range coupling (and
+        # so the coarse amplitudes the network sees) of the benchmark sizes
+        c = layouts.uniform_centers(10000, 0.003, 30000 + base_seed + s)
+        prob = INTERIOR if s % 3 else EXTERIOR
+        f, t, r = layout_samples(c, 0.003, prob)
+        F.append(f)
+        T.append(t)
+        log(f"  data: N=10000 layout {s + 1}/{n_xl} iters {r['iters_fp64']} ({time.time() - t0:.0f} s)")
     return torch.cat(F), torch.cat(T)
 
 
@@ -128,15 +138,16 @@ def main():
     ap.add_argument("--out", default=str(WEIGHTS))
     ap.add_argument("--small", type=int, default=200)
     ap.add_argument("--large", type=int, default=50)
+    ap.add_argument("--xl", type=int, default=8, help="layouts of N=10,000 (eps 0.003)")
     ap.add_argument("--steps", type=int, default=6000)
     args = ap.parse_args()
     os.environ.setdefault("NCE_CACHE", "/tmp")
     t0 = time.time()
-    F, T = generate(args.small, args.large, log=lambda *a: print(*a, flush=True))
+    F, T = generate(args.small, args.large, log=lambda *a: print(*a, flush=True), n_xl=args.xl)
     print(f"samples {F.shape[0]} ({time.time() - t0:.0f} s)", flush=True)
     net = train(F, T, steps=args.steps, log=lambda *a: print(*a, flush=True))
     save(net, Path(args.out), {"samples": int(F.shape[0]), "small_layouts": args.small,
-                               "large_layouts": args.large, "steps": args.steps})
+                               "large_layouts": args.large, "xl_layouts": args.xl, "steps": args.steps})
     print(f"saved {args.out} ({time.time() - t0:.0f} s)", flush=True)
 
 
