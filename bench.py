@@ -24,17 +24,23 @@ import numpy as np  # noqa: E402
 
 import layouts  # noqa: E402
 
-# Green's function pair cost in lane-cycles: the VALU instructions of the P2L
-# inner loop (AMD assembly of the compiled library, 4 pairs per iteration) priced at the
-# chip's issue rates -- FP64 add/mul/fma and 64-bit integer ops 1 (78.6 TFLOP/s
-# FP64 vector), 32-bit ops 0.5 (157.3 TFLOP/s FP32 vector), FP32
-# transcendentals 2, FP64 rcp/rsq 4. The ALU ceiling is
-# 256 CUs * 64 lanes * 2.4 GHz / c_pair pairs per second.
-# Keyed by (precision, problem, P2L grid points per thread).
-C_PAIR = {("fp64", 0, 4): 28.25, ("fp64", 0, 8): 28.1, ("fp64", 1, 4): 27.25, ("fp64", 1, 8): 27.1,
-          ("fp32", 0, 4): 8.25, ("fp32", 0, 8): 8.1, ("fp32", 1, 4): 7.75, ("fp32", 1, 8): 7.6}
-# shape 0 runs R = 4 and R = 8 launches; priced at the cheaper of the two (the higher ceiling)
-C_PAIR.update({(p, b, 0): min(C_PAIR[(p, b, 4)], C_PAIR[(p, b, 8)]) for p in ("fp64", "fp32") for b in (0, 1)})
+# Algorithmic work of one Green's function pair (one source point, one
+# target point): the squared distance from staged coordinates (one add, three
+# fma = 8 flops), 2/d from it and d/2 (one multiply), the logarithm's argument
+# (one fma) and the accumulation of strength x G (one add, one fma): 12 flops
+# plus three transcendentals (rsqrt, log, and the reciprocal folded into the
+# rsqrt), the same in FP64 and FP32. The roofline headline prices only the 12
+# flops against the vector peak (FP64 78.6, FP32 157.3 TFLOP/s).
+FLOPS_PER_PAIR = 12
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# Issue efficiency (a separate figure): the pair's minimal VALU instruction mix
+# priced in lane-cycles at the rates the issue-cost probe measured on gfx950
+# (FP64 add/mul/fma 1.0, FP64 rsq 4.07, 32-bit ops 0.6, FP32 transcendentals
+# 2.06): FP64 22 FP64 ops (distance 4, rsqrt correction 4, d/2 1, argument 1,
+# logarithm 10: mantissa, exponent, its conversion, reduction, degree-4
+# series, table term; accumulation 3) + one rsq + two 32-bit table-index ops
+# = 27.3; FP32 8 32-bit ops + rsq + log2 = 8.9.
+C_PAIR_MIN = {"fp64": 22 * 1.0 + 4.07 + 2 * 0.6, "fp32": 8 * 0.6 + 2 * 2.06}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
@@ -42,6 +48,9 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # class: two launches over item lists, which read more through L2 misses).
 TRAFFIC = {("cfg5", "fp64", 4): 8.572e9, ("cfg5", "fp64", 8): 8.575e9, ("cfg5", "fp64", 0): 9.026e9,
            ("cfg5", "fp32", 4): 5.002e9, ("cfg5", "fp32", 8): 4.554e9, ("cfg5", "fp32", 0): 5.021e9}
+# largest relative difference allowed between a mixed or warm-started solve's
+# scalar and the plain FP64 solve's (all solved to a 1e-8 residual)
+MIXED_SCALAR_TOL = 1e-6
 WARM_WEIGHTS = __import__("pathlib").Path(ROOT) / "paper_1906_04209_amd" / "weights" / "warmstart.npz"
 
 WORKLOADS = {
@@ -56,14 +65,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, tol_id, x, centers, nrows=3):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, tol_id, x, centers, nrows=4):
     """Time the oracle's dense compressed matvec on `nrows` sampled target
     patches (plain C loop over all N source patches, all host cores) and scale
-    to one full matvec."""
+    to one full matvec. The sample is kept to tens of seconds of CPU work."""
     from oracle import csum, system, tables
     tab = tables.get(cfg["problem"], cfg["eps"], 15, tol_id)
     lay = system.Layout(centers, tab)
-    rows = np.arange(nrows)
+    rows = np.sort(layouts.rng(99).choice(cfg["N"], nrows, replace=False))
     t0 = time.perf_counter()
     U = csum.incoming_layout(lay, x, rows)
     y = x[rows] + U @ tab.P.T
@@ -71,9 +91,23 @@ def cpu_baseline(cfg, tol_id, x, centers, nrows=3):
     per_matvec = dt * cfg["N"] / nrows
     cores = len(os.sched_getaffinity(0))
     return {"value": 1.0 / per_matvec, "unit": "matvec/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{nrows} of {cfg['N']} target patches of the dense compressed matvec "
                       f"({dt:.1f} s), scaled by N/{nrows}",
             "seconds_per_matvec_extrapolated": per_matvec}, rows, y
+
+
+def golden_rows(name, tol_id):
+    """The oracle's stored rows of the same apply (written by
+    tests/golden/make_golden.py from the oracle alone), when they match."""
+    from pathlib import Path
+    f = Path(ROOT) / "tests" / "golden" / f"{name}_rows.npz"
+    if not f.exists():
+        return None
+    g = np.load(f, allow_pickle=False)
+    if int(g["x_seed"]) != 777 or float(g["tol_id"]) != tol_id:
+        return None
+    return g["rows"], g["y"]
 
 
 def run_batch(args):
@@ -178,7 +212,6 @@ def run_batch(args):
     rel_seq = np.abs(seq_res[:nseq] - solves["mixed"]["result"][:nseq]) / np.abs(seq_res[:nseq])
     log(f"sequential single solves: {t_seq:.2f} s (scaled from {nseq}), setup {t_seq_setup:.1f} s")
     pairs = work["pairs_far"]
-    cp = C_PAIR[("fp32", 0, 4)]
     for sname in solves:
         if sname != "mixed":
             solves[sname]["max_rel_diff_vs_mixed"] = float(np.max(np.abs(solves[sname]["result"] - solves["mixed"]["result"])
@@ -200,9 +233,11 @@ def run_batch(args):
         "max_rel_diff_batched_vs_single": float(rel_seq.max()),
         "speedup_batched_vs_sequential": t_seq / solves["mixed"]["time_incl_preprocessing_s"],
         "roofline": {"bound": "alu", "kernel": "far-field Green's sum (FP32, whole apply)",
-                     "achieved": pairs / (out_ms["fp32"] * 1e-3) / 1e9, "peak": LANE_CYCLES_PER_S / cp / 1e9,
-                     "unit": "Gpair/s", "frac": pairs / (out_ms["fp32"] * 1e-3) / (LANE_CYCLES_PER_S / cp),
-                     "traffic": None, "note": "far pairs / whole apply time (a lower bound on the P2L rate)"},
+                     "achieved": FLOPS_PER_PAIR * pairs / (out_ms["fp32"] * 1e-3) / 1e12,
+                     "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                     "frac": FLOPS_PER_PAIR * pairs / (out_ms["fp32"] * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"],
+                     "traffic": None, "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                     "note": "far pairs / whole apply time (a lower bound on the P2L rate)"},
     }
     print(json.dumps(out))
 
@@ -271,9 +306,10 @@ def main():
     dom = 1  # far field (direct all-pairs sum or P2L)
     pairs = work["pairs_far"]
     ptag = "fp64" if prec == nce.FP64 else "fp32"
-    cp = C_PAIR[(ptag, cfg["problem"], tuned[0] if tuned else 4)]
-    achieved = pairs / (st[dom] * 1e-3)
-    peak = LANE_CYCLES_PER_S / cp
+    t_far = st[dom] * 1e-3
+    achieved = FLOPS_PER_PAIR * pairs / t_far / 1e12
+    peak = PEAK_TFLOPS[ptag]
+    lane_rate = pairs / t_far * C_PAIR_MIN[ptag] / LANE_CYCLES_PER_S
     out = {
         "metric": "GMRES matvecs/s (FP64 system apply) at N=1e5; time to 1e-8 residual reported alongside",
         "value": 1e3 / ms_step, "unit": "matvec/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -287,11 +323,16 @@ def main():
                    **({"tol_id_fp32": args.tol_id_fp32} if args.tol_id_fp32 is not None else {})},
         "step_ms": {"block_apply": st[0], "far": st[1], "near": st[2], "interp": st[3], "p_apply": st[4]},
         "setup_s": t_setup, "autotuned_shapes": tuned,
-        "roofline": {"bound": "alu", "kernel": "far-field Green's sum", "achieved": achieved / 1e9,
-                     "peak": peak / 1e9, "unit": "Gpair/s", "frac": achieved / peak,
+        "roofline": {"bound": "alu", "kernel": f"far-field Green's sum ({ptag.upper()} P2L + per-grid reduction)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (TRAFFIC.get((args.workload, ptag, tuned[0] if tuned else 4))
                                  if args.tol_grid_fp32 is None and args.tol_id_fp32 is None else None),
-                     "c_pair_lane_cycles": cp, "pairs_per_launch": pairs},
+                     "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs,
+                     "pair_rate_Gpair_s": pairs / t_far / 1e9,
+                     "frac_transcendentals_as_one_flop": (FLOPS_PER_PAIR + 3) * pairs / t_far / 1e12 / peak,
+                     "issue_efficiency": {"c_pair_min_lane_cycles": C_PAIR_MIN[ptag], "frac": lane_rate,
+                                          "note": "pairs x the minimal instruction mix's lane-cycles / "
+                                                  "(256 CUs x 64 lanes x 2.4 GHz x time)"}},
     }
     out["median_ms_per_step_events"] = float(np.median([m.sum() for m in steps_ms]))
     if prec == nce.FP64 and far == nce.FAR_TREE:
@@ -380,9 +421,16 @@ def main():
         out["start_preprocessing_s"] = prep
     if not args.no_cpu_baseline:
         cb, rows, yref = cpu_baseline(cfg, args.tol_id, x_np, centers)
-        yg = y.cpu().numpy()[rows] if args.precision == "fp64" else None
+        yg = y.cpu().numpy() if args.precision == "fp64" else None
         if yg is not None:
-            cb["parity_rel_err_sampled_rows"] = float(np.max(np.abs(yg - yref)) / np.max(np.abs(yref - x_np[rows])))
+            cb["parity_rel_err_sampled_rows"] = float(np.max(np.abs(yg[rows] - yref))
+                                                      / np.max(np.abs(yref - x_np[rows])))
+            gold = golden_rows(args.workload, args.tol_id)
+            if gold is not None:
+                gr, gy = gold
+                cb["parity_rel_err_stored_oracle_rows"] = float(np.max(np.abs(yg[gr] - gy))
+                                                                / np.max(np.abs(gy - x_np[gr])))
+                cb["stored_oracle_rows"] = int(len(gr))
         if "solve_fp64" in out:
             # the oracle's time to 1e-8 at the GPU's FP64 iteration count (labelled extrapolated)
             cb["time_to_1e-8_extrapolated_s"] = cb["seconds_per_matvec_extrapolated"] * out["solve_fp64"]["iters_fp64"]
@@ -395,6 +443,20 @@ def main():
                                 "seconds_per_iteration": 108.0, "iterations": 35, "total_iteration_s": 3793.0,
                                 "matvec_per_s": 1.0 / 108.0, "note": "context, not a target"}
     print(json.dumps(out))
+    # the mixed and warm-started solves must reproduce the plain FP64 solve's
+    # scalar; the FP64 apply must match the oracle's rows
+    bad = []
+    for k, v in out.items():
+        if k.startswith("solve_") and isinstance(v, dict) and "converged" in v:
+            diffs = [d for name, d in v.items() if name.startswith("rel_diff_")]
+            if not v["converged"] or (diffs and diffs[0] > MIXED_SCALAR_TOL):
+                bad.append(k)
+    cbo = out.get("cpu_baseline", {})
+    if max(cbo.get("parity_rel_err_sampled_rows", 0.0), cbo.get("parity_rel_err_stored_oracle_rows", 0.0)) > 1e-7:
+        bad.append("cpu_baseline parity")
+    if bad:
+        log(f"FAILED checks: {bad}")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

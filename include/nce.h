@@ -67,14 +67,14 @@ typedef struct nce_ctx nce_ctx;
 
 typedef struct nce_opts {
     int problem;        /* NCE_INTERIOR or NCE_EXTERIOR */
-    int M;              /* Zernike truncation; K = (M+1)(M+2)/2. Default 15 (K = 136) */
+    int M;              /* Zernike truncation; K = (M+1)(M+2)/2, 0 <= M <= 15 (the kernels hold at
+                           most 2 (M+1)^2 = 512 sampling nodes per patch). Default 15 (K = 136) */
     double tol_id;      /* ID tolerance of the compressed outgoing representation. Default 1e-11 */
     double tol_grid;    /* incoming-grid truncation tolerance (tree only). Default 1e-8 */
     double tol_gmres;   /* relative residual ||b - A x|| / ||b|| to stop at. Default 1e-10 */
     int max_iter;       /* GMRES iteration limit (FP64) or inner limit (mixed). Default 200 */
     int precision;      /* NCE_FP64 or NCE_MIXED for the solves. Default NCE_FP64 */
     int far_field;      /* NCE_FAR_AUTO / NCE_FAR_DIRECT / NCE_FAR_TREE. Default AUTO */
-    int warm_start;     /* reserved, must be 0 (use nce_set_warm_start). Default 0 */
     void *stream;       /* hipStream_t to run on; NULL = the library creates one */
     const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
     double tol_grid_fp32; /* grid tolerance of the FP32 applies (mixed solves): a second, coarser

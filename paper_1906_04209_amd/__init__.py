@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("problem", ctypes.c_int), ("M", ctypes.c_int), ("tol_id", ctypes.c_double),
                 ("tol_grid", ctypes.c_double), ("tol_gmres", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("precision", ctypes.c_int),
-                ("far_field", ctypes.c_int), ("warm_start", ctypes.c_int),
+                ("far_field", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("cache_dir", ctypes.c_char_p), ("tol_grid_fp32", ctypes.c_double),
                 ("tol_id_fp32", ctypes.c_double), ("tol_coarse", ctypes.c_double), ("deflation", ctypes.c_int)]
 
@@ -109,7 +109,8 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_batch_set_deflation.argtypes = [vp, ctypes.c_int]
     lib.nce_batch_set_deflation.restype = ctypes.c_int
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
-                 "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step", "nce_features",
+                 "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step",
+                 "nce_features",
                  "nce_set_warm_start"):
         getattr(lib, name).restype = ctypes.c_int
     lib.nce_setup_batch.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(Opts), ctypes.POINTER(vp)]

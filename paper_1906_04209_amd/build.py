@@ -41,7 +41,7 @@ def _run(cmd):
     return r.stdout
 
 
-RATES = PKG / "valu_rates"   # instruction issue-cost probe (roofline pricing)
+RATES = PKG / "valu_rates"   # instruction issue-cost probe (built on request only, by build_rates)
 
 
 def build(verbose: bool = False) -> Path:
@@ -58,7 +58,6 @@ def build(verbose: bool = False) -> Path:
         o = BUILD / (Path(src).stem + ".hip.o")
         jobs.append([hipcc, *HIPCC_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
         objs.append(str(o))
-    jobs.append([hipcc, *HIPCC_FLAGS, str(CSRC / "valu_rates.hip"), "-o", str(RATES)])
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(max_workers=workers) as ex:
         list(ex.map(_run, jobs))
@@ -70,5 +69,15 @@ def build(verbose: bool = False) -> Path:
     return OUT
 
 
+def build_rates() -> Path:
+    """The instruction issue-cost microbenchmark (not part of the library):
+    python -m paper_1906_04209_amd.build --rates"""
+    _run([_hipcc(), *HIPCC_FLAGS, str(CSRC / "valu_rates.hip"), "-o", str(RATES)])
+    return RATES
+
+
 if __name__ == "__main__":
-    build(verbose=True)
+    if "--rates" in sys.argv:
+        print("built", build_rates())
+    else:
+        build(verbose=True)

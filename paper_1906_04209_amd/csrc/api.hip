@@ -489,7 +489,8 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
 
 int validate_opts(const nce_opts& o, double eps) {
     if (!(eps > 0.0 && eps <= M_PI / 3.0)) return fail(NCE_EINVAL, "eps must lie in (0, pi/3]");
-    if (o.M < 0 || o.M > 30) return fail(NCE_EINVAL, "M must lie in [0, 30]");
+    if (o.M < 0 || o.M > 15)
+        return fail(NCE_EINVAL, "M must lie in [0, 15] (at most 2 (M+1)^2 = 512 Zernike sampling nodes per patch)");
     if (o.problem != NCE_INTERIOR && o.problem != NCE_EXTERIOR) return fail(NCE_EINVAL, "bad problem");
     if (!(o.tol_id > 0 && o.tol_id < 1e-3)) return fail(NCE_EINVAL, "tol_id must lie in (0, 1e-3)");
     if (!(o.tol_grid > 0 && o.tol_grid < 1e-2)) return fail(NCE_EINVAL, "tol_grid must lie in (0, 1e-2)");
@@ -504,7 +505,6 @@ int validate_opts(const nce_opts& o, double eps) {
     if (o.precision != NCE_FP64 && o.precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
     if (o.far_field != NCE_FAR_AUTO && o.far_field != NCE_FAR_DIRECT && o.far_field != NCE_FAR_TREE)
         return fail(NCE_EINVAL, "bad far_field");
-    if (o.warm_start != 0) return fail(NCE_EINVAL, "opts.warm_start is reserved (set a network with nce_set_warm_start)");
     return NCE_OK;
 }
 
@@ -688,7 +688,6 @@ void nce_default_opts(nce_opts* o) {
     o->max_iter = 100;
     o->precision = NCE_FP64;
     o->far_field = NCE_FAR_AUTO;
-    o->warm_start = 0;
     o->stream = nullptr;
     o->cache_dir = nullptr;
     o->tol_grid_fp32 = 1e-4;

@@ -4,9 +4,11 @@ Calls only `oracle/` and the seeded generators in `layouts`. Outputs (under
 tests/golden/):
   tables/<key>.npz      oracle precompute (T, skeleton, I) per (problem, eps, M, tol_id)
   cfg1.npz              N=10 exterior, eps=0.1, seed 1: matvec of seeded x, dense-LU solve
+  cfg1i.npz             the same centres, interior: matvec of seeded x, dense-LU solve (mu,
+                        I_sigma, per-patch flux, solution coefficients)
   cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
   cfg3_rows.npz         N=10000 exterior clustered, eps=0.005, seed 3: 12 sampled rows
-  cfg5_rows.npz         N=100000 interior, eps=0.001, seed 5: 6 sampled rows (tol_id 1e-11)
+  cfg5_rows.npz         N=100000 interior, eps=0.001, seed 5: 16 sampled rows (tol_id 1e-11)
   MANIFEST.json         SHA-256 of every file, with the command that made it
 
 Run:  python tests/golden/make_golden.py [name ...]
@@ -59,6 +61,23 @@ def make_cfg1():
     print(f"  cfg1 capture rate {r['capture_rate']:.15g}, GMRES iters {it['iters']}", flush=True)
 
 
+def make_cfg1i():
+    """Interior twin of cfg1 (same centres): the narrow escape scalars of
+    Section 2.3 (eq. mufromsigma2) and the per-patch flux from the dense LU
+    solve of the compressed system."""
+    cfg = layouts.CONFIGS["cfg1"]
+    tab = _tab(0, cfg["eps"])
+    c = layouts.config_layout(cfg)
+    lay = system.Layout(c, tab)
+    x = layouts.random_coeffs(cfg["N"], tab.K, X_SEED, decay=0.1)
+    y = system.matvec_dense(lay, x)
+    r = system.solve_dense(lay)
+    it = system.solve_gmres(lay, tol=1e-10)
+    np.savez(GOLD / "cfg1i.npz", y=y, x_seed=X_SEED, mu=r["mu"], I_sigma=r["I_sigma"], flux=r["flux"],
+             coeffs=r["x"], gmres_iters=it["iters"])
+    print(f"  cfg1i mu {r['mu']:.15g}, GMRES iters {it['iters']}", flush=True)
+
+
 def make_cfg2_rows():
     cfg = layouts.CONFIGS["cfg2"]
     tab = _tab(cfg["problem"], cfg["eps"])
@@ -94,8 +113,8 @@ def _rows_job(name, nrows, tol_id):
     return job
 
 
-JOBS = {"cfg1": make_cfg1, "cfg2_rows": make_cfg2_rows, "cfg3_rows": _rows_job("cfg3", 12, 1e-12),
-        "cfg5_rows": _rows_job("cfg5", 6, 1e-11)}
+JOBS = {"cfg1": make_cfg1, "cfg1i": make_cfg1i, "cfg2_rows": make_cfg2_rows,
+        "cfg3_rows": _rows_job("cfg3", 12, 1e-12), "cfg5_rows": _rows_job("cfg5", 16, 1e-11)}
 
 
 def manifest():

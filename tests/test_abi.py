@@ -47,8 +47,8 @@ def test_default_opts():
     assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse, o.deflation) == (1e-4, 1e-6, 1e-5, 1)
 
 
-@pytest.mark.parametrize("case", ["empty", "nonunit", "nan", "eps0", "epsbig", "badM", "badprob", "badcoarse",
-                                  "badgrid32", "baddefl"])
+@pytest.mark.parametrize("case", ["empty", "nonunit", "nan", "eps0", "epsbig", "badM", "bigM", "badprob",
+                                  "badcoarse", "badgrid32", "baddefl"])
 def test_invalid_arguments(case):
     c = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
     eps, kw = 0.1, {}
@@ -64,6 +64,8 @@ def test_invalid_arguments(case):
         eps = 1.2
     elif case == "badM":
         kw = {"M": -1}
+    elif case == "bigM":
+        kw = {"M": 16}   # 2 (M+1)^2 = 578 sampling nodes: more than the kernels hold
     elif case == "badprob":
         kw = {"problem": 3}
     elif case == "badcoarse":

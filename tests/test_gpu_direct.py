@@ -48,7 +48,7 @@ def test_cfg1_matvec_fp64(torch):
     ref = g["y"]
     err = np.max(np.abs(y - ref)) / np.max(np.abs(ref - x))
     print("cfg1 FP64 matvec rel err", err)
-    assert err < 1e-10
+    assert err < 1e-12
 
 
 def test_cfg1_matvec_mixed(torch):
@@ -89,7 +89,72 @@ def test_cfg2_rows_fp64(torch):
     rows = g["rows"]
     err = np.max(np.abs(y[rows] - g["y"])) / np.max(np.abs(g["y"] - x[rows]))
     print("cfg2 FP64 rows rel err", err)
-    assert err < 1e-10
+    assert err < 1e-12
+
+
+def _cfg1i_ctx(**kw):
+    cfg = dict(layouts.CONFIGS["cfg1"], problem=0)
+    return cfg, _ctx(cfg, **kw)
+
+
+def test_cfg1_interior_matvec(torch):
+    """Interior twin of cfg1 (G_I of Section 2.1): FP64 and FP32 applies
+    against the oracle's dense compressed matvec."""
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / "cfg1i.npz")
+    cfg, ctx = _cfg1i_ctx()
+    x, xd = _x(torch, cfg["N"], ctx.K)
+    ref = g["y"]
+    err = np.max(np.abs(ctx.matvec(xd).cpu().numpy() - ref)) / np.max(np.abs(ref - x))
+    errm = np.max(np.abs(ctx.matvec(xd, precision=nce.MIXED).cpu().numpy() - ref)) / np.max(np.abs(ref - x))
+    print(f"cfg1 interior matvec rel err FP64 {err:.2e} FP32 {errm:.2e}")
+    assert err < 1e-12 and errm < 2e-5
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_cfg1_interior_mu_and_flux(torch, mixed):
+    """Narrow escape scalars against the oracle's dense LU solve: mu = 1/(3
+    I_sigma) - 3/5 (eq. mufromsigma2), I_sigma = I . sum_i f_i (eq. getI) and
+    the per-patch flux I . f_i, element by element; the coefficients
+    themselves (same frame convention on both sides) to the ID tolerance."""
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / "cfg1i.npz")
+    cfg, ctx = _cfg1i_ctx(precision=nce.MIXED if mixed else nce.FP64, tol_gmres=1e-12)
+    r = ctx.solve()
+    mu_ref = float(g["mu"])
+    rel = abs(r["mu"] - mu_ref) / mu_ref
+    flux = r["flux"].cpu().numpy()
+    ferr = np.max(np.abs(flux - g["flux"])) / np.max(np.abs(g["flux"]))
+    x = r["x"].cpu().numpy().reshape(cfg["N"], ctx.K)
+    xerr = np.max(np.abs(x - g["coeffs"])) / np.max(np.abs(g["coeffs"]))
+    Is = float(np.sum(flux))   # I_sigma = I . sum_i f_i
+    print(f"cfg1 interior {'mixed' if mixed else 'fp64'}: mu {r['mu']:.15f} oracle {mu_ref:.15f} rel {rel:.2e}; "
+          f"flux {ferr:.2e}; coefficients {xerr:.2e}; I_sigma {Is:.15e} vs {float(g['I_sigma']):.15e}")
+    assert r["converged"]
+    assert rel < 1e-9
+    assert abs(Is - float(g["I_sigma"])) < 1e-10 * abs(float(g["I_sigma"]))
+    assert abs(1 / (3 * Is) - 0.6 - r["mu"]) < 1e-13 * r["mu"]
+    assert ferr < 1e-9
+    assert xerr < 1e-9
+    if not mixed:
+        assert abs(r["iters_fp64"] - int(g["gmres_iters"])) <= 2
+
+
+@pytest.mark.parametrize("problem,eps", [(0, 0.1), (0, 0.01), (1, 0.1), (1, 0.005)])
+def test_integral_vector_vs_oracle(torch, problem, eps):
+    """The library's integral vector I (eq. getI: I_k = integral of the k-th
+    one-patch density, from its own one-patch solve) against the oracle's
+    independently computed I for both problems. Only the m = 0 entries are
+    non-zero."""
+    import paper_1906_04209_amd as nce
+    from oracle import tables
+    ref = tables.load(tables.GOLDEN_DIR / (tables.key(problem, eps, 15, TOL_ID) + ".npz")).I
+    c1 = np.array([[0.0, 0.6, 0.8]])
+    I = nce.Context(c1, eps, problem=problem, tol_id=TOL_ID).integral_vector()
+    err = np.max(np.abs(I - ref)) / np.max(np.abs(ref))
+    print(f"I vector problem {problem} eps {eps}: rel err {err:.2e}, I_0 {I[0]:.15e} vs {ref[0]:.15e}")
+    assert err < 1e-11
+    assert np.count_nonzero(np.abs(ref) > 1e-14 * abs(ref[0])) == 8
 
 
 def test_single_patch_and_pair(torch):

@@ -122,15 +122,17 @@ def _weights_match():
 @pytest.mark.skipif(not _weights_match(), reason="trained weights for the current features not present")
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_trained_network_gain(torch, precision):
-    """On held-out layouts the network's refinement of the coarse start cuts the
-    initial residual below the coarse start's, the solution is unchanged, and
-    the solve costs no more system applies than from zero. Applies saved are
-    printed for the cold, coarse and learned starts."""
+    """What the trained network adds, on held-out layouts (training used seeds
+    20000-20049 at this size): per layout its refinement of the coarse start
+    has a lower initial residual than the coarse start, and over the layouts
+    it needs fewer system applies on average than a cold start and no more
+    than the coarse start alone; the solution is unchanged."""
     import paper_1906_04209_amd as nce
     from paper_1906_04209_amd import warmstart
     net = warmstart.load(WEIGHTS)
     pr = nce.FP64 if precision == "fp64" else nce.MIXED
-    for seed in (90001, 90002, 90003):  # held out: training used seeds 20000-20049
+    tot = {"cold": 0, "coarse": 0, "learned": 0}
+    for seed in (90001, 90002, 90003):
         c = layouts.uniform_centers(1000, 0.01, seed)
         ctx = nce.Context(c, 0.01, problem=nce.INTERIOR, tol_id=1e-11, tol_gmres=1e-8, precision=pr)
         runs = {}
@@ -145,4 +147,8 @@ def test_trained_network_gain(torch, precision):
             assert abs(v["mu"] - runs["cold"]["mu"]) < 1e-7 * runs["cold"]["mu"]
         assert not runs["learned"]["used_fallback"]
         assert x0["learned"] < x0["coarse"]
-        assert n["learned"] <= n["cold"] + 1
+        for k in tot:
+            tot[k] += n[k]
+    print(f"{precision}: total applies over the three layouts {tot}")
+    assert tot["learned"] < tot["cold"]
+    assert tot["learned"] <= tot["coarse"]
