@@ -226,6 +226,20 @@ int nce_mlp_get_params(const nce_mlp *m, float *params_host);
 int nce_mlp_set_params(nce_mlp *m, const float *params_host);
 /* y (B x n_out) = network(x (B x n_in)). */
 int nce_mlp_forward(nce_mlp *m, const float *x_dev, int64_t B, float *y_dev, void *stream);
+/*
+ * nce_mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that forbid hipMalloc): the same arguments
+ * and results, with no allocation of any kind. The hidden activations live in
+ * a fixed 16 MiB device array of the library (one per GPU, held until the
+ * process ends); rows are processed in chunks that fit it (8192 rows at width
+ * 256) and the output is written straight to y_dev (B x n_out). Nothing in
+ * the array needs clearing between calls. Calls that overlap on one GPU (other
+ * streams or host threads) share the array and race: serialize them. Runs on
+ * the current HIP device, on `stream`.
+ * Errors: NCE_EINVAL for a NULL argument, B < 1, or hidden layers so wide that
+ * one row (2 x width floats) does not fit the array; NCE_EHIP.
+ */
+int nce_mlp_forward_noalloc(nce_mlp *m, const float *x_dev, int64_t B, float *y_dev, void *stream);
 /* Mean squared error L = sum (y - t)^2 / (B n_out) and its gradient with
  * respect to the parameters (grad_host may be NULL; it is left on the device). */
 int nce_mlp_loss_grad(nce_mlp *m, const float *x_dev, const float *t_dev, int64_t B, double *loss_host,

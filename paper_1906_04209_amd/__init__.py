@@ -28,7 +28,7 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
            "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
-           "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_loss_grad",
+           "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_forward_noalloc", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
            "nce_destroy_batch", "nce_batch_dims", "nce_batch_offsets", "nce_batch_work", "nce_batch_matvec",
            "nce_batch_set_solver", "nce_solve_batch", "nce_autotune", "nce_batch_autotune", "nce_coarse_solve",
@@ -96,6 +96,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_mlp_get_params.argtypes = [vp, vp]
     lib.nce_mlp_set_params.argtypes = [vp, vp]
     lib.nce_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.nce_mlp_forward_noalloc.argtypes = [vp, vp, i64, vp, vp]
     lib.nce_mlp_loss_grad.argtypes = [vp, vp, vp, i64, dp, vp, vp]
     lib.nce_mlp_train_step.argtypes = [vp, vp, vp, i64, ctypes.c_float, dp, vp]
     lib.nce_features.argtypes = [vp, vp]
@@ -109,7 +110,7 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_batch_set_deflation.argtypes = [vp, ctypes.c_int]
     lib.nce_batch_set_deflation.restype = ctypes.c_int
     for name in ("nce_mlp_create", "nce_mlp_num_params", "nce_mlp_get_params", "nce_mlp_set_params",
-                 "nce_mlp_forward", "nce_mlp_loss_grad", "nce_mlp_train_step",
+                 "nce_mlp_forward", "nce_mlp_forward_noalloc", "nce_mlp_loss_grad", "nce_mlp_train_step",
                  "nce_features",
                  "nce_set_warm_start"):
         getattr(lib, name).restype = ctypes.c_int
@@ -207,6 +208,14 @@ class Mlp:
         torch = self.torch
         y = torch.empty((x.shape[0], self.shape[3]), dtype=torch.float32, device="cuda")
         self._run(lambda st: _check(self.lib, self.lib.nce_mlp_forward(
+            self.h, _ptr(x, torch.float32), x.shape[0], _ptr(y, torch.float32), st)))
+        return y
+
+    def forward_noalloc(self, x, y):
+        """nce_mlp_forward_noalloc into the caller's y (B x n_out FP32 CUDA
+        tensor): no device allocation inside the library."""
+        torch = self.torch
+        self._run(lambda st: _check(self.lib, self.lib.nce_mlp_forward_noalloc(
             self.h, _ptr(x, torch.float32), x.shape[0], _ptr(y, torch.float32), st)))
         return y
 

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
@@ -894,6 +895,46 @@ int nce_mlp_forward(nce_mlp* m, const float* x, int64_t B, float* y, void* strea
         hipStream_t s = (hipStream_t)stream;
         const float* out = m->net.forward(s, x, B);
         HIPCHK(hipMemcpyAsync(y, out, sizeof(float) * B * m->net.n_out, hipMemcpyDeviceToDevice, s));
+        return NCE_OK;
+    });
+}
+
+// ---- network forward pass without allocation ------------------------------
+// Workspace of nce_mlp_forward_noalloc: a fixed device array (16 MiB on every
+// GPU the library runs on, held until the process ends). Host code never
+// passes its name to a kernel: the name is a host-side stand-in; the device
+// address of each GPU's copy comes from hipGetSymbolAddress.
+static constexpr int64_t kNoallocFloats = (int64_t)4 << 20;
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device with that device current.
+float* scratch_on_current_device() {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw HipError("device index beyond the workspace table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int nce_mlp_forward_noalloc(nce_mlp* m, const float* x, int64_t B, float* y, void* stream) {
+    if (!m || !x || !y || B < 1) return fail(NCE_EINVAL, "bad argument");
+    if (2 * m->net.widest_hidden() > kNoallocFloats)
+        return fail(NCE_EINVAL, "hidden layers wider than the fixed workspace holds (2 x width floats per row, 16 MiB)");
+    return guarded([&]() -> int {
+        float* ws = scratch_on_current_device();
+        m->net.forward_ws((hipStream_t)stream, x, B, y, ws, kNoallocFloats);
         return NCE_OK;
     });
 }

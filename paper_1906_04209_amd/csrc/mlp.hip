@@ -4,6 +4,7 @@
 // Parameter layout: per layer W (row-major, n_out_l x n_in_l) then b.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <random>
 #include <stdexcept>
@@ -30,6 +31,15 @@ __global__ void k_bias_act(int64_t B, int n, const float* __restrict__ bias, flo
         const float z = Z[e] + bias[e % n];
         Z[e] = z;
         H[e] = act ? silu(z) : z;
+    }
+}
+
+// the same, in place (X = act(X + b)): the allocation-free forward pass
+__global__ void k_bias_act_inplace(int64_t B, int n, const float* __restrict__ bias, float* __restrict__ X, int act) {
+    const int64_t total = B * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const float z = X[e] + bias[e % n];
+        X[e] = act ? silu(z) : z;
     }
 }
 
@@ -177,6 +187,35 @@ const float* Mlp::forward(hipStream_t s, const float* x, int64_t B) {
         in = H[l];
     }
     return H.back();
+}
+
+int64_t Mlp::widest_hidden() const {
+    int64_t w = 0;
+    for (size_t l = 0; l + 1 < lout.size(); ++l) w = std::max<int64_t>(w, lout[l]);
+    return w;
+}
+
+void Mlp::forward_ws(hipStream_t s, const float* x, int64_t B, float* y, float* ws, int64_t ws_floats) {
+    const size_t L = lout.size();
+    const int64_t wmax = widest_hidden();
+    // rows per chunk: two activation buffers of rows x wmax floats must fit
+    const int64_t rows = std::min<int64_t>(B, ws_floats / (2 * std::max<int64_t>(wmax, 1)));
+    if (rows < 1) throw std::runtime_error("workspace holds less than one row of activations");
+    float* buf[2] = {ws, ws + rows * wmax};
+    for (int64_t r0 = 0; r0 < B; r0 += rows) {
+        const int64_t nb = std::min(rows, B - r0);
+        const float* in = x + r0 * n_in;
+        for (size_t l = 0; l < L; ++l) {
+            float* out = l + 1 == L ? y + r0 * n_out : buf[l % 2];
+            chk(gemm_strided<float>(s, (int)nb, lout[l], lin[l], in, lin[l], 1, theta + woff[l], 1, lin[l], out,
+                                    lout[l], 1.0f, 0),
+                "gemm");
+            hipLaunchKernelGGL(k_bias_act_inplace, ew(nb * lout[l]), dim3(256), 0, s, nb, lout[l], theta + boff[l],
+                               out, (int)(l + 1 < L));
+            chk(hipGetLastError(), "bias_act");
+            in = out;
+        }
+    }
 }
 
 void Mlp::loss_grad(hipStream_t s, const float* x, const float* t, int64_t B) {

@@ -33,6 +33,13 @@ struct Mlp {
     void release_ws();
     // returns the device output (B x n_out), valid until the next call
     const float* forward(hipStream_t s, const float* x, int64_t B);
+    // widest hidden layer (0 without hidden layers)
+    int64_t widest_hidden() const;
+    // the same forward pass with no allocation: the hidden activations go to
+    // the caller's device workspace ws (ws_floats floats, two row-chunks of the
+    // widest hidden layer), rows in chunks that fit it, the output straight to
+    // y (B x n_out); nothing else is written
+    void forward_ws(hipStream_t s, const float* x, int64_t B, float* y, float* ws, int64_t ws_floats);
     // forward + MSE gradient into `grad`; squared-error sum into lossd
     void loss_grad(hipStream_t s, const float* x, const float* t, int64_t B);
     void adam_step(hipStream_t s, float lr);

@@ -89,7 +89,8 @@ def test_null_handles_rejected():
                      (lib.nce_batch_set_warm_start, (None, None, 1)), (lib.nce_matvec, (None, None, None, 0)),
                      (lib.nce_solve_interior, (None, None, None, ctypes.byref(mu), None)),
                      (lib.nce_solve_batch, (None, None, None, None)), (lib.nce_batch_matvec, (None, None, None, 0)),
-                     (lib.nce_setup_batch, (None, None, None, None, 0, None, ctypes.byref(h)))]:
+                     (lib.nce_setup_batch, (None, None, None, None, 0, None, ctypes.byref(h))),
+                     (lib.nce_mlp_forward_noalloc, (None, None, 1, None, None))]:
         assert fn(*args) == -1, fn.__name__
         assert lib.nce_last_error()
     assert not h.value
