@@ -292,6 +292,42 @@ int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m, int use_coarse);
 /* Integral vector I (K host doubles): I_sigma = I . sum_i f_i (eq. getI). */
 int nce_integral_vector(const nce_ctx *ctx, double *I_host);
 
+/*
+ * Field of the patch densities at points of the domain (Sections 2.2, 2.3):
+ * the single-layer potential u(x) = sum_j int G_E(x, x') sigma_j(x') dS'
+ * (exterior, eq. urep) or v(x) with G_I (interior, eq. intBVPansatz), G the
+ * off-surface Neumann Green's function (eqs. Gextoffsurface, Gintoffsurface)
+ * and sigma_j = B f_j the density of coefficients f_j; with physical = 1 the
+ * physical field instead: ubar = 1 - u (exterior; 1 at infinity, 0 on the
+ * patches) or the mean first passage time vbar = (v - 1)/(3 D) +
+ * (1 - |x|^2)/6, D = -I_sigma (interior, eq. vtilde).
+ * coeffs_dev: N x K device coefficients (for example a solve's output);
+ * points_dev: n x 3 device doubles, |x| <= 1 (interior) or |x| >= 1
+ * (exterior), points on the sphere allowed (on a patch: that patch's term is
+ * its data sum_k f_ik Z_k); values_dev: n device doubles out.
+ * Patches whose centre lies at arclength >= 3 eps from x/|x| enter through the
+ * compressed outgoing representation, nearer ones by quadrature of their
+ * density (260 radial nodes x 256 angles): accurate to about the ID tolerance
+ * for points at least eps/10 from every patch they do not lie on.
+ * Synchronises the context's stream. Errors: NCE_EINVAL (NULL pointer, n < 0,
+ * non-finite point or one outside the problem's domain), NCE_ESTATE (a
+ * context of several configurations), NCE_EHIP.
+ */
+int nce_field(nce_ctx *ctx, const double *coeffs_dev, const double *points_dev, int64_t n, int physical,
+              double *values_dev);
+
+/*
+ * L2 residual of the absorbing condition on patches (eq. l2res, normalised
+ * as printed): residual_host[a] = (1/|Gamma_i|) ||v - 1||_{L2(Gamma_i)} for
+ * patch i = patches_host[a] (0 <= i < N), with v the potential of nce_field
+ * for coefficients coeffs_dev, by the rule n_t Gauss-Legendre nodes in
+ * arclength on [0, eps] times n_theta equispaced angles offset by half a step
+ * (1 <= n_t <= 64, 1 <= n_theta <= 256); |Gamma_i| = 2 pi (1 - cos eps).
+ * Synchronises. Errors: NCE_EINVAL, NCE_ESTATE, NCE_EHIP.
+ */
+int nce_patch_residual(nce_ctx *ctx, const double *coeffs_dev, const int64_t *patches_host, int npatch, int n_t,
+                       int n_theta, double *residual_host);
+
 /* ------------------------------------------------------------------------
  * Batched solves: many independent configurations (their own centres, eps and
  * problem) in one set of launches. Not in the paper, whose solver treats one

@@ -27,6 +27,7 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 # every symbol include/nce.h declares
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
+           "nce_field", "nce_patch_residual",
            "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_forward_noalloc", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
@@ -88,6 +89,10 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
     lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
     lib.nce_integral_vector.argtypes = [vp, vp]
+    lib.nce_field.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp]
+    lib.nce_field.restype = ctypes.c_int
+    lib.nce_patch_residual.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    lib.nce_patch_residual.restype = ctypes.c_int
     lib.nce_mlp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                                    ctypes.POINTER(vp)]
     lib.nce_mlp_destroy.argtypes = [vp]
@@ -307,6 +312,29 @@ class Context:
         _check(self.lib, self.lib.nce_integral_vector(self.h, out.ctypes.data))
         return out
 
+    def field(self, coeffs, points, physical: bool = False):
+        """nce_field: the potential u / v (or, physical=True, ubar / vbar) at
+        points (n x 3 float64 CUDA tensor) for coefficients (N K float64 CUDA
+        tensor)."""
+        torch = self.torch
+        pts = points.reshape(-1, 3)
+        out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+        self._enter()
+        _check(self.lib, self.lib.nce_field(self.h, _ptr(coeffs), _ptr(pts), pts.shape[0], int(bool(physical)),
+                                            _ptr(out)))
+        self._leave()
+        return out
+
+    def patch_residual(self, coeffs, patches, n_t: int = 20, n_theta: int = 40) -> np.ndarray:
+        """nce_patch_residual: (1/|Gamma_i|) ||v - 1||_L2 on each listed patch."""
+        idx = np.ascontiguousarray(np.atleast_1d(patches), dtype=np.int64)
+        out = np.empty(len(idx))
+        self._enter()
+        _check(self.lib, self.lib.nce_patch_residual(self.h, _ptr(coeffs), idx.ctypes.data, len(idx), int(n_t),
+                                                     int(n_theta), out.ctypes.data))
+        self._leave()
+        return out
+
     def work(self, precision: int = FP64):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(self.lib, self.lib.nce_work(self.h, int(precision), ctypes.byref(a), ctypes.byref(b),
@@ -483,6 +511,29 @@ class Batch:
         """View of configuration b's N_b x K block of a batch vector."""
         o = int(self.offsets[b])
         return v[o:o + int(self.N[b]) * self.K].view(int(self.N[b]), self.K)
+
+    def field(self, coeffs, points, physical: bool = False):
+        """nce_field: the potential u / v (or, physical=True, ubar / vbar) at
+        points (n x 3 float64 CUDA tensor) for coefficients (N K float64 CUDA
+        tensor)."""
+        torch = self.torch
+        pts = points.reshape(-1, 3)
+        out = torch.empty(pts.shape[0], dtype=torch.float64, device="cuda")
+        self._enter()
+        _check(self.lib, self.lib.nce_field(self.h, _ptr(coeffs), _ptr(pts), pts.shape[0], int(bool(physical)),
+                                            _ptr(out)))
+        self._leave()
+        return out
+
+    def patch_residual(self, coeffs, patches, n_t: int = 20, n_theta: int = 40) -> np.ndarray:
+        """nce_patch_residual: (1/|Gamma_i|) ||v - 1||_L2 on each listed patch."""
+        idx = np.ascontiguousarray(np.atleast_1d(patches), dtype=np.int64)
+        out = np.empty(len(idx))
+        self._enter()
+        _check(self.lib, self.lib.nce_patch_residual(self.h, _ptr(coeffs), idx.ctypes.data, len(idx), int(n_t),
+                                                     int(n_theta), out.ctypes.data))
+        self._leave()
+        return out
 
     def work(self, precision: int = FP64):
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

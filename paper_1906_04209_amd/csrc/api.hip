@@ -535,11 +535,24 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->N = N;
     ctx->eps = eps;
     ctx->cfg_first = cfg_first;
+    if (o.stream) {
+        ctx->stream = (hipStream_t)o.stream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+        ctx->own_stream = true;
+    }
     std::string dir;
     if (o.cache_dir) dir = o.cache_dir;
     else if (const char* e = std::getenv("NCE_CACHE")) dir = e;
+    // tables not in the cache are built with their modal solves and IDs on the
+    // GPU (NCE_HOST_PRECOMPUTE=1: all on the host)
+    std::unique_ptr<nce::PrecomputeDevice> pdev;
+    {
+        const char* hp = std::getenv("NCE_HOST_PRECOMPUTE");
+        if (!(hp && hp[0] == '1')) pdev = nce::make_gpu_precompute(ctx->stream);
+    }
     if (!nce::load_tables(dir, o.problem, eps, o.M, o.tol_id, ctx->tab)) {
-        ctx->tab = nce::build_tables(o.problem, eps, o.M, o.tol_id);
+        ctx->tab = nce::build_tables(o.problem, eps, o.M, o.tol_id, 0, pdev.get());
         nce::save_tables(dir, ctx->tab);
     }
     ctx->K = ctx->tab.K;
@@ -549,18 +562,12 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     const double tid32 = o.tol_id_fp32 > 0 ? o.tol_id_fp32 : o.tol_id;
     ctx->has_tab32 = tid32 != o.tol_id;
     if (ctx->has_tab32 && !nce::load_tables(dir, o.problem, eps, o.M, tid32, ctx->tab32)) {
-        ctx->tab32 = nce::build_tables(o.problem, eps, o.M, tid32);
+        ctx->tab32 = nce::build_tables(o.problem, eps, o.M, tid32, 0, pdev.get());
         nce::save_tables(dir, ctx->tab32);
     }
     const nce::PatchTables& t32 = ctx->has_tab32 ? ctx->tab32 : ctx->tab;
     ctx->p32 = t32.p;
     build_frames(centers, N, ctx->frames);
-    if (o.stream) {
-        ctx->stream = (hipStream_t)o.stream;
-    } else {
-        HIPCHK(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
-        ctx->own_stream = true;
-    }
     hipStream_t s = ctx->stream;
     const size_t n = (size_t)N * ctx->K;
     // far field of a single configuration: the tree or the direct all-pairs sum

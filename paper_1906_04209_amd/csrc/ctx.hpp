@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "precompute.hpp"
+#include "precompute_gpu.hpp"
 #include "tree.hpp"
 
 namespace nce_detail {

@@ -487,45 +487,95 @@ static inline double dist3(const double* a, const double* b) {
     return std::sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// Training points of the ID for targets at arclength >= D: rings on the
+// sphere at Chebyshev radii in dyadic shells from D to pi, 2 kThetaFine
+// angles each (n x 3).
+static std::vector<double> training_points(double D) {
+    std::vector<double> radii;
+    const int per = 9;
+    double lo = D;
+    const double rmax = kPi * (1.0 - 1e-6);
+    radii.push_back(lo);
+    while (lo < rmax) {
+        double hi = std::min(2.0 * lo, rmax);
+        for (int q = 1; q <= per; ++q) {
+            double x = -std::cos(kPi * q / per);  // Chebyshev-Lobatto, q = 1..per
+            radii.push_back(lo + 0.5 * (x + 1.0) * (hi - lo));
+        }
+        lo = hi;
+    }
+    const int nth_t = 2 * kThetaFine;
+    std::vector<double> txyz(radii.size() * nth_t * 3);
+    for (size_t a = 0; a < radii.size(); ++a)
+        for (int c = 0; c < nth_t; ++c)
+            polar_xyz(radii[a], 2.0 * kPi * c / nth_t, &txyz[((size_t)a * nth_t + c) * 3]);
+    return txyz;
+}
+
+// 48 held-out points of the region {arclength >= D} (12 on its edge).
+static std::vector<double> heldout_points(double D) {
+    std::mt19937_64 g2(77);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    const int nh = 48;
+    std::vector<double> hx((size_t)3 * nh);
+    for (int h = 0; h < nh; ++h) {
+        const double r = (h < 12) ? D * (1.0 + 1e-6) : D * std::exp(U(g2) * std::log(kPi / D * 0.999));
+        polar_xyz(r, 2.0 * kPi * U(g2), &hx[(size_t)3 * h]);
+    }
+    return hx;
+}
+
+// Skeleton coordinates of the first out.p pivots (fine-grid index l * kThetaFine + c).
+static void skeleton_of(FarTable& out, const std::vector<int>& piv, const std::vector<double>& rt) {
+    const int p = out.p;
+    out.skel_t.resize(p);
+    out.skel_theta.resize(p);
+    out.skel_off.resize((size_t)3 * p);
+    for (int a = 0; a < p; ++a) {
+        const int f = piv[a];
+        const int l = f / kThetaFine, c = f % kThetaFine;
+        const double t = rt[l], th = 2.0 * kPi * c / kThetaFine;
+        out.skel_t[a] = t;
+        out.skel_theta[a] = th;
+        const double sh = std::sin(0.5 * t);
+        out.skel_off[3 * a] = -2.0 * sh * sh;
+        out.skel_off[3 * a + 1] = std::sin(t) * std::cos(th);
+        out.skel_off[3 * a + 2] = std::sin(t) * std::sin(th);
+    }
+}
+
 // Interpolative decomposition of A = G(x^t, x^f) for training points x^t at
 // arclength >= D from the patch centre (Section 7.1): randomized sketch,
 // column-pivoted QR, rank by tolerance relative to the largest pivot,
 // T = Pi W B and the skeleton (a subset of the fine grid).
 static FarTable compress_outgoing(int problem, double D, double tol_id, const std::vector<double>& fxyz,
                                   const std::vector<double>& wB, int K, const std::vector<double>& rt, int ell0,
-                                  uint64_t seed) {
+                                  uint64_t seed, PrecomputeDevice* dev) {
     FarTable out;
     out.D = D;
-    // training rings on the region {arclength >= D}: Chebyshev points in
-    // dyadic shells from D to pi, 2 * kThetaFine angles each.
-    std::vector<double> radii;
-    {
-        const int per = 9;
-        double lo = D;
-        const double rmax = kPi * (1.0 - 1e-6);
-        radii.push_back(lo);
-        while (lo < rmax) {
-            double hi = std::min(2.0 * lo, rmax);
-            for (int q = 1; q <= per; ++q) {
-                double x = -std::cos(kPi * q / per);  // Chebyshev-Lobatto, q = 1..per
-                radii.push_back(lo + 0.5 * (x + 1.0) * (hi - lo));
-            }
-            lo = hi;
-        }
-    }
-    const int nth_t = 2 * kThetaFine;
-    const int nt = (int)radii.size() * nth_t;
+    const std::vector<double> txyz = training_points(D);
+    const int nt = (int)(txyz.size() / 3);
     out.n_train = nt;
     const int nf = (int)(fxyz.size() / 3);
-    std::vector<double> txyz((size_t)nt * 3);
-    for (size_t a = 0; a < radii.size(); ++a)
-        for (int c = 0; c < nth_t; ++c)
-            polar_xyz(radii[a], 2.0 * kPi * c / nth_t, &txyz[((size_t)a * nth_t + c) * 3]);
-
-    int ell = ell0;
     std::vector<int> piv;
-    std::vector<double> Rtop;   // p x nf rows of R (column order = piv)
     int p = 0;
+    if (dev) {
+        dev->id(problem, txyz, tol_id, ell0, seed, p, piv, out.T);
+        out.p = p;
+        skeleton_of(out, piv, rt);
+        const std::vector<double> hx = heldout_points(D);
+        std::vector<double> sx((size_t)3 * p);
+        for (int a = 0; a < p; ++a)
+            for (int d = 0; d < 3; ++d) sx[(size_t)3 * a + d] = fxyz[(size_t)3 * piv[a] + d];
+        double maxerr = 0, maxval = 0;
+        dev->check(problem, hx, sx, out.T, maxerr, maxval);
+        out.check = maxerr / maxval;
+        if (!(out.check <= 100.0 * tol_id))
+            throw std::runtime_error("compressed outgoing representation failed its held-out check");
+        return out;
+    }
+    int ell = ell0;
+    std::vector<double> Rtop;   // p x nf rows of R (column order = piv)
     std::mt19937_64 gen(seed);
     while (true) {
         std::normal_distribution<double> nd(0.0, 1.0);
@@ -649,32 +699,16 @@ static FarTable compress_outgoing(int problem, double D, double tol_id, const st
     }
     for (const std::vector<double>& Tloc : Tparts)
         for (size_t q = 0; q < Tloc.size(); ++q) out.T[q] += Tloc[q];
-    out.skel_t.resize(p);
-    out.skel_theta.resize(p);
-    out.skel_off.resize((size_t)3 * p);
-    for (int a = 0; a < p; ++a) {
-        const int f = piv[a];
-        const int l = f / kThetaFine, c = f % kThetaFine;
-        const double t = rt[l], th = 2.0 * kPi * c / kThetaFine;
-        out.skel_t[a] = t;
-        out.skel_theta[a] = th;
-        const double sh = std::sin(0.5 * t);
-        out.skel_off[3 * a] = -2.0 * sh * sh;
-        out.skel_off[3 * a + 1] = std::sin(t) * std::cos(th);
-        out.skel_off[3 * a + 2] = std::sin(t) * std::sin(th);
-    }
+    skeleton_of(out, piv, rt);
 
     // self-check: far field at held-out points of the region, skeleton vs fine grid
     {
-        std::mt19937_64 g2(77);
-        std::uniform_real_distribution<double> U(0.0, 1.0);
-        const int nh = 48;
+        const std::vector<double> hx = heldout_points(D);
+        const int nh = (int)(hx.size() / 3);
         double maxerr = 0.0, maxval = 0.0;
         std::vector<double> full(K), sk(K);
         for (int h = 0; h < nh; ++h) {
-            double r = (h < 12) ? D * (1.0 + 1e-6) : D * std::exp(U(g2) * std::log(kPi / D * 0.999));
-            double x[3];
-            polar_xyz(r, 2.0 * kPi * U(g2), x);
+            const double* x = &hx[(size_t)3 * h];
             std::fill(full.begin(), full.end(), 0.0);
             std::fill(sk.begin(), sk.end(), 0.0);
             for (int f = 0; f < nf; ++f) {
@@ -698,7 +732,7 @@ static FarTable compress_outgoing(int problem, double D, double tol_id, const st
     return out;
 }
 
-PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads) {
+PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads, PrecomputeDevice* dev) {
     if (nthreads > 0) omp_set_num_threads(nthreads);
     PatchTables out;
     out.problem = problem;
@@ -716,18 +750,36 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
     std::vector<double> A;
     assemble_modal(problem, R, M, A);
     std::vector<double> sigma((size_t)K * nr);
-    for (int ma = 0; ma <= M; ++ma) {
-        std::vector<int> cols;
-        for (int k = 0; k < K; ++k)
-            if (std::abs(zm[k]) == ma) cols.push_back(k);
-        std::vector<double> Am(A.begin() + (size_t)ma * nr * nr, A.begin() + (size_t)(ma + 1) * nr * nr);
-        const int nc = (int)cols.size();
-        std::vector<double> F((size_t)nr * nc);
-        for (int i = 0; i < nr; ++i)
-            for (int c = 0; c < nc; ++c) F[(size_t)i * nc + c] = zernike_radial(zn[cols[c]], ma, R.t[i] / eps);
-        lu_solve_multi(nr, Am, nc, F);
-        for (int c = 0; c < nc; ++c)
-            for (int i = 0; i < nr; ++i) sigma[(size_t)cols[c] * nr + i] = F[(size_t)i * nc + c];
+    std::vector<std::vector<int>> cols(M + 1);
+    for (int k = 0; k < K; ++k) cols[std::abs(zm[k])].push_back(k);
+    if (dev) {
+        // all orders at once: A_m (nr x nr) and F_m (nr x ncmax) packed per order
+        int ncmax = 0;
+        for (const auto& c : cols) ncmax = std::max(ncmax, (int)c.size());
+        std::vector<double> F((size_t)(M + 1) * nr * ncmax, 0.0);
+        std::vector<int> nrhs(M + 1);
+        for (int ma = 0; ma <= M; ++ma) {
+            nrhs[ma] = (int)cols[ma].size();
+            for (int i = 0; i < nr; ++i)
+                for (int c = 0; c < nrhs[ma]; ++c)
+                    F[((size_t)ma * nr + i) * ncmax + c] = zernike_radial(zn[cols[ma][c]], ma, R.t[i] / eps);
+        }
+        dev->modal_solve(nr, M + 1, A, F, nrhs, ncmax);
+        for (int ma = 0; ma <= M; ++ma)
+            for (int c = 0; c < nrhs[ma]; ++c)
+                for (int i = 0; i < nr; ++i)
+                    sigma[(size_t)cols[ma][c] * nr + i] = F[((size_t)ma * nr + i) * ncmax + c];
+    } else {
+        for (int ma = 0; ma <= M; ++ma) {
+            std::vector<double> Am(A.begin() + (size_t)ma * nr * nr, A.begin() + (size_t)(ma + 1) * nr * nr);
+            const int nc = (int)cols[ma].size();
+            std::vector<double> F((size_t)nr * nc);
+            for (int i = 0; i < nr; ++i)
+                for (int c = 0; c < nc; ++c) F[(size_t)i * nc + c] = zernike_radial(zn[cols[ma][c]], ma, R.t[i] / eps);
+            lu_solve_multi(nr, Am, nc, F);
+            for (int c = 0; c < nc; ++c)
+                for (int i = 0; i < nr; ++i) sigma[(size_t)cols[ma][c] * nr + i] = F[(size_t)i * nc + c];
+        }
     }
     // fine grid: radial nodes x kThetaFine angles, index l*kThetaFine + c
     const int nf = nr * kThetaFine;
@@ -743,17 +795,22 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
                 wB[(size_t)f * K + k] = wf[f] * sigma[(size_t)k * nr + l] * ang;
             }
         }
+    out.rad_t = R.t;
+    out.rad_w.resize(nr);
+    for (int l = 0; l < nr; ++l) out.rad_w[l] = R.wsig[l] * std::sin(R.t[l]);
+    out.sig = sigma;
     // (c) I = w^T B
     out.I.assign(K, 0.0);
     for (int f = 0; f < nf; ++f)
         for (int k = 0; k < K; ++k) out.I[k] += wB[(size_t)f * K + k];
 
+    if (dev) dev->set_fine(fxyz, wB, K);
     // (b) compressed outgoing representation for targets at arclength >= 2 eps
     // (the far-field region of Section 7), then a ladder of recompressions for
     // targets at arclength >= D_k = 2 eps 2^(k/2) (Section 8.1, additional
     // compression of the outgoing representation).
     {
-        FarTable base = compress_outgoing(problem, 2.0 * eps, tol_id, fxyz, wB, K, R.t, 384, 0x5eed1234abcdULL);
+        FarTable base = compress_outgoing(problem, 2.0 * eps, tol_id, fxyz, wB, K, R.t, 384, 0x5eed1234abcdULL, dev);
         out.p = base.p;
         out.T = base.T;
         out.skel_t = base.skel_t;
@@ -766,7 +823,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
             const double D = 2.0 * eps * std::pow(2.0, 0.5 * k);
             if (D > kPi / 3.0) break;
             FarTable ft = compress_outgoing(problem, D, tol_id, fxyz, wB, K, R.t, std::min(384, prev + 64),
-                                            0x5eed1234abcdULL + 977 * k);
+                                            0x5eed1234abcdULL + 977 * k, dev);
             prev = ft.p;
             out.far.push_back(std::move(ft));
         }
@@ -813,7 +870,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
 
 static std::string cache_name(const std::string& dir, int problem, double eps, int M, double tol_id) {
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "/nce_tables_v2_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
+    std::snprintf(buf, sizeof(buf), "/nce_tables_v3_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
     return dir + buf;
 }
 
@@ -837,7 +894,7 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
     std::ifstream f(cache_name(dir, problem, eps, M, tol_id), std::ios::binary);
     if (!f) return false;
     char magic[8];
-    if (!f.read(magic, 8) || std::memcmp(magic, "NCETAB02", 8) != 0) return false;
+    if (!f.read(magic, 8) || std::memcmp(magic, "NCETAB03", 8) != 0) return false;
     int hdr[5];
     double dh[4];
     if (!f.read((char*)hdr, sizeof(hdr)) || !f.read((char*)dh, sizeof(dh))) return false;
@@ -851,7 +908,8 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
     t.id_check = dh[2];
     t.n_train = (int)dh[3];
     bool ok = rvec(f, t.skel_t) && rvec(f, t.skel_theta) && rvec(f, t.skel_off) && rvec(f, t.node_t) &&
-              rvec(f, t.node_theta) && rvec(f, t.node_off) && rvec(f, t.T) && rvec(f, t.P) && rvec(f, t.I);
+              rvec(f, t.node_theta) && rvec(f, t.node_off) && rvec(f, t.T) && rvec(f, t.P) && rvec(f, t.I) &&
+              rvec(f, t.rad_t) && rvec(f, t.rad_w) && rvec(f, t.sig);
     uint64_t nfar = 0;
     ok = ok && (bool)f.read((char*)&nfar, sizeof(nfar)) && nfar < 64;
     t.far.assign(ok ? nfar : 0, FarTable());
@@ -865,6 +923,7 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
     }
     if (!ok || t.problem != problem || t.M != M || t.eps != eps) return false;
     if ((int)t.T.size() != t.p * t.K || (int)t.P.size() != t.K * t.Kstar) return false;
+    if (t.rad_w.size() != t.rad_t.size() || t.sig.size() != t.rad_t.size() * (size_t)t.K) return false;
     return true;
 }
 
@@ -875,7 +934,7 @@ void save_tables(const std::string& dir, const PatchTables& t) {
     {
         std::ofstream f(tmp, std::ios::binary);
         if (!f) return;
-        f.write("NCETAB02", 8);
+        f.write("NCETAB03", 8);
         int hdr[5] = {t.problem, t.M, t.K, t.Kstar, t.p};
         double dh[4] = {t.eps, t.tol_id, t.id_check, (double)t.n_train};
         f.write((const char*)hdr, sizeof(hdr));
@@ -889,6 +948,9 @@ void save_tables(const std::string& dir, const PatchTables& t) {
         wvec(f, t.T);
         wvec(f, t.P);
         wvec(f, t.I);
+        wvec(f, t.rad_t);
+        wvec(f, t.rad_w);
+        wvec(f, t.sig);
         uint64_t nfar = t.far.size();
         f.write((const char*)&nfar, sizeof(nfar));
         for (const auto& ft : t.far) {

@@ -41,6 +41,13 @@ struct PatchTables {
     std::vector<double> T;   // p x K, row-major
     std::vector<double> P;   // K x K*, row-major
     std::vector<double> I;   // K
+    // The one-patch densities themselves, for quadrature of a patch's field
+    // near it: radial collocation nodes t_l (13 panels x 20), their weights
+    // for integrals of sigma over the patch in t (incl. sin t and, on the last
+    // panel, the Jacobi factor), and sig[k][l] = the radial profile of basis
+    // density k at t_l (density = sig[k][l] times cos(m theta) or sin(|m| theta)).
+    std::vector<double> rad_t, rad_w;   // nr, nr
+    std::vector<double> sig;            // K x nr, row-major
     // recompressions for targets beyond D_k = 2 eps 2^(k/2), k = 1, 2, ...
     std::vector<FarTable> far;
     // diagnostics of the build
@@ -52,8 +59,26 @@ struct PatchTables {
 void zernike_modes(int M, std::vector<int>& n, std::vector<int>& m);
 double zernike_radial(int n, int m, double r);
 
-// Build the tables (may take seconds). Throws std::runtime_error on failure.
-PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads = 0);
+// Steps of the precompute that may run on a device instead of the host.
+struct PrecomputeDevice {
+    virtual ~PrecomputeDevice() = default;
+    // nmodes systems A_m X = F_m (nr x nr; nr x ncmax, nrhs[m] columns used), F overwritten
+    virtual void modal_solve(int nr, int nmodes, std::vector<double>& A, std::vector<double>& F,
+                             const std::vector<int>& nrhs, int ncmax) = 0;
+    // the fine grid (nf x 3) and W B (nf x K) used by the following calls
+    virtual void set_fine(const std::vector<double>& fxyz, const std::vector<double>& wB, int K) = 0;
+    // randomized ID of G(x^t, x^f): rank p, column order piv, T = Pi W B (p x K)
+    virtual void id(int problem, const std::vector<double>& txyz, double tol_id, int ell0, uint64_t seed, int& p,
+                    std::vector<int>& piv, std::vector<double>& T) = 0;
+    // outgoing field at held-out points, fine grid vs skeleton: max error and max value
+    virtual void check(int problem, const std::vector<double>& hxyz, const std::vector<double>& skel_xyz,
+                       const std::vector<double>& T, double& maxerr, double& maxval) = 0;
+};
+
+// Build the tables (may take seconds): on the host, or with the modal solves,
+// the IDs and their checks on `dev`. Throws std::runtime_error on failure.
+PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads = 0,
+                         PrecomputeDevice* dev = nullptr);
 
 // Cache: load/save by key under dir (empty dir = no cache). load returns false if absent.
 bool load_tables(const std::string& dir, int problem, double eps, int M, double tol_id,

@@ -15,3 +15,17 @@ def pytest_sessionstart(session):
     # one per-eps table cache for the whole session (the library reads NCE_CACHE)
     import tempfile
     os.environ.setdefault("NCE_CACHE", tempfile.mkdtemp(prefix="nce_cache_"))
+
+
+_ONEPATCH = {}
+
+
+def oracle_onepatch(problem, eps, tol_id=1e-12):
+    """(Tables, OnePatch) of the oracle's full precompute, computed once per
+    session for each (problem, eps, tol_id)."""
+    from oracle import tables
+    key = (problem, eps, tol_id)
+    if key not in _ONEPATCH:
+        tab, op, _ = tables.compute(problem, eps, 15, tol_id)
+        _ONEPATCH[key] = (tab, op)
+    return _ONEPATCH[key]

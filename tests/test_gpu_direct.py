@@ -174,10 +174,9 @@ def test_single_patch_and_pair(torch):
 @pytest.fixture(scope="module")
 def cfg1_onepatch():
     """The oracle's exterior one-patch solution and tables at eps = 0.1 (CPU)."""
-    from oracle import tables
+    from conftest import oracle_onepatch
     from oracle.greens import EXTERIOR
-    tab, op, _ = tables.compute(EXTERIOR, 0.1, 15, 1e-12)
-    return tab, op
+    return oracle_onepatch(EXTERIOR, 0.1)
 
 
 @pytest.mark.parametrize("mixed", [False, True])

@@ -110,10 +110,9 @@ def test_autotune_shapes_keep_result(torch):
 @pytest.fixture(scope="module")
 def cfg2_onepatch():
     """The oracle's interior one-patch solution and tables at eps = 0.01 (CPU)."""
-    from oracle import tables
+    from conftest import oracle_onepatch
     cfg = layouts.CONFIGS["cfg2"]
-    tab, op, _ = tables.compute(cfg["problem"], cfg["eps"], 15, 1e-12)
-    return tab, op
+    return oracle_onepatch(cfg["problem"], cfg["eps"])
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
