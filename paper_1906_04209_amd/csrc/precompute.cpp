@@ -410,6 +410,56 @@ void graded(double lo, double hi, double s, std::vector<std::pair<double, double
 }
 }  // namespace
 
+// The quadrature nodes of the modal collocation integrals, per (target node i,
+// panel p) pair (index i * kPanels + p): the same graded rules as
+// assemble_modal, with the weight 2 pi w sin t' (and the Jacobi substitution on
+// the last panel) and the panel's Lagrange basis at each node.
+static ModalNodes modal_nodes(const Radial& R) {
+    const int n = (int)R.t.size();
+    ModalNodes out;
+    out.n = n;
+    out.order = kOrder;
+    out.pair_t.resize((size_t)n * kPanels);
+    out.pair_ptr.assign(1, 0);
+    std::vector<double> xo, wo;
+    gauss_legendre(kNout, xo, wo);
+    std::vector<std::pair<double, double>> iv;
+    std::vector<double> basis(kOrder);
+    for (int i = 0; i < n; ++i) {
+        const double ti = R.t[i];
+        for (int p = 0; p < kPanels; ++p) {
+            out.pair_t[(size_t)i * kPanels + p] = ti;
+            const double lo = R.br[p], hi = R.br[p + 1], h = hi - lo;
+            const bool last = (p == kPanels - 1);
+            if (!last) graded(lo, hi, ti, iv);
+            else graded(0.0, std::sqrt(h), std::sqrt(R.eps - ti), iv);
+            for (auto& ab : iv) {
+                const double a = ab.first, b = ab.second, hh = 0.5 * (b - a), c = 0.5 * (a + b);
+                for (int q = 0; q < kNout; ++q) {
+                    const double u = c + hh * xo[q];
+                    double tq, wq;
+                    if (!last) {
+                        tq = u;
+                        wq = hh * wo[q] * std::sin(tq);
+                        lagrange_row(R.xg, R.lamg, 2.0 * (tq - lo) / h - 1.0, basis.data());
+                    } else {
+                        tq = R.eps - u * u;
+                        wq = 2.0 * hh * wo[q] * std::sin(tq);
+                        lagrange_row(R.xj, R.lamj, 2.0 * (tq - lo) / h - 1.0, basis.data());
+                        for (int l = 0; l < kOrder; ++l) basis[l] *= std::sqrt(R.eps - R.t[p * kOrder + l]);
+                    }
+                    if (tq == ti) continue;
+                    out.tq.push_back(tq);
+                    out.wq.push_back(2.0 * kPi * wq);
+                    out.basis.insert(out.basis.end(), basis.begin(), basis.end());
+                }
+            }
+            out.pair_ptr.push_back((int64_t)out.tq.size());
+        }
+    }
+    return out;
+}
+
 // Modal collocation matrices A[m][i][l] (m = 0..M, n = 260).
 static void assemble_modal(int problem, const Radial& R, int M, std::vector<double>& A) {
     const int n = (int)R.t.size();
@@ -748,7 +798,11 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
     Radial R = make_radial(eps);
     const int nr = (int)R.t.size();
     std::vector<double> A;
-    assemble_modal(problem, R, M, A);
+    if (dev) {
+        dev->modal_assemble(problem, M, modal_nodes(R), A);
+    } else {
+        assemble_modal(problem, R, M, A);
+    }
     std::vector<double> sigma((size_t)K * nr);
     std::vector<std::vector<int>> cols(M + 1);
     for (int k = 0; k < K; ++k) cols[std::abs(zm[k])].push_back(k);

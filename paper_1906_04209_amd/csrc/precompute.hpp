@@ -59,9 +59,24 @@ struct PatchTables {
 void zernike_modes(int M, std::vector<int>& n, std::vector<int>& m);
 double zernike_radial(int n, int m, double r);
 
+// Quadrature nodes of the modal collocation integrals (Section 9.2), per
+// (target node i, panel p) pair, pair index i * panels + p: nodes
+// [pair_ptr[q], pair_ptr[q+1]) at t' = tq with weight wq (2 pi, sin t' and the
+// rule folded in) and the panel's `order` basis functions there.
+struct ModalNodes {
+    int n = 0, order = 0;
+    std::vector<double> pair_t;       // target t_i per pair
+    std::vector<int64_t> pair_ptr;    // pairs + 1
+    std::vector<double> tq, wq;       // per node
+    std::vector<double> basis;        // per node x order
+};
+
 // Steps of the precompute that may run on a device instead of the host.
 struct PrecomputeDevice {
     virtual ~PrecomputeDevice() = default;
+    // A[m][i][p * order + l] = sum over the pair's nodes of wq G_m(t_i, tq) basis_l
+    // (m = 0..M; A is (M+1) x n x n, row-major)
+    virtual void modal_assemble(int problem, int M, const ModalNodes& nodes, std::vector<double>& A) = 0;
     // nmodes systems A_m X = F_m (nr x nr; nr x ncmax, nrhs[m] columns used), F overwritten
     virtual void modal_solve(int nr, int nmodes, std::vector<double>& A, std::vector<double>& F,
                              const std::vector<int>& nrhs, int ncmax) = 0;

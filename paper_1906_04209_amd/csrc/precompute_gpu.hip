@@ -337,6 +337,143 @@ __global__ __launch_bounds__(256) void k_lu_solve(int n, int nrhs_max, double* _
         }
 }
 
+
+// ---------------------------------------------------------------------------
+// Modal kernels G_m(t, t'), m = 0..M (Section 9.1), on the device: G^(1) from
+// Legendre functions of the second kind of half-integer degree (complete
+// elliptic integrals by the arithmetic-geometric mean, then the upward
+// recurrence near chi = 1 or Miller's backward recurrence), G^(2) in closed
+// form, G^(3) by composite 20-point Gauss-Legendre rules graded toward phi = 0;
+// G_m = G^(1) + s G^(2) - G^(3), s = -1 exterior, +1 interior.
+constexpr int kMaxM = 16;
+
+__device__ void elliptic_KE_dev(double kp, double& K, double& E) {
+    double a = 1.0, b = kp;
+    double sum = 0.5 * (1.0 - kp) * (1.0 + kp);
+    double pw = 0.5;
+    for (int it = 0; it < 64; ++it) {
+        const double c = 0.5 * (a - b);
+        const double an = 0.5 * (a + b), bn = sqrt(a * b);
+        pw *= 2.0;
+        sum += pw * c * c;
+        a = an;
+        b = bn;
+        if (fabs(c) <= 1e-18 * a) break;
+    }
+    K = M_PI / (2.0 * a);
+    E = K * (1.0 - sum);
+}
+
+__device__ void toroidal_q_dev(double chim1, int M, double* Q) {
+    const double chi = 1.0 + chim1;
+    const double k = sqrt(2.0 / (chi + 1.0));
+    const double kp = sqrt(chim1 / (chi + 1.0));
+    double K, E;
+    elliptic_KE_dev(kp, K, E);
+    const double q0 = k * K;
+    Q[0] = q0;
+    if (M == 0) return;
+    if (chim1 < 0.01) {
+        Q[1] = chi * k * K - (2.0 / k) * E;
+        for (int m = 1; m < M; ++m) Q[m + 1] = (2.0 * m * chi * Q[m] - (m - 0.5) * Q[m - 1]) / (m + 0.5);
+        return;
+    }
+    const double r = chi + sqrt(chim1 * (chi + 1.0));
+    const int L = M + 12 + (int)ceil(37.0 / log(r));
+    double up = 0.0, u = 1e-200;
+    for (int m = L; m >= 1; --m) {
+        const double dn = (2.0 * m * chi * u - (m + 0.5) * up) / (m - 0.5);
+        up = u;
+        u = dn;
+        if (m - 1 <= M) Q[m - 1] = u;
+        if (fabs(u) > 1e200) {
+            u *= 1e-200;
+            up *= 1e-200;
+            for (int j = m - 1; j <= M; ++j) Q[j] *= 1e-200;
+        }
+    }
+    const double f = q0 / Q[0];
+    for (int m = 0; m <= M; ++m) Q[m] *= f;
+}
+
+__device__ void modal_g3_dev(double A2, double B2, int M, const double* __restrict__ gx,
+                             const double* __restrict__ gw, double* out) {
+    const double width = 2.0 * sqrt(A2 / B2);
+    int L = (int)ceil(log2(M_PI / fmax(width, 1e-300)));
+    L = max(2, min(L, 40));
+    for (int m = 0; m <= M; ++m) out[m] = 0.0;
+    double lo = 0.0;
+    for (int j = L; j >= 0; --j) {
+        const double hi = M_PI * ldexp(1.0, -j);
+        const double h = 0.5 * (hi - lo), c = 0.5 * (hi + lo);
+        for (int q = 0; q < 20; ++q) {
+            const double phi = c + h * gx[q];
+            const double sp = sin(0.5 * phi);
+            const double d = sqrt(A2 + B2 * sp * sp);
+            const double f = h * gw[q] * log1p(0.5 * d);
+            const double c1 = cos(phi);
+            double cm1 = 1.0, cm = c1;
+            out[0] += f;
+            for (int m = 1; m <= M; ++m) {
+                out[m] += f * cm;
+                const double cn = 2.0 * c1 * cm - cm1;
+                cm1 = cm;
+                cm = cn;
+            }
+        }
+        lo = hi;
+    }
+    for (int m = 0; m <= M; ++m) out[m] /= M_PI;
+}
+
+// One thread per quadrature node: Gw[node][m] = wq G_m(t_i, tq).
+__global__ void k_modal_nodes(int problem, int M, int64_t nnodes, const int* __restrict__ node_pair,
+                              const double* __restrict__ pair_t, const double* __restrict__ tqv,
+                              const double* __restrict__ wqv, const double* __restrict__ gx,
+                              const double* __restrict__ gw, double* __restrict__ Gw) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnodes) return;
+    const double t = pair_t[node_pair[q]], tp = tqv[q];
+    const double st = sin(t), stp = sin(tp);
+    const double sh = sin(0.5 * (t - tp));
+    const double chim1 = fmax(2.0 * sh * sh / (st * stp), 1e-300);
+    double Q[kMaxM], g3[kMaxM];
+    toroidal_q_dev(chim1, M, Q);
+    modal_g3_dev(4.0 * sh * sh, 4.0 * st * stp, M, gx, gw, g3);
+    const double t1 = fmin(t, tp), t2 = fmax(t, tp);
+    const double ratio = tan(0.5 * t1) / tan(0.5 * t2);
+    const double pref = 2.0 / (M_PI * sqrt(st * stp));
+    const double s2 = problem == 1 ? -1.0 : 1.0;
+    const double w = wqv[q];
+    double rp = 1.0;
+    for (int m = 0; m <= M; ++m) {
+        double g2;
+        if (m == 0) {
+            g2 = -log(cos(0.5 * t1) * sin(0.5 * t2));
+        } else {
+            rp *= ratio;
+            g2 = rp / (2.0 * m);
+        }
+        Gw[q * (M + 1) + m] = w * (pref * Q[m] + s2 * g2 - g3[m]);
+    }
+}
+
+// One block per (i, p) pair: A[m][i][p * order + l] = sum over the pair's nodes
+// of Gw[node][m] basis[node][l], in node order.
+__global__ __launch_bounds__(256) void k_modal_reduce(int M, int n, int panels, int order,
+                                                      const int64_t* __restrict__ pair_ptr,
+                                                      const double* __restrict__ basis,
+                                                      const double* __restrict__ Gw, double* __restrict__ A) {
+    const int pr = blockIdx.x;
+    const int i = pr / panels, p = pr % panels;
+    const int64_t q0 = pair_ptr[pr], q1 = pair_ptr[pr + 1];
+    for (int o = threadIdx.x; o < (M + 1) * order; o += blockDim.x) {
+        const int m = o / order, l = o % order;
+        double acc = 0.0;
+        for (int64_t q = q0; q < q1; ++q) acc += Gw[q * (M + 1) + m] * basis[q * order + l];
+        A[((int64_t)m * n + i) * n + (int64_t)p * order + l] = acc;
+    }
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -473,6 +610,37 @@ namespace {
 class GpuPrecompute final : public PrecomputeDevice {
 public:
     explicit GpuPrecompute(hipStream_t s) : s_(s) {}
+    void modal_assemble(int problem, int M, const ModalNodes& nd, std::vector<double>& A) override {
+        if (M + 1 > kMaxM) throw std::runtime_error("M too large for the device modal kernels");
+        const int64_t nnodes = (int64_t)nd.tq.size();
+        const int npairs = (int)nd.pair_t.size();
+        const int panels = npairs / nd.n;
+        std::vector<int> node_pair((size_t)nnodes);
+        for (int pr = 0; pr < npairs; ++pr)
+            for (int64_t q = nd.pair_ptr[pr]; q < nd.pair_ptr[pr + 1]; ++q) node_pair[(size_t)q] = pr;
+        std::vector<double> gx, gw;
+        gauss_legendre(20, gx, gw);
+        Buf<int> dnp(node_pair.size());
+        Buf<int64_t> dptr(nd.pair_ptr.size());
+        Buf<double> dpt(nd.pair_t.size()), dtq(nd.tq.size()), dwq(nd.wq.size()), dbas(nd.basis.size()), dgx(20),
+            dgw(20), Gw((size_t)nnodes * (M + 1)), dA((size_t)(M + 1) * nd.n * nd.n);
+        dnp.put(node_pair, s_);
+        dptr.put(nd.pair_ptr, s_);
+        dpt.put(nd.pair_t, s_);
+        dtq.put(nd.tq, s_);
+        dwq.put(nd.wq, s_);
+        dbas.put(nd.basis, s_);
+        dgx.put(gx, s_);
+        dgw.put(gw, s_);
+        hipLaunchKernelGGL(k_modal_nodes, dim3((unsigned)((nnodes + 127) / 128)), dim3(128), 0, s_, problem, M, nnodes,
+                           dnp.p, dpt.p, dtq.p, dwq.p, dgx.p, dgw.p, Gw.p);
+        chk(hipGetLastError(), "modal kernels");
+        hipLaunchKernelGGL(k_modal_reduce, dim3(npairs), dim3(256), 0, s_, M, nd.n, panels, nd.order, dptr.p, dbas.p,
+                           Gw.p, dA.p);
+        chk(hipGetLastError(), "modal reduction");
+        dA.get(A, s_, (size_t)(M + 1) * nd.n * nd.n);
+        chk(hipStreamSynchronize(s_), "sync");
+    }
     void modal_solve(int nr, int nmodes, std::vector<double>& A, std::vector<double>& F, const std::vector<int>& nrhs,
                      int ncmax) override {
         modal_solve_gpu(s_, nr, nmodes, A, F, nrhs, ncmax);
