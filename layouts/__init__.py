@@ -30,6 +30,7 @@ __all__ = [
     "min_separation",
     "random_coeffs",
     "eps_from_area_fraction",
+    "multi_radius_centers",
     "CONFIGS",
     "config_layout",
 ]
@@ -102,6 +103,40 @@ def _accept_loop(N: int, eps: float, propose, max_attempts: int, sep_factor: flo
                 if n == N:
                     break
     return out
+
+
+def multi_radius_centers(N: int, radii, seed: int, weights=None):
+    """Uniform random centres carrying one of several patch radii each (a
+    type index into `radii`, drawn with probabilities `weights`, uniform by
+    default); any two patches i, j are accepted only with centre arclength >=
+    eps_i + eps_j + max(eps_i, eps_j), the gap between them at least the larger
+    radius (3 eps for equal radii). Returns (centres N x 3, types N)."""
+    radii = np.asarray(radii, dtype=np.float64)
+    w = np.full(len(radii), 1.0 / len(radii)) if weights is None else np.asarray(weights, dtype=np.float64)
+    g = rng(seed)
+    grid = _CellHash(3.0 * float(radii.max()) * (1.0 + 1e-9))
+    out = np.empty((N, 3))
+    typ = np.empty(N, dtype=np.int64)
+    n = attempts = 0
+    while n < N:
+        v = g.standard_normal(3)
+        p = v / np.linalg.norm(v)
+        t = int(g.choice(len(radii), p=w))
+        attempts += 1
+        if attempts > 1000 * N:
+            raise RuntimeError(f"layout generator: could only place {n} of {N} patches")
+        ok = True
+        for j in grid.near(p):
+            sep = radii[t] + radii[typ[j]] + max(radii[t], radii[typ[j]])
+            if math.atan2(np.linalg.norm(np.cross(p, out[j])), float(p @ out[j])) < sep * (1.0 + 1e-9):
+                ok = False
+                break
+        if ok:
+            out[n] = p
+            typ[n] = t
+            grid.add(p, n)
+            n += 1
+    return out, typ
 
 
 def uniform_centers(N: int, eps: float, seed: int) -> np.ndarray:

@@ -6,6 +6,8 @@ tests/golden/):
   cfg1.npz              N=10 exterior, eps=0.1, seed 1: matvec of seeded x, dense-LU solve
   cfg1i.npz             the same centres, interior: matvec of seeded x, dense-LU solve (mu,
                         I_sigma, per-patch flux, solution coefficients)
+  mt_p<problem>.npz     N=10 with two patch radii (0.1 and 0.05, seed 51), both problems: matvec of
+                        seeded x and the dense-LU solve (scalars, per-patch flux, coefficients)
   cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
   cfg3_rows.npz         N=10000 exterior clustered, eps=0.005, seed 3: 12 sampled rows
   cfg5_rows.npz         N=100000 interior, eps=0.001, seed 5: 16 sampled rows (tol_id 1e-11)
@@ -27,7 +29,7 @@ ROOT = Path(__file__).resolve().parents[2]
 sys.path.insert(0, str(ROOT))
 
 import layouts  # noqa: E402
-from oracle import csum, system, tables  # noqa: E402
+from oracle import csum, multitype, system, tables  # noqa: E402
 
 GOLD = ROOT / "tests" / "golden"
 TOL_ID = 1e-12
@@ -78,6 +80,25 @@ def make_cfg1i():
     print(f"  cfg1i mu {r['mu']:.15g}, GMRES iters {it['iters']}", flush=True)
 
 
+MT_RADII = (0.1, 0.05)
+MT_SEED = 51
+
+
+def make_mt():
+    """Two patch radii in one configuration (oracle/multitype.py)."""
+    c, types = layouts.multi_radius_centers(10, MT_RADII, MT_SEED)
+    for problem in (0, 1):
+        tabs = [_tab(problem, e) for e in MT_RADII]
+        lay = multitype.Layout(c, types, tabs)
+        x = layouts.random_coeffs(10, tabs[0].K, X_SEED, decay=0.1)
+        y = multitype.matvec_dense(lay, x)
+        r = multitype.solve_dense(lay)
+        extra = {"mu": r["mu"]} if problem == 0 else {"capture_rate": r["capture_rate"]}
+        np.savez(GOLD / f"mt_p{problem}.npz", y=y, x_seed=X_SEED, I_sigma=r["I_sigma"], flux=r["flux"],
+                 coeffs=r["x"], types=types, radii=np.array(MT_RADII), seed=MT_SEED, **extra)
+        print(f"  mt problem {problem}: types {types.tolist()} I_sigma {r['I_sigma']:.15g}", flush=True)
+
+
 def make_cfg2_rows():
     cfg = layouts.CONFIGS["cfg2"]
     tab = _tab(cfg["problem"], cfg["eps"])
@@ -113,7 +134,7 @@ def _rows_job(name, nrows, tol_id):
     return job
 
 
-JOBS = {"cfg1": make_cfg1, "cfg1i": make_cfg1i, "cfg2_rows": make_cfg2_rows,
+JOBS = {"cfg1": make_cfg1, "cfg1i": make_cfg1i, "mt": make_mt, "cfg2_rows": make_cfg2_rows,
         "cfg3_rows": _rows_job("cfg3", 12, 1e-12), "cfg5_rows": _rows_job("cfg5", 16, 1e-11)}
 
 
