@@ -125,6 +125,32 @@ void nce_default_opts(nce_opts *opts);
 int nce_setup(const double *centers_host, int64_t N, double eps, const nce_opts *opts,
               nce_ctx **out);
 
+/*
+ * A configuration of patches of several radii (the paper's Section 11 names
+ * patches of different sizes as an extension; the formulation of Sections 3,
+ * 6 and 8 holds with one precompute per radius): radius_host[i] is the
+ * arclength radius of patch i, at most 8 distinct values in (0, pi/3]; any two
+ * patches must satisfy centre arclength >= eps_i + eps_j + max(eps_i, eps_j)
+ * (a gap of at least the larger radius; 3 eps for equal radii), so that every
+ * patch lies in the far-field region of every other. Every radius gets its
+ * own tables; patch j radiates through its radius's outgoing representation
+ * and patch i is sampled at its radius's nodes. nce_matvec, nce_solve_*,
+ * nce_frames, nce_dims, nce_work, nce_autotune and nce_set_solver work on the
+ * context as on any other (coefficient vectors in the caller's patch order);
+ * the learned and coarse starts, the deflation, nce_integral_vector (use
+ * nce_types), nce_field and nce_patch_residual return NCE_ESTATE. One
+ * distinct radius is the same as nce_setup.
+ * Errors: NCE_EINVAL, NCE_ESEP, NCE_ENOMEM, NCE_EHIP, NCE_ETABLE.
+ */
+int nce_setup_radii(const double *centers_host, const double *radius_host, int64_t N, const nce_opts *opts,
+                    nce_ctx **out);
+
+/* The context's patch radii in ascending order (*ntypes of them, at most 8),
+ * each radius's integral vector I (ntypes x K host doubles, may be NULL) and
+ * the radius index of every patch (N ints in the caller's order, may be NULL).
+ * eps_host may be NULL. */
+int nce_types(const nce_ctx *ctx, int *ntypes, double *eps_host, double *I_host, int *type_host);
+
 /* Free every host and device resource of ctx (NULL is allowed). */
 void nce_destroy(nce_ctx *ctx);
 

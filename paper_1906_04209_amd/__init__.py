@@ -27,7 +27,7 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 # every symbol include/nce.h declares
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
-           "nce_field", "nce_patch_residual",
+           "nce_field", "nce_patch_residual", "nce_setup_radii", "nce_types",
            "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_forward_noalloc", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
@@ -89,6 +89,10 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
     lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
     lib.nce_integral_vector.argtypes = [vp, vp]
+    lib.nce_setup_radii.argtypes = [vp, vp, i64, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+    lib.nce_setup_radii.restype = ctypes.c_int
+    lib.nce_types.argtypes = [vp, ip, vp, vp, vp]
+    lib.nce_types.restype = ctypes.c_int
     lib.nce_field.argtypes = [vp, vp, vp, i64, ctypes.c_int, vp]
     lib.nce_field.restype = ctypes.c_int
     lib.nce_patch_residual.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
@@ -242,7 +246,9 @@ class Mlp:
 
 
 class Context:
-    """One patch layout on the current HIP device (nce_setup ... nce_destroy)."""
+    """One patch layout on the current HIP device (nce_setup ... nce_destroy).
+    eps: the common patch radius, or one radius per patch (several radii:
+    nce_setup_radii)."""
 
     def __init__(self, centers: np.ndarray, eps: float, problem: int = INTERIOR, M: int = 15,
                  tol_id: float = 1e-11, tol_grid: float = 1e-8, tol_gmres: float = 1e-10,
@@ -276,10 +282,18 @@ class Context:
         o.cache_dir = self._cache
         h = ctypes.c_void_p()
         torch.cuda.synchronize()
-        _check(self.lib, self.lib.nce_setup(c.ctypes.data, len(c), float(eps), ctypes.byref(o), ctypes.byref(h)))
+        if np.ndim(eps) == 0:
+            _check(self.lib, self.lib.nce_setup(c.ctypes.data, len(c), float(eps), ctypes.byref(o), ctypes.byref(h)))
+            self.eps = float(eps)
+        else:
+            r = np.ascontiguousarray(eps, dtype=np.float64)
+            if r.shape != (len(c),):
+                raise ValueError("one radius per patch expected")
+            _check(self.lib, self.lib.nce_setup_radii(c.ctypes.data, r.ctypes.data, len(c), ctypes.byref(o),
+                                                      ctypes.byref(h)))
+            self.eps = r.copy()
         self.h = h
         self.N = len(c)
-        self.eps = float(eps)
         self.problem = problem
         K, Ks, p, L = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(self.lib, self.lib.nce_dims(h, ctypes.byref(K), ctypes.byref(Ks), ctypes.byref(p), ctypes.byref(L)))
@@ -311,6 +325,15 @@ class Context:
         out = np.empty(self.K)
         _check(self.lib, self.lib.nce_integral_vector(self.h, out.ctypes.data))
         return out
+
+    def types(self):
+        """nce_types: (radii, integral vectors (one row per radius), type of every patch)."""
+        n = ctypes.c_int()
+        eps = np.empty(8)
+        I = np.empty((8, self.K))
+        t = np.empty(self.N, dtype=np.int32)
+        _check(self.lib, self.lib.nce_types(self.h, ctypes.byref(n), eps.ctypes.data, I.ctypes.data, t.ctypes.data))
+        return eps[:n.value].copy(), I[:n.value].copy(), t
 
     def field(self, coeffs, points, physical: bool = False):
         """nce_field: the potential u / v (or, physical=True, ubar / vbar) at
@@ -511,6 +534,15 @@ class Batch:
         """View of configuration b's N_b x K block of a batch vector."""
         o = int(self.offsets[b])
         return v[o:o + int(self.N[b]) * self.K].view(int(self.N[b]), self.K)
+
+    def types(self):
+        """nce_types: (radii, integral vectors (one row per radius), type of every patch)."""
+        n = ctypes.c_int()
+        eps = np.empty(8)
+        I = np.empty((8, self.K))
+        t = np.empty(self.N, dtype=np.int32)
+        _check(self.lib, self.lib.nce_types(self.h, ctypes.byref(n), eps.ctypes.data, I.ctypes.data, t.ctypes.data))
+        return eps[:n.value].copy(), I[:n.value].copy(), t
 
     def field(self, coeffs, points, physical: bool = False):
         """nce_field: the potential u / v (or, physical=True, ubar / vbar) at

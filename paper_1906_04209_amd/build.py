@@ -17,7 +17,7 @@ CSRC = PKG / "csrc"
 OUT = PKG / "libnce.so"
 BUILD = PKG / "_build"
 
-HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip", "batch.hip", "tree.hip", "mlp.hip", "coarse.hip", "deflate.hip", "field.hip", "precompute_gpu.hip"]
+HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip", "batch.hip", "tree.hip", "mlp.hip", "coarse.hip", "deflate.hip", "field.hip", "precompute_gpu.hip", "types.hip"]
 CPP_SOURCES = ["precompute.cpp", "tree_build.cpp", "features.cpp", "deflate_basis.cpp"]
 
 HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -113,8 +113,23 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         xin = reinterpret_cast<const T*>(ctx->d_x32.p);
     }
     // Step 1: rho_i = T f_i for every patch and every outgoing table in use
-    // (one GEMM with the shared, concatenated T)
-    HIPCHK(nce::gemm_nt<T>(s, N, pt, K, xin, K, Tm, K, rho, pt, nullptr, 0));
+    // (one GEMM with the shared, concatenated T; with several radii one GEMM
+    // per radius over its range of patches, rows of length ld)
+    constexpr bool f64 = sizeof(T) == 8;
+    const bool types = ctx->ntype > 1;
+    const int ld = types ? (f64 ? ctx->ldr : ctx->ldr32) : pt;
+    if (types) {
+        const std::vector<int>& Toff = f64 ? ctx->type_Toff : ctx->type_Toff32;
+        const std::vector<int>& tp = f64 ? ctx->type_ptot : ctx->type_ptot32;
+        for (int ty = 0; ty < ctx->ntype; ++ty) {
+            const int64_t a = ctx->type_first[ty];
+            const int nr = (int)(ctx->type_first[ty + 1] - a);
+            HIPCHK(nce::gemm_nt<T>(s, nr, tp[ty], K, xin + a * K, K, Tm + (int64_t)Toff[ty] * K, K, rho + a * ld, ld,
+                                   nullptr, 0));
+        }
+    } else {
+        HIPCHK(nce::gemm_nt<T>(s, N, pt, K, xin, K, Tm, K, rho, pt, nullptr, 0));
+    }
     mark(1);
     if (ctx->use_tree) {
         const int ti = sizeof(T) == 8 ? 0 : 1;
@@ -129,8 +144,17 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         HIPCHK(nce::tree_interp<T>(s, dt, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
         mark(4);
     } else {
+        nce::TypeTabs tt;
+        if (types) {
+            tt.ptype = ctx->d_ptype.p;
+            tt.t_soff = f64 ? ctx->d_tsoff.p : ctx->d_tsoff32.p;
+            tt.t_col = f64 ? ctx->d_tcol.p : ctx->d_tcol32.p;
+            tt.t_p = f64 ? ctx->d_tp.p : ctx->d_tp32.p;
+            tt.ntab = f64 ? ctx->tl.ntab : ctx->tl32.ntab;
+            tt.node_stride = 3 * Ks;
+        }
         HIPCHK(nce::direct_sum<T>(s, ctx->tab.problem, N, Ks, p, ctx->d_frames.p, noff, soff, rho, U,
-                                  ctx->d_logtab.p));
+                                  ctx->d_logtab.p, tt, ld));
         mark(2);
         mark(3);
         mark(4);
@@ -476,11 +500,27 @@ int solve(nce_ctx* ctx, double* coeffs, double* flux, double* Is_out, nce_info* 
         }
         inf.rel_residual = rel;
     }
-    HIPCHK(nce::patch_flux(s, (int)N, ctx->K, ctx->d_I.p, x, flux, ctx->d_partial.p, ctx->d_scal.p));
     double Is = 0;
-    HIPCHK(hipMemcpyAsync(&Is, ctx->d_scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
-    if (coeffs) HIPCHK(hipMemcpyAsync(coeffs, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->ntype > 1) {
+        // each radius's integral vector over its patches; outputs in the caller's order
+        double* fl = flux ? ctx->d_fluxp.p : nullptr;
+        for (int ty = 0; ty < ctx->ntype; ++ty) {
+            const int64_t a = ctx->type_first[ty];
+            HIPCHK(nce::patch_flux(s, (int)(ctx->type_first[ty + 1] - a), ctx->K, ctx->d_Ityp.p + (size_t)ty * ctx->K,
+                                   x + a * ctx->K, fl ? fl + a : nullptr, ctx->d_partial.p, ctx->d_scal.p + ty));
+        }
+        double part[8];
+        HIPCHK(hipMemcpyAsync(part, ctx->d_scal.p, sizeof(double) * ctx->ntype, hipMemcpyDeviceToHost, s));
+        if (coeffs) HIPCHK(nce::permute_rows(s, N, ctx->K, ctx->d_perm.p, x, coeffs, 1));
+        if (flux) HIPCHK(nce::permute_rows(s, N, 1, ctx->d_perm.p, fl, flux, 1));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int ty = 0; ty < ctx->ntype; ++ty) Is += part[ty];
+    } else {
+        HIPCHK(nce::patch_flux(s, (int)N, ctx->K, ctx->d_I.p, x, flux, ctx->d_partial.p, ctx->d_scal.p));
+        HIPCHK(hipMemcpyAsync(&Is, ctx->d_scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        if (coeffs) HIPCHK(hipMemcpyAsync(coeffs, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     *Is_out = Is;
     inf.t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = inf;
@@ -746,7 +786,12 @@ int nce_dims(const nce_ctx* ctx, int* K, int* Kstar, int* p, int* levels) {
 
 int nce_frames(const nce_ctx* ctx, double* fr) {
     if (!ctx || !fr) return fail(NCE_EINVAL, "NULL argument");
-    std::memcpy(fr, ctx->frames.data(), sizeof(double) * ctx->frames.size());
+    if (ctx->ntype > 1) {
+        for (int64_t a = 0; a < ctx->N; ++a)
+            std::memcpy(fr + 9 * ctx->perm[a], ctx->frames.data() + 9 * a, sizeof(double) * 9);
+    } else {
+        std::memcpy(fr, ctx->frames.data(), sizeof(double) * ctx->frames.size());
+    }
     return NCE_OK;
 }
 
@@ -773,7 +818,14 @@ int nce_matvec(nce_ctx* ctx, const double* x, double* y, int precision) {
     if (x == y) return fail(NCE_EINVAL, "x and y may not alias");
     if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
     return guarded([&]() -> int {
-        matvec(ctx, x, y, precision);
+        if (ctx->ntype > 1) {
+            // the context holds its patches sorted by radius
+            HIPCHK(nce::permute_rows(ctx->stream, ctx->N, ctx->K, ctx->d_perm.p, x, ctx->d_xp.p, 0));
+            matvec(ctx, ctx->d_xp.p, ctx->d_yp.p, precision);
+            HIPCHK(nce::permute_rows(ctx->stream, ctx->N, ctx->K, ctx->d_perm.p, ctx->d_yp.p, y, 1));
+        } else {
+            matvec(ctx, x, y, precision);
+        }
         return NCE_OK;
     });
 }
@@ -786,7 +838,13 @@ int nce_matvec_profile(nce_ctx* ctx, const double* x, double* y, int precision, 
         hipEvent_t ev[6] = {};
         for (auto& e : ev) HIPCHK(hipEventCreate(&e));
         try {
-            matvec(ctx, x, y, precision, ev);
+            if (ctx->ntype > 1) {
+                HIPCHK(nce::permute_rows(ctx->stream, ctx->N, ctx->K, ctx->d_perm.p, x, ctx->d_xp.p, 0));
+                matvec(ctx, ctx->d_xp.p, ctx->d_yp.p, precision, ev);
+                HIPCHK(nce::permute_rows(ctx->stream, ctx->N, ctx->K, ctx->d_perm.p, ctx->d_yp.p, y, 1));
+            } else {
+                matvec(ctx, x, y, precision, ev);
+            }
             HIPCHK(hipEventSynchronize(ev[5]));
             for (int k = 0; k < 5; ++k) {
                 float ms = 0;
@@ -982,6 +1040,7 @@ int nce_mlp_train_step(nce_mlp* m, const float* x, const float* t, int64_t B, fl
 }
 
 int nce_features(nce_ctx* ctx, float* feat) {
+    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx || !feat) return fail(NCE_EINVAL, "NULL argument");
     return guarded([&]() -> int {
         const std::vector<float> f = features_host(ctx);
@@ -992,6 +1051,7 @@ int nce_features(nce_ctx* ctx, float* feat) {
 }
 
 int nce_set_deflation(nce_ctx* ctx, int on) {
+    if (ctx && ctx->ntype > 1 && on) return fail(NCE_ESTATE, "no deflation for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     if (on != 0 && on != 1) return fail(NCE_EINVAL, "on must be 0 or 1");
     ctx->opts.deflation = on;
@@ -999,6 +1059,7 @@ int nce_set_deflation(nce_ctx* ctx, int on) {
 }
 
 int nce_deflation_matrix(nce_ctx* ctx, int* k, double* T_host) {
+    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx || !k) return fail(NCE_EINVAL, "ctx and k must not be NULL");
     return guarded([&]() -> int {
         ensure_deflation(ctx);
@@ -1009,6 +1070,7 @@ int nce_deflation_matrix(nce_ctx* ctx, int* k, double* T_host) {
 }
 
 int nce_coarse_solve(nce_ctx* ctx, double* a, int* iters, double* chi0) {
+    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     return guarded([&]() -> int {
         const double* d = coarse_amplitudes(ctx);
@@ -1021,6 +1083,7 @@ int nce_coarse_solve(nce_ctx* ctx, double* a, int* iters, double* chi0) {
 }
 
 int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
+    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != ctx->K))
         return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
@@ -1060,6 +1123,7 @@ int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
 
 int nce_integral_vector(const nce_ctx* ctx, double* I) {
     if (!ctx || !I) return fail(NCE_EINVAL, "NULL argument");
+    if (ctx->ntype > 1) return fail(NCE_ESTATE, "several patch radii: use nce_types for each radius's vector");
     std::memcpy(I, ctx->tab.I.data(), sizeof(double) * ctx->K);
     return NCE_OK;
 }

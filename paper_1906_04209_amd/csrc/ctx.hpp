@@ -135,6 +135,22 @@ struct nce_ctx {
     // coarse-space deflation of the FP32 inner solves (built at the first mixed solve)
     std::unique_ptr<nce::Deflation> defl;
     DevBuf<double> d_dtmp;
+    // several patch radii (ntype > 1): patches are held sorted by radius; the
+    // context's patch a is the caller's patch perm[a], and patches of type t
+    // are [type_first[t], type_first[t + 1])
+    int ntype = 1;
+    std::vector<double> type_eps;
+    std::vector<int64_t> type_first;
+    std::vector<int64_t> perm;
+    std::vector<nce::PatchTables> tabs, tabs32;
+    nce::TypeLayout tl, tl32;                 // per-(type, table) skeleton starts, columns, sizes
+    std::vector<int> type_Toff, type_Toff32;  // first row of each type's tables in d_T / d_T32
+    std::vector<int> type_ptot, type_ptot32;  // strengths per patch of each type
+    int ldr = 0, ldr32 = 0;                   // row length of rho / rho32
+    DevBuf<int64_t> d_perm;
+    DevBuf<int> d_ptype, d_tsoff, d_tcol, d_tp, d_tsoff32, d_tcol32, d_tp32;
+    DevBuf<double> d_Ityp;                    // ntype x K integral vectors
+    DevBuf<double> d_xp, d_yp, d_fluxp;       // vectors in the context's order
 };
 
 struct nce_mlp {
@@ -167,6 +183,11 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
               const nce_opts& o, bool forest);
 // Checks option ranges.
 int validate_opts(const nce_opts& o, double eps);
+// Patch frames (c, e1, e2 per patch) of unit centres.
+void build_frames(const double* c, int64_t N, std::vector<double>& fr);
+// Fills a context for one configuration of several patch radii (radius[i] of
+// patch i, at least two distinct values).
+void init_ctx_types(nce_ctx* ctx, const double* centers, const double* radius, int64_t N, const nce_opts& o);
 // Checks unit centres and 3 eps separation within every configuration.
 int validate_centers(const double* centers, const std::vector<int64_t>& cfg_first, double eps);
 // y = A x (FP64 in and out; precision selects the FP64 or FP32 apply),

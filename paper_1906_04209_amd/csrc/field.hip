@@ -423,7 +423,8 @@ extern "C" {
 
 int nce_field(nce_ctx* ctx, const double* coeffs, const double* points, int64_t n, int physical, double* values) {
     if (!ctx || !coeffs || !points || !values || n < 0) return fail(NCE_EINVAL, "bad argument");
-    if (ctx->cfg_first.size() != 2) return fail(NCE_ESTATE, "field evaluation needs a single-configuration context");
+    if (ctx->cfg_first.size() != 2 || ctx->ntype > 1)
+        return fail(NCE_ESTATE, "field evaluation needs a single-configuration context of one patch radius");
     if (physical != 0 && physical != 1) return fail(NCE_EINVAL, "physical must be 0 or 1");
     if (n == 0) return NCE_OK;
     return guarded([&]() -> int {
@@ -451,7 +452,8 @@ int nce_patch_residual(nce_ctx* ctx, const double* coeffs, const int64_t* patche
     if (!ctx || !coeffs || !patches || !residual || npatch < 1 || n_t < 1 || n_theta < 1 || n_t > 64 ||
         n_theta > 256)
         return fail(NCE_EINVAL, "bad argument");
-    if (ctx->cfg_first.size() != 2) return fail(NCE_ESTATE, "residual evaluation needs a single-configuration context");
+    if (ctx->cfg_first.size() != 2 || ctx->ntype > 1)
+        return fail(NCE_ESTATE, "residual evaluation needs a single-configuration context of one patch radius");
     for (int a = 0; a < npatch; ++a)
         if (patches[a] < 0 || patches[a] >= ctx->N) return fail(NCE_EINVAL, "patch index out of range");
     return guarded([&]() -> int {

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 namespace nce {
 
 // ---------------------------------------------------------------------------
@@ -21,12 +23,13 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
                                                   const double* __restrict__ rho, int ldr, double* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
                                                   const int* __restrict__ pt_cfg, const int* __restrict__ live,
-                                                  const LogEntry* __restrict__ logtab) {
+                                                  const LogEntry* __restrict__ logtab, TypeTabs tt) {
     extern __shared__ double4 sm64[];  // p source points (x, y, z, rho), half-scaled
     __shared__ LogEntry ltab[kLogTab];
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
     for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
+    if (tt.ptype) node_off += (int64_t)tt.ptype[i] * tt.node_stride;
     const double* fi = frames + 9 * (int64_t)i;
     const double cix = fi[0], ciy = fi[1], ciz = fi[2];
     double zx[NPT], zy[NPT], zz[NPT], acc[NPT];
@@ -50,18 +53,27 @@ __global__ __launch_bounds__(256) void k_direct64(int N, int Kstar, int p, const
         if (j == i) continue;
         const double* fj = frames + 9 * (int64_t)j;
         const double dcx = fj[0] - cix, dcy = fj[1] - ciy, dcz = fj[2] - ciz;
+        // the source's base skeleton (its own radius's with several radii)
+        int pj = p, col = 0;
+        const double* so = skel_off;
+        if (tt.ptype) {
+            const int b = tt.ptype[j] * tt.ntab;
+            pj = tt.t_p[b];
+            col = tt.t_col[b];
+            so = skel_off + 3 * (int64_t)tt.t_soff[b];
+        }
         __syncthreads();
-        for (int m = threadIdx.x; m < p; m += blockDim.x) {
-            const double o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+        for (int m = threadIdx.x; m < pj; m += blockDim.x) {
+            const double o0 = so[3 * m], o1 = so[3 * m + 1], o2 = so[3 * m + 2];
             double4 v;
             v.x = 0.5 * (dcx + (o0 * fj[0] + o1 * fj[3] + o2 * fj[6]));
             v.y = 0.5 * (dcy + (o0 * fj[1] + o1 * fj[4] + o2 * fj[7]));
             v.z = 0.5 * (dcz + (o0 * fj[2] + o1 * fj[5] + o2 * fj[8]));
-            v.w = rho[(int64_t)j * ldr + m];
+            v.w = rho[(int64_t)j * ldr + col + m];
             sm64[m] = v;
         }
         __syncthreads();
-        for (int m = 0; m < p; ++m) {
+        for (int m = 0; m < pj; ++m) {
             const double4 a = sm64[m];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
@@ -84,10 +96,11 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
                                                   const float* __restrict__ rho, int ldr, float* __restrict__ U,
                                                   const int64_t* __restrict__ lptr, const int* __restrict__ lsrc,
                                                   const int* __restrict__ pt_cfg, const int* __restrict__ live,
-                                                  const LogEntry* __restrict__ logtab) {
+                                                  const LogEntry* __restrict__ logtab, TypeTabs tt) {
     extern __shared__ float4 sm32[];  // p source points (x, y, z, rho), half-scaled
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
+    if (tt.ptype) node_off += (int64_t)tt.ptype[i] * tt.node_stride;
     const double* fi = frames + 9 * (int64_t)i;
     const double cix = fi[0], ciy = fi[1], ciz = fi[2];
     float zx[NPT], zy[NPT], zz[NPT];
@@ -113,21 +126,29 @@ __global__ __launch_bounds__(256) void k_direct32(int N, int Kstar, int p, const
         if (j == i) continue;
         const double* fj = frames + 9 * (int64_t)j;
         const float dcx = (float)(fj[0] - cix), dcy = (float)(fj[1] - ciy), dcz = (float)(fj[2] - ciz);
+        int pj = p, col = 0;
+        const float* so = skel_off;
+        if (tt.ptype) {
+            const int b = tt.ptype[j] * tt.ntab;
+            pj = tt.t_p[b];
+            col = tt.t_col[b];
+            so = skel_off + 3 * (int64_t)tt.t_soff[b];
+        }
         __syncthreads();
-        for (int m = threadIdx.x; m < p; m += blockDim.x) {
-            const float o0 = skel_off[3 * m], o1 = skel_off[3 * m + 1], o2 = skel_off[3 * m + 2];
+        for (int m = threadIdx.x; m < pj; m += blockDim.x) {
+            const float o0 = so[3 * m], o1 = so[3 * m + 1], o2 = so[3 * m + 2];
             float4 v;
             v.x = 0.5f * (dcx + (o0 * (float)fj[0] + o1 * (float)fj[3] + o2 * (float)fj[6]));
             v.y = 0.5f * (dcy + (o0 * (float)fj[1] + o1 * (float)fj[4] + o2 * (float)fj[7]));
             v.z = 0.5f * (dcz + (o0 * (float)fj[2] + o1 * (float)fj[5] + o2 * (float)fj[8]));
-            v.w = rho[(int64_t)j * ldr + m];
+            v.w = rho[(int64_t)j * ldr + col + m];
             sm32[m] = v;
         }
         __syncthreads();
         float aw[NPT], al[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) aw[r] = al[r] = 0.0f;
-        for (int m = 0; m < p; ++m) {
+        for (int m = 0; m < pj; ++m) {
             const float4 a = sm32[m];
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
@@ -153,64 +174,82 @@ template <>
 hipError_t list_sum<double>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
                             const double* node_off, const double* skel_off, const double* rho, int ldr, double* U,
                             const int64_t* lptr, const int* lsrc, const LogEntry* logtab, const int* pt_cfg,
-                            const int* live) {
+                            const int* live, const TypeTabs& tt) {
     const size_t sh = 4 * sizeof(double) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
         else
             hipLaunchKernelGGL((k_direct64<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct64<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
         else
             hipLaunchKernelGGL((k_direct64<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
     }
     return hipGetLastError();
 }
 
 template <>
 hipError_t list_sum<float>(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                           const float* node_off, const float* skel_off, const float* rho, int ldr, float* U,
-                           const int64_t* lptr, const int* lsrc, const LogEntry* logtab, const int* pt_cfg,
-                           const int* live) {
+                            const float* node_off, const float* skel_off, const float* rho, int ldr, float* U,
+                            const int64_t* lptr, const int* lsrc, const LogEntry* logtab, const int* pt_cfg,
+                            const int* live, const TypeTabs& tt) {
     const size_t sh = 4 * sizeof(float) * (size_t)p;
     if (Kstar > 4 * 256) return hipErrorInvalidValue;
     // nodes per thread: 2 covers K* <= 512 without idle accumulators
     if (Kstar <= 2 * 256) {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
         else
             hipLaunchKernelGGL((k_direct32<0, 2>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
     } else {
         if (problem == 1)
             hipLaunchKernelGGL((k_direct32<1, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
         else
             hipLaunchKernelGGL((k_direct32<0, 4>), dim3(N), dim3(256), sh, s, N, Kstar, p, frames, node_off, skel_off,
-                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab);
+                               rho, ldr, U, lptr, lsrc, pt_cfg, live, logtab, tt);
     }
     return hipGetLastError();
 }
 
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
-                      const T* skel_off, const T* rho, T* U, const LogEntry* logtab) {
-    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, p, U, nullptr, nullptr, logtab,
-                       nullptr, nullptr);
+                      const T* skel_off, const T* rho, T* U, const LogEntry* logtab, const TypeTabs& tt, int ldr) {
+    return list_sum<T>(s, problem, N, Kstar, p, frames, node_off, skel_off, rho, tt.ptype ? ldr : p, U, nullptr,
+                       nullptr, logtab, nullptr, nullptr, tt);
 }
 template hipError_t direct_sum<double>(hipStream_t, int, int, int, int, const double*, const double*, const double*,
-                                       const double*, double*, const LogEntry*);
+                                       const double*, double*, const LogEntry*, const TypeTabs&, int);
 template hipError_t direct_sum<float>(hipStream_t, int, int, int, int, const double*, const float*, const float*,
-                                      const float*, float*, const LogEntry*);
+                                      const float*, float*, const LogEntry*, const TypeTabs&, int);
+
+__global__ void k_permute_rows(int64_t N, int K, const int64_t* __restrict__ perm, const double* __restrict__ src,
+                               double* __restrict__ dst, int scatter) {
+    const int64_t n = N * K;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t a = e / K, k = e % K;
+        if (scatter) dst[perm[a] * K + k] = src[e];
+        else dst[e] = src[perm[a] * K + k];
+    }
+}
+
+hipError_t permute_rows(hipStream_t s, int64_t N, int K, const int64_t* perm, const double* src, double* dst,
+                        int scatter) {
+    const int64_t blocks = std::min<int64_t>(4096, (N * K + 255) / 256);
+    hipLaunchKernelGGL(k_permute_rows, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, N, K, perm, src,
+                       dst, scatter);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // Krylov vector operations (FP64). Reductions are two-stage and deterministic:

@@ -31,14 +31,32 @@ template <class T>
 hipError_t p_apply(hipStream_t s, int N, int K, int Kstar, const T* U, const T* P, const double* x,
                    double* y);
 
+// Several patch radii in one configuration: the patch type of every patch and,
+// per (type, outgoing table), where its skeleton starts in the concatenated
+// skeleton offsets, where its strengths start in a patch's row of rho, and its
+// size; each type's sampling-node offsets follow one another (node_stride
+// entries apart). ptype == nullptr: one patch radius, the arguments of the
+// call itself apply.
+struct TypeTabs {
+    const int* ptype = nullptr;
+    const int* t_soff = nullptr;
+    const int* t_col = nullptr;
+    const int* t_p = nullptr;
+    int ntab = 1;
+    int node_stride = 0;
+};
+
 // Direct all-pairs incoming field at the Zernike nodes of every patch:
 // U[i][q] = sum_{j != i} sum_m G(|z_iq - s_jm|) rho[j][m]
 // frames: N x 9 FP64 (c, e1, e2); node_off: Kstar x 3, skel_off: p x 3 local
 // offsets in T precision; rho: N x p in T.
 // logtab: the FP64 logarithm's table (device, kLogTab entries; unused by FP32).
+// With several radii (tt.ptype set) p is the largest base skeleton and ldr the
+// row length of rho.
 template <class T>
 hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames,
-                      const T* node_off, const T* skel_off, const T* rho, T* U, const LogEntry* logtab);
+                      const T* node_off, const T* skel_off, const T* rho, T* U, const LogEntry* logtab,
+                      const TypeTabs& tt = TypeTabs(), int ldr = 0);
 
 // Same with the sources of target i restricted to lsrc[lptr[i] .. lptr[i+1]) (CSR)
 // and the strengths of patch j at rho[j * ldr .. j * ldr + p).
@@ -46,7 +64,12 @@ hipError_t direct_sum(hipStream_t s, int problem, int N, int Kstar, int p, const
 template <class T>
 hipError_t list_sum(hipStream_t s, int problem, int N, int Kstar, int p, const double* frames, const T* node_off,
                     const T* skel_off, const T* rho, int ldr, T* U, const int64_t* lptr, const int* lsrc,
-                    const LogEntry* logtab, const int* pt_cfg = nullptr, const int* live = nullptr);
+                    const LogEntry* logtab, const int* pt_cfg = nullptr, const int* live = nullptr,
+                    const TypeTabs& tt = TypeTabs());
+
+// Rows of K values: scatter = 0: dst[a] = src[perm[a]]; scatter = 1: dst[perm[a]] = src[a].
+hipError_t permute_rows(hipStream_t s, int64_t N, int K, const int64_t* perm, const double* src, double* dst,
+                        int scatter);
 
 // Krylov helpers (FP64).
 hipError_t dots(hipStream_t s, int64_t n, int nv, const double* V, int64_t ldv, const double* w,

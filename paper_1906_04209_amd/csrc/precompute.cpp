@@ -782,13 +782,16 @@ static FarTable compress_outgoing(int problem, double D, double tol_id, const st
     return out;
 }
 
-PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads, PrecomputeDevice* dev) {
+PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads, PrecomputeDevice* dev,
+                         double ladder_eps) {
     if (nthreads > 0) omp_set_num_threads(nthreads);
     PatchTables out;
     out.problem = problem;
     out.eps = eps;
     out.M = M;
     out.tol_id = tol_id;
+    if (!(ladder_eps > 0.0)) ladder_eps = eps;
+    out.ladder_eps = ladder_eps;
     std::vector<int> zn, zm;
     zernike_modes(M, zn, zm);
     const int K = (int)zn.size();
@@ -874,7 +877,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
         out.n_train = base.n_train;
         int prev = base.p;
         for (int k = 1; k < 40; ++k) {
-            const double D = 2.0 * eps * std::pow(2.0, 0.5 * k);
+            const double D = 2.0 * ladder_eps * std::pow(2.0, 0.5 * k);
             if (D > kPi / 3.0) break;
             FarTable ft = compress_outgoing(problem, D, tol_id, fxyz, wB, K, R.t, std::min(384, prev + 64),
                                             0x5eed1234abcdULL + 977 * k, dev);
@@ -922,9 +925,14 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
 // ----------------------------------------------------------------------------
 // Cache.
 
-static std::string cache_name(const std::string& dir, int problem, double eps, int M, double tol_id) {
-    char buf[256];
-    std::snprintf(buf, sizeof(buf), "/nce_tables_v3_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
+static std::string cache_name(const std::string& dir, int problem, double eps, int M, double tol_id,
+                              double ladder_eps) {
+    char buf[320];
+    if (ladder_eps > 0.0 && ladder_eps != eps)
+        std::snprintf(buf, sizeof(buf), "/nce_tables_v3_p%d_eps%.17g_M%d_id%.3g_ladder%.17g.bin", problem, eps, M,
+                      tol_id, ladder_eps);
+    else
+        std::snprintf(buf, sizeof(buf), "/nce_tables_v3_p%d_eps%.17g_M%d_id%.3g.bin", problem, eps, M, tol_id);
     return dir + buf;
 }
 
@@ -943,9 +951,10 @@ static bool rvec(std::ifstream& f, std::vector<T>& v) {
     return (bool)f.read((char*)v.data(), sizeof(T) * n);
 }
 
-bool load_tables(const std::string& dir, int problem, double eps, int M, double tol_id, PatchTables& t) {
+bool load_tables(const std::string& dir, int problem, double eps, int M, double tol_id, PatchTables& t,
+                 double ladder_eps) {
     if (dir.empty()) return false;
-    std::ifstream f(cache_name(dir, problem, eps, M, tol_id), std::ios::binary);
+    std::ifstream f(cache_name(dir, problem, eps, M, tol_id, ladder_eps), std::ios::binary);
     if (!f) return false;
     char magic[8];
     if (!f.read(magic, 8) || std::memcmp(magic, "NCETAB03", 8) != 0) return false;
@@ -976,6 +985,7 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
         ok = ok && (int)ft.T.size() == ft.p * t.K;
     }
     if (!ok || t.problem != problem || t.M != M || t.eps != eps) return false;
+    t.ladder_eps = ladder_eps > 0.0 ? ladder_eps : eps;
     if ((int)t.T.size() != t.p * t.K || (int)t.P.size() != t.K * t.Kstar) return false;
     if (t.rad_w.size() != t.rad_t.size() || t.sig.size() != t.rad_t.size() * (size_t)t.K) return false;
     return true;
@@ -983,7 +993,7 @@ bool load_tables(const std::string& dir, int problem, double eps, int M, double 
 
 void save_tables(const std::string& dir, const PatchTables& t) {
     if (dir.empty()) return;
-    std::string name = cache_name(dir, t.problem, t.eps, t.M, t.tol_id);
+    std::string name = cache_name(dir, t.problem, t.eps, t.M, t.tol_id, t.ladder_eps);
     std::string tmp = name + ".tmp";
     {
         std::ofstream f(tmp, std::ios::binary);

@@ -50,6 +50,7 @@ struct PatchTables {
     std::vector<double> sig;            // K x nr, row-major
     // recompressions for targets beyond D_k = 2 eps 2^(k/2), k = 1, 2, ...
     std::vector<FarTable> far;
+    double ladder_eps = 0;   // the ladder's radius (eps unless shared with larger patches)
     // diagnostics of the build
     double id_check = 0;     // held-out far-field error / max field
     int n_train = 0;
@@ -92,12 +93,14 @@ struct PrecomputeDevice {
 
 // Build the tables (may take seconds): on the host, or with the modal solves,
 // the IDs and their checks on `dev`. Throws std::runtime_error on failure.
+// ladder_eps > 0: the recompressions sit at D_k = 2 ladder_eps 2^(k/2) instead
+// of 2 eps 2^(k/2) (several patch radii share one ladder, that of the largest).
 PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthreads = 0,
-                         PrecomputeDevice* dev = nullptr);
+                         PrecomputeDevice* dev = nullptr, double ladder_eps = 0.0);
 
 // Cache: load/save by key under dir (empty dir = no cache). load returns false if absent.
 bool load_tables(const std::string& dir, int problem, double eps, int M, double tol_id,
-                 PatchTables& out);
+                 PatchTables& out, double ladder_eps = 0.0);
 void save_tables(const std::string& dir, const PatchTables& t);
 
 // Quadrature rules (exposed for the host self-tests).

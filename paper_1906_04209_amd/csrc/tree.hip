@@ -3,6 +3,8 @@
 // interpolation at the sampling nodes (Section 8, Step 3 items 2-4). gfx950.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <stdexcept>
 #include <string>
 
@@ -92,6 +94,8 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
+                                               const int* __restrict__ it_type, const int* __restrict__ t_col,
+                                               int ntab,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
                                                const int* __restrict__ it_list, const LogEntry* __restrict__ logtab) {
@@ -107,7 +111,9 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
-    const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
+    // outgoing table: the grid's, of the item's source type with several radii
+    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
+    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -144,7 +150,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                 ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
                 ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
                 az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
-                w = rho[(int64_t)j * ptot + toff + m];
+                w = rho[(int64_t)j * ptot + col + m];
             }
             // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a: grid points lie within the cap
             // and sources at least a cap radius beyond it, so the cancellation
@@ -201,6 +207,8 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part,
+                                               const int* __restrict__ it_type, const int* __restrict__ t_col,
+                                               int ntab,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const float* __restrict__ gpt,
                                                const int* __restrict__ it_list) {
@@ -214,7 +222,9 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
-    const int tb = g_table[g], toff = t_off[tb], pt = t_p[tb];
+    // outgoing table: the grid's, of the item's source type with several radii
+    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
+    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -252,7 +262,7 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                 ax = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
                 ay = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
                 az = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
-                w = rho[(int64_t)j * ptot + toff + m];
+                w = rho[(int64_t)j * ptot + col + m];
             }
             // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a (cancellation at most a factor 5,
             // as in the FP64 kernel)
@@ -449,7 +459,8 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
                                                     const double* __restrict__ g_R, const int* __restrict__ g_nr,
                                                     const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
                                                     const T* __restrict__ coef, T* __restrict__ U,
-                                                    const int* __restrict__ pt_cfg, const int* __restrict__ live) {
+                                                    const int* __restrict__ pt_cfg, const int* __restrict__ live,
+                                                    const int* __restrict__ ptype, int node_stride) {
     constexpr int kThreads = 512 / NPT;
     constexpr int kPre = (kMaxGridQ + kThreads - 1) / kThreads;  // coefficients per thread per grid
     __shared__ T cs[2][kMaxGridQ];
@@ -457,6 +468,7 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
     if (live && !live[pt_cfg[i]]) return;
     const int64_t a0 = l2t_ptr[i], a1 = l2t_ptr[i + 1];
     if (a0 == a1) return;
+    if (ptype) node_off += (int64_t)ptype[i] * node_stride;
     const double* fi = frames + 9 * (int64_t)i;
     T ox[NPT], oy[NPT], oz[NPT], val[NPT];
 #pragma unroll
@@ -570,13 +582,31 @@ T* dev_alloc(int64_t n) {
 }  // namespace
 
 void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
-                 hipStream_t s, DeviceTree& d) {
+                 hipStream_t s, DeviceTree& d, const TypeLayout* tl) {
     d.ngrid = t.ngrid;
     d.max_q = t.max_q;
-    d.ptot = tab_off.back() + tab_p.back();
     d.g_table = dev_copy(t.g_table);
-    d.t_off = dev_copy(tab_off);
-    d.t_p = dev_copy(tab_p);
+    if (tl) {
+        // strength row length: the longest type's tables
+        int ldr = 0;
+        const int ntype = (int)tl->t_p.size() / tl->ntab;
+        for (int ty = 0; ty < ntype; ++ty) {
+            const int b = ty * tl->ntab + tl->ntab - 1;
+            ldr = std::max(ldr, tl->t_col[b] + tl->t_p[b]);
+        }
+        d.ptot = ldr;
+        d.t_off = dev_copy(tl->t_soff);
+        d.t_col = dev_copy(tl->t_col);
+        d.t_p = dev_copy(tl->t_p);
+        d.ptype = dev_copy(tl->ptype);
+        d.it_type = dev_copy(t.it_type);
+        d.ntab = tl->ntab;
+        d.node_stride = tl->node_stride;
+    } else {
+        d.ptot = tab_off.back() + tab_p.back();
+        d.t_off = dev_copy(tab_off);
+        d.t_p = dev_copy(tab_p);
+    }
     d.nitems = (int)t.it_grid.size();
     d.N = t.N;
     d.Kstar = Kstar;
@@ -643,7 +673,8 @@ void free_tree(DeviceTree& d) {
     void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
-                    d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab};
+                    d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
+                    d.it_type, d.t_col, d.ptype};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -656,11 +687,13 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
     if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
-                           skel_off, rho, d.ptot, d.part64, d.it_cfg, live, d.g_off, d.gpt64, it_list, d.logtab);
+                           skel_off, rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
+                           it_list, d.logtab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
-                           skel_off, rho, d.ptot, d.part32, d.it_cfg, live, d.g_off, d.gpt32, it_list);
+                           skel_off, rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
+                           it_list);
 }
 
 template <class T, int PROB>
@@ -707,8 +740,17 @@ hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const doub
                      const T* skel_off, const T* rho, T* U, const int* live) {
     if (!d.pt_cfg) live = nullptr;
     // near field uses the base table (the first p columns of every strength row)
+    TypeTabs tt;
+    if (d.ptype) {
+        tt.ptype = d.ptype;
+        tt.t_soff = d.t_off;
+        tt.t_col = d.t_col;
+        tt.t_p = d.t_p;
+        tt.ntab = d.ntab;
+        tt.node_stride = d.node_stride;
+    }
     return list_sum<T>(s, problem, (int)d.N, d.Kstar, d.p, frames, node_off, skel_off, rho, d.ptot, U, d.dl_ptr,
-                       d.dl_src, d.logtab, d.pt_cfg, live);
+                       d.dl_src, d.logtab, d.pt_cfg, live, tt);
 }
 template hipError_t tree_near<double>(hipStream_t, const DeviceTree&, int, const double*, const double*,
                                       const double*, const double*, double*, const int*);
@@ -728,13 +770,16 @@ hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames,
     if ((npt != 2 && npt != 4 && npt != 8) || threads * npt < d.Kstar) return hipErrorInvalidValue;
     if (npt == 2)
         hipLaunchKernelGGL((k_l2t<T, 2>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.ptype, d.node_stride);
     else if (npt == 4)
         hipLaunchKernelGGL((k_l2t<T, 4>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.ptype, d.node_stride);
     else
         hipLaunchKernelGGL((k_l2t<T, 8>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live);
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.ptype, d.node_stride);
     return hipGetLastError();
 }
 template hipError_t tree_interp<double>(hipStream_t, const DeviceTree&, const double*, const double*, double*,

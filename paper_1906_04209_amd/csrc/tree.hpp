@@ -37,6 +37,14 @@ struct DeviceTree {
     int* it_cfg = nullptr;
     int* g_cfg = nullptr;
     int* pt_cfg = nullptr;
+    // several patch radii (null for one): per item its sources' type, per
+    // (type, table) the strength column (t_off then gives the skeleton start),
+    // per patch its type; node offsets of type t at node_off + t node_stride
+    int* it_type = nullptr;
+    int* t_col = nullptr;
+    int* ptype = nullptr;
+    int ntab = 1;
+    int node_stride = 0;
     int max_q = 0;
     // half-scaled grid points relative to each cap centre (3 per point, Σq points)
     double* gpt64 = nullptr;
@@ -57,8 +65,11 @@ struct DeviceTree {
 
 // tab_off / tab_p: offsets and sizes of the outgoing tables in the
 // concatenated skeleton and strength arrays (table 0 = base, first).
+// tl (several radii, may be null): per-(type, table) skeleton starts,
+// strength columns and sizes replace tab_off / tab_p; p is then the largest
+// base skeleton.
 void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_off, const std::vector<int>& tab_p,
-                 hipStream_t s, DeviceTree& d);
+                 hipStream_t s, DeviceTree& d, const TypeLayout* tl = nullptr);
 void free_tree(DeviceTree& d);
 
 // `live` (may be null): per configuration of a forest, 0 = skip its work in

@@ -370,6 +370,53 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     }
 }
 
+void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar) {
+    std::vector<int> it_grid, it_src0, it_src1, it_type, p2l_src;
+    std::vector<int64_t> it_off;
+    int64_t poff = 0;
+    t.pairs_far = 0;
+    for (int g = 0; g < t.ngrid; ++g) {
+        const int q = t.g_nr[g] * t.g_nt[g];
+        const int first = t.it_src0[t.g_item0[g]], last = t.it_src1[t.g_item1[g] - 1];
+        // the grid's sources, stably grouped by type
+        std::vector<int> src(t.p2l_src.begin() + first, t.p2l_src.begin() + last);
+        std::stable_sort(src.begin(), src.end(), [&](int a, int b) { return tl.ptype[a] < tl.ptype[b]; });
+        t.g_item0[g] = (int)it_grid.size();
+        size_t a = 0;
+        while (a < src.size()) {
+            const int ty = tl.ptype[src[a]];
+            size_t e = a;
+            while (e < src.size() && tl.ptype[src[e]] == ty) ++e;
+            const int pg = tl.t_p[ty * tl.ntab + t.g_table[g]];
+            const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + (size_t)q * pg - 1) / ((size_t)q * pg));
+            for (size_t b = a; b < e; b += spi) {
+                const size_t f = std::min(e, b + spi);
+                it_grid.push_back(g);
+                it_src0.push_back((int)(p2l_src.size() + b));
+                it_src1.push_back((int)(p2l_src.size() + f));
+                it_type.push_back(ty);
+                it_off.push_back(poff);
+                poff += q;
+            }
+            t.pairs_far += (double)(e - a) * q * pg;
+            a = e;
+        }
+        p2l_src.insert(p2l_src.end(), src.begin(), src.end());
+        t.g_item1[g] = (int)it_grid.size();
+    }
+    t.it_grid.swap(it_grid);
+    t.it_src0.swap(it_src0);
+    t.it_src1.swap(it_src1);
+    t.it_type.swap(it_type);
+    t.it_off.swap(it_off);
+    t.p2l_src.swap(p2l_src);
+    t.total_partial = poff;
+    t.pairs_near = 0;
+    for (int64_t i = 0; i < t.N; ++i)
+        for (int64_t q = t.dl_ptr[i]; q < t.dl_ptr[i + 1]; ++q)
+            t.pairs_near += (double)Kstar * tl.t_p[tl.ptype[t.dl_src[q]] * tl.ntab];
+}
+
 void start_forest(Tree& t) {
     t = Tree();
     t.dl_ptr = {0};

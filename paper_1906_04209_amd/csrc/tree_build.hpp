@@ -59,6 +59,8 @@ struct Tree {
     std::vector<int> l2t_grid;
     // configuration of every item, grid and patch (forest; empty for one tree)
     std::vector<int> it_cfg, g_cfg, pt_cfg;
+    // patch type of every item's sources (several patch radii; empty for one)
+    std::vector<int> it_type;
     int ncfg = 0;
     // work per matrix-vector product
     double pairs_far = 0, pairs_near = 0, interp_fma = 0;
@@ -71,6 +73,24 @@ void grid_size(double rho, double tol, int& nr, int& nt);
 
 void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab,
                 double tol_grid, Tree& out);
+
+// Several patch radii in one configuration: the type of every patch and, per
+// (type, outgoing table) with `ntab` tables per type, the first skeleton point
+// in the concatenated skeleton offsets, the first strength column in a
+// patch's row and the skeleton size; node_stride = entries of a type's
+// sampling-node offsets (3 K*).
+struct TypeLayout {
+    std::vector<int> ptype;
+    std::vector<int> t_soff, t_col, t_p;
+    int ntab = 1;
+    int node_stride = 0;
+};
+
+// After build_tree on a layout of several radii (built with the largest radius
+// and a common ladder of outgoing-table distances): splits every P2L item so
+// that its sources share one type (it_type), and recounts the work with each
+// source's own skeleton sizes.
+void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar);
 
 // A forest: several independent configurations in one patch numbering, each
 // contributing its own tree or all-pairs direct lists; the far-field kernels

@@ -109,3 +109,22 @@ def test_strerror_codes():
     lib = nce.load()
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert lib.nce_strerror(code)
+
+
+def test_radii_validation():
+    """nce_setup_radii rejects bad radii, more than 8 of them and patches
+    closer than eps_i + eps_j + max(eps_i, eps_j), before any device work."""
+    lib = nce.load()
+    o = nce.Opts()
+    lib.nce_default_opts(ctypes.byref(o))
+    h = ctypes.c_void_p()
+    c = np.array([[0.0, 0.0, 1.0], [np.sin(0.35), 0.0, np.cos(0.35)]])
+    for r, want in (([0.1, -0.1], -1), ([0.1, 1.2], -1), ([0.1, 0.15], -2)):
+        rr = np.ascontiguousarray(r, dtype=np.float64)
+        assert lib.nce_setup_radii(c.ctypes.data, rr.ctypes.data, 2, ctypes.byref(o), ctypes.byref(h)) == want
+        assert lib.nce_last_error() and not h.value
+    # 0.1 + 0.15 + 0.15 = 0.4 > 0.35 failed above; 0.1 + 0.12 + 0.12 = 0.34 passes the separation test
+    cc = np.array([[np.cos(2 * np.pi * k / 9), np.sin(2 * np.pi * k / 9), 0.0] for k in range(9)])
+    rr = np.linspace(0.01, 0.02, 9)
+    assert lib.nce_setup_radii(cc.ctypes.data, rr.ctypes.data, 9, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert b"8" in lib.nce_last_error()

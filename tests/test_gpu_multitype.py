@@ -1,0 +1,120 @@
+"""Several patch radii in one configuration (nce_setup_radii): applies and
+solves against the oracle's dense two-radius system (oracle/multitype.py,
+goldens by make_golden.py), the tree against the all-pairs sum with two
+radii, the absorbing condition on patches of both radii, and the one-radius
+case through the same entry point."""
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import layouts
+
+pytestmark = pytest.mark.gpu
+GOLD = Path(__file__).resolve().parent / "golden"
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _golden_ctx(problem, **kw):
+    import paper_1906_04209_amd as nce
+    g = np.load(GOLD / f"mt_p{problem}.npz")
+    c, types = layouts.multi_radius_centers(10, g["radii"], int(g["seed"]))
+    assert np.array_equal(types, g["types"])
+    radius = g["radii"][types]
+    kw.setdefault("far_field", nce.FAR_DIRECT)
+    return g, c, types, nce.Context(c, radius, problem=problem, tol_id=1e-12, **kw)
+
+
+@pytest.mark.parametrize("problem", [0, 1])
+def test_two_radii_apply_and_solve_vs_oracle(torch, problem):
+    import paper_1906_04209_amd as nce
+    g, c, types, ctx = _golden_ctx(problem, tol_gmres=1e-12)
+    x = layouts.random_coeffs(10, ctx.K, 777, decay=0.1)
+    xd = torch.from_numpy(x).cuda()
+    ref = g["y"]
+    err = np.max(np.abs(ctx.matvec(xd).cpu().numpy() - ref)) / np.max(np.abs(ref - x))
+    errm = np.max(np.abs(ctx.matvec(xd, precision=nce.MIXED).cpu().numpy() - ref)) / np.max(np.abs(ref - x))
+    key = "mu" if problem == 0 else "capture_rate"
+    out = {}
+    for name, pr in (("fp64", nce.FP64), ("mixed", nce.MIXED)):
+        ctx.set_solver(1e-12, 100, pr)
+        r = ctx.solve()
+        assert r["converged"]
+        rel = abs(r[key] - float(g[key])) / float(g[key])
+        ferr = np.max(np.abs(r["flux"].cpu().numpy() - g["flux"])) / np.max(np.abs(g["flux"]))
+        xerr = np.max(np.abs(r["x"].cpu().numpy().reshape(10, ctx.K) - g["coeffs"])) / np.max(np.abs(g["coeffs"]))
+        out[name] = (rel, ferr, xerr)
+    radii, I, t = ctx.types()
+    print(f"problem {problem}: radii {radii}, types {t.tolist()}; apply FP64 {err:.2e} FP32 {errm:.2e}; "
+          f"(scalar, flux, coefficients) vs oracle {out}")
+    # the library numbers radii in ascending order; the patch of each radius is the same
+    assert np.allclose(radii, sorted(set(g["radii"].tolist())))
+    assert np.array_equal(radii[t], g["radii"][types])
+    assert err < 1e-12 and errm < 2e-5
+    for rel, ferr, xerr in out.values():
+        assert rel < 1e-12 and ferr < 1e-11 and xerr < 1e-11
+
+
+def test_two_radii_absorbing_condition(torch):
+    """The GPU solution meets u = 1 on patches of both radii (the oracle
+    evaluates each patch's own data plus every other patch's fine quadrature)."""
+    from conftest import oracle_onepatch
+    from oracle import multitype
+    g, c, types, ctx = _golden_ctx(1, tol_gmres=1e-12)
+    r = ctx.solve()
+    x = r["x"].cpu().numpy().reshape(10, ctx.K)
+    (t0, o0), (t1, o1) = oracle_onepatch(1, float(g["radii"][0])), oracle_onepatch(1, float(g["radii"][1]))
+    lay = multitype.Layout(c, types, [t0, t1])
+    rng = np.random.default_rng(4)
+    worst = 0.0
+    for i in range(10):
+        eps = float(g["radii"][types[i]])
+        t = eps * np.sqrt(rng.random(10))
+        th = 2 * np.pi * rng.random(10)
+        worst = max(worst, float(np.max(np.abs(multitype.patch_residual(lay, [o0, o1], x, i, t, th)))))
+    print(f"two radii: max |u - 1| on the patches {worst:.2e}")
+    assert worst < 1e-10
+
+
+@pytest.mark.parametrize("problem", [0, 1])
+def test_two_radii_tree_vs_direct(torch, problem):
+    """N = 2000 with radii 0.006 and 0.003: the tree (largest radius's caps and
+    ladder, one radius per work item) against the all-pairs sum, FP64 and FP32,
+    and the solves through both."""
+    import paper_1906_04209_amd as nce
+    c, types = layouts.multi_radius_centers(2000, (0.006, 0.003), 61)
+    radius = np.array((0.006, 0.003))[types]
+    d = nce.Context(c, radius, problem=problem, tol_id=1e-11, far_field=nce.FAR_DIRECT, tol_gmres=1e-10)
+    t = nce.Context(c, radius, problem=problem, tol_id=1e-11, tol_grid=1e-8, far_field=nce.FAR_TREE,
+                    tol_gmres=1e-10)
+    x_np = layouts.random_coeffs(2000, d.K, 6, decay=0.1)
+    x = torch.from_numpy(x_np).cuda()
+    yd = d.matvec(x).cpu().numpy()
+    yt = t.matvec(x).cpu().numpy()
+    err = np.max(np.abs(yt - yd)) / np.max(np.abs(yd - x_np))
+    ym = t.matvec(x, precision=nce.MIXED).cpu().numpy()
+    errm = np.max(np.abs(ym - yd)) / np.max(np.abs(yd - x_np))
+    key = "mu" if problem == 0 else "capture_rate"
+    rd, rt = d.solve(want_coeffs=False), t.solve(want_coeffs=False)
+    t.set_solver(1e-10, 100, nce.MIXED)
+    rm = t.solve(want_coeffs=False)
+    print(f"problem {problem}: levels {t.levels} work {t.work()}; tree vs direct {err:.2e}, FP32 tree {errm:.2e}; "
+          f"{key} direct {rd[key]:.12f} tree {rt[key]:.12f} mixed {rm[key]:.12f}")
+    assert err < 1e-8 and errm < 2e-5
+    assert rd["converged"] and rt["converged"] and rm["converged"]
+    assert abs(rt[key] - rd[key]) < 1e-9 * abs(rd[key]) and abs(rm[key] - rd[key]) < 1e-8 * abs(rd[key])
+
+
+def test_one_radius_through_radii_entry(torch):
+    import paper_1906_04209_amd as nce
+    c = layouts.uniform_centers(30, 0.05, 9)
+    a = nce.Context(c, 0.05, problem=1, tol_id=1e-12, far_field=nce.FAR_DIRECT)
+    b = nce.Context(c, np.full(30, 0.05), problem=1, tol_id=1e-12, far_field=nce.FAR_DIRECT)
+    x = torch.from_numpy(layouts.random_coeffs(30, a.K, 3, decay=0.1)).cuda()
+    assert torch.equal(a.matvec(x), b.matvec(x))
