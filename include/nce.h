@@ -190,14 +190,26 @@ int nce_matvec_profile(nce_ctx *ctx, const double *x_dev, double *y_dev, int pre
 
 /*
  * Autotuner: times every valid shape of the far-field kernels on this
- * context's own tree at the given precision -- P2L grid points per thread
- * (4 or 8) and interpolation nodes per thread (2, 4 or 8 with 256, 128 or 64
- * threads per patch) -- and keeps the fastest for later applies. choice_host
+ * context's own tree at the given precision -- the P2L form (4 or 8 grid
+ * points per thread, per-item choice of the two, or matrix-core tiles; see
+ * nce_set_shapes) and interpolation nodes per thread (2, 4 or 8 with 256, 128
+ * or 64 threads per patch) -- and keeps the fastest for later applies. choice_host
  * (may be NULL): the two chosen values. Synchronises the stream; no effect on
  * a context that sums its far field directly. Results do not depend on the
  * shapes beyond rounding order.
  */
 int nce_autotune(nce_ctx *ctx, int precision, int *choice_host);
+
+/*
+ * Sets the far-field kernel shapes directly (what nce_autotune chooses):
+ * p2l_shape 4 or 8 grid points per thread, 0 = per work item the one of the
+ * two that keeps more lanes busy, 16 = the matrix-core form (16 x 16 tiles of
+ * pair distances on the MFMA units, Green's function on the vector units);
+ * l2t_npt 2, 4 or 8 interpolation nodes per thread. Results differ only in
+ * summation order. NCE_EINVAL for other values, or a shape the tree's largest
+ * grid does not fit (4 points per thread hold grids of up to 1024 points).
+ */
+int nce_set_shapes(nce_ctx *ctx, int precision, int p2l_shape, int l2t_npt);
 
 /*
  * Change the solver settings of an existing context (tables and tree are

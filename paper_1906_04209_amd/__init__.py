@@ -27,7 +27,7 @@ FAR_AUTO, FAR_DIRECT, FAR_TREE = 0, 1, 2
 # every symbol include/nce.h declares
 SYMBOLS = ["nce_default_opts", "nce_setup", "nce_destroy", "nce_dims", "nce_frames", "nce_work",
            "nce_matvec", "nce_matvec_profile", "nce_set_solver", "nce_solve_interior", "nce_solve_exterior", "nce_integral_vector",
-           "nce_field", "nce_patch_residual", "nce_setup_radii", "nce_types",
+           "nce_field", "nce_patch_residual", "nce_setup_radii", "nce_types", "nce_set_shapes",
            "nce_strerror", "nce_last_error", "nce_mlp_create", "nce_mlp_destroy", "nce_mlp_num_params",
            "nce_mlp_get_params", "nce_mlp_set_params", "nce_mlp_forward", "nce_mlp_forward_noalloc", "nce_mlp_loss_grad",
            "nce_mlp_train_step", "nce_features", "nce_set_warm_start", "nce_setup_batch",
@@ -89,6 +89,8 @@ def load(path: Optional[os.PathLike] = None):
     lib.nce_solve_interior.argtypes = [vp, vp, vp, dp, ctypes.POINTER(Info)]
     lib.nce_solve_exterior.argtypes = [vp, vp, vp, dp, dp, ctypes.POINTER(Info)]
     lib.nce_integral_vector.argtypes = [vp, vp]
+    lib.nce_set_shapes.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.nce_set_shapes.restype = ctypes.c_int
     lib.nce_setup_radii.argtypes = [vp, vp, i64, ctypes.POINTER(Opts), ctypes.POINTER(vp)]
     lib.nce_setup_radii.restype = ctypes.c_int
     lib.nce_types.argtypes = [vp, ip, vp, vp, vp]
@@ -428,6 +430,10 @@ class Context:
         _check(self.lib, self.lib.nce_deflation_matrix(self.h, ctypes.byref(k), T.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         self._leave()
         return k.value, T[:k.value * k.value].reshape(k.value, k.value)
+
+    def set_shapes(self, precision: int, p2l: int, l2t: int) -> None:
+        """nce_set_shapes: far-field kernel shapes (P2L 0, 4, 8 or 16; interpolation 2, 4 or 8)."""
+        _check(self.lib, self.lib.nce_set_shapes(self.h, int(precision), int(p2l), int(l2t)))
 
     def set_solver(self, tol_gmres: float, max_iter: int, precision: int):
         _check(self.lib, self.lib.nce_set_solver(self.h, float(tol_gmres), int(max_iter), int(precision)))

@@ -24,6 +24,9 @@ HIPCC_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wno-unused-command-line-argument"]
 GXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fopenmp", "-march=x86-64-v3"]
+# The far-field matrix-core kernels feed each MFMA result straight into VALU
+# work; with the accumulators in AGPRs every tile pays 16 accvgpr moves.
+SOURCE_FLAGS = {"tree.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _hipcc() -> str:
@@ -56,7 +59,8 @@ def build(verbose: bool = False) -> Path:
         objs.append(str(o))
     for src in HIP_SOURCES:
         o = BUILD / (Path(src).stem + ".hip.o")
-        jobs.append([hipcc, *HIPCC_FLAGS, *inc, "-c", str(CSRC / src), "-o", str(o)])
+        jobs.append([hipcc, *HIPCC_FLAGS, *SOURCE_FLAGS.get(src, []), *inc,
+                     "-c", str(CSRC / src), "-o", str(o)])
         objs.append(str(o))
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(max_workers=workers) as ex:

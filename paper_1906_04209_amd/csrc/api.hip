@@ -248,8 +248,8 @@ void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
     };
     try {
         float tbest = 1e30f;
-        for (int r : {4, 8, 0}) {
-            if (d.max_q > 256 * (r == 4 ? 4 : 8)) continue;
+        for (int r : {4, 8, 0, 16}) {
+            if (r != 16 && d.max_q > 256 * (r == 4 ? 4 : 8)) continue;
             const float t = best_of([&] {
                 return nce::tree_far<T>(s, d, ctx->tab.problem, ctx->d_frames.p, soff, rho, nullptr, r);
             });
@@ -872,6 +872,23 @@ int nce_autotune(nce_ctx* ctx, int precision, int* choice) {
         }
         return NCE_OK;
     });
+}
+
+int nce_set_shapes(nce_ctx* ctx, int precision, int p2l_shape, int l2t_npt) {
+    if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (precision != NCE_FP64 && precision != NCE_MIXED) return fail(NCE_EINVAL, "bad precision");
+    if (p2l_shape != 0 && p2l_shape != 4 && p2l_shape != 8 && p2l_shape != 16)
+        return fail(NCE_EINVAL, "P2L shape must be 0, 4, 8 or 16");
+    if (l2t_npt != 2 && l2t_npt != 4 && l2t_npt != 8) return fail(NCE_EINVAL, "interpolation nodes per thread: 2, 4 or 8");
+    const int ti = precision == NCE_FP64 ? 0 : 1;
+    if (ctx->use_tree) {
+        const nce::DeviceTree& d = (ti == 1 && ctx->has_tree32) ? ctx->dtree32 : ctx->dtree;
+        if (p2l_shape != 16 && d.max_q > 256 * (p2l_shape == 4 ? 4 : 8))
+            return fail(NCE_EINVAL, "a grid of this tree is too large for that P2L shape");
+    }
+    ctx->tune_p2l[ti] = p2l_shape;
+    ctx->tune_l2t[ti] = l2t_npt;
+    return NCE_OK;
 }
 
 int nce_set_solver(nce_ctx* ctx, double tol, int max_iter, int precision) {

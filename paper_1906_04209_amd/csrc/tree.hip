@@ -315,6 +315,233 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
     }
 }
 
+// ------------------------------------------------- P2L on the matrix cores
+// The squared half-distances of a 16 x 16 tile of (grid point, source point)
+// pairs are one 16 x 16 x 4 product, h2 = |z|^2 + [z, 1] . [-2 a, |a|^2], which
+// the matrix cores compute (v_mfma_*_16x16x4) while the vector units evaluate
+// G on the previous tile: per pair the VALU keeps the reciprocal square root,
+// the logarithm and the accumulation, and the four distance multiply-adds
+// move to the MFMA pipe. Wave w takes the 16-point row tiles w, w + 4, ...
+// of the grid; each lane ends a tile with 4 pairs' G for one source column and
+// its 4 rows, and the 16 columns are summed across lanes at the end of every
+// staged batch into a per-grid-point LDS partial. Staging (positions relative
+// to the cap centre, padded with zero-strength points far away) as in k_p2l64.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+constexpr int kStageM = 640;  // staged source points per batch (multiple of 16)
+
+template <int PROB>
+__global__ __launch_bounds__(256) void k_p2l64_mfma(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
+                                                    const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
+                                                    const int* __restrict__ src, const double* __restrict__ g_frame,
+                                                    const int* __restrict__ g_nr, const int* __restrict__ g_nt,
+                                                    const int* __restrict__ g_table, const int* __restrict__ t_off,
+                                                    const int* __restrict__ t_p, const double* __restrict__ frames,
+                                                    const double* __restrict__ skel_off, const double* __restrict__ rho,
+                                                    int ptot, double* __restrict__ part,
+                                                    const int* __restrict__ it_type, const int* __restrict__ t_col,
+                                                    int ntab, const int* __restrict__ it_cfg,
+                                                    const int* __restrict__ live, const int64_t* __restrict__ g_off,
+                                                    const double* __restrict__ gpt, const int* __restrict__ it_list,
+                                                    const LogEntry* __restrict__ logtab) {
+    __shared__ double4 smem4[kStageM];
+    __shared__ double srho[kStageM];
+    __shared__ double red[kMaxGridQ];
+    __shared__ LogEntry ltab[kLogTab];
+    const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
+    if (live && !live[it_cfg[item]]) return;
+    for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
+    const int g = it_grid[item];
+    const int q = g_nr[g] * g_nt[g];
+    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
+    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    const double* fg = g_frame + 9 * (int64_t)g;
+    const double* zg = gpt + 3 * g_off[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, kq = lane >> 4;
+    const int nrt = (q + 15) >> 4;
+    for (int t = threadIdx.x; t < q; t += blockDim.x) red[t] = 0.0;
+    const int s0 = it_src0[item];
+    const int total = (it_src1[item] - s0) * pt;
+    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
+    for (int c0 = 0; c0 < total; c0 += kStageM) {
+        const int cl = min(kStageM, total - c0);
+        const int cl16 = (cl + 15) & ~15;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cl16; idx += blockDim.x) {
+            double ax = 8.0, ay = 8.0, az = 8.0, w = 0.0;  // padding: far away, zero strength
+            if (idx < cl) {
+                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
+                const int j = src[s0 + js];
+                const double* fj = frames + 9 * (int64_t)j;
+                const double* o = skel_off + 3 * (int64_t)(toff + m);
+                ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
+                ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
+                az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
+                w = rho[(int64_t)j * ptot + col + m];
+            }
+            smem4[idx] = make_double4(-2.0 * ax, -2.0 * ay, -2.0 * az, ax * ax + ay * ay + az * az);
+            srho[idx] = w;
+        }
+        __syncthreads();
+        const int nst = cl16 >> 4;
+        const double* sm = reinterpret_cast<const double*>(smem4);
+        for (int rt = wave; rt < nrt; rt += 4) {
+            // A(i, k): component k of grid point 16 rt + i (1 for k = 3); C: |z|^2 of this lane's rows
+            const int ra = rt * 16 + c;
+            const double aop = kq == 3 ? 1.0 : (ra < q ? zg[3 * ra + kq] : 0.0);
+            v4d_t cin;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + kq + 4 * r;
+                double z2 = 0.0;
+                if (row < q) {
+                    const double* z = zg + 3 * row;
+                    z2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+                }
+                cin[r] = z2;
+            }
+            double acc[4] = {0.0, 0.0, 0.0, 0.0}, ace[4] = {0.0, 0.0, 0.0, 0.0};
+            // software pipeline: the next tile's product is in flight on the
+            // matrix core while this tile's Green's functions are evaluated
+            v4d_t hn = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sm[4 * c + kq], cin, 0, 0, 0);
+            double wn = srho[c];
+            for (int st = 0; st < nst; ++st) {
+                const v4d_t h = hn;
+                const double w = wn;
+                if (st + 1 < nst) {
+                    hn = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sm[4 * ((st + 1) * 16 + c) + kq], cin, 0, 0, 0);
+                    wn = srho[(st + 1) * 16 + c];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double de;
+                    const double gs = green64_half_split<PROB>(h[r], ltab, de);
+                    acc[r] = fma(gs, w, acc[r]);
+                    ace[r] = fma(de, w, ace[r]);
+                }
+            }
+            // sum over the 16 source columns (the lanes with the same kq)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = fma(-kLn2Hi, ace[r], fma(-kLn2Lo, ace[r], acc[r]));
+                for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+                const int row = rt * 16 + kq + 4 * r;
+                if (c == 0 && row < q) red[row] += v;
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t off = it_off[item];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) part[off + t] = red[t];
+}
+
+template <int PROB>
+__global__ __launch_bounds__(256) void k_p2l32_mfma(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
+                                                    const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
+                                                    const int* __restrict__ src, const double* __restrict__ g_frame,
+                                                    const int* __restrict__ g_nr, const int* __restrict__ g_nt,
+                                                    const int* __restrict__ g_table, const int* __restrict__ t_off,
+                                                    const int* __restrict__ t_p, const double* __restrict__ frames,
+                                                    const float* __restrict__ skel_off, const float* __restrict__ rho,
+                                                    int ptot, float* __restrict__ part,
+                                                    const int* __restrict__ it_type, const int* __restrict__ t_col,
+                                                    int ntab, const int* __restrict__ it_cfg,
+                                                    const int* __restrict__ live, const int64_t* __restrict__ g_off,
+                                                    const float* __restrict__ gpt, const int* __restrict__ it_list) {
+    __shared__ float4 smem4[kStage];
+    __shared__ float srho[kStage];
+    __shared__ double red[kMaxGridQ];
+    const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
+    if (live && !live[it_cfg[item]]) return;
+    const int g = it_grid[item];
+    const int q = g_nr[g] * g_nt[g];
+    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
+    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    const double* fg = g_frame + 9 * (int64_t)g;
+    const float* zg = gpt + 3 * g_off[g];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, kq = lane >> 4;
+    const int nrt = (q + 15) >> 4;
+    for (int t = threadIdx.x; t < q; t += blockDim.x) red[t] = 0.0;
+    constexpr float kLn2 = 0.69314718055994530942f;
+    const int s0 = it_src0[item];
+    const int total = (it_src1[item] - s0) * pt;
+    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
+    for (int c0 = 0; c0 < total; c0 += kStage) {
+        const int cl = min(kStage, total - c0);
+        const int cl16 = (cl + 15) & ~15;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < cl16; idx += blockDim.x) {
+            float ax = 8.0f, ay = 8.0f, az = 8.0f, w = 0.0f;
+            if (idx < cl) {
+                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
+                const int j = src[s0 + js];
+                const double* fj = frames + 9 * (int64_t)j;
+                const float* o = skel_off + 3 * (int64_t)(toff + m);
+                ax = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
+                ay = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
+                az = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
+                w = rho[(int64_t)j * ptot + col + m];
+            }
+            smem4[idx] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
+            srho[idx] = w;
+        }
+        __syncthreads();
+        const int nst = cl16 >> 4;
+        const float* sm = reinterpret_cast<const float*>(smem4);
+        for (int rt = wave; rt < nrt; rt += 4) {
+            const int ra = rt * 16 + c;
+            const float aop = kq == 3 ? 1.0f : (ra < q ? zg[3 * ra + kq] : 0.0f);
+            v4f_t cin;
+            // FP32 16x16x4 layout: this lane's rows are 4 kq + r
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + 4 * kq + r;
+                float z2 = 0.0f;
+                if (row < q) {
+                    const float* z = zg + 3 * row;
+                    z2 = z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+                }
+                cin[r] = z2;
+            }
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            // FP32 sums over at most 64 tiles (64 terms per lane), carried in FP64
+            for (int st0 = 0; st0 < nst; st0 += 64) {
+                const int st1 = min(nst, st0 + 64);
+                float aw[4] = {0.0f, 0.0f, 0.0f, 0.0f}, al[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                v4f_t hn = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, sm[4 * (st0 * 16 + c) + kq], cin, 0, 0, 0);
+                float wn = srho[st0 * 16 + c];
+                for (int st = st0; st < st1; ++st) {
+                    const v4f_t h = hn;
+                    const float sw = wn;
+                    if (st + 1 < st1) {
+                        hn = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, sm[4 * ((st + 1) * 16 + c) + kq], cin, 0, 0, 0);
+                        wn = srho[(st + 1) * 16 + c];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float w, l2;
+                        green32_parts_half<PROB>(h[r], w, l2);
+                        aw[r] = fmaf(w, sw, aw[r]);
+                        al[r] = fmaf(l2, sw, al[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] += (double)(aw[r] - kLn2 * al[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double v = acc[r];
+                for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m, 64);
+                const int row = rt * 16 + 4 * kq + r;
+                if (c == 0 && row < q) red[row] += v;
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t off = it_off[item];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) part[off + t] = (float)red[t];
+}
+
 // ---------------------------------------------------- reduce + transform
 // One block per grid: sum the items' partial sums, then the angular DFT and
 // the parity-restricted radial Chebyshev transform. Coefficient layout:
@@ -697,9 +924,26 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
 }
 
 template <class T, int PROB>
+void launch_p2l_mfma(hipStream_t s, const DeviceTree& d, const double* frames, const T* skel_off, const T* rho,
+                     const int* live) {
+    if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL((k_p2l64_mfma<PROB>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames, skel_off,
+                           rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
+                           (const int*)nullptr, d.logtab);
+    else
+        hipLaunchKernelGGL((k_p2l32_mfma<PROB>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames, skel_off,
+                           rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
+                           (const int*)nullptr);
+}
+
+template <class T, int PROB>
 void launch_p2l_shape(hipStream_t s, const DeviceTree& d, const double* frames, const T* skel_off, const T* rho,
                       const int* live, int r_tgt) {
-    if (r_tgt == 8) {
+    if (r_tgt == 16) {
+        launch_p2l_mfma<T, PROB>(s, d, frames, skel_off, rho, live);
+    } else if (r_tgt == 8) {
         launch_p2l<T, PROB, 8>(s, d, frames, skel_off, rho, live, d.nitems, nullptr);
     } else if (r_tgt == 4) {
         launch_p2l<T, PROB, 4>(s, d, frames, skel_off, rho, live, d.nitems, nullptr);
@@ -714,8 +958,8 @@ template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
                     const T* rho, const int* live, int r_tgt) {
     if (!d.it_cfg) live = nullptr;
-    if (r_tgt != 4 && r_tgt != 8 && r_tgt != 0) return hipErrorInvalidValue;
-    if (d.max_q > 256 * (r_tgt == 4 ? 4 : 8)) return hipErrorInvalidValue;
+    if (r_tgt != 4 && r_tgt != 8 && r_tgt != 0 && r_tgt != 16) return hipErrorInvalidValue;
+    if (r_tgt != 16 && d.max_q > 256 * (r_tgt == 4 ? 4 : 8)) return hipErrorInvalidValue;
     if (d.nitems > 0) {
         if (problem == 1) launch_p2l_shape<T, 1>(s, d, frames, skel_off, rho, live, r_tgt);
         else launch_p2l_shape<T, 0>(s, d, frames, skel_off, rho, live, r_tgt);

@@ -78,7 +78,8 @@ void free_tree(DeviceTree& d);
 // Step 2: outgoing skeleton sums onto every incoming grid (P2L), reduced per
 // grid and turned into Chebyshev-Fourier coefficients.
 // r_tgt: grid points per thread of the P2L kernel: 4 (needs max q <= 1024), 8,
-// or 0 = per item, whichever keeps more lanes busy for its grid.
+// 0 = per item, whichever keeps more lanes busy for its grid, or 16 = the
+// matrix-core form (16 x 16 tiles of pair distances on the MFMA units).
 template <class T>
 hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* skel_off,
                     const T* rho, const int* live = nullptr, int r_tgt = 4);

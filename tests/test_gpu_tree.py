@@ -102,9 +102,18 @@ def test_autotune_shapes_keep_result(torch):
     e64 = (y64 - ref64).abs().max().item() / d
     e32 = (y32 - ref32).abs().max().item() / d
     print(f"autotune FP64 {ch64} FP32 {ch32}: change FP64 {e64:.2e} FP32 {e32:.2e}")
-    assert ch64[0] in (4, 8) and ch64[1] in (2, 4, 8) and ch32[0] in (4, 8) and ch32[1] in (2, 4, 8)
+    assert ch64[0] in (0, 4, 8, 16) and ch64[1] in (2, 4, 8) and ch32[0] in (0, 4, 8, 16) and ch32[1] in (2, 4, 8)
     assert e64 < 1e-13
     assert e32 < 1e-6
+    # every P2L form, the matrix-core one included, against the 8-point form
+    for pr, tol in ((nce.FP64, 1e-13), (nce.MIXED, 1e-6)):
+        ctx.set_shapes(pr, 8, 2)
+        ref = ctx.matvec(x, precision=pr)
+        for shape in (0, 4, 16):
+            ctx.set_shapes(pr, shape, 2)
+            e = (ctx.matvec(x, precision=pr) - ref).abs().max().item() / d
+            print(f"P2L shape {shape} precision {pr}: change {e:.2e}")
+            assert e < tol
 
 
 @pytest.fixture(scope="module")
