@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include <stdexcept>
 #include <string>
@@ -18,18 +19,20 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// grid point t = a * nt + b of a grid with nr radial Chebyshev nodes on [0, R]
-// (positive half of the 2 nr first-kind nodes on [-R, R]) and nt angles;
-// returns its local offset (cos r - 1, sin r cos th, sin r sin th).
-__device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, double& o0, double& o1, double& o2) {
+// grid point t = a * nt + b of a grid with nr radial Chebyshev nodes on
+// [0, 1] (positive half of the 2 nr first-kind nodes on [-1, 1]) and nt
+// angles, in the stereographic polar coordinates of its cap: the node x sits
+// at u = Tc x, u = tan(phi / 2) for a point at arclength phi from the cap
+// centre, Tc = tan(R / 2) for the cap radius R. Returns the point's local
+// offset (cos phi - 1, sin phi cos th, sin phi sin th).
+__device__ __forceinline__ void grid_point(int t, int nr, int nt, double Tc, double& o0, double& o1, double& o2) {
     const int a = t / nt, b = t - a * nt;
-    const double x = cospi((2.0 * a + 1.0) / (4.0 * nr));
-    const double r = R * x;
+    const double u = Tc * cospi((2.0 * a + 1.0) / (4.0 * nr));
     double sb, cb;
     sincospi(2.0 * b / nt, &sb, &cb);
-    const double sr = sin(0.5 * r);
-    o0 = -2.0 * sr * sr;
-    const double s = sin(r);
+    const double d = 1.0 / (1.0 + u * u);
+    o0 = -2.0 * u * u * d;
+    const double s = 2.0 * u * d;
     o1 = s * cb;
     o2 = s * sb;
 }
@@ -37,7 +40,7 @@ __device__ __forceinline__ void grid_point(int t, int nr, int nt, double R, doub
 // Half-scaled grid points of every grid, relative to its cap centre, in the
 // global frame (FP64 and FP32 copies); one block per grid, once per tree.
 __global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_nr, const int* __restrict__ g_nt,
-                                                     const double* __restrict__ g_R, const double* __restrict__ g_frame,
+                                                     const double* __restrict__ g_T, const double* __restrict__ g_frame,
                                                      const int64_t* __restrict__ g_off, double* __restrict__ out64,
                                                      float* __restrict__ out32) {
     const int g = blockIdx.x;
@@ -45,7 +48,7 @@ __global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_n
     const double* fg = g_frame + 9 * (int64_t)g;
     for (int t = threadIdx.x; t < q; t += blockDim.x) {
         double o0, o1, o2;
-        grid_point(t, nr, nt, g_R[g], o0, o1, o2);
+        grid_point(t, nr, nt, g_T[g], o0, o1, o2);
         const int64_t e = 3 * (g_off[g] + t);
         for (int c = 0; c < 3; ++c) {
             const double v = 0.5 * (o0 * fg[c] + o1 * fg[3 + c] + o2 * fg[6 + c]);
@@ -89,7 +92,7 @@ template <int PROB, int R>
 __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
-                                               const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                               const double* __restrict__ g_T, const int* __restrict__ g_nr,
                                                const int* __restrict__ g_nt, const int* __restrict__ g_table,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
@@ -202,7 +205,7 @@ template <int PROB, int R>
 __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
-                                               const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                               const double* __restrict__ g_T, const int* __restrict__ g_nr,
                                                const int* __restrict__ g_nt, const int* __restrict__ g_table,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
@@ -602,29 +605,64 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
 
 // ------------------------------------------------------------------ L2T
 // One block per patch: evaluate every grid of the patch's list at the patch's
-// K* nodes, in the grid's geodesic polar coordinates (r / R, theta), and add
-// the total into U once. The expansion of a grid is
-//     sum_k [cos k theta C_k(r) + sin k theta S_k(r)],
+// K* nodes, in the grid's stereographic polar coordinates (tan(phi/2) / Tc,
+// theta), and add the total into U once. The expansion of a grid is
+//     sum_k [cos k theta C_k(x) + sin k theta S_k(x)],
 // C_k, S_k Chebyshev series over the degrees of the parity of k. Per grid, a
 // thread forms the Chebyshev values of its nodes once per parity and reuses
-// them for every angular row of that parity; cos k theta and sin k theta
-// advance by rotation through 2 theta. Coefficients are staged in LDS through
-// a double buffer filled from registers loaded one grid ahead, so the next
-// grid's global loads are in flight while the current one is summed and
-// each grid costs one barrier.
+// them for every angular row of that parity; cos k theta and sin k theta of
+// one parity follow the three-term recurrence f_{k+2} = 2 cos 2theta f_k -
+// f_{k-2} (one fma each, the two newest values leapfrogging so that no
+// register moves are needed). Coefficients are staged in LDS through a double
+// buffer filled from registers loaded one grid ahead, so the next grid's
+// global loads are in flight while the current one is summed and each grid
+// costs one barrier.
+template <class T, int NPT, int NR>
+__device__ __forceinline__ void l2t_row(const T* __restrict__ cs, int half, int k, const T (&tb)[NPT][NR],
+                                        const T (&ck)[NPT], const T (&sk)[NPT], T (&val)[NPT]) {
+    const T* cc = cs + k * NR;
+    T rc[NPT];
+#pragma unroll
+    for (int r = 0; r < NPT; ++r) rc[r] = cc[0] * tb[r][0];
+#pragma unroll
+    for (int n = 1; n < NR; ++n) {
+        const T cv = cc[n];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) rc[r] += cv * tb[r][n];
+    }
+    if (k > 0 && k < half) {
+        const T* sc = cs + (half + k) * NR;
+        T rs[NPT];
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) rs[r] = sc[0] * tb[r][0];
+#pragma unroll
+        for (int n = 1; n < NR; ++n) {
+            const T sv = sc[n];
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) rs[r] += sv * tb[r][n];
+        }
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r] + sk[r] * rs[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r];
+    }
+}
+
 template <class T, int NPT, int NR>
 __device__ __forceinline__ void l2t_sum(const T* __restrict__ cs, int half, const T (&xs)[NPT],
                                         const T (&ct)[NPT], const T (&st)[NPT], T (&val)[NPT]) {
-    T c2[NPT], s2[NPT];
+    T c2[NPT], s2[NPT], t2[NPT];
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
         c2[r] = ct[r] * ct[r] - st[r] * st[r];
         s2[r] = T(2) * ct[r] * st[r];
+        t2[r] = T(2) * c2[r];
     }
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
         // tb[r][n] = T_{2n+par}(x): T_{m+2} = 2 T_2 T_m - T_{m-2}, T_2 = 2 x^2 - 1
-        T tb[NPT][NR], ck[NPT], sk[NPT];
+        T tb[NPT][NR], ca[NPT], sa[NPT], cb[NPT], sb[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const T x = xs[r], y = T(2) * x * x - T(1), ty = T(2) * y;
@@ -632,42 +670,25 @@ __device__ __forceinline__ void l2t_sum(const T* __restrict__ cs, int half, cons
             if (NR > 1) tb[r][1] = par ? x * (ty - T(1)) : y;
 #pragma unroll
             for (int n = 2; n < NR; ++n) tb[r][n] = ty * tb[r][n - 1] - tb[r][n - 2];
-            ck[r] = par ? ct[r] : T(1);
-            sk[r] = par ? st[r] : T(0);
+            // (ca, sa) = cos, sin of k theta; (cb, sb) = of (k - 2) theta
+            ca[r] = par ? ct[r] : T(1);
+            sa[r] = par ? st[r] : T(0);
+            cb[r] = par ? ct[r] : c2[r];
+            sb[r] = par ? -st[r] : -s2[r];
         }
-        for (int k = par; k <= half; k += 2) {
-            const T* cc = cs + k * NR;
-            T rc[NPT];
-#pragma unroll
-            for (int r = 0; r < NPT; ++r) rc[r] = cc[0] * tb[r][0];
-#pragma unroll
-            for (int n = 1; n < NR; ++n) {
-                const T cv = cc[n];
-#pragma unroll
-                for (int r = 0; r < NPT; ++r) rc[r] += cv * tb[r][n];
-            }
-            if (k > 0 && k < half) {
-                const T* sc = cs + (half + k) * NR;
-                T rs[NPT];
-#pragma unroll
-                for (int r = 0; r < NPT; ++r) rs[r] = sc[0] * tb[r][0];
-#pragma unroll
-                for (int n = 1; n < NR; ++n) {
-                    const T sv = sc[n];
-#pragma unroll
-                    for (int r = 0; r < NPT; ++r) rs[r] += sv * tb[r][n];
-                }
-#pragma unroll
-                for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r] + sk[r] * rs[r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < NPT; ++r) val[r] += ck[r] * rc[r];
-            }
+        for (int k = par; k <= half; k += 4) {
+            l2t_row<T, NPT, NR>(cs, half, k, tb, ca, sa, val);
 #pragma unroll
             for (int r = 0; r < NPT; ++r) {
-                const T cn = ck[r] * c2[r] - sk[r] * s2[r];
-                sk[r] = sk[r] * c2[r] + ck[r] * s2[r];
-                ck[r] = cn;
+                cb[r] = t2[r] * ca[r] - cb[r];
+                sb[r] = t2[r] * sa[r] - sb[r];
+            }
+            if (k + 2 > half) break;
+            l2t_row<T, NPT, NR>(cs, half, k + 2, tb, cb, sb, val);
+#pragma unroll
+            for (int r = 0; r < NPT; ++r) {
+                ca[r] = t2[r] * cb[r] - ca[r];
+                sa[r] = t2[r] * sb[r] - sa[r];
             }
         }
     }
@@ -679,11 +700,17 @@ __device__ __forceinline__ T rsqrt_t(T v) {
     else return rsqrtf(v);
 }
 
+template <class T>
+__device__ __forceinline__ T rcp_t(T v) {
+    if constexpr (sizeof(T) == 8) return 1.0 / v;
+    else return __builtin_amdgcn_rcpf(v);
+}
+
 template <class T, int NPT>
 __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __restrict__ frames,
                                                     const T* __restrict__ node_off, const int64_t* __restrict__ l2t_ptr,
                                                     const int* __restrict__ l2t_grid, const double* __restrict__ g_frame,
-                                                    const double* __restrict__ g_R, const int* __restrict__ g_nr,
+                                                    const double* __restrict__ g_T, const int* __restrict__ g_nr,
                                                     const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
                                                     const T* __restrict__ coef, T* __restrict__ U,
                                                     const int* __restrict__ pt_cfg, const int* __restrict__ live,
@@ -738,8 +765,10 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
         const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
         const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
         const T cgx = (T)fg[0], cgy = (T)fg[1], cgz = (T)fg[2];
-        const T invR = (T)(1.0 / g_R[g]);
-        // polar coordinates of every node about the grid's cap centre
+        const T invT = (T)(1.0 / g_T[g]);
+        // stereographic polar coordinates of every node about the grid's cap
+        // centre: with x3 = cos phi - 1 and rh = sin phi, tan(phi / 2) =
+        // rh / (2 + x3) (no cancellation: 2 + x3 >= 1 inside the cap)
         T xs[NPT], ct[NPT], st[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
@@ -753,7 +782,7 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
             const T rh = off_axis ? s * w : T(0);
             ct[r] = off_axis ? x1 * w : T(1);
             st[r] = off_axis ? x2 * w : T(0);
-            const T x = atan2(rh, T(1) + x3) * invR;
+            const T x = rh * invT * rcp_t<T>(T(2) + x3);
             xs[r] = x > T(1) ? T(1) : x;
         }
         const T* c = cs[buf];
@@ -839,7 +868,11 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
     d.Kstar = Kstar;
     d.p = p;
     d.g_frame = dev_copy(t.g_frame);
-    d.g_R = dev_copy(t.g_R);
+    {
+        std::vector<double> tc(t.g_R.size());
+        for (size_t g = 0; g < tc.size(); ++g) tc[g] = std::tan(0.5 * t.g_R[g]);
+        d.g_T = dev_copy(tc);
+    }
     d.g_nr = dev_copy(t.g_nr);
     d.g_nt = dev_copy(t.g_nt);
     d.g_off = dev_copy(t.g_off);
@@ -889,7 +922,7 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
     d.gpt64 = dev_alloc<double>(3 * t.total_q);
     d.gpt32 = dev_alloc<float>(3 * t.total_q);
     if (d.ngrid > 0) {
-        hipLaunchKernelGGL(k_grid_points, dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_R, d.g_frame, d.g_off,
+        hipLaunchKernelGGL(k_grid_points, dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_T, d.g_frame, d.g_off,
                            d.gpt64, d.gpt32);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             throw std::runtime_error("grid point setup failed");
@@ -897,7 +930,7 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
 }
 
 void free_tree(DeviceTree& d) {
-    void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_R,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
+    void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_T,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
                     d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
@@ -913,12 +946,12 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
     if (nblocks <= 0) return;
     if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
                            it_list, d.logtab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
                            it_list);
 }
@@ -1014,15 +1047,15 @@ hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames,
     if ((npt != 2 && npt != 4 && npt != 8) || threads * npt < d.Kstar) return hipErrorInvalidValue;
     if (npt == 2)
         hipLaunchKernelGGL((k_l2t<T, 2>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
                            d.ptype, d.node_stride);
     else if (npt == 4)
         hipLaunchKernelGGL((k_l2t<T, 4>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
                            d.ptype, d.node_stride);
     else
         hipLaunchKernelGGL((k_l2t<T, 8>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
-                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_R, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
+                           d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
                            d.ptype, d.node_stride);
     return hipGetLastError();
 }

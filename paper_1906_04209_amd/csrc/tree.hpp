@@ -18,7 +18,7 @@ struct DeviceTree {
     int* t_off = nullptr;      // per table: first strength column / skeleton point
     int* t_p = nullptr;        // per table: skeleton size
     double* g_frame = nullptr;
-    double* g_R = nullptr;
+    double* g_T = nullptr;     // per grid: tan(R / 2), its cap radius R in the stereographic radius
     int* g_nr = nullptr;
     int* g_nt = nullptr;
     int64_t* g_off = nullptr;
