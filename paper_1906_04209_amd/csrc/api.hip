@@ -47,6 +47,24 @@ void build_frames(const double* c, int64_t N, std::vector<double>& fr) {
     }
 }
 
+void upload_transform_factors(nce_ctx* ctx, hipStream_t s) {
+    std::vector<double> trig, rad;
+    std::vector<int> mode;
+    nce::transform_factors(ctx->tab.M, trig, rad, mode);
+    // trig rows zero padded to a multiple of 4 (16-byte reads in the kernel)
+    const int nth = 2 * ctx->tab.M + 2, ld = (nth + 3) / 4 * 4, nm = 2 * ctx->tab.M + 1;
+    std::vector<double> tp((size_t)nm * ld, 0.0);
+    for (int j = 0; j < nm; ++j)
+        for (int b = 0; b < nth; ++b) tp[(size_t)j * ld + b] = trig[(size_t)j * nth + b];
+    trig.swap(tp);
+    ctx->trig_ld = ld;
+    ctx->d_Ptrig.upload(trig, s);
+    ctx->d_Prad.upload(rad, s);
+    ctx->d_Ptrig32.upload(to_f32(trig), s);
+    ctx->d_Prad32.upload(to_f32(rad), s);
+    ctx->d_Pmode.upload(mode, s);
+}
+
 // Every pair of centres closer than 3 eps (arclength) -> NCE_ESEP. Uniform grid
 // hash in R^3 with cells of the corresponding chord length.
 int check_separation(const double* c, int64_t N, double eps) {
@@ -140,8 +158,23 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         // Step 3: leaf neighbours directly at the sampling nodes (writes U)
         HIPCHK(nce::tree_near<T>(s, dt, ctx->tab.problem, ctx->d_frames.p, noff, soff, rho, U, live));
         mark(3);
-        // Step 4: interpolation of every ancestor's incoming grid (adds into U)
-        HIPCHK(nce::tree_interp<T>(s, dt, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti]));
+        // Step 4: interpolation of every ancestor's incoming grid, and Step 5,
+        // y = x + P U, in the same kernel's epilogue (U is not written back)
+        nce::PApply<T> pa;
+        if constexpr (f64) {
+            pa.trig = ctx->d_Ptrig.p;
+            pa.rad = ctx->d_Prad.p;
+        } else {
+            pa.trig = ctx->d_Ptrig32.p;
+            pa.rad = ctx->d_Prad32.p;
+        }
+        pa.mode = ctx->d_Pmode.p;
+        pa.trig_ld = ctx->trig_ld;
+        pa.M = ctx->tab.M;
+        pa.K = K;
+        pa.x = x;
+        pa.y = y;
+        HIPCHK(nce::tree_interp<T>(s, dt, ctx->d_frames.p, noff, U, live, ctx->tune_l2t[ti], &pa));
         mark(4);
     } else {
         nce::TypeTabs tt;
@@ -158,9 +191,9 @@ void matvec_t(nce_ctx* ctx, const double* x, double* y, const T* Tm, const T* Pm
         mark(2);
         mark(3);
         mark(4);
+        // Step 5: y = x + P U
+        HIPCHK(nce::p_apply<T>(s, N, K, Ks, U, Pm, x, y));
     }
-    // Step 5: y = x + P U
-    HIPCHK(nce::p_apply<T>(s, N, K, Ks, U, Pm, x, y));
     mark(5);
 }
 
@@ -262,7 +295,23 @@ void autotune_t(nce_ctx* ctx, const T* soff, const T* noff, T* rho, T* U) {
         for (int npt : {2, 4, 8}) {
             const int threads = npt == 2 ? 256 : (npt == 4 ? 128 : 64);
             if (threads * npt < ctx->Kstar) continue;
-            const float t = best_of([&] { return nce::tree_interp<T>(s, d, ctx->d_frames.p, noff, U, nullptr, npt); });
+            // the fused form the applies run (x = y = the residual buffer as scratch)
+            nce::PApply<T> pa;
+            if constexpr (sizeof(T) == 8) {
+                pa.trig = ctx->d_Ptrig.p;
+                pa.rad = ctx->d_Prad.p;
+            } else {
+                pa.trig = ctx->d_Ptrig32.p;
+                pa.rad = ctx->d_Prad32.p;
+            }
+            pa.mode = ctx->d_Pmode.p;
+            pa.trig_ld = ctx->trig_ld;
+            pa.M = ctx->tab.M;
+            pa.K = ctx->K;
+            pa.x = ctx->d_r.p;
+            pa.y = ctx->d_r.p;
+            const float t =
+                best_of([&] { return nce::tree_interp<T>(s, d, ctx->d_frames.p, noff, U, nullptr, npt, &pa); });
             if (t < tbest) {
                 tbest = t;
                 ctx->tune_l2t[ti] = npt;
@@ -659,6 +708,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
     ctx->d_skel_off.upload(soff, s);
     ctx->d_T32.upload(to_f32(Tall32), s);
     ctx->d_P32.upload(to_f32(ctx->tab.P), s);
+    upload_transform_factors(ctx, s);
     ctx->d_node_off32.upload(to_f32(ctx->tab.node_off), s);
     ctx->d_skel_off32.upload(to_f32(soff32), s);
     {

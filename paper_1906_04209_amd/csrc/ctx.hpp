@@ -117,6 +117,11 @@ struct nce_ctx {
     // device tables
     DevBuf<double> d_frames, d_T, d_P, d_I, d_node_off, d_skel_off;
     DevBuf<float> d_T32, d_P32, d_node_off32, d_skel_off32;
+    // P's factors (transform_factors) for the interpolation kernel's fused P apply
+    DevBuf<double> d_Ptrig, d_Prad;
+    DevBuf<float> d_Ptrig32, d_Prad32;
+    DevBuf<int> d_Pmode;
+    int trig_ld = 0;                    // row stride of d_Ptrig(32)
     DevBuf<nce::LogEntry> d_logtab;     // FP64 logarithm table of the direct sums
     // matvec work arrays
     DevBuf<double> d_rho, d_U;
@@ -185,6 +190,8 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
 int validate_opts(const nce_opts& o, double eps);
 // Patch frames (c, e1, e2 per patch) of unit centres.
 void build_frames(const double* c, int64_t N, std::vector<double>& fr);
+// uploads P's factors for the fused P apply (enqueued on s)
+void upload_transform_factors(nce_ctx* ctx, hipStream_t s);
 // Fills a context for one configuration of several patch radii (radius[i] of
 // patch i, at least two distinct values).
 void init_ctx_types(nce_ctx* ctx, const double* centers, const double* radius, int64_t N, const nce_opts& o);

@@ -152,6 +152,31 @@ double zernike_radial(int n, int m, double r) {
     return ((s & 1) ? -1.0 : 1.0) * std::pow(r, m) * pn;
 }
 
+void transform_factors(int M, std::vector<double>& trig, std::vector<double>& rad, std::vector<int>& mode) {
+    std::vector<int> zn, zm;
+    zernike_modes(M, zn, zm);
+    const int K = (int)zn.size(), nth = 2 * M + 2, nrad = M + 1;
+    std::vector<double> x, w;
+    gauss_legendre(nrad, x, w);
+    trig.assign((size_t)(2 * M + 1) * nth, 0.0);
+    for (int j = 0; j <= 2 * M; ++j)
+        for (int b = 0; b < nth; ++b) {
+            const double th = 2.0 * kPi * b / nth;
+            trig[(size_t)j * nth + b] = j <= M ? std::cos(j * th) : std::sin((j - M) * th);
+        }
+    rad.assign((size_t)K * nrad, 0.0);
+    mode.assign(K, 0);
+    for (int k = 0; k < K; ++k) {
+        mode[k] = zm[k] >= 0 ? zm[k] : M - zm[k];
+        // orthogonality: the integral of Z_k^2 over the unit disk
+        const double nrm = (zm[k] == 0 ? 2.0 : 1.0) * kPi / (2.0 * zn[k] + 2.0);
+        for (int a = 0; a < nrad; ++a) {
+            const double rho = 0.5 * (x[a] + 1.0), wr = 0.5 * w[a];
+            rad[(size_t)k * nrad + a] = zernike_radial(zn[k], zm[k], rho) * rho * wr * (2.0 * kPi / nth) / nrm;
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Modal kernels (Section 9.1).
 
@@ -886,8 +911,11 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
         }
     }
 
-    // Zernike sampling nodes and transform P
+    // Zernike sampling nodes and transform P (from its two factors)
     {
+        std::vector<double> trig, rad;
+        std::vector<int> mode;
+        transform_factors(M, trig, rad, mode);
         std::vector<double> x, w;
         gauss_legendre(M + 1, x, w);
         const int nth = 2 * M + 2;
@@ -897,7 +925,7 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
         out.node_off.resize((size_t)3 * out.Kstar);
         out.P.assign((size_t)K * out.Kstar, 0.0);
         for (int a = 0; a <= M; ++a) {
-            const double rho = 0.5 * (x[a] + 1.0), wr = 0.5 * w[a];
+            const double rho = 0.5 * (x[a] + 1.0);
             for (int b = 0; b < nth; ++b) {
                 const int q = a * nth + b;
                 const double th = 2.0 * kPi * b / nth, t = eps * rho;
@@ -907,12 +935,8 @@ PatchTables build_tables(int problem, double eps, int M, double tol_id, int nthr
                 out.node_off[3 * q] = -2.0 * sh * sh;
                 out.node_off[3 * q + 1] = std::sin(t) * std::cos(th);
                 out.node_off[3 * q + 2] = std::sin(t) * std::sin(th);
-                for (int k = 0; k < K; ++k) {
-                    const double ang = zm[k] >= 0 ? std::cos(zm[k] * th) : std::sin(-zm[k] * th);
-                    const double nrm = (zm[k] == 0 ? 2.0 : 1.0) * kPi / (2.0 * zn[k] + 2.0);
-                    out.P[(size_t)k * out.Kstar + q] =
-                        zernike_radial(zn[k], zm[k], rho) * ang * rho * wr * (2.0 * kPi / nth) / nrm;
-                }
+                for (int k = 0; k < K; ++k)
+                    out.P[(size_t)k * out.Kstar + q] = rad[(size_t)k * (M + 1) + a] * trig[(size_t)mode[k] * nth + b];
             }
         }
     }

@@ -60,6 +60,14 @@ struct PatchTables {
 void zernike_modes(int M, std::vector<int>& n, std::vector<int>& m);
 double zernike_radial(int n, int m, double r);
 
+// The transform P (K x K*) factors over the sampling grid (M + 1 Gauss-Legendre
+// radii x 2M + 2 angles, node q = a (2M + 2) + b) as
+//   P[k][q] = rad[k][a] trig[mode[k]][b],
+// trig ((2M + 1) x (2M + 2)): rows j = 0..M cos(j theta_b), rows M + m sin(m
+// theta_b); rad (K x (M + 1)): the Zernike radial factor with the quadrature
+// weights and the normalisation; mode[k] the trig row of basis function k.
+void transform_factors(int M, std::vector<double>& trig, std::vector<double>& rad, std::vector<int>& mode);
+
 // Quadrature nodes of the modal collocation integrals (Section 9.2), per
 // (target node i, panel p) pair, pair index i * panels + p: nodes
 // [pair_ptr[q], pair_ptr[q+1]) at t' = tq with weight wq (2 pi, sin t' and the

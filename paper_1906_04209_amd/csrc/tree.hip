@@ -617,6 +617,12 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_n
 // buffer filled from registers loaded one grid ahead, so the next grid's
 // global loads are in flight while the current one is summed and each grid
 // costs one barrier.
+// LDS per buffer: a grid's coefficients; at the end (fused P apply) the
+// node values and angular coefficients of the largest basis (M = 15: 16 x 36
+// + 31 x 16 values)
+constexpr int kL2tBuf = kMaxGridQ;
+static_assert(16 * 36 + 31 * 16 <= 2 * kL2tBuf, "fused P apply does not fit the L2T buffers");
+
 template <class T, int NPT, int NR>
 __device__ __forceinline__ void l2t_row(const T* __restrict__ cs, int half, int k, const T (&tb)[NPT][NR],
                                         const T (&ck)[NPT], const T (&sk)[NPT], T (&val)[NPT]) {
@@ -700,11 +706,6 @@ __device__ __forceinline__ T rsqrt_t(T v) {
     else return rsqrtf(v);
 }
 
-template <class T>
-__device__ __forceinline__ T rcp_t(T v) {
-    if constexpr (sizeof(T) == 8) return 1.0 / v;
-    else return __builtin_amdgcn_rcpf(v);
-}
 
 template <class T, int NPT>
 __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __restrict__ frames,
@@ -714,14 +715,16 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
                                                     const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
                                                     const T* __restrict__ coef, T* __restrict__ U,
                                                     const int* __restrict__ pt_cfg, const int* __restrict__ live,
-                                                    const int* __restrict__ ptype, int node_stride) {
+                                                    const int* __restrict__ ptype, int node_stride, PApply<T> pa) {
     constexpr int kThreads = 512 / NPT;
     constexpr int kPre = (kMaxGridQ + kThreads - 1) / kThreads;  // coefficients per thread per grid
-    __shared__ T cs[2][kMaxGridQ];
+    // the grid coefficients' double buffer; at the end (fused P apply) the
+    // node values, the trig rows and the angular coefficients
+    __shared__ __align__(16) T cs_all[2 * kL2tBuf];
     const int i = blockIdx.x;
     if (live && !live[pt_cfg[i]]) return;
     const int64_t a0 = l2t_ptr[i], a1 = l2t_ptr[i + 1];
-    if (a0 == a1) return;
+    if (a0 == a1 && !pa.y) return;
     if (ptype) node_off += (int64_t)ptype[i] * node_stride;
     const double* fi = frames + 9 * (int64_t)i;
     T ox[NPT], oy[NPT], oz[NPT], val[NPT];
@@ -747,13 +750,13 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
             pre[j] = t < q ? src[t] : T(0);
         }
     };
-    int gn = l2t_grid[a0];
-    fetch(gn);
+    int gn = a0 < a1 ? l2t_grid[a0] : 0;
+    if (a0 < a1) fetch(gn);
     int buf = 0;
     for (int64_t aa = a0; aa < a1; ++aa) {
         const int g = gn;
 #pragma unroll
-        for (int j = 0; j < kPre; ++j) cs[buf][threadIdx.x + j * kThreads] = pre[j];
+        for (int j = 0; j < kPre; ++j) cs_all[buf * kL2tBuf + threadIdx.x + j * kThreads] = pre[j];
         __syncthreads();
         if (aa + 1 < a1) {
             gn = l2t_grid[aa + 1];
@@ -764,28 +767,28 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
         const T dcx = (T)(fi[0] - fg[0]), dcy = (T)(fi[1] - fg[1]), dcz = (T)(fi[2] - fg[2]);
         const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
         const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
-        const T cgx = (T)fg[0], cgy = (T)fg[1], cgz = (T)fg[2];
         const T invT = (T)(1.0 / g_T[g]);
         // stereographic polar coordinates of every node about the grid's cap
-        // centre: with x3 = cos phi - 1 and rh = sin phi, tan(phi / 2) =
-        // rh / (2 + x3) (no cancellation: 2 + x3 >= 1 inside the cap)
+        // centre: for v = node - centre (both on the unit sphere) at angle
+        // phi, |v|^2 = 2 - 2 cos phi and the in-plane part has length sin phi,
+        // so tan(phi / 2) = (1 - cos phi) / sin phi = |v|^2 / (2 sin phi):
+        // one reciprocal square root per node and grid, no cancellation
         T xs[NPT], ct[NPT], st[NPT];
 #pragma unroll
         for (int r = 0; r < NPT; ++r) {
             const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
             const T x1 = vx * e1x + vy * e1y + vz * e1z;
             const T x2 = vx * e2x + vy * e2y + vz * e2z;
-            const T x3 = vx * cgx + vy * cgy + vz * cgz;
             const T s = x1 * x1 + x2 * x2;
             const bool off_axis = s > T(0);
             const T w = rsqrt_t<T>(off_axis ? s : T(1));
-            const T rh = off_axis ? s * w : T(0);
             ct[r] = off_axis ? x1 * w : T(1);
             st[r] = off_axis ? x2 * w : T(0);
-            const T x = rh * invT * rcp_t<T>(T(2) + x3);
+            const T v2 = vx * vx + vy * vy + vz * vz;
+            const T x = off_axis ? T(0.5) * v2 * w * invT : T(0);
             xs[r] = x > T(1) ? T(1) : x;
         }
-        const T* c = cs[buf];
+        const T* c = cs_all + buf * kL2tBuf;
         static_assert(kMaxGridNr == 16, "one case per radial order");
         switch (nr) {
 #define NCE_L2T_CASE(n) \
@@ -810,10 +813,74 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
         }
         buf ^= 1;
     }
+    if (!pa.y) {
+#pragma unroll
+        for (int r = 0; r < NPT; ++r) {
+            const int qn = threadIdx.x + r * kThreads;
+            if (qn < Kstar) U[(int64_t)i * Kstar + qn] += val[r];
+        }
+        return;
+    }
+    // Step 5 in the epilogue: u = U (the near field) + the interpolated far
+    // field stays in LDS, and y_i = x_i + P u through P's two factors: an
+    // angular transform per ring of nodes, F[j][a] = sum_b trig[j][b] u[a][b],
+    // then a radial sum per basis function, (P u)_k = sum_a rad[k][a] F[mode_k][a]
+    const int M = pa.M, nrad = M + 1, nth = 2 * M + 2, nmode = 2 * M + 1;
+    constexpr int W = 16 / sizeof(T);           // values per 16-byte read
+    constexpr int kMaxV = 32 / W;               // 16-byte reads per ring (nth <= 32)
+    const int nv = (nth + W - 1) / W, ld = nv * W + 4;
+    T* su = cs_all;                             // 16 x ld node values, zero padded to nv W
+    T* sf = su + 16 * ld;                       // nmode x 16 angular coefficients
+    __syncthreads();                            // the last grid's coefficients are consumed
+    const float inv_nth = __builtin_amdgcn_rcpf((float)nth);
 #pragma unroll
     for (int r = 0; r < NPT; ++r) {
         const int qn = threadIdx.x + r * kThreads;
-        if (qn < Kstar) U[(int64_t)i * Kstar + qn] += val[r];
+        if (qn < Kstar) {
+            const int a = div_small(qn, inv_nth), b = qn - a * nth;
+            su[a * ld + b] = U[(int64_t)i * Kstar + qn] + val[r];
+        }
+    }
+    if (nv * W > nth)
+        for (int t = threadIdx.x; t < nrad * W; t += kThreads) {
+            const int a = t / W, e = nth + t % W;
+            if (e < nv * W) su[a * ld + e] = T(0);
+        }
+    __syncthreads();
+    typedef T vec_t __attribute__((ext_vector_type(W)));
+    {
+        // thread (ring a, modes j = j0, j0 + kThreads / 16, ...): the ring's
+        // values stay in registers; the trig rows (zero padded to trig_ld)
+        // come from the cache
+        const int a = threadIdx.x & 15;
+        if (a < nrad) {
+            vec_t u[kMaxV];
+            const vec_t* ur = reinterpret_cast<const vec_t*>(su + a * ld);
+#pragma unroll
+            for (int v = 0; v < kMaxV; ++v)
+                if (v < nv) u[v] = ur[v];
+            for (int j = threadIdx.x >> 4; j < nmode; j += kThreads >> 4) {
+                const vec_t* tr = reinterpret_cast<const vec_t*>(pa.trig + (int64_t)j * pa.trig_ld);
+                T acc = T(0);
+#pragma unroll
+                for (int v = 0; v < kMaxV; ++v)
+                    if (v < nv) {
+                        const vec_t c = tr[v];
+#pragma unroll
+                        for (int e = 0; e < W; ++e) acc += c[e] * u[v][e];
+                    }
+                sf[j * 16 + a] = acc;
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < pa.K; k += kThreads) {
+        const T* rr = pa.rad + (int64_t)k * nrad;
+        const T* fr = sf + pa.mode[k] * 16;
+        T acc = T(0);
+        for (int a = 0; a < nrad; ++a) acc += rr[a] * fr[a];
+        const int64_t e = (int64_t)i * pa.K + k;
+        pa.y[e] = pa.x[e] + (double)acc;
     }
 }
 
@@ -1036,8 +1103,15 @@ template hipError_t tree_near<float>(hipStream_t, const DeviceTree&, int, const 
 
 template <class T>
 hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U,
-                       const int* live, int npt) {
-    if (d.ngrid == 0) return hipSuccess;
+                       const int* live, int npt, const PApply<T>* pa) {
+    PApply<T> p;
+    if (pa) {
+        p = *pa;
+        if (!p.y || !p.x || !p.trig || !p.rad || !p.mode || p.M < 0 || p.M > 15 || p.trig_ld % 4 != 0 ||
+            p.trig_ld < 2 * p.M + 2)
+            return hipErrorInvalidValue;
+    }
+    if (d.ngrid == 0 && !p.y) return hipSuccess;
     if (!d.pt_cfg) live = nullptr;
     const T* coef;
     if constexpr (sizeof(T) == 8) coef = d.coef64;
@@ -1048,20 +1122,20 @@ hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames,
     if (npt == 2)
         hipLaunchKernelGGL((k_l2t<T, 2>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride);
+                           d.ptype, d.node_stride, p);
     else if (npt == 4)
         hipLaunchKernelGGL((k_l2t<T, 4>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride);
+                           d.ptype, d.node_stride, p);
     else
         hipLaunchKernelGGL((k_l2t<T, 8>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride);
+                           d.ptype, d.node_stride, p);
     return hipGetLastError();
 }
 template hipError_t tree_interp<double>(hipStream_t, const DeviceTree&, const double*, const double*, double*,
-                                        const int*, int);
+                                        const int*, int, const PApply<double>*);
 template hipError_t tree_interp<float>(hipStream_t, const DeviceTree&, const double*, const float*, float*,
-                                       const int*, int);
+                                       const int*, int, const PApply<float>*);
 
 }  // namespace nce

@@ -87,10 +87,28 @@ hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const doubl
 template <class T>
 hipError_t tree_near(hipStream_t s, const DeviceTree& d, int problem, const double* frames, const T* node_off,
                      const T* skel_off, const T* rho, T* U, const int* live = nullptr);
-// Step 4: interpolate every listed incoming grid at the sampling nodes; adds into U.
+// Step 5 fused into step 4 (tree_interp with pa): y_i = x_i + P u_i, u_i the
+// patch's node values (near field from U plus the interpolated grids), P
+// applied through its factors (transform_factors: trig with its rows zero
+// padded to trig_ld, a multiple of 4, rad and mode, as device arrays of the
+// apply's precision; M the basis order, K its size). x, y: N x K doubles (may
+// alias). U is then read, not written.
+template <class T>
+struct PApply {
+    const T* trig = nullptr;
+    int trig_ld = 0;
+    const T* rad = nullptr;
+    const int* mode = nullptr;
+    int M = 0, K = 0;
+    const double* x = nullptr;
+    double* y = nullptr;
+};
+
+// Step 4: interpolate every listed incoming grid at the sampling nodes; adds
+// into U, or with pa (non-null) finishes the apply as above.
 // npt: sampling nodes per thread (2, 4 or 8 with 256, 128 or 64 threads per patch).
 template <class T>
 hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames, const T* node_off, T* U,
-                       const int* live = nullptr, int npt = 2);
+                       const int* live = nullptr, int npt = 2, const PApply<T>* pa = nullptr);
 
 }  // namespace nce

@@ -200,6 +200,7 @@ void init_ctx_types(nce_ctx* ctx, const double* centers, const double* radius, i
     ctx->d_skel_off.upload(soff, s);
     ctx->d_T32.upload(to_f32(Tall32), s);
     ctx->d_P32.upload(to_f32(ctx->tab.P), s);
+    upload_transform_factors(ctx, s);
     ctx->d_node_off32.upload(to_f32(noff), s);
     ctx->d_skel_off32.upload(to_f32(soff32), s);
     ctx->d_ptype.upload(ctx->tl.ptype, s);
