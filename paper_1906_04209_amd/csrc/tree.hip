@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                 for (int r = 0; r < R; ++r) {
                     const double h2 = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
                     double de;
-                    const double gs = green64_half_split<PROB>(h2, ltab, de);
+                    const double gs = green64_grid_split<PROB>(h2, ltab, de);
                     acc[r] = fma(gs, w, acc[r]);
                     ace[r] = fma(de, w, ace[r]);
                 }
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(256) void k_p2l64_mfma(const int* __restrict__ it_g
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     double de;
-                    const double gs = green64_half_split<PROB>(h[r], ltab, de);
+                    const double gs = green64_grid_split<PROB>(h[r], ltab, de);
                     acc[r] = fma(gs, w, acc[r]);
                     ace[r] = fma(de, w, ace[r]);
                 }

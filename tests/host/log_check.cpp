@@ -15,7 +15,7 @@ int main() {
     nce::build_log_table(tab);
     std::mt19937_64 g(7);
     std::uniform_real_distribution<double> U(0.0, 1.0);
-    double worst_log = 0, worst_gi = 0, worst_ge = 0, worst_si = 0, worst_se = 0;
+    double worst_log = 0, worst_gi = 0, worst_ge = 0, worst_si = 0, worst_se = 0, worst_grid = 0, worst_rsq = 0;
     for (int i = 0; i < 2000000; ++i) {
         double x = (i % 4 == 0) ? 1.0 + (U(g) - 0.5) * 1e-3 : std::exp(U(g) * std::log(1e7));
         long double ref = std::log((long double)x);
@@ -36,8 +36,31 @@ int main() {
         const double ve = std::fma(-nce::kLn2Hi, de, std::fma(-nce::kLn2Lo, de, se));
         worst_si = std::max(worst_si, (double)(std::fabs(vi - gi) / std::fabs(gi)) / 2.220446049250313e-16);
         worst_se = std::max(worst_se, (double)(std::fabs(ve - ge) / std::fabs(ge)) / 2.220446049250313e-16);
+        // the far-field grid form (degree-3 series): absolute error of G
+        // against 2^-44 (the host build takes an exact rsqrt)
+        for (int prob = 0; prob < 2; ++prob) {
+            const double sg = prob ? nce::green64_grid_split<1>(0.25 * d * d, tab, de)
+                                   : nce::green64_grid_split<0>(0.25 * d * d, tab, de);
+            const double vg = std::fma(-nce::kLn2Hi, de, std::fma(-nce::kLn2Lo, de, sg));
+            const long double ref = prob ? ge : gi;
+            worst_grid = std::max(worst_grid, (double)(std::fabs(vg - ref) / std::max(std::fabs(ref), 1.0L)));
+        }
+        // first-order correction of an estimate at the largest error measured
+        // for the gfx950 FP64 rsq (2^-24.2), either sign: about 1.5 d^2
+        const double h2 = 0.25 * d * d;
+        const long double r = 1.0L / std::sqrt((long double)h2);
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+            const double y0 = (double)(r * (1.0L + sgn * 5.2e-8L));
+            const double y1 = nce::rsqrt_first_order(h2, y0);
+            worst_rsq = std::max(worst_rsq, (double)std::fabs(y1 / r - 1.0L));
+        }
     }
     std::printf("log64 %.2f ulp, green interior %.2f ulp, green exterior %.2f ulp, split %.2f / %.2f ulp\n", worst_log,
                 worst_gi, worst_ge, worst_si, worst_se);
-    return (worst_log < 4 && worst_gi < 6 && worst_ge < 6 && worst_si < 8 && worst_se < 8) ? 0 : 1;
+    std::printf("grid form: G within %.3e (abs, or rel above 1); first-order rsq correction within %.3e\n", worst_grid,
+                worst_rsq);
+    return (worst_log < 4 && worst_gi < 6 && worst_ge < 6 && worst_si < 8 && worst_se < 8 &&
+            worst_grid < std::ldexp(1.0, -44) && worst_rsq < 5e-15)
+               ? 0
+               : 1;
 }
