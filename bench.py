@@ -34,13 +34,13 @@ import layouts  # noqa: E402
 FLOPS_PER_PAIR = 12
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # Issue efficiency (a separate figure): the pair's minimal VALU instruction mix
-# priced in lane-cycles at the rates the issue-cost probe measured on gfx950
-# (FP64 add/mul/fma 1.0, FP64 rsq 4.07, 32-bit ops 0.6, FP32 transcendentals
-# 2.06): FP64 22 FP64 ops (distance 4, rsqrt correction 4, d/2 1, argument 1,
-# logarithm 10: mantissa, exponent, its conversion, reduction, degree-4
-# series, table term; accumulation 3) + one rsq + two 32-bit table-index ops
-# = 27.3; FP32 8 32-bit ops + rsq + log2 = 8.9.
-C_PAIR_MIN = {"fp64": 22 * 1.0 + 4.07 + 2 * 0.6, "fp32": 8 * 0.6 + 2 * 2.06}
+# at the grids' precision, priced in lane-cycles at the rates the issue-cost
+# probe measured on gfx950 (FP64 add/mul/fma 1.0, FP64 rsq 4.07, 32-bit ops
+# 0.6, FP32 transcendentals 2.06): FP64 21 FP64 ops (distance 4, first-order
+# rsqrt correction 4, d/2 1, argument 1, logarithm 8: mantissa, exponent, its
+# conversion, reduction, degree-3 series 3, table term; accumulation 3) + one
+# rsq + two 32-bit table-index ops = 26.3; FP32 8 32-bit ops + rsq + log2 = 8.9.
+C_PAIR_MIN = {"fp64": 21 * 1.0 + 4.07 + 2 * 0.6, "fp32": 8 * 0.6 + 2 * 2.06}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the

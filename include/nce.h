@@ -79,13 +79,13 @@ typedef struct nce_opts {
     const char *cache_dir; /* directory for per-eps tables; NULL = $NCE_CACHE or no cache */
     double tol_grid_fp32; /* grid tolerance of the FP32 applies (mixed solves): a second, coarser
                              set of incoming grids when it differs from tol_grid; 0 = tol_grid.
-                             Default 1e-4 (measured grid errors are about 0.04 of the tolerance,
-                             below the FP32 inner solve's 1e-5 target; the FP64 residuals
-                             always use tol_grid) */
+                             Default 3e-4 (FP32 apply errors then measure 2e-5 to 3.4e-5 of the
+                             scattered field; the FP64 residuals always use tol_grid, so this
+                             only sets how far one refinement step gets) */
     double tol_id_fp32;   /* ID tolerance of the outgoing representation used by the FP32 applies
-                             (mixed solves); 0 = tol_id. Default 1e-6 (with tol_grid_fp32 an FP32
-                             apply error near 5e-6, small enough for one refinement step from a
-                             5e-4 start to reach 1e-8; the FP64 residuals always use tol_id) */
+                             (mixed solves); 0 = tol_id. Default 1e-5 (with tol_grid_fp32, one
+                             refinement step from a 5e-4 start still reaches 1e-8 with a margin
+                             of 2; the FP64 residuals always use tol_id) */
     double tol_coarse;    /* relative residual to which the coarse (monopole) solve of the initial
                              guess is taken (nce_set_warm_start, nce_coarse_solve); in (0, 0.1).
                              Default 1e-5 (the guess's own residual is set by the monopole

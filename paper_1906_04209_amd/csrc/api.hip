@@ -788,8 +788,8 @@ void nce_default_opts(nce_opts* o) {
     o->far_field = NCE_FAR_AUTO;
     o->stream = nullptr;
     o->cache_dir = nullptr;
-    o->tol_grid_fp32 = 1e-4;
-    o->tol_id_fp32 = 1e-6;
+    o->tol_grid_fp32 = 3e-4;
+    o->tol_id_fp32 = 1e-5;
     o->tol_coarse = 1e-5;
     o->deflation = 1;
 }

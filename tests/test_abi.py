@@ -44,7 +44,7 @@ def test_default_opts():
     o = nce.Opts()
     lib.nce_default_opts(ctypes.byref(o))
     assert (o.M, o.tol_id, o.tol_grid, o.tol_gmres, o.precision) == (15, 1e-11, 1e-8, 1e-10, 0)
-    assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse, o.deflation) == (1e-4, 1e-6, 1e-5, 1)
+    assert (o.tol_grid_fp32, o.tol_id_fp32, o.tol_coarse, o.deflation) == (3e-4, 1e-5, 1e-5, 1)
 
 
 @pytest.mark.parametrize("case", ["empty", "nonunit", "nan", "eps0", "epsbig", "badM", "bigM", "badprob",

@@ -91,8 +91,9 @@ def test_two_radii_tree_vs_direct(torch, problem):
     c, types = layouts.multi_radius_centers(2000, (0.006, 0.003), 61)
     radius = np.array((0.006, 0.003))[types]
     d = nce.Context(c, radius, problem=problem, tol_id=1e-11, far_field=nce.FAR_DIRECT, tol_gmres=1e-10)
+    # FP32 at grids 1e-4 and tables 1e-6, the settings of the 2e-5 bound below
     t = nce.Context(c, radius, problem=problem, tol_id=1e-11, tol_grid=1e-8, far_field=nce.FAR_TREE,
-                    tol_gmres=1e-10)
+                    tol_gmres=1e-10, tol_grid_fp32=1e-4, tol_id_fp32=1e-6)
     x_np = layouts.random_coeffs(2000, d.K, 6, decay=0.1)
     x = torch.from_numpy(x_np).cuda()
     yd = d.matvec(x).cpu().numpy()
