@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 
 #include <stdexcept>
 #include <string>
@@ -58,6 +59,115 @@ __global__ __launch_bounds__(256) void k_grid_points(const int* __restrict__ g_n
     }
 }
 
+// ---------------------------------------------------- reduce + transform
+// A grid's q values sv (LDS, doubles) to its Chebyshev-Fourier coefficients:
+// the angular DFT and the parity-restricted radial Chebyshev transform.
+// Coefficient layout: mode m = 0..nt-1 (m <= nt/2: cos(m th); m > nt/2:
+// sin((m - nt/2) th)), radial index n' (Chebyshev degree 2 n' + parity of the
+// angular order). sa: LDS scratch of q doubles; tc, ts (nt) and tch (8 nr):
+// LDS tables, contiguous (ts = tc + nt, tch = tc + 2 nt). Every thread of the
+// block calls it after sv is complete.
+template <class T, class TT>
+__device__ void grid_transform(const double* sv, double* sa, TT* tc, TT* ts, TT* tch, int nr, int nt,
+                               const double* __restrict__ gtab, T* __restrict__ coef) {
+    const int q = nr * nt;
+    // trigonometric tables (gtab, per (nr, nt), from the host): cos, sin(2 pi
+    // j / nt) and cos(2 pi j / (8 nr)), contiguous as tc, ts, tch
+    for (int j = threadIdx.x; j < 2 * nt + 8 * nr; j += blockDim.x) tc[j] = (TT)gtab[j];
+    __syncthreads();
+    const int half = nt / 2;
+    // angular transform: sa[m * nr + a]
+    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
+        const int m = idx / nr, a = idx - m * nr;
+        const bool is_sin = m > half;
+        const int k = is_sin ? m - half : m;
+        const double wgt = (k == 0 || k == half) ? 1.0 / nt : 2.0 / nt;
+        double acc = 0.0;
+        int red = 0;
+        for (int b = 0; b < nt; ++b) {
+            acc += sv[a * nt + b] * (double)(is_sin ? ts[red] : tc[red]);
+            red += k;
+            if (red >= nt) red -= nt;
+        }
+        sa[idx] = wgt * acc;
+    }
+    __syncthreads();
+    // radial transform on the positive first-kind Chebyshev nodes (parity):
+    // T_n(x_a) = cos(2 pi n (2a+1) / (8 nr))
+    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
+        const int m = idx / nr, np = idx - m * nr;
+        const int k = m > half ? m - half : m;
+        const int n = 2 * np + (k & 1);
+        double acc = 0.0;
+        for (int a = 0; a < nr; ++a) acc += sa[m * nr + a] * (double)tch[(n * (2 * a + 1)) % (8 * nr)];
+        coef[idx] = (T)((n == 0 ? 1.0 : 2.0) / nr * acc);
+    }
+}
+
+// The end of a P2L block: the group partial sums red[sp q + t] (sp < ns) of
+// the item. An item that is its grid's only one (solo) sums them and turns
+// them into the grid's coefficients itself, in the staging LDS (sv, sa in
+// `big`, at least 2 kMaxGridQ doubles; the tables in `tab`, at least 2
+// kMaxGridNt + 8 kMaxGridNr values); any other writes its partial sums for
+// k_reduce_coef. Every thread of the block calls it after red is complete.
+template <class T, class TT>
+__device__ __forceinline__ void p2l_finish(const double* red, int ns, int q, bool solo, int nr, int nt,
+                                           double* big, TT* tab, const double* __restrict__ gtab,
+                                           T* __restrict__ part, T* __restrict__ coef) {
+    if (!solo) {
+        for (int t = threadIdx.x; t < q; t += blockDim.x) {
+            double v = 0.0;
+            for (int sp = 0; sp < ns; ++sp) v += red[sp * q + t];
+            part[t] = (T)v;
+        }
+        return;
+    }
+    constexpr int kPer = kMaxGridQ / 256;
+    double v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int t = threadIdx.x + k * 256;
+        v[k] = 0.0;
+        if (t < q)
+            for (int sp = 0; sp < ns; ++sp) v[k] += red[sp * q + t];
+    }
+    __syncthreads();  // red (which may share `big`) is consumed
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int t = threadIdx.x + k * 256;
+        if (t < q) big[t] = v[k];
+    }
+    __syncthreads();
+    grid_transform<T, TT>(big, big + q, tab, tab + nt, tab + 2 * nt, nr, nt, gtab, coef);
+}
+
+// One block per grid of `glist` (the grids with more than one P2L item, or
+// every grid when glist is null): sum the items' partial sums in item order,
+// then the transform.
+template <class T>
+__global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ glist, const int* __restrict__ g_nr,
+                                                     const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
+                                                     const int* __restrict__ g_item0, const int* __restrict__ g_item1,
+                                                     const int64_t* __restrict__ it_off, const T* __restrict__ part,
+                                                     T* __restrict__ coef, const int* __restrict__ g_cfg,
+                                                     const int* __restrict__ live, const double* __restrict__ ttab,
+                                                     const int* __restrict__ g_ttab) {
+    __shared__ double sv[kMaxGridQ];
+    __shared__ double sa[kMaxGridQ];
+    __shared__ T tab[2 * kMaxGridNt + 8 * kMaxGridNr];
+    const int g = glist ? glist[blockIdx.x] : (int)blockIdx.x;
+    if (live && !live[g_cfg[g]]) return;
+    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
+    const int i0 = g_item0[g], i1 = g_item1[g];
+    for (int t = threadIdx.x; t < q; t += blockDim.x) {
+        double acc = 0.0;
+        for (int it = i0; it < i1; ++it) acc += (double)part[it_off[it] + t];
+        sv[t] = acc;
+    }
+    __syncthreads();
+    grid_transform<T, T>(sv, sa, tab, tab + nt, tab + 2 * nt, nr, nt, ttab + g_ttab[g], coef + g_off[g]);
+}
+
 // ----------------------------------------------------------------- P2L
 // One block per work item (one grid and a run of its source patches). The
 // 256 threads are split into ns groups; each thread owns up to R grid points
@@ -101,7 +211,9 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                int ntab,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
-                                               const int* __restrict__ it_list, const LogEntry* __restrict__ logtab) {
+                                               const int* __restrict__ it_list, const LogEntry* __restrict__ logtab,
+                                               const int* __restrict__ it_solo, double* __restrict__ coef,
+                                               const double* __restrict__ ttab, const int* __restrict__ g_ttab) {
     // staging (kStage64 points: (-2 a, |a|^2) with a the half-scaled offset
     // from the cap centre, and the strengths) and, after the sums, the split
     // partials (ns q <= 256 R)
@@ -193,16 +305,12 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
             if (t < q) red[split * q + t] = fma(-kLn2Hi, ace[r], fma(-kLn2Lo, ace[r], acc[r]));
         }
     __syncthreads();
-    const int64_t off = it_off[item];
-    for (int t = threadIdx.x; t < q; t += blockDim.x) {
-        double v = 0.0;
-        for (int sp = 0; sp < ns; ++sp) v += red[sp * q + t];
-        part[off + t] = v;
-    }
+    p2l_finish<double, double>(red, ns, q, it_solo && it_solo[item], nr, nt, smem, srho, ttab + g_ttab[g],
+                               part + it_off[item], coef + g_off[g]);
 }
 
 template <int PROB, int R>
-__global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 4 ? 7 : 1))) void k_p2l32(const int* __restrict__ it_grid, const int* __restrict__ it_src0,
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
                                                const double* __restrict__ g_T, const int* __restrict__ g_nr,
@@ -214,7 +322,9 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
                                                int ntab,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const float* __restrict__ gpt,
-                                               const int* __restrict__ it_list) {
+                                               const int* __restrict__ it_list,
+                                               const int* __restrict__ it_solo, float* __restrict__ coef,
+                                               const double* __restrict__ ttab, const int* __restrict__ g_ttab) {
     // staging (kStage points: (-2 a, |a|^2) with a the half-scaled offset from
     // the cap centre, and the strengths) and, after the sums, the split
     // partials (ns q <= 256 R doubles, in smem4)
@@ -310,12 +420,8 @@ __global__ __launch_bounds__(256) void k_p2l32(const int* __restrict__ it_grid, 
             if (t < q) red[split * q + t] = acc[r];
         }
     __syncthreads();
-    const int64_t off = it_off[item];
-    for (int t = threadIdx.x; t < q; t += blockDim.x) {
-        double v = 0.0;
-        for (int sp = 0; sp < ns; ++sp) v += red[sp * q + t];
-        part[off + t] = (float)v;
-    }
+    p2l_finish<float, float>(red, ns, q, it_solo && it_solo[item], nr, nt, smem, srho, ttab + g_ttab[g],
+                             part + it_off[item], coef + g_off[g]);
 }
 
 // ------------------------------------------------- P2L on the matrix cores
@@ -543,64 +649,6 @@ __global__ __launch_bounds__(256) void k_p2l32_mfma(const int* __restrict__ it_g
     __syncthreads();
     const int64_t off = it_off[item];
     for (int t = threadIdx.x; t < q; t += blockDim.x) part[off + t] = (float)red[t];
-}
-
-// ---------------------------------------------------- reduce + transform
-// One block per grid: sum the items' partial sums, then the angular DFT and
-// the parity-restricted radial Chebyshev transform. Coefficient layout:
-// mode m = 0..nt-1 (m <= nt/2: cos(m th); m > nt/2: sin((m - nt/2) th)),
-// radial index n' (Chebyshev degree 2 n' + parity of the angular order).
-template <class T>
-__global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ g_nr, const int* __restrict__ g_nt,
-                                                     const int64_t* __restrict__ g_off,
-                                                     const int* __restrict__ g_item0, const int* __restrict__ g_item1,
-                                                     const int64_t* __restrict__ it_off, const T* __restrict__ part,
-                                                     T* __restrict__ vals, T* __restrict__ coef,
-                                                     const int* __restrict__ g_cfg, const int* __restrict__ live) {
-    __shared__ double sv[kMaxGridQ];
-    __shared__ double sa[kMaxGridQ];
-    __shared__ double tc[256], ts[256], tch[8 * kMaxGridNr];
-    const int g = blockIdx.x;
-    if (live && !live[g_cfg[g]]) return;
-    const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
-    const int i0 = g_item0[g], i1 = g_item1[g];
-    // trigonometric tables: cos, sin(2 pi j / nt) and cos(2 pi j / (8 nr))
-    for (int j = threadIdx.x; j < nt; j += blockDim.x) sincospi(2.0 * j / nt, &ts[j], &tc[j]);
-    for (int j = threadIdx.x; j < 8 * nr; j += blockDim.x) tch[j] = cospi(2.0 * j / (8.0 * nr));
-    for (int t = threadIdx.x; t < q; t += blockDim.x) {
-        double s = 0.0;
-        for (int it = i0; it < i1; ++it) s += (double)part[it_off[it] + t];
-        sv[t] = s;
-        vals[g_off[g] + t] = (T)s;
-    }
-    __syncthreads();
-    const int half = nt / 2;
-    // angular transform: sa[m * nr + a]
-    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
-        const int m = idx / nr, a = idx - m * nr;
-        const bool is_sin = m > half;
-        const int k = is_sin ? m - half : m;
-        const double wgt = (k == 0 || k == half) ? 1.0 / nt : 2.0 / nt;
-        double s = 0.0;
-        int red = 0;
-        for (int b = 0; b < nt; ++b) {
-            s += sv[a * nt + b] * (is_sin ? ts[red] : tc[red]);
-            red += k;
-            if (red >= nt) red -= nt;
-        }
-        sa[idx] = wgt * s;
-    }
-    __syncthreads();
-    // radial transform on the positive first-kind Chebyshev nodes (parity):
-    // T_n(x_a) = cos(2 pi n (2a+1) / (8 nr))
-    for (int idx = threadIdx.x; idx < q; idx += blockDim.x) {
-        const int m = idx / nr, np = idx - m * nr;
-        const int k = m > half ? m - half : m;
-        const int n = 2 * np + (k & 1);
-        double s = 0.0;
-        for (int a = 0; a < nr; ++a) s += sa[m * nr + a] * tch[(n * (2 * a + 1)) % (8 * nr)];
-        coef[g_off[g] + idx] = (T)((n == 0 ? 1.0 : 2.0) / nr * s);
-    }
 }
 
 // ------------------------------------------------------------------ L2T
@@ -957,10 +1005,36 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
     d.it_cfg = dev_copy(t.it_cfg);
     d.g_cfg = dev_copy(t.g_cfg);
     d.pt_cfg = dev_copy(t.pt_cfg);
-    d.vals64 = dev_alloc<double>(t.total_q);
+    {
+        // items that are their grid's only one finish the grid themselves
+        std::vector<int> solo(t.it_grid.size(), 0), multi;
+        for (int g = 0; g < t.ngrid; ++g) {
+            if (t.g_item1[g] - t.g_item0[g] == 1) solo[t.g_item0[g]] = 1;
+            else if (t.g_item1[g] > t.g_item0[g]) multi.push_back(g);
+        }
+        d.it_solo = dev_copy(solo);
+        d.n_multi = (int)multi.size();
+        d.g_multi = dev_copy(multi);
+        // transform tables per distinct (nr, nt): cos, sin(2 pi j / nt), cos(2 pi j / (8 nr))
+        std::map<std::pair<int, int>, int> at;
+        std::vector<double> tt;
+        std::vector<int> gt(t.ngrid);
+        for (int g = 0; g < t.ngrid; ++g) {
+            const int nr = t.g_nr[g], nt = t.g_nt[g];
+            auto it = at.find({nr, nt});
+            if (it == at.end()) {
+                it = at.emplace(std::make_pair(nr, nt), (int)tt.size()).first;
+                for (int j = 0; j < nt; ++j) tt.push_back(std::cos(2.0 * kPi * j / nt));
+                for (int j = 0; j < nt; ++j) tt.push_back(std::sin(2.0 * kPi * j / nt));
+                for (int j = 0; j < 8 * nr; ++j) tt.push_back(std::cos(2.0 * kPi * j / (8.0 * nr)));
+            }
+            gt[g] = it->second;
+        }
+        d.ttab = dev_copy(tt);
+        d.g_ttab = dev_copy(gt);
+    }
     d.coef64 = dev_alloc<double>(t.total_q);
     d.part64 = dev_alloc<double>(t.total_partial);
-    d.vals32 = dev_alloc<float>(t.total_q);
     d.coef32 = dev_alloc<float>(t.total_q);
     d.part32 = dev_alloc<float>(t.total_partial);
     {
@@ -999,7 +1073,7 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
 void free_tree(DeviceTree& d) {
     void* ptrs[] = {d.g_table, d.t_off, d.t_p, d.g_frame, d.g_T,   d.g_nr,     d.g_nt,     d.g_off,  d.g_item0, d.g_item1,
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
-                    d.l2t_ptr, d.l2t_grid, d.vals64, d.coef64,  d.part64, d.vals32,  d.coef32, d.part32,
+                    d.l2t_ptr, d.l2t_grid, d.it_solo, d.coef64,  d.part64, d.g_multi,  d.coef32, d.part32, d.ttab, d.g_ttab,
                     d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
                     d.it_type, d.t_col, d.ptype};
     for (void* q : ptrs)
@@ -1015,12 +1089,12 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
-                           it_list, d.logtab);
+                           it_list, d.logtab, d.it_solo, d.coef64, d.ttab, d.g_ttab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
-                           it_list);
+                           it_list, d.it_solo, d.coef32, d.ttab, d.g_ttab);
 }
 
 template <class T, int PROB>
@@ -1064,13 +1138,17 @@ hipError_t tree_far(hipStream_t s, const DeviceTree& d, int problem, const doubl
         if (problem == 1) launch_p2l_shape<T, 1>(s, d, frames, skel_off, rho, live, r_tgt);
         else launch_p2l_shape<T, 0>(s, d, frames, skel_off, rho, live, r_tgt);
     }
-    if (d.ngrid > 0) {
+    // the vector-unit shapes finish the grids of one item in the P2L block;
+    // the others (every grid after the matrix-core shape) are reduced here
+    const int* glist = r_tgt == 16 ? nullptr : d.g_multi;
+    const int nred = r_tgt == 16 ? d.ngrid : d.n_multi;
+    if (nred > 0) {
         if constexpr (sizeof(T) == 8)
-            hipLaunchKernelGGL((k_reduce_coef<double>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                               d.g_item0, d.g_item1, d.it_off, d.part64, d.vals64, d.coef64, d.g_cfg, live);
+            hipLaunchKernelGGL((k_reduce_coef<double>), dim3(nred), dim3(256), 0, s, glist, d.g_nr, d.g_nt, d.g_off,
+                               d.g_item0, d.g_item1, d.it_off, d.part64, d.coef64, d.g_cfg, live, d.ttab, d.g_ttab);
         else
-            hipLaunchKernelGGL((k_reduce_coef<float>), dim3(d.ngrid), dim3(256), 0, s, d.g_nr, d.g_nt, d.g_off,
-                               d.g_item0, d.g_item1, d.it_off, d.part32, d.vals32, d.coef32, d.g_cfg, live);
+            hipLaunchKernelGGL((k_reduce_coef<float>), dim3(nred), dim3(256), 0, s, glist, d.g_nr, d.g_nt, d.g_off,
+                               d.g_item0, d.g_item1, d.it_off, d.part32, d.coef32, d.g_cfg, live, d.ttab, d.g_ttab);
     }
     return hipGetLastError();
 }

@@ -54,11 +54,17 @@ struct DeviceTree {
     int n_items4 = 0;
     int* items4 = nullptr;
     int* items8 = nullptr;
+    // per item: 1 if it is its grid's only item (the P2L block then finishes
+    // the grid's coefficients); the grids with several items
+    int* it_solo = nullptr;
+    int n_multi = 0;
+    int* g_multi = nullptr;
+    // the transform's trigonometric tables per distinct (nr, nt) and each grid's offset
+    double* ttab = nullptr;
+    int* g_ttab = nullptr;
     // work buffers (FP64 and FP32)
-    double* vals64 = nullptr;
     double* coef64 = nullptr;
     double* part64 = nullptr;
-    float* vals32 = nullptr;
     float* coef32 = nullptr;
     float* part32 = nullptr;
 };
