@@ -8,6 +8,8 @@ tests/golden/):
                         I_sigma, per-patch flux, solution coefficients)
   mt_p<problem>.npz     N=10 with two patch radii (0.1 and 0.05, seed 51), both problems: matvec of
                         seeded x and the dense-LU solve (scalars, per-patch flux, coefficients)
+  orders_M<M>_p<problem>.npz  the cfg1 centres at basis orders other than 15 (M = 4 exterior, M = 10
+                        interior): matvec of seeded x and the dense-LU scalars
   cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
   cfg3_rows.npz         N=10000 exterior clustered, eps=0.005, seed 3: 12 sampled rows
   cfg5_rows.npz         N=100000 interior, eps=0.001, seed 5: 16 sampled rows (tol_id 1e-11)
@@ -134,7 +136,25 @@ def _rows_job(name, nrows, tol_id):
     return job
 
 
-JOBS = {"cfg1": make_cfg1, "cfg1i": make_cfg1i, "mt": make_mt, "cfg2_rows": make_cfg2_rows,
+def make_orders():
+    """Basis orders other than the paper's M = 15 (its P, nodes and skeletons
+    all change with M)."""
+    cfg = layouts.CONFIGS["cfg1"]
+    c = layouts.config_layout(cfg)
+    for problem, M in ((1, 4), (0, 10)):
+        t0 = time.time()
+        tab, _, _ = tables.compute(problem, cfg["eps"], M, TOL_ID)
+        lay = system.Layout(c, tab)
+        x = layouts.random_coeffs(cfg["N"], tab.K, X_SEED, decay=0.1)
+        y = system.matvec_dense(lay, x)
+        r = system.solve_dense(lay)
+        key = "capture_rate" if problem == 1 else "mu"
+        np.savez(GOLD / f"orders_M{M}_p{problem}.npz", y=y, x_seed=X_SEED, M=M, problem=problem,
+                 eps=cfg["eps"], scalar=r[key], flux=r["flux"])
+        print(f"  orders M={M} problem {problem}: {key} {r[key]:.15g} ({time.time() - t0:.0f} s)", flush=True)
+
+
+JOBS = {"cfg1": make_cfg1, "cfg1i": make_cfg1i, "mt": make_mt, "orders": make_orders, "cfg2_rows": make_cfg2_rows,
         "cfg3_rows": _rows_job("cfg3", 12, 1e-12), "cfg5_rows": _rows_job("cfg5", 16, 1e-11)}
 
 
