@@ -25,8 +25,8 @@ _FULL = {}
 def _full(problem):
     """(Tables, OnePatch) at eps = 0.1, computed once per module."""
     if problem not in _FULL:
-        tab, op, _ = tables.compute(problem, 0.1, 15, 1e-12)
-        _FULL[problem] = (tab, op)
+        from conftest import oracle_onepatch
+        _FULL[problem] = oracle_onepatch(problem, 0.1)
     return _FULL[problem]
 
 
@@ -85,7 +85,7 @@ def test_scalar_bounds(tab_i, tab_e):
 @pytest.mark.slow
 def test_compressed_equals_uncompressed():
     # the ID (Section 7.1) changes the system only at the level of tol_id
-    tab, res, cp = tables.compute(EXTERIOR, 0.1, 15, 1e-12)
+    tab, res = _full(EXTERIOR)
     c = layouts.uniform_centers(4, 0.1, 31)
     lay = system.Layout(c, tab)
     x = layouts.random_coeffs(4, tab.K, 5, decay=0.2)
