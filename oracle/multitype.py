@@ -18,11 +18,19 @@ larger radius: centre arclength >= eps_i + eps_j + max(eps_i, eps_j), so that
 patch i lies in the far-field region (arclength > 2 eps_j) of every other
 patch j.
 
+Fields (Sections 2.2, 2.3 and eq. l2res with each patch's own radius):
+potential integrates every patch by its own radius's radial rule and density
+profiles (field._patch_quadrature with that radius's one-patch solve), a point
+on patch i taking patch i's term from its data; l2_residual uses the rule of
+field.residual_grid on [0, eps_i] and |Gamma_i| of eps_i.
+
 Pins (tests/test_oracle_multitype.py): two types of equal radius reproduce
-the single-radius system; the compressed operator equals the uncompressed
-one (each patch's own fine grid and densities); the solved densities meet
-the absorbing condition on every patch of both radii; a single patch of each
-type gives its own one-patch scalars.
+the single-radius system and the single-radius field; the compressed operator
+equals the uncompressed one (each patch's own fine grid and densities); the
+solved densities meet the absorbing condition on every patch of both radii,
+by the on-surface sums and by the field; the interior field's normal
+derivative on the reflecting surface is -I_sigma; a single patch of each type
+gives its own one-patch scalars.
 """
 from __future__ import annotations
 
@@ -30,8 +38,8 @@ import math
 
 import numpy as np
 
-from . import zernike
-from .greens import INTERIOR
+from . import field, zernike
+from .greens import INTERIOR, g_offsurface
 from .system import frames, green_block, patch_points, rhs
 
 
@@ -134,3 +142,50 @@ def patch_residual(lay: Layout, ops, x, i, t, theta):
             Xf = patch_points(lay.c[j:j + 1], lay.e1[j:j + 1], lay.e2[j:j + 1], op.fine_t, op.fine_theta)[0]
             far += green_block(X, Xf, lay.problem) @ ((op.B @ x[j]) * op.w)
     return self_part + far - 1.0
+
+
+def on_patch(lay: Layout, point, tol: float = 1e-12):
+    """Index of the patch containing `point` (on the sphere), or -1."""
+    p = np.asarray(point, dtype=np.float64)
+    if abs(np.linalg.norm(p) - 1.0) > tol:
+        return -1
+    ang = np.arctan2(np.linalg.norm(np.cross(lay.c, p), axis=1), lay.c @ p)
+    i = int(np.argmin(ang))
+    return i if ang[i] <= lay.tab(i).eps * (1 + tol) else -1
+
+
+def self_term(lay: Layout, x, i, point):
+    """sum_k x_ik Z_k(t/eps_i, theta) at a point of patch i."""
+    p = np.asarray(point, dtype=np.float64)
+    tab = lay.tab(i)
+    t = math.atan2(np.linalg.norm(np.cross(lay.c[i], p)), float(lay.c[i] @ p))
+    th = math.atan2(float(lay.e2[i] @ p), float(lay.e1[i] @ p))
+    r = min(t / tab.eps, 1.0)
+    return sum(x[i, k] * float(zernike.basis(n, m, r, th)) for k, (n, m) in enumerate(zernike.modes(tab.M)))
+
+
+def potential(lay: Layout, ops, x, points, ntheta: int = 256):
+    """u (exterior) or v (interior) at each of `points` (n, 3); ops: the
+    OnePatch of each type."""
+    points = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    quad = [field._patch_quadrature(lay, ops[lay.types[j]], x, j, ntheta) for j in range(lay.N)]
+    out = np.zeros(len(points))
+    for a, p in enumerate(points):
+        i = on_patch(lay, p)
+        for j in range(lay.N):
+            if j == i:
+                out[a] += self_term(lay, x, i, p)
+            else:
+                pts, sw = quad[j]
+                out[a] += float(np.sum(g_offsurface(p[None, :], pts, lay.problem) * sw))
+    return out
+
+
+def l2_residual(lay: Layout, ops, x, i: int, nt: int = 20, ntheta: int = 40, ntheta_quad: int = 256):
+    """(1/|Gamma_i|) ||v - 1||_{L2(Gamma_i)} on patch i (eq. l2res) with eps_i."""
+    eps = lay.tab(i).eps
+    t, th, w = field.residual_grid(eps, nt, ntheta)
+    pts = patch_points(lay.c[i:i + 1], lay.e1[i:i + 1], lay.e2[i:i + 1], t, th)[0]
+    r = potential(lay, ops, x, pts, ntheta_quad) - 1.0
+    area = 2.0 * math.pi * (1.0 - math.cos(eps))
+    return math.sqrt(float(np.sum(w * r * r))) / area, r

@@ -7,7 +7,8 @@ tests/golden/):
   cfg1i.npz             the same centres, interior: matvec of seeded x, dense-LU solve (mu,
                         I_sigma, per-patch flux, solution coefficients)
   mt_p<problem>.npz     N=10 with two patch radii (0.1 and 0.05, seed 51), both problems: matvec of
-                        seeded x and the dense-LU solve (scalars, per-patch flux, coefficients)
+                        seeded x, the dense-LU solve (scalars, per-patch flux, coefficients), and the
+                        solution's field at seeded points and eq. l2res on a patch of each radius
   orders_M<M>_p<problem>.npz  the cfg1 centres at basis orders other than 15 (M = 4 exterior, M = 10
                         interior): matvec of seeded x and the dense-LU scalars
   cfg2_rows.npz         N=1000 interior, eps=0.01, seed 2: matvec rows at 16 sampled patches
@@ -86,19 +87,49 @@ MT_RADII = (0.1, 0.05)
 MT_SEED = 51
 
 
+def _mt_field_points(lay, problem, seed):
+    """Targets of the two-radius field check: eps_j/5 off patches of both
+    radii, on them, on the reflecting surface, near it and deep in the domain."""
+    g = np.random.default_rng(seed)
+    sgn = -1.0 if problem == 0 else 1.0
+    pts = []
+    for i in (int(np.flatnonzero(lay.types == 0)[0]), int(np.flatnonzero(lay.types == 1)[0])):
+        eps = lay.tab(i).eps
+        t = eps * np.sqrt(g.random(3))
+        th = 2 * np.pi * g.random(3)
+        on = system.patch_points(lay.c[i:i + 1], lay.e1[i:i + 1], lay.e2[i:i + 1], t, th)[0]
+        pts += [(1.0 + sgn * eps / 5) * on[0], (1.0 + sgn * eps / 5) * on[1], on[2]]
+    while len(pts) < 9:
+        d = g.standard_normal(3)
+        d /= np.linalg.norm(d)
+        if np.min(np.arccos(np.clip(lay.c @ d, -1, 1))) > 0.3:
+            pts += [d, (1.0 + sgn * 1e-3) * d]
+    pts += [np.array([0.1, -0.2, 0.3]) if problem == 0 else np.array([1.5, -0.4, 0.9])]
+    return np.array(pts)
+
+
 def make_mt():
-    """Two patch radii in one configuration (oracle/multitype.py)."""
+    """Two patch radii in one configuration (oracle/multitype.py): apply,
+    dense solve, and the field of the solution (potential at seeded points,
+    eq. l2res on one patch of each radius)."""
     c, types = layouts.multi_radius_centers(10, MT_RADII, MT_SEED)
     for problem in (0, 1):
         tabs = [_tab(problem, e) for e in MT_RADII]
+        ops = [tables.compute(problem, e, 15, TOL_ID)[1] for e in MT_RADII]
         lay = multitype.Layout(c, types, tabs)
         x = layouts.random_coeffs(10, tabs[0].K, X_SEED, decay=0.1)
         y = multitype.matvec_dense(lay, x)
         r = multitype.solve_dense(lay)
         extra = {"mu": r["mu"]} if problem == 0 else {"capture_rate": r["capture_rate"]}
+        fpts = _mt_field_points(lay, problem, 90 + problem)
+        fval = multitype.potential(lay, ops, r["x"], fpts)
+        rpat = np.array([int(np.flatnonzero(types == 0)[0]), int(np.flatnonzero(types == 1)[0])])
+        rval = np.array([multitype.l2_residual(lay, ops, r["x"], int(i), nt=6, ntheta=10)[0] for i in rpat])
         np.savez(GOLD / f"mt_p{problem}.npz", y=y, x_seed=X_SEED, I_sigma=r["I_sigma"], flux=r["flux"],
-                 coeffs=r["x"], types=types, radii=np.array(MT_RADII), seed=MT_SEED, **extra)
-        print(f"  mt problem {problem}: types {types.tolist()} I_sigma {r['I_sigma']:.15g}", flush=True)
+                 coeffs=r["x"], types=types, radii=np.array(MT_RADII), seed=MT_SEED, field_points=fpts,
+                 field_values=fval, residual_patches=rpat, residual_values=rval, **extra)
+        print(f"  mt problem {problem}: types {types.tolist()} I_sigma {r['I_sigma']:.15g}; "
+              f"residuals {rval}", flush=True)
 
 
 def make_cfg2_rows():

@@ -79,3 +79,56 @@ def test_single_patch_of_each_radius():
         assert abs(r["capture_rate"] - 4 * math.pi * tab.I[0]) < 1e-15
     # a larger patch captures more
     assert t0.I[0] > t1.I[0]
+
+
+@pytest.mark.parametrize("problem", [INTERIOR, EXTERIOR])
+def test_field_equal_radii_reduces_to_single_radius(problem):
+    # two types of one radius: the field is the single-radius one, at points
+    # off the surface, on a patch and on the reflecting surface
+    from oracle import field
+    tab, op = _full(problem, RADII[0])
+    c = layouts.uniform_centers(5, RADII[0], 71)
+    types = np.array([0, 1, 0, 1, 1])
+    lay = multitype.Layout(c, types, [tab, tab])
+    ref = system.Layout(c, tab)
+    x = layouts.random_coeffs(5, tab.K, 8, decay=0.1)
+    r = 0.9 if problem == INTERIOR else 1.1
+    g = np.random.default_rng(4)
+    d = g.standard_normal((3, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    on = system.patch_points(c[1:2], ref.e1[1:2], ref.e2[1:2], np.array([0.04]), np.array([1.0]))[0]
+    pts = np.vstack([r * d, on, d[:1]])
+    a = multitype.potential(lay, [op, op], x, pts, ntheta=64)
+    b = field.potential(ref, op, x, pts, ntheta=64)
+    assert np.max(np.abs(a - b)) < 1e-14 * np.max(np.abs(b)), (a, b)
+
+
+def test_field_absorbing_condition_and_flux_two_radii():
+    """For the solved densities of two radii (interior): the field-based
+    residual (eq. l2res, each patch's own radius) is at the discretisation
+    level on patches of both radii, and dv/dn = -I_sigma on the reflecting
+    surface (Section 2.3), by one-sided second-order differences."""
+    (t0, o0), (t1, o1) = _full(INTERIOR, RADII[0]), _full(INTERIOR, RADII[1])
+    c, types = layouts.multi_radius_centers(5, RADII, 52)
+    assert len(set(types.tolist())) == 2
+    lay = multitype.Layout(c, types, [t0, t1])
+    sol = multitype.solve_dense(lay)
+    x, Is = sol["x"], sol["I_sigma"]
+    for i in (int(np.flatnonzero(types == 0)[0]), int(np.flatnonzero(types == 1)[0])):
+        res, _ = multitype.l2_residual(lay, [o0, o1], x, i, nt=6, ntheta=10)
+        assert res < 1e-8, (i, res)
+    xp = x.copy()
+    xp[0, 0] *= 1 + 1e-6
+    assert multitype.l2_residual(lay, [o0, o1], xp, 0, nt=6, ntheta=10)[0] > 1e-6
+    g = np.random.default_rng(6)
+    h = 1e-5
+    n_ok = 0
+    while n_ok < 3:
+        p = g.standard_normal(3)
+        p /= np.linalg.norm(p)
+        if np.min(np.arccos(np.clip(c @ p, -1, 1))) < 0.4:
+            continue
+        v = multitype.potential(lay, [o0, o1], x, np.stack([p, (1 - h) * p, (1 - 2 * h) * p]))
+        dvdn = -(-3 * v[0] + 4 * v[1] - v[2]) / (2 * h)
+        assert abs(dvdn + Is) < 1e-7 * abs(Is), (dvdn, -Is)
+        n_ok += 1
