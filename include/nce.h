@@ -136,9 +136,10 @@ int nce_setup(const double *centers_host, int64_t N, double eps, const nce_opts 
  * own tables; patch j radiates through its radius's outgoing representation
  * and patch i is sampled at its radius's nodes. nce_matvec, nce_solve_*,
  * nce_frames, nce_dims, nce_work, nce_autotune and nce_set_solver work on the
- * context as on any other (coefficient vectors in the caller's patch order);
- * the learned and coarse starts, the deflation, nce_integral_vector (use
- * nce_types), nce_field and nce_patch_residual return NCE_ESTATE. One
+ * context as on any other (coefficient vectors in the caller's patch order),
+ * and so do nce_field and nce_patch_residual (each patch by its own radius's
+ * densities, skeleton and quadrature); the learned and coarse starts, the
+ * deflation and nce_integral_vector (use nce_types) return NCE_ESTATE. One
  * distinct radius is the same as nce_setup.
  * Errors: NCE_EINVAL, NCE_ESEP, NCE_ENOMEM, NCE_EHIP, NCE_ETABLE.
  */
@@ -346,7 +347,8 @@ int nce_integral_vector(const nce_ctx *ctx, double *I_host);
  * Patches whose centre lies at arclength >= 3 eps from x/|x| enter through the
  * compressed outgoing representation, nearer ones by quadrature of their
  * density (260 radial nodes x 256 angles): accurate to about the ID tolerance
- * for points at least eps/10 from every patch they do not lie on.
+ * for points at least eps/10 from every patch they do not lie on (with
+ * several radii, eps is each patch's own).
  * Synchronises the context's stream. Errors: NCE_EINVAL (NULL pointer, n < 0,
  * non-finite point or one outside the problem's domain), NCE_ESTATE (a
  * context of several configurations), NCE_EHIP.
@@ -360,7 +362,8 @@ int nce_field(nce_ctx *ctx, const double *coeffs_dev, const double *points_dev, 
  * patch i = patches_host[a] (0 <= i < N), with v the potential of nce_field
  * for coefficients coeffs_dev, by the rule n_t Gauss-Legendre nodes in
  * arclength on [0, eps] times n_theta equispaced angles offset by half a step
- * (1 <= n_t <= 64, 1 <= n_theta <= 256); |Gamma_i| = 2 pi (1 - cos eps).
+ * (1 <= n_t <= 64, 1 <= n_theta <= 256); |Gamma_i| = 2 pi (1 - cos eps), eps
+ * the patch's radius; patch numbers in the caller's order.
  * Synchronises. Errors: NCE_EINVAL, NCE_ESTATE, NCE_EHIP.
  */
 int nce_patch_residual(nce_ctx *ctx, const double *coeffs_dev, const int64_t *patches_host, int npatch, int n_t,

@@ -64,13 +64,18 @@ __device__ __forceinline__ double green_off(double dx, double dy, double dz, dou
 // skeleton points of each source patch are staged in LDS. Targets skip the
 // patches of their own skip list (near patches and the patch they lie on),
 // sorted by patch index: skip[sptr[t] .. sptr[t+1]).
+// Several radii (ptype non-null): source j uses its radius's base skeleton
+// (t_p[ptype[j] ntab] points from skeleton index t_soff[ptype[j] ntab]);
+// strengths rho have rows of ldr.
 template <int PROB>
 __global__ __launch_bounds__(256) void k_field_far(int64_t n, const double4* __restrict__ pts, int N, int p,
                                                    const double* __restrict__ frames,
                                                    const double* __restrict__ skel_off,
-                                                   const double* __restrict__ rho, const int64_t* __restrict__ sptr,
-                                                   const int* __restrict__ skip, int chunk,
-                                                   double* __restrict__ partial) {
+                                                   const double* __restrict__ rho, int ldr,
+                                                   const int64_t* __restrict__ sptr, const int* __restrict__ skip,
+                                                   int chunk, double* __restrict__ partial,
+                                                   const int* __restrict__ ptype, const int* __restrict__ t_soff,
+                                                   const int* __restrict__ t_p, int ntab) {
     __shared__ double4 sm[kFarStage];
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool act = t < n;
@@ -86,16 +91,18 @@ __global__ __launch_bounds__(256) void k_field_far(int64_t n, const double4* __r
         while (q < qe && skip[q] < j) ++q;
         const bool use = act && !(q < qe && skip[q] == j);
         const double* f = frames + 9 * (int64_t)j;
-        for (int m0 = 0; m0 < p; m0 += kFarStage) {
-            const int cnt = min(kFarStage, p - m0);
+        const int pj = ptype ? t_p[ptype[j] * ntab] : p;
+        const double* so = ptype ? skel_off + 3 * (int64_t)t_soff[ptype[j] * ntab] : skel_off;
+        for (int m0 = 0; m0 < pj; m0 += kFarStage) {
+            const int cnt = min(kFarStage, pj - m0);
             __syncthreads();
             for (int m = threadIdx.x; m < cnt; m += 256) {
-                const double* o = skel_off + 3 * (m0 + m);
+                const double* o = so + 3 * (m0 + m);
                 double4 v;
                 v.x = f[0] + (o[0] * f[0] + o[1] * f[3] + o[2] * f[6]);
                 v.y = f[1] + (o[0] * f[1] + o[1] * f[4] + o[2] * f[7]);
                 v.z = f[2] + (o[0] * f[2] + o[1] * f[5] + o[2] * f[8]);
-                v.w = rho[(int64_t)j * p + m0 + m];
+                v.w = rho[(int64_t)j * ldr + m0 + m];
                 sm[m] = v;
             }
             __syncthreads();
@@ -118,8 +125,9 @@ template <int PROB>
 __global__ __launch_bounds__(kNearTheta) void k_field_near(
     const double4* __restrict__ pts, const int64_t* __restrict__ pair_t, const int* __restrict__ pair_j,
     const double* __restrict__ frames, const double* __restrict__ coeffs, int K, int M,
-    const int* __restrict__ kmode, int nr, const double* __restrict__ rad_t, const double* __restrict__ rad_w,
-    const double* __restrict__ sig, double* __restrict__ out) {
+    const int* __restrict__ kmode, const int* __restrict__ ptype, const int* __restrict__ t_nr,
+    const int64_t* __restrict__ t_roff, const int64_t* __restrict__ t_soff, const double* __restrict__ rad_t_all,
+    const double* __restrict__ rad_w_all, const double* __restrict__ sig_all, double* __restrict__ out) {
     __shared__ double F[kNearChunk][2 * kMaxModes];   // [l][m] cos, [l][kMaxModes + m] sin
     __shared__ double fj[136];   // K <= 136 (M <= 15)
     __shared__ double red[kNearTheta / 64];
@@ -130,6 +138,12 @@ __global__ __launch_bounds__(kNearTheta) void k_field_near(
     const double r = P.w;
     const double hs = r > 0.0 ? 1.0 / r : 0.0;
     const double* f = frames + 9 * (int64_t)j;
+    // the radial rule and density profiles of patch j's radius
+    const int ty = ptype ? ptype[j] : 0;
+    const int nr = t_nr[ty];
+    const double* rad_t = rad_t_all + t_roff[ty];
+    const double* rad_w = rad_w_all + t_roff[ty];
+    const double* sig = sig_all + t_soff[ty];
     // target relative to the patch centre (x - c_j and h - c_j)
     const double px = P.x - f[0], py = P.y - f[1], pz = P.z - f[2];
     const double qx = P.x * hs - f[0], qy = P.y * hs - f[1], qz = P.z * hs - f[2];
@@ -215,10 +229,11 @@ __device__ void zernike_radial_all(int m, int M, double rho, double* R) {
     }
 }
 
-// Self term of a target on the sphere inside patch i: sum_k f_ik Z_k(t/eps, theta).
+// Self term of a target on the sphere inside patch i: sum_k f_ik Z_k(t/eps_i, theta).
 __global__ void k_field_self(int64_t n, const double4* __restrict__ pts, const int* __restrict__ selfp,
                              const double* __restrict__ frames, const double* __restrict__ coeffs, int K, int M,
-                             double eps, double* __restrict__ out) {
+                             const int* __restrict__ ptype, const double* __restrict__ t_eps,
+                             double* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int i = selfp[t];
@@ -233,6 +248,7 @@ __global__ void k_field_self(int64_t n, const double4* __restrict__ pts, const i
     const double x2 = P.x * f[6] + P.y * f[7] + P.z * f[8];
     const double tt = atan2(sqrt(x1 * x1 + x2 * x2), xc);
     const double th = atan2(x2, x1);
+    const double eps = t_eps[ptype ? ptype[i] : 0];
     const double rho = fmin(tt / eps, 1.0);
     const double* fi = coeffs + (int64_t)i * K;
     double R[kMaxModes];
@@ -280,20 +296,32 @@ __global__ void k_field_combine(int64_t n, int nchunk, const double* __restrict_
 namespace nce_detail {
 
 // Targets (host, n x 3) with their self patch (-1: none; -2: the patch a
-// point on the sphere lies on, found here); evaluates the potential (or the
-// physical field) into values_dev. Synchronises the stream.
+// point on the sphere lies on, found here; otherwise a patch of the context's
+// order); evaluates the potential (or the physical field) into values_dev.
+// coeffs: N x K in the caller's order. Synchronises the stream.
 static void field_core(nce_ctx* ctx, const double* coeffs, const std::vector<double>& X, std::vector<int>& selfp,
                        int physical, double* values) {
     const int64_t n = (int64_t)X.size() / 3;
     const int64_t N = ctx->N;
-    const int K = ctx->K, p = ctx->p, M = ctx->tab.M;
-    const double eps = ctx->eps;
+    const int K = ctx->K, M = ctx->tab.M;
     hipStream_t s = ctx->stream;
     const nce::PatchTables& tab = ctx->tab;
-    // patches near each target: centre within arclength 3 eps of x/|x|
-    // (uniform 3-D cell hash of the centres, cell = chord of 3 eps)
-    const double near_ang = 3.0 * eps;
-    const double cell = 2.0 * std::sin(0.5 * near_ang) * (1.0 + 1e-9);
+    // several radii: patch j of the context has radius type_eps[ptype[j]];
+    // its coefficients, frames and tables are in the context's order
+    const bool types = ctx->ntype > 1;
+    const int ntype = types ? ctx->ntype : 1;
+    std::vector<double> teps = types ? ctx->type_eps : std::vector<double>{ctx->eps};
+    const int* hptype = types ? ctx->tl.ptype.data() : nullptr;
+    auto eps_of = [&](int64_t j) { return teps[hptype ? hptype[j] : 0]; };
+    const double eps_max = *std::max_element(teps.begin(), teps.end());
+    const double* cf = coeffs;
+    if (types) {
+        HIPCHK(nce::permute_rows(s, N, K, ctx->d_perm.p, coeffs, ctx->d_xp.p, 0));
+        cf = ctx->d_xp.p;
+    }
+    // patches near each target: centre within arclength 3 eps_j of x/|x|
+    // (uniform 3-D cell hash of the centres, cell = chord of 3 eps_max)
+    const double cell = 2.0 * std::sin(0.5 * 3.0 * eps_max) * (1.0 + 1e-9);
     auto key = [&](int64_t a, int64_t b, int64_t c) { return (a * 1000003 + b) * 1000033 + c; };
     std::unordered_map<int64_t, std::vector<int>> grid;
     const std::vector<double>& fr = ctx->frames;
@@ -332,7 +360,7 @@ static void field_core(nce_ctx* ctx, const double* coeffs, const std::vector<dou
                             const double cx = hy * cj[2] - hz * cj[1], cy = hz * cj[0] - hx * cj[2],
                                          cz = hx * cj[1] - hy * cj[0];
                             const double ang = std::atan2(std::sqrt(cx * cx + cy * cy + cz * cz), dt);
-                            if (ang < near_ang) nb.push_back(j);
+                            if (ang < 3.0 * eps_of(j)) nb.push_back(j);
                             if (selfp[t] == -2 && ang < self_ang) {
                                 self_ang = ang;
                                 self = j;
@@ -341,8 +369,9 @@ static void field_core(nce_ctx* ctx, const double* coeffs, const std::vector<dou
                     }
         }
         if (selfp[t] == -2) {
-            // on the sphere (to rounding) and within the closed patch
-            const bool on = std::fabs(r - 1.0) <= 1e-12 && self_ang <= eps * (1.0 + 1e-12);
+            // on the sphere (to rounding) and within the closed patch of the
+            // nearest centre (separation makes that the only candidate)
+            const bool on = self >= 0 && std::fabs(r - 1.0) <= 1e-12 && self_ang <= eps_of(self) * (1.0 + 1e-12);
             selfp[t] = on ? self : -1;
         }
         std::sort(nb.begin(), nb.end());
@@ -361,58 +390,110 @@ static void field_core(nce_ctx* ctx, const double* coeffs, const std::vector<dou
         nptr[t + 1] = (int64_t)pj.size();
     }
     const int64_t npair = (int64_t)pj.size();
-    DevBuf<double> d_pts, d_partial, d_near, d_self, d_flux;
-    DevBuf<int64_t> d_sptr, d_nptr, d_pt;
-    DevBuf<int> d_skip, d_pj, d_self_idx, d_kmode;
+    DevBuf<double> d_pts, d_partial, d_near, d_self, d_teps, d_Is;
+    DevBuf<int64_t> d_sptr, d_nptr, d_pt, d_troff, d_tsigoff;
+    DevBuf<int> d_skip, d_pj, d_self_idx, d_kmode, d_tnr;
     DevBuf<double> d_rad_t, d_rad_w, d_sig;
     d_pts.upload(P4, s);
     d_sptr.upload(sptr, s);
     d_nptr.upload(nptr, s);
     if (!skip.empty()) d_skip.upload(skip, s);
     d_self_idx.upload(selfp, s);
-    // rho = T f with the base outgoing table (valid at arclength >= 2 eps)
-    HIPCHK(nce::gemm_nt<double>(s, (int)N, p, K, coeffs, K, ctx->d_T.p, K, ctx->d_rho.p, p, nullptr, 0));
+    d_teps.upload(teps, s);
+    // rho = T f with each radius's base outgoing table (valid at arclength
+    // >= 2 eps_j), rows of ldr = the largest base skeleton
+    const int ldr = ctx->p;
+    if (types) {
+        for (int ty = 0; ty < ntype; ++ty) {
+            const int64_t a0 = ctx->type_first[ty];
+            const int nrow = (int)(ctx->type_first[ty + 1] - a0);
+            HIPCHK(nce::gemm_nt<double>(s, nrow, ctx->tabs[ty].p, K, cf + a0 * K, K,
+                                        ctx->d_T.p + (int64_t)ctx->type_Toff[ty] * K, K, ctx->d_rho.p + a0 * ldr,
+                                        ldr, nullptr, 0));
+        }
+    } else {
+        HIPCHK(nce::gemm_nt<double>(s, (int)N, ldr, K, cf, K, ctx->d_T.p, K, ctx->d_rho.p, ldr, nullptr, 0));
+    }
+    const int* dptype = types ? ctx->d_ptype.p : nullptr;
+    const int* dtsoff = types ? ctx->d_tsoff.p : nullptr;
+    const int* dtp = types ? ctx->d_tp.p : nullptr;
+    const int ntab = types ? ctx->tl.ntab : 1;
     const int ntb = (int)((n + 255) / 256);
     const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(N, (2048 + ntb - 1) / ntb));
     const int chunk = (int)((N + nchunk - 1) / nchunk);
     d_partial.alloc((size_t)nchunk * n);
     const dim3 gfar(ntb, nchunk);
     if (tab.problem == NCE_INTERIOR)
-        hipLaunchKernelGGL(nce::k_field_far<0>, gfar, dim3(256), 0, s, n, (const double4*)d_pts.p, (int)N, p,
-                           ctx->d_frames.p, ctx->d_skel_off.p, ctx->d_rho.p, d_sptr.p, d_skip.p, chunk, d_partial.p);
+        hipLaunchKernelGGL(nce::k_field_far<0>, gfar, dim3(256), 0, s, n, (const double4*)d_pts.p, (int)N, ldr,
+                           ctx->d_frames.p, ctx->d_skel_off.p, ctx->d_rho.p, ldr, d_sptr.p, d_skip.p, chunk,
+                           d_partial.p, dptype, dtsoff, dtp, ntab);
     else
-        hipLaunchKernelGGL(nce::k_field_far<1>, gfar, dim3(256), 0, s, n, (const double4*)d_pts.p, (int)N, p,
-                           ctx->d_frames.p, ctx->d_skel_off.p, ctx->d_rho.p, d_sptr.p, d_skip.p, chunk, d_partial.p);
+        hipLaunchKernelGGL(nce::k_field_far<1>, gfar, dim3(256), 0, s, n, (const double4*)d_pts.p, (int)N, ldr,
+                           ctx->d_frames.p, ctx->d_skel_off.p, ctx->d_rho.p, ldr, d_sptr.p, d_skip.p, chunk,
+                           d_partial.p, dptype, dtsoff, dtp, ntab);
     HIPCHK(hipGetLastError());
     d_near.alloc(std::max<int64_t>(npair, 1));
     if (npair > 0) {
         std::vector<int> zn, zm;
         nce::zernike_modes(M, zn, zm);
         d_kmode.upload(zm, s);
-        d_rad_t.upload(tab.rad_t, s);
-        d_rad_w.upload(tab.rad_w, s);
-        d_sig.upload(tab.sig, s);
+        // each radius's radial rule and density profiles, concatenated
+        std::vector<double> rt, rw, sg;
+        std::vector<int> tnr;
+        std::vector<int64_t> troff, tsoff;
+        for (int ty = 0; ty < ntype; ++ty) {
+            const nce::PatchTables& tt = types ? ctx->tabs[ty] : tab;
+            troff.push_back((int64_t)rt.size());
+            tsoff.push_back((int64_t)sg.size());
+            tnr.push_back((int)tt.rad_t.size());
+            rt.insert(rt.end(), tt.rad_t.begin(), tt.rad_t.end());
+            rw.insert(rw.end(), tt.rad_w.begin(), tt.rad_w.end());
+            sg.insert(sg.end(), tt.sig.begin(), tt.sig.end());
+        }
+        d_rad_t.upload(rt, s);
+        d_rad_w.upload(rw, s);
+        d_sig.upload(sg, s);
+        d_tnr.upload(tnr, s);
+        d_troff.upload(troff, s);
+        d_tsigoff.upload(tsoff, s);
         d_pt.upload(pt, s);
         d_pj.upload(pj, s);
-        const int nr = (int)tab.rad_t.size();
         if (tab.problem == NCE_INTERIOR)
             hipLaunchKernelGGL(nce::k_field_near<0>, dim3((unsigned)npair), dim3(nce::kNearTheta), 0, s,
-                               (const double4*)d_pts.p, d_pt.p, d_pj.p, ctx->d_frames.p, coeffs, K, M, d_kmode.p, nr,
-                               d_rad_t.p, d_rad_w.p, d_sig.p, d_near.p);
+                               (const double4*)d_pts.p, d_pt.p, d_pj.p, ctx->d_frames.p, cf, K, M, d_kmode.p, dptype,
+                               d_tnr.p, d_troff.p, d_tsigoff.p, d_rad_t.p, d_rad_w.p, d_sig.p, d_near.p);
         else
             hipLaunchKernelGGL(nce::k_field_near<1>, dim3((unsigned)npair), dim3(nce::kNearTheta), 0, s,
-                               (const double4*)d_pts.p, d_pt.p, d_pj.p, ctx->d_frames.p, coeffs, K, M, d_kmode.p, nr,
-                               d_rad_t.p, d_rad_w.p, d_sig.p, d_near.p);
+                               (const double4*)d_pts.p, d_pt.p, d_pj.p, ctx->d_frames.p, cf, K, M, d_kmode.p, dptype,
+                               d_tnr.p, d_troff.p, d_tsigoff.p, d_rad_t.p, d_rad_w.p, d_sig.p, d_near.p);
         HIPCHK(hipGetLastError());
     }
     d_self.alloc(n);
     hipLaunchKernelGGL(nce::k_field_self, dim3(ntb), dim3(256), 0, s, n, (const double4*)d_pts.p, d_self_idx.p,
-                       ctx->d_frames.p, coeffs, K, M, eps, d_self.p);
+                       ctx->d_frames.p, cf, K, M, dptype, d_teps.p, d_self.p);
     HIPCHK(hipGetLastError());
-    if (physical && tab.problem == NCE_INTERIOR)
-        HIPCHK(nce::patch_flux(s, (int)N, K, ctx->d_I.p, coeffs, nullptr, ctx->d_partial.p, ctx->d_scal.p));
+    const double* Is_dev = ctx->d_scal.p;
+    if (physical && tab.problem == NCE_INTERIOR) {
+        if (types) {
+            // I_sigma: each radius's integral vector over its patches
+            for (int ty = 0; ty < ntype; ++ty) {
+                const int64_t a0 = ctx->type_first[ty];
+                HIPCHK(nce::patch_flux(s, (int)(ctx->type_first[ty + 1] - a0), K, ctx->d_Ityp.p + (size_t)ty * K,
+                                       cf + a0 * K, nullptr, ctx->d_partial.p, ctx->d_scal.p + ty));
+            }
+            std::vector<double> part(ntype);
+            HIPCHK(hipMemcpyAsync(part.data(), ctx->d_scal.p, sizeof(double) * ntype, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double Is = 0.0;
+            for (double v : part) Is += v;
+            d_Is.upload(std::vector<double>{Is}, s);
+            Is_dev = d_Is.p;
+        } else {
+            HIPCHK(nce::patch_flux(s, (int)N, K, ctx->d_I.p, cf, nullptr, ctx->d_partial.p, ctx->d_scal.p));
+        }
+    }
     hipLaunchKernelGGL(nce::k_field_combine, dim3(ntb), dim3(256), 0, s, n, nchunk, d_partial.p, d_nptr.p, d_near.p,
-                       d_self.p, (const double4*)d_pts.p, physical, tab.problem, ctx->d_scal.p, values);
+                       d_self.p, (const double4*)d_pts.p, physical, tab.problem, Is_dev, values);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
 }
@@ -423,8 +504,8 @@ extern "C" {
 
 int nce_field(nce_ctx* ctx, const double* coeffs, const double* points, int64_t n, int physical, double* values) {
     if (!ctx || !coeffs || !points || !values || n < 0) return fail(NCE_EINVAL, "bad argument");
-    if (ctx->cfg_first.size() != 2 || ctx->ntype > 1)
-        return fail(NCE_ESTATE, "field evaluation needs a single-configuration context of one patch radius");
+    if (ctx->cfg_first.size() != 2)
+        return fail(NCE_ESTATE, "field evaluation needs a single-configuration context");
     if (physical != 0 && physical != 1) return fail(NCE_EINVAL, "physical must be 0 or 1");
     if (n == 0) return NCE_OK;
     return guarded([&]() -> int {
@@ -452,19 +533,28 @@ int nce_patch_residual(nce_ctx* ctx, const double* coeffs, const int64_t* patche
     if (!ctx || !coeffs || !patches || !residual || npatch < 1 || n_t < 1 || n_theta < 1 || n_t > 64 ||
         n_theta > 256)
         return fail(NCE_EINVAL, "bad argument");
-    if (ctx->cfg_first.size() != 2 || ctx->ntype > 1)
-        return fail(NCE_ESTATE, "residual evaluation needs a single-configuration context of one patch radius");
+    if (ctx->cfg_first.size() != 2)
+        return fail(NCE_ESTATE, "residual evaluation needs a single-configuration context");
     for (int a = 0; a < npatch; ++a)
         if (patches[a] < 0 || patches[a] >= ctx->N) return fail(NCE_EINVAL, "patch index out of range");
     return guarded([&]() -> int {
-        const double eps = ctx->eps;
+        // the caller's patch numbers in the context's order, and each one's radius
+        std::vector<int64_t> inv;
+        if (ctx->ntype > 1) {
+            inv.resize(ctx->N);
+            for (int64_t a = 0; a < ctx->N; ++a) inv[ctx->perm[a]] = a;
+        }
+        auto internal = [&](int64_t i) { return inv.empty() ? i : inv[i]; };
+        auto eps_of = [&](int64_t a) { return ctx->ntype > 1 ? ctx->type_eps[ctx->tl.ptype[a]] : ctx->eps; };
         std::vector<double> xg, wg;
         nce::gauss_legendre(n_t, xg, wg);
         const int per = n_t * n_theta;
-        std::vector<double> X((size_t)3 * per * npatch), W(per);
+        std::vector<double> X((size_t)3 * per * npatch), W((size_t)per * npatch);
         std::vector<int> selfp((size_t)per * npatch);
         for (int a = 0; a < npatch; ++a) {
-            const double* f = &ctx->frames[9 * patches[a]];
+            const int64_t ia = internal(patches[a]);
+            const double eps = eps_of(ia);
+            const double* f = &ctx->frames[9 * ia];
             for (int u = 0; u < n_t; ++u) {
                 const double t = 0.5 * eps * (xg[u] + 1.0);
                 for (int v = 0; v < n_theta; ++v) {
@@ -473,8 +563,8 @@ int nce_patch_residual(nce_ctx* ctx, const double* coeffs, const int64_t* patche
                     const double ct = std::cos(t), st = std::sin(t), c = std::cos(th), sn = std::sin(th);
                     double* x = &X[3 * ((size_t)a * per + q)];
                     for (int d = 0; d < 3; ++d) x[d] = ct * f[d] + st * (c * f[3 + d] + sn * f[6 + d]);
-                    selfp[(size_t)a * per + q] = (int)patches[a];
-                    W[q] = 0.5 * eps * wg[u] * st * (2.0 * M_PI / n_theta);
+                    selfp[(size_t)a * per + q] = (int)ia;
+                    W[(size_t)a * per + q] = 0.5 * eps * wg[u] * st * (2.0 * M_PI / n_theta);
                 }
             }
         }
@@ -483,12 +573,12 @@ int nce_patch_residual(nce_ctx* ctx, const double* coeffs, const int64_t* patche
         field_core(ctx, coeffs, X, selfp, 0, d_v.p);
         std::vector<double> v((size_t)per * npatch);
         HIPCHK(hipMemcpy(v.data(), d_v.p, sizeof(double) * v.size(), hipMemcpyDeviceToHost));
-        const double area = 2.0 * M_PI * (1.0 - std::cos(eps));
         for (int a = 0; a < npatch; ++a) {
+            const double area = 2.0 * M_PI * (1.0 - std::cos(eps_of(internal(patches[a]))));
             double sum = 0.0;
             for (int q = 0; q < per; ++q) {
                 const double e = v[(size_t)a * per + q] - 1.0;
-                sum += W[q] * e * e;
+                sum += W[(size_t)a * per + q] * e * e;
             }
             residual[a] = std::sqrt(sum) / area;
         }

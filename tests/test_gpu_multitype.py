@@ -119,3 +119,36 @@ def test_one_radius_through_radii_entry(torch):
     b = nce.Context(c, np.full(30, 0.05), problem=1, tol_id=1e-12, far_field=nce.FAR_DIRECT)
     x = torch.from_numpy(layouts.random_coeffs(30, a.K, 3, decay=0.1)).cuda()
     assert torch.equal(a.matvec(x), b.matvec(x))
+
+
+@pytest.mark.parametrize("problem", [0, 1])
+def test_two_radii_field_vs_oracle(torch, problem):
+    """nce_field and nce_patch_residual with two radii, for the oracle's dense
+    solution: the potential at points eps_j/5 off patches of both radii, on
+    them, on and near the reflecting surface and deep in the domain against
+    the oracle's quadrature of every patch; eq. l2res on a patch of each
+    radius at the discretisation level, and a 1e-6 change of one coefficient
+    raising it."""
+    g, c, types, ctx = _golden_ctx(problem)
+    x = torch.from_numpy(np.ascontiguousarray(g["coeffs"])).cuda()
+    pts = torch.from_numpy(np.ascontiguousarray(g["field_points"])).cuda()
+    v = ctx.field(x, pts).cpu().numpy()
+    ref = g["field_values"]
+    err = np.max(np.abs(v - ref)) / np.max(np.abs(ref))
+    res = ctx.patch_residual(x, g["residual_patches"], n_t=6, n_theta=10)
+    xp = x.clone()
+    xp[0, 0] *= 1 + 1e-6
+    resp = ctx.patch_residual(xp, g["residual_patches"][:1], n_t=6, n_theta=10)
+    # the physical field (interior: I_sigma over the patches of both radii)
+    phys = ctx.field(x, pts, physical=True).cpu().numpy()
+    P = g["field_points"]
+    if problem == 0:
+        want = (ref - 1.0) / (-3.0 * float(g["I_sigma"])) + (1.0 - np.sum(P * P, axis=1)) / 6.0
+    else:
+        want = 1.0 - ref
+    perr = np.max(np.abs(phys - want)) / np.max(np.abs(want))
+    print(f"problem {problem}: field vs oracle {err:.2e} over {len(ref)} points, physical {perr:.2e}; residual "
+          f"{res} (oracle {g['residual_values']}), perturbed {resp}")
+    assert err < 1e-12 and perr < 1e-12
+    assert np.all(res < 1e-12)
+    assert resp[0] > 100 * res[0]
