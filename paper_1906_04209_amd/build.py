@@ -73,10 +73,14 @@ def build(verbose: bool = False) -> Path:
     return OUT
 
 
+RSQ_CHECK = PKG / "rsq_check"   # accuracy of the FP64 rsq estimate and its corrections (on request)
+
+
 def build_rates() -> Path:
-    """The instruction issue-cost microbenchmark (not part of the library):
-    python -m paper_1906_04209_amd.build --rates"""
+    """The instruction issue-cost microbenchmark and the rsq accuracy check
+    (not part of the library): python -m paper_1906_04209_amd.build --rates"""
     _run([_hipcc(), *HIPCC_FLAGS, str(CSRC / "valu_rates.hip"), "-o", str(RATES)])
+    _run([_hipcc(), *HIPCC_FLAGS, str(CSRC / "rsq_check.hip"), "-o", str(RSQ_CHECK)])
     return RATES
 
 
