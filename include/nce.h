@@ -138,9 +138,11 @@ int nce_setup(const double *centers_host, int64_t N, double eps, const nce_opts 
  * nce_frames, nce_dims, nce_work, nce_autotune and nce_set_solver work on the
  * context as on any other (coefficient vectors in the caller's patch order),
  * and so do nce_field and nce_patch_residual (each patch by its own radius's
- * densities, skeleton and quadrature); the learned and coarse starts, the
- * deflation and nce_integral_vector (use nce_types) return NCE_ESTATE. One
- * distinct radius is the same as nce_setup.
+ * densities, skeleton and quadrature), the coarse solve and start and the
+ * deflation (every patch's charge chi0 that of its own radius). The learned
+ * start (a network in nce_set_warm_start), nce_features and
+ * nce_integral_vector (use nce_types) return NCE_ESTATE. One distinct radius
+ * is the same as nce_setup.
  * Errors: NCE_EINVAL, NCE_ESEP, NCE_ENOMEM, NCE_EHIP, NCE_ETABLE.
  */
 int nce_setup_radii(const double *centers_host, const double *radius_host, int64_t N, const nce_opts *opts,
@@ -294,10 +296,12 @@ int nce_features(nce_ctx *ctx, float *feat_dev);
  * Coarse (monopole) model of the system: with f_i = a_i e_0 and every far
  * field taken as its total charge at the patch centre, row 0 of eq.
  * opinteqnsdisc becomes a_i + chi0 sum_{j != i} G(c_i, c_j) a_j = 1 (chi0 =
- * total charge of e_0 in the outgoing table). Solved on the device by GMRES to
- * 1e-6 (FP32 pair sums); once per context. a_dev: N doubles out (may be NULL);
- * iters_host: GMRES iterations (may be NULL); chi0_host: chi0 (may be NULL).
- * Not in the paper.
+ * total charge of e_0 in the outgoing table; with several patch radii, patch
+ * j's own radius's chi0_j inside the sum). Solved on the device by GMRES to
+ * opts.tol_coarse (FP32 pair sums); once per context. a_dev: N doubles out, in
+ * the caller's patch order (may be NULL); iters_host: GMRES iterations (may be
+ * NULL); chi0_host: chi0, or with several radii one value per radius in the
+ * order of nce_types (ntypes doubles; may be NULL). Not in the paper.
  */
 int nce_coarse_solve(nce_ctx *ctx, double *a_dev, int *iters_host, double *chi0_host);
 
@@ -306,7 +310,8 @@ int nce_coarse_solve(nce_ctx *ctx, double *a_dev, int *iters_host, double *chi0_
  * paper): *k (<= 16) independent basis columns, the orthonormalized harmonic
  * polynomials of degree <= 3 in the patch centres, and T = I + chi0 Z^T G Z,
  * the coarse model of the system on them (G(c_i, c_j) between centres, i != j;
- * chi0 as for nce_coarse_solve). T_host: k*k host doubles, row-major (room for
+ * chi0 as for nce_coarse_solve; with several radii T = I + Z^T G D Z, D the
+ * diagonal of every patch's chi0_j). T_host: k*k host doubles, row-major (room for
  * 256 suffices), may be NULL. Builds the deflation if the context has not yet;
  * k = 0 for N < 64, where none is used.
  */
@@ -324,7 +329,9 @@ int nce_set_deflation(nce_ctx *ctx, int on);
  * coarse solve, and the network's features, computed on host threads while
  * the coarse solve runs) is done here, not in the next solve. m = NULL and
  * use_coarse = 0 disable and drop that work, so a later call redoes it; m
- * without use_coarse is NCE_EINVAL. The caller keeps m alive while it is set.
+ * without use_coarse is NCE_EINVAL; m on a context of several patch radii is
+ * NCE_ESTATE (the network's features are those of one radius). The caller
+ * keeps m alive while it is set.
  */
 int nce_set_warm_start(nce_ctx *ctx, nce_mlp *m, int use_coarse);
 

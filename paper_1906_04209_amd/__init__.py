@@ -409,14 +409,21 @@ class Context:
         _check(self.lib, self.lib.nce_set_warm_start(self.h, mlp.h if mlp is not None else None, int(bool(coarse))))
 
     def coarse(self, with_chi0: bool = False):
-        """(coarse amplitudes a as an N float64 device tensor, GMRES iterations
-        [, chi0])."""
+        """(coarse amplitudes a as an N float64 device tensor in the caller's
+        patch order, GMRES iterations [, chi0]); chi0 is a float for one patch
+        radius and an array of one value per radius (order of types()) for
+        several."""
         a = self.torch.empty(self.N, dtype=self.torch.float64, device="cuda")
-        it, chi0 = ctypes.c_int(), ctypes.c_double()
+        it = ctypes.c_int()
+        chi0 = np.zeros(8)
         self._enter()
-        _check(self.lib, self.lib.nce_coarse_solve(self.h, _ptr(a), ctypes.byref(it), ctypes.byref(chi0)))
+        _check(self.lib, self.lib.nce_coarse_solve(self.h, _ptr(a), ctypes.byref(it), chi0.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_double))))
         self._leave()
-        return (a, it.value, chi0.value) if with_chi0 else (a, it.value)
+        if not with_chi0:
+            return a, it.value
+        nt = len(self.types()[0])
+        return a, it.value, (float(chi0[0]) if nt == 1 else chi0[:nt].copy())
 
     def set_deflation(self, on: bool) -> None:
         _check(self.lib, self.lib.nce_set_deflation(self.h, int(bool(on))))

@@ -212,11 +212,24 @@ void matvec(nce_ctx* ctx, const double* x, double* y, int precision, hipEvent_t*
                         ctx->d_rho32.p, ctx->d_U32.p, ev, live, ctx->p32, ctx->ptot32);
 }
 
-// total charge of the isolated-patch solution e_0 in the base outgoing table
-double coarse_chi0(const nce_ctx* ctx) {
+// total charge of the isolated-patch solution e_0 in a base outgoing table
+static double table_chi0(const nce::PatchTables& t) {
     double chi0 = 0.0;
-    for (int m = 0; m < ctx->p; ++m) chi0 += ctx->tab.T[(size_t)m * ctx->K];
+    for (int m = 0; m < t.p; ++m) chi0 += t.T[(size_t)m * t.K];
     return chi0;
+}
+
+double coarse_chi0(const nce_ctx* ctx) { return table_chi0(ctx->tab); }
+
+// Several patch radii: every patch's charge chi0 of its own radius, in the
+// context's (radius-sorted) patch order; empty for one radius.
+std::vector<double> coarse_charges(const nce_ctx* ctx) {
+    std::vector<double> chi;
+    if (ctx->ntype == 1) return chi;
+    chi.resize((size_t)ctx->N);
+    for (int t = 0; t < ctx->ntype; ++t)
+        std::fill(chi.begin() + ctx->type_first[t], chi.begin() + ctx->type_first[t + 1], table_chi0(ctx->tabs[t]));
+    return chi;
 }
 
 // Builds the coarse-space deflation of the mixed inner solves and the coarse
@@ -224,7 +237,9 @@ double coarse_chi0(const nce_ctx* ctx) {
 void ensure_deflation(nce_ctx* ctx) {
     if (ctx->defl || ctx->N < nce::kDeflMinN) return;
     auto d = std::make_unique<nce::Deflation>();
-    d->build(ctx->stream, (int)ctx->N, ctx->K, ctx->tab.problem, coarse_chi0(ctx), ctx->frames, ctx->d_frames.p);
+    const std::vector<double> chi = coarse_charges(ctx);
+    d->build(ctx->stream, (int)ctx->N, ctx->K, ctx->tab.problem, coarse_chi0(ctx), ctx->frames, ctx->d_frames.p,
+             chi.empty() ? nullptr : &chi);
     ctx->d_dtmp.alloc((size_t)ctx->N * ctx->K);
     ctx->defl = std::move(d);
 }
@@ -232,8 +247,10 @@ void ensure_deflation(nce_ctx* ctx) {
 const double* coarse_amplitudes(nce_ctx* ctx) {
     if (ctx->coarse_iters >= 0) return ctx->d_a.p;
     const double chi0 = coarse_chi0(ctx);
-    if (!ctx->coarse)
+    if (!ctx->coarse) {
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
+        if (ctx->ntype > 1) ctx->coarse->set_charges(ctx->stream, coarse_charges(ctx));
+    }
     ctx->d_a.alloc((size_t)ctx->N);
     // the deflation's smooth modes are the coarse model's own slow ones: it
     // preconditions this solve as well
@@ -1118,7 +1135,6 @@ int nce_features(nce_ctx* ctx, float* feat) {
 }
 
 int nce_set_deflation(nce_ctx* ctx, int on) {
-    if (ctx && ctx->ntype > 1 && on) return fail(NCE_ESTATE, "no deflation for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     if (on != 0 && on != 1) return fail(NCE_EINVAL, "on must be 0 or 1");
     ctx->opts.deflation = on;
@@ -1126,7 +1142,6 @@ int nce_set_deflation(nce_ctx* ctx, int on) {
 }
 
 int nce_deflation_matrix(nce_ctx* ctx, int* k, double* T_host) {
-    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx || !k) return fail(NCE_EINVAL, "ctx and k must not be NULL");
     return guarded([&]() -> int {
         ensure_deflation(ctx);
@@ -1137,21 +1152,27 @@ int nce_deflation_matrix(nce_ctx* ctx, int* k, double* T_host) {
 }
 
 int nce_coarse_solve(nce_ctx* ctx, double* a, int* iters, double* chi0) {
-    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
     return guarded([&]() -> int {
         const double* d = coarse_amplitudes(ctx);
-        if (a) HIPCHK(hipMemcpyAsync(a, d, sizeof(double) * ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
+        if (a && ctx->ntype > 1)
+            HIPCHK(nce::permute_rows(ctx->stream, ctx->N, 1, ctx->d_perm.p, d, a, 1));
+        else if (a)
+            HIPCHK(hipMemcpyAsync(a, d, sizeof(double) * ctx->N, hipMemcpyDeviceToDevice, ctx->stream));
         if (iters) *iters = ctx->coarse_iters;
-        if (chi0) *chi0 = ctx->coarse->chi0;
+        if (chi0 && ctx->ntype > 1)
+            for (int t = 0; t < ctx->ntype; ++t) chi0[t] = table_chi0(ctx->tabs[t]);
+        else if (chi0)
+            *chi0 = ctx->coarse->chi0;
         HIPCHK(hipStreamSynchronize(ctx->stream));
         return NCE_OK;
     });
 }
 
 int nce_set_warm_start(nce_ctx* ctx, nce_mlp* m, int use_coarse) {
-    if (ctx && ctx->ntype > 1) return fail(NCE_ESTATE, "not available for a layout of several patch radii");
     if (!ctx) return fail(NCE_EINVAL, "ctx is NULL");
+    if (m && ctx->ntype > 1)
+        return fail(NCE_ESTATE, "the network's features are for one patch radius: use the coarse start alone");
     if (m && (m->net.n_in != nce::kFeatureDim || m->net.n_out != ctx->K))
         return fail(NCE_ESTATE, "network shape does not match NCE_FEATURES -> K");
     if (m && !use_coarse) return fail(NCE_EINVAL, "the network refines the coarse solve: use_coarse must be 1");

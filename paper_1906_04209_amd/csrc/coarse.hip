@@ -11,7 +11,10 @@
 //     a_i + chi0 sum_{j != i} G(c_i, c_j) a_j = 1,
 //
 // whose matrix carries the strong, long-range coupling of many patches that
-// makes plain GMRES slow. It is solved here by GMRES on the device, with the
+// makes plain GMRES slow. With patches of several radii the charge is patch
+// j's own, chi0_j from its radius's outgoing table, inside the sum (P acts on
+// functions of t/eps and is the same for every radius, and so are row 0 and
+// the right-hand side e_0). It is solved here by GMRES on the device, with the
 // all-pairs sum over centres in FP32 (FP64 accumulation): O(N^2) pair
 // evaluations, about a hundredth of one full system apply at N = 1e5.
 #include <hip/hip_runtime.h>
@@ -37,13 +40,14 @@ void chk(hipError_t e, const char* what) {
     if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// src[j] = (c_j / 2, a_j)
+// src[j] = (c_j / 2, a_j), or (c_j / 2, chi0_j a_j) with per-patch charges
 __global__ void k_coarse_src(int N, const double* __restrict__ frames, const double* __restrict__ a,
-                             float4* __restrict__ src) {
+                             const double* __restrict__ chi, float4* __restrict__ src) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const double* f = frames + 9 * (int64_t)j;
-    src[j] = make_float4((float)(0.5 * f[0]), (float)(0.5 * f[1]), (float)(0.5 * f[2]), (float)a[j]);
+    const double q = chi ? chi[j] * a[j] : a[j];
+    src[j] = make_float4((float)(0.5 * f[0]), (float)(0.5 * f[1]), (float)(0.5 * f[2]), (float)q);
 }
 
 // partial[split * N + i] = sum over this split's sources j != i of G(c_i, c_j) a_j.
@@ -116,14 +120,15 @@ __global__ __launch_bounds__(256) void k_coarse_sum(int N, const float4* __restr
     }
 }
 
-// y_i = a_i + chi0 sum_split partial[split][i]
+// y_i = a_i + scale sum_split partial[split][i] (scale = chi0, or 1 when the
+// sources carry their own charges)
 __global__ void k_coarse_finish(int N, int nsplit, const double* __restrict__ partial, const double* __restrict__ a,
-                                double chi0, double* __restrict__ y) {
+                                double scale, double* __restrict__ y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double s = 0.0;
     for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)k * N + i];
-    y[i] = a[i] + chi0 * s;
+    y[i] = a[i] + scale * s;
 }
 
 }  // namespace
@@ -150,20 +155,29 @@ CoarseSolver::CoarseSolver(int N_, int problem_, double chi0_, int maxit_)
 }
 
 CoarseSolver::~CoarseSolver() {
-    for (void* p : {(void*)src, (void*)part, (void*)V, (void*)h, (void*)rpart, (void*)scal, (void*)tmp})
+    for (void* p : {(void*)src, (void*)part, (void*)V, (void*)h, (void*)rpart, (void*)scal, (void*)tmp, (void*)chi})
         if (p) (void)hipFree(p);
+}
+
+void CoarseSolver::set_charges(hipStream_t s, const std::vector<double>& chi0_patch) {
+    if (chi0_patch.empty() || chi0_patch.size() > (size_t)N)
+        throw std::runtime_error("coarse charges: one value per patch of at most N patches");
+    if (!chi) chk(hipMalloc((void**)&chi, sizeof(double) * (size_t)N), "hipMalloc");
+    chk(hipMemcpyAsync(chi, chi0_patch.data(), sizeof(double) * chi0_patch.size(), hipMemcpyHostToDevice, s), "copy");
+    chk(hipStreamSynchronize(s), "sync");
 }
 
 void CoarseSolver::apply(hipStream_t s, int n, const double* frames, const double* a, double* y) {
     if (n < 1 || n > N) throw std::runtime_error("coarse apply: layout larger than the solver");
     const int nsplit = splits_for(n), chunk = (n + nsplit - 1) / nsplit;
-    hipLaunchKernelGGL(k_coarse_src, dim3((n + 255) / 256), dim3(256), 0, s, n, frames, a, src);
+    hipLaunchKernelGGL(k_coarse_src, dim3((n + 255) / 256), dim3(256), 0, s, n, frames, a, chi, src);
     const dim3 grid((n + 256 * kTgt - 1) / (256 * kTgt), nsplit);
     if (problem == 1)
         hipLaunchKernelGGL(k_coarse_sum<1>, grid, dim3(256), 0, s, n, src, chunk, part);
     else
         hipLaunchKernelGGL(k_coarse_sum<0>, grid, dim3(256), 0, s, n, src, chunk, part);
-    hipLaunchKernelGGL(k_coarse_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, nsplit, part, a, chi0, y);
+    hipLaunchKernelGGL(k_coarse_finish, dim3((n + 255) / 256), dim3(256), 0, s, n, nsplit, part, a,
+                       chi ? 1.0 : chi0, y);
     chk(hipGetLastError(), "coarse apply");
 }
 

@@ -1,10 +1,11 @@
 // Monopole (coarse) model of the system: one unknown a_i per patch,
-//     a_i + chi0 sum_{j != i} G(c_i, c_j) a_j = 1,
-// solved on the device; see coarse.hip.
+//     a_i + sum_{j != i} G(c_i, c_j) chi0_j a_j = 1
+// (chi0_j = chi0 for one patch radius), solved on the device; see coarse.hip.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 #include "deflate.hpp"
 
@@ -21,11 +22,16 @@ struct CoarseSolver {
     double* rpart = nullptr;
     double* scal = nullptr;
     double* tmp = nullptr;   // N doubles: the preconditioned Krylov vector
+    double* chi = nullptr;   // per-patch charges chi0_j (N doubles) after set_charges; else chi0 for all
 
     CoarseSolver(int N, int problem, double chi0, int maxit);
     ~CoarseSolver();
     CoarseSolver(const CoarseSolver&) = delete;
     CoarseSolver& operator=(const CoarseSolver&) = delete;
+    // Per-patch charges chi0_j (a layout of several patch radii: each patch's
+    // radius's chi0), n <= N values in the layout's patch order; replaces the
+    // common chi0 in later applies and solves.
+    void set_charges(hipStream_t s, const std::vector<double>& chi0_patch);
     // y = C a for a layout of n <= N centres (device vectors of n doubles);
     // frames: n x 9 device (c, e1, e2)
     void apply(hipStream_t s, int n, const double* frames, const double* a, double* y);

@@ -272,7 +272,9 @@ Deflation::~Deflation() {
 
 int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::vector<double>& frames,
                      const double* frames_dev, std::vector<double>& Zh, std::vector<double>& M,
-                     std::vector<double>* Tout) {
+                     std::vector<double>* Tout, const std::vector<double>* chi_patch) {
+    if (chi_patch && chi_patch->size() != (size_t)N)
+        throw std::runtime_error("deflation: one charge per patch");
     M.assign((size_t)kDefl * kDefl, 0.0);
     if (N < kDeflMinN) {
         Zh.assign((size_t)N * kDefl, 0.0);
@@ -289,7 +291,15 @@ int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::
     }
     std::vector<double> Sh(Zh.size());
     try {
-        chk(hipMemcpyAsync(Zd, Zh.data(), sizeof(double) * Zh.size(), hipMemcpyHostToDevice, s), "copy");
+        // the sources of the pass: Z, or D Z with D = diag(chi0_j) for per-patch charges
+        std::vector<double> Zs;
+        if (chi_patch) {
+            Zs = Zh;
+            for (int j = 0; j < N; ++j)
+                for (int q = 0; q < kDefl; ++q) Zs[(size_t)j * kDefl + q] *= (*chi_patch)[j];
+        }
+        const std::vector<double>& src = chi_patch ? Zs : Zh;
+        chk(hipMemcpyAsync(Zd, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, s), "copy");
         coarse_multi(s, problem, N, frames_dev, Zd, Sd);
         chk(hipMemcpy(Sh.data(), Sd, sizeof(double) * Sh.size(), hipMemcpyDeviceToHost), "copy");
     } catch (...) {
@@ -299,9 +309,10 @@ int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::
     }
     (void)hipFree(Zd);
     (void)hipFree(Sd);
-    // T = Z^T (I + chi0 G) Z on the k independent columns (Z^T Z = I)
+    // T = Z^T (I + chi0 G) Z on the k independent columns (Z^T Z = I); with
+    // per-patch charges T = Z^T (I + G D) Z, S already holding G D Z
     std::vector<double> T;
-    deflation_coarse_matrix(Zh, Sh, N, k, chi0, T);
+    deflation_coarse_matrix(Zh, Sh, N, k, chi_patch ? 1.0 : chi0, T);
     if (Tout) *Tout = T;
     // a singular T (not met in practice) leaves the configuration undeflated:
     // M = 0 makes M^{-1} the identity
@@ -313,11 +324,11 @@ int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::
 }
 
 void Deflation::build(hipStream_t s, int N_, int K_, int problem, double chi0, const std::vector<double>& frames,
-                      const double* frames_dev) {
+                      const double* frames_dev, const std::vector<double>* chi_patch) {
     N = N_;
     K = K_;
     std::vector<double> Zh, M;
-    k = deflation_member(s, N, problem, chi0, frames, frames_dev, Zh, M, &T);
+    k = deflation_member(s, N, problem, chi0, frames, frames_dev, Zh, M, &T, chi_patch);
     chk(hipMalloc((void**)&Z, sizeof(double) * Zh.size()), "hipMalloc");
     chk(hipMalloc((void**)&Minv, sizeof(double) * kDefl * kDefl), "hipMalloc");
     chk(hipMalloc((void**)&partial, sizeof(double) * kDotBlocks * kDefl), "hipMalloc");

@@ -5,7 +5,8 @@
 // modes the coarse (monopole) model of coarse.hip describes. With Z the
 // N x k orthonormal basis of the polynomials of degree <= 3 in the patch
 // centres (k = 16 on the sphere), placed in every patch's e_0 coefficient,
-// and T = Z^T C Z the coarse operator C = I + chi0 G restricted to it, the
+// and T = Z^T C Z the coarse operator C = I + chi0 G restricted to it (I + G D,
+// D = diag(chi0_j), for patches of several radii), the
 // right preconditioner
 //
 //     M^{-1} v = v + Z (T^{-1} - I) Z^T v
@@ -39,9 +40,11 @@ struct Deflation {
     Deflation& operator=(const Deflation&) = delete;
     ~Deflation();
     // Builds Z from the centres (frames: N x 9 host, (c, e1, e2) per patch) and
-    // T from the coarse model (chi0, problem); frames_dev is the device copy.
+    // T from the coarse model (chi0, problem; chi_patch, when given, N
+    // per-patch charges in place of chi0, for patches of several radii);
+    // frames_dev is the device copy.
     void build(hipStream_t s, int N, int K, int problem, double chi0, const std::vector<double>& frames,
-               const double* frames_dev);
+               const double* frames_dev, const std::vector<double>* chi_patch = nullptr);
     // out = M^{-1} in for N x K vectors (out may equal in).
     hipError_t apply(hipStream_t s, const double* in, double* out) const { return apply_stride(s, in, out, K); }
     // the same for N x stride vectors (stride 1: one value per patch, as the
@@ -51,11 +54,13 @@ struct Deflation {
 
 // One configuration's deflation data on the host: Z (N x kDefl, zero beyond
 // the k independent columns) and M = T^{-1} - I (kDefl x kDefl, zero beyond
-// k); T (k x k) into *T when given. Returns k; N < kDeflMinN (zero Z and M)
-// or a singular T (zero M) give 0, and the apply is then the identity.
+// k); T (k x k) into *T when given. With chi_patch (N per-patch charges) the
+// coarse operator is I + G D, D = diag(chi_patch), instead of I + chi0 G.
+// Returns k; N < kDeflMinN (zero Z and M) or a singular T (zero M) give 0,
+// and the apply is then the identity.
 int deflation_member(hipStream_t s, int N, int problem, double chi0, const std::vector<double>& frames,
                      const double* frames_dev, std::vector<double>& Z, std::vector<double>& M,
-                     std::vector<double>* T);
+                     std::vector<double>* T, const std::vector<double>* chi_patch = nullptr);
 
 // M^{-1} for ncfg configurations stored one after another (configuration c =
 // patches [pseg[c], pseg[c + 1]), patch_cfg[i] = c; Z: npatch x kDefl, M: ncfg

@@ -106,7 +106,6 @@ static void layout_types(const std::vector<nce::PatchTables>& tabs, bool ladder,
 
 void init_ctx_types(nce_ctx* ctx, const double* centers, const double* radius, int64_t N, const nce_opts& o) {
     ctx->opts = o;
-    ctx->opts.deflation = 0;   // the coarse model of the deflation is built for one radius
     ctx->N = N;
     ctx->cfg_first = {0, N};
     // distinct radii in ascending order = types; patches sorted by type (stable)

@@ -152,3 +152,79 @@ def test_two_radii_field_vs_oracle(torch, problem):
     assert err < 1e-12 and perr < 1e-12
     assert np.all(res < 1e-12)
     assert resp[0] > 100 * res[0]
+
+
+def _oracle_chi0(problem, eps):
+    """Total charge of e_0 in the oracle's stored outgoing table of one radius."""
+    from oracle import tables
+    t = tables.load(tables.GOLDEN_DIR / (tables.key(problem, eps, 15, 1e-12) + ".npz"))
+    return float(t.T[:, 0].sum())
+
+
+@pytest.mark.parametrize("problem,radii,seed", [(0, (0.01, 0.05), 71), (1, (0.005, 0.05), 72)])
+def test_two_radii_coarse_solve_and_deflation_matrix(torch, problem, radii, seed):
+    """The coarse model with two radii (ratio 5 and 10), N = 300: each radius's
+    charge chi0 against the oracle's outgoing table of that radius, the coarse
+    solve satisfying a_i + sum_{j != i} G(c_i, c_j) chi0_j a_j = 1 with the
+    closed-form G and the oracle's charges, and the deflation's coarse matrix
+    against I + Z^T G D Z, D = diag(chi0_j)."""
+    import paper_1906_04209_amd as nce
+    from oracle import greens
+    from test_host_deflate import harmonic_polys, mgs
+    N = 300
+    c, types = layouts.multi_radius_centers(N, radii, seed)
+    radius = np.asarray(radii)[types]
+    ctx = nce.Context(c, radius, problem=problem, tol_id=1e-11, tol_coarse=1e-6)
+    a, iters, chi0 = ctx.coarse(with_chi0=True)
+    a = a.cpu().numpy()
+    lr, _, lt = ctx.types()
+    assert np.allclose(lr, sorted(radii))
+    want = np.array([_oracle_chi0(problem, float(e)) for e in lr])
+    cerr = float(np.max(np.abs(chi0 - want) / np.abs(want)))
+    q = want[lt]   # every patch's charge, caller's order
+    d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=-1)
+    np.fill_diagonal(d, 1.0)
+    G = greens.g_surface(d, problem)
+    np.fill_diagonal(G, 0.0)
+    res = np.linalg.norm(a + G @ (q * a) - 1.0) / np.sqrt(N)
+    # one common charge instead (the largest radius's) misses the equations
+    res1 = np.linalg.norm(a + want[-1] * (G @ a) - 1.0) / np.sqrt(N)
+    k, T = ctx.deflation_matrix()
+    Z = mgs(harmonic_polys(c))
+    ref = np.eye(16) + Z.T @ G @ (q[:, None] * Z)
+    terr = np.max(np.abs(T - ref)) / np.max(np.abs(ref - np.eye(16)))
+    print(f"problem {problem} radii {lr}: chi0 {chi0} (oracle rel err {cerr:.2e}); coarse {iters} iterations, "
+          f"residual {res:.2e} (one charge: {res1:.2e}); deflation matrix k {k} rel err {terr:.2e}")
+    assert cerr < 1e-9
+    assert iters >= 1 and res < 1e-5 and res1 > 100 * res
+    assert k == 16 and terr < 1e-5
+
+
+@pytest.mark.parametrize("problem", [0, 1])
+def test_two_radii_deflation_and_coarse_start_keep_result(torch, problem):
+    """Mixed solves of N = 3000 patches of radii 0.01 and 0.005 without and
+    with the deflation, then with the coarse start as well: the same scalar
+    to 1e-8, fewer FP32 applies with the deflation, and a coarse start that
+    halves the initial residual at least; the FP64 solve from the coarse start
+    gives the same scalar as well."""
+    import paper_1906_04209_amd as nce
+    c, types = layouts.multi_radius_centers(3000, (0.01, 0.005), 73)
+    radius = np.array((0.01, 0.005))[types]
+    key = "mu" if problem == 0 else "capture_rate"
+    ctx = nce.Context(c, radius, problem=problem, tol_id=1e-11, tol_gmres=1e-10, precision=nce.MIXED,
+                      deflation=False)
+    out = {"plain": ctx.solve(want_coeffs=False, want_flux=False)}
+    ctx.set_deflation(True)
+    out["deflated"] = ctx.solve(want_coeffs=False, want_flux=False)
+    ctx.set_warm_start(None, True)
+    out["coarse start"] = ctx.solve(want_coeffs=False, want_flux=False)
+    ctx.set_solver(1e-10, 200, nce.FP64)
+    out["coarse start FP64"] = ctx.solve(want_coeffs=False, want_flux=False)
+    for name, r in out.items():
+        print(f"problem {problem} {name}: {key} {r[key]:.12f}, FP32 {r['iters_fp32']} FP64 {r['iters_fp64']} "
+              f"applies, x0 residual {r['rel_residual_x0']:.2e}, fallback {r['used_fallback']}")
+        assert r["converged"]
+        assert abs(r[key] - out["plain"][key]) < 1e-8 * abs(out["plain"][key])
+    assert out["deflated"]["iters_fp32"] < out["plain"]["iters_fp32"]
+    assert out["coarse start"]["rel_residual_x0"] < 0.5 and not out["coarse start"]["used_fallback"]
+    assert out["coarse start FP64"]["rel_residual_x0"] < 0.5

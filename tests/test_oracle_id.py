@@ -4,7 +4,7 @@ import math
 import numpy as np
 import pytest
 
-from oracle import idcomp, onepatch
+from oracle import idcomp, onepatch, tables
 from oracle.greens import EXTERIOR, INTERIOR, g_surface
 
 
@@ -31,3 +31,18 @@ def test_skeleton_field_matches_fine_grid(problem, eps):
     full = _G(x, idcomp.polar_to_xyz(res.fine_t, res.fine_theta), problem) @ (res.w[:, None] * res.B)
     skel = _G(x, idcomp.polar_to_xyz(cp.skel_t, cp.skel_theta), problem) @ cp.T
     assert np.max(np.abs(full - skel)) <= 10 * tol * np.max(np.abs(full))
+
+
+@pytest.mark.parametrize("key", ["p0_eps0.1_M15_id1e-12_nt64", "p1_eps0.05_M15_id1e-12_nt64",
+                                 "p0_eps0.01_M15_id1e-12_nt64", "p1_eps0.005_M15_id1e-12_nt64",
+                                 "p0_eps0.001_M15_id1e-11_nt64"])
+def test_outgoing_charges_equal_density_integrals(key):
+    # Far from the patch every field is that of its total charge, so the
+    # skeleton strengths of basis function k (column k of T, eq.
+    # outgoingcompressed) must sum to the integral of its density, I_k of eq.
+    # getI, which the oracle gets independently by quadrature of the density
+    # profiles. The coarse model's charge chi0 = sum_m T[m][0] rests on this.
+    t = tables.load(tables.GOLDEN_DIR / (key + ".npz"))
+    err = np.max(np.abs(t.T.sum(axis=0) - t.I)) / np.max(np.abs(t.I))
+    print(f"{key}: p = {t.p}, max |sum_m T[m][k] - I_k| / max |I| = {err:.2e}")
+    assert err < 1e-10
