@@ -194,6 +194,69 @@ __host__ __device__ __forceinline__ double green64_grid_split(double h2, const L
     return fma(-2.0, p.h, w - p.t);
 }
 
+// The grid form with the logarithm's binary exponent folded into its table.
+// A window of kWinOct consecutive octaves of the argument x, x in [2^E0,
+// 2^(E0 + kWinOct)), kWinBins bins per octave, is indexed straight by the high
+// word of x: the low kWinOctBits bits of the biased exponent and the top
+// kWinBinBits bits of the mantissa (octave E sits in slot (E + 1023) mod
+// kWinOct). The entry of bin k of octave E is r = r_k 2^-(E+1), with r_k the
+// double nearest 1 / c_k, c_k = 1 + (k + 1/2) / kWinBins the bin centre, and
+// t = E ln 2 - log(r_k) rounded once: then v = x r - 1/2 lies within
+// 2^-(kWinBinBits + 2) of zero, log x = t + log(1 + 2 v), and the
+// series of log(1 + 2 v) / 2 to degree 4 leaves under 2^-48 absolute. Against
+// the split form this drops the exponent's extraction and conversion and its
+// second accumulator, for one more series term. The caller guarantees x in
+// the window for every pair of nonzero strength (an index outside it reads
+// another octave's entry: a finite wrong value).
+constexpr int kWinOctBits = 3;
+constexpr int kWinBinBits = 8;
+constexpr int kWinOct = 1 << kWinOctBits;
+constexpr int kWinBins = 1 << kWinBinBits;
+constexpr int kWinTab = kWinOct * kWinBins;
+
+// Host: entries of octaves e_first .. e_first + noct - 1, noct x kWinBins.
+inline void build_log_window_table(int e_first, int noct, LogEntry* tab) {
+    const long double ln2 = 0.693147180559945309417232121458176568L;
+    for (int k = 0; k < kWinBins; ++k) {
+        const long double c = 1.0L + (k + 0.5L) / kWinBins;
+        const double rk = (double)(1.0L / c);
+        const long double base = -std::log((long double)rk);
+        for (int o = 0; o < noct; ++o) {
+            const int e = e_first + o;
+            tab[(size_t)o * kWinBins + k].r = std::ldexp(rk, -(e + 1));
+            tab[(size_t)o * kWinBins + k].t = (double)(base + (long double)e * ln2);
+        }
+    }
+}
+
+// The octave held by slot `slot` of the window that starts at octave e0.
+__host__ __device__ __forceinline__ int window_octave(int e0, int slot) {
+    return e0 + ((slot - e0 - 1023) & (kWinOct - 1));
+}
+
+template <int PROB>
+__host__ __device__ __forceinline__ double green64_grid_win(double h2, const LogEntry* __restrict__ win) {
+    const double w = rsqrt64_grid(h2);
+    double x;
+    if (PROB == 1) {
+        x = 1.0 + w;
+    } else {
+        const double u = h2 * w;
+        x = fma(u, u, u);
+    }
+#if defined(__HIP_DEVICE_COMPILE__)
+    const unsigned hi = (unsigned)__double2hiint(x);
+#else
+    unsigned long long bits;
+    std::memcpy(&bits, &x, sizeof bits);
+    const unsigned hi = (unsigned)(bits >> 32);
+#endif
+    const LogEntry& L = win[(hi >> (20 - kWinBinBits)) & (kWinTab - 1)];
+    const double v = fma(x, L.r, -0.5);
+    const double q = fma(fma(v, 2.0, -4.0 / 3.0), v, 1.0);
+    return fma(-2.0, fma(-v * q, v, v), w - L.t);
+}
+
 // G as a function of d^2 (FP64).
 template <int PROB>
 __host__ __device__ __forceinline__ double green64(double d2, const LogEntry* __restrict__ tab) {

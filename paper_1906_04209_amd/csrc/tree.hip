@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_reduce_coef(const int* __restrict__ gli
 // on the scalar unit). The groups' partial sums are combined in LDS and
 // written per item to `part`.
 constexpr int kStage = 1024;
-constexpr int kStage64 = 768;  // FP64: 40 bytes per staged point
+constexpr int kStage64 = 448;  // FP64: 40 bytes per staged point (with the 32 KiB logarithm window, 3 blocks per CU)
 constexpr int kStagePad = 64;  // >= the largest ns
 
 // floor(a / b) for 0 <= a < 2^21, 1 <= b < 2^12, by one reciprocal: the
@@ -211,19 +211,29 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                int ntab,
                                                const int* __restrict__ it_cfg, const int* __restrict__ live,
                                                const int64_t* __restrict__ g_off, const double* __restrict__ gpt,
-                                               const int* __restrict__ it_list, const LogEntry* __restrict__ logtab,
+                                               const int* __restrict__ it_list, const int* __restrict__ it_win,
+                                               const LogEntry* __restrict__ logwin, int win_first,
                                                const int* __restrict__ it_solo, double* __restrict__ coef,
                                                const double* __restrict__ ttab, const int* __restrict__ g_ttab) {
     // staging (kStage64 points: (-2 a, |a|^2) with a the half-scaled offset
     // from the cap centre, and the strengths) and, after the sums, the split
-    // partials (ns q <= 256 R)
+    // partials (ns q <= 256 R); the item's logarithm window, and after the
+    // sums the transform's tables
     __shared__ double4 smem4[kStage64 + kStagePad];
     __shared__ double srho[kStage64 + kStagePad];
-    __shared__ LogEntry ltab[kLogTab];
+    __shared__ LogEntry ltab[kWinTab];
+    static_assert((kStage64 + kStagePad) * 4 >= 2 * kMaxGridQ, "split partials and the grid transform's values");
+    static_assert(kWinTab * 2 >= 2 * kMaxGridNt + 8 * kMaxGridNr, "the grid transform's tables");
     double* smem = reinterpret_cast<double*>(smem4);
     const int item = it_list ? it_list[blockIdx.x] : (int)blockIdx.x;
     if (live && !live[it_cfg[item]]) return;
-    for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
+    {
+        // slot s of the window holds octave window_octave(e0, s), one of the
+        // kWinOct octaves from e0 on (all inside the table by construction)
+        const int e0 = it_win[item];
+        for (int k = threadIdx.x; k < kWinTab; k += blockDim.x)
+            ltab[k] = logwin[(window_octave(e0, k >> kWinBinBits) - win_first) * kWinBins + (k & (kWinBins - 1))];
+    }
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     // outgoing table: the grid's, of the item's source type with several radii
@@ -233,12 +243,11 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
     const bool active = split < ns;
-    // acc: sum of rho (G + e ln 2), ace: sum of rho e (e the logarithm's binary exponent)
-    double zx[R], zy[R], zz[R], z2[R], acc[R], ace[R];
+    double zx[R], zy[R], zz[R], z2[R], acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int t = t0 + r * qq;
-        acc[r] = ace[r] = 0.0;
+        acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
         if (active && t < q) {
             // half-scaled offsets from the cap centre, precomputed per tree
@@ -288,10 +297,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const double h2 = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
-                    double de;
-                    const double gs = green64_grid_split<PROB>(h2, ltab, de);
-                    acc[r] = fma(gs, w, acc[r]);
-                    ace[r] = fma(de, w, ace[r]);
+                    acc[r] = fma(green64_grid_win<PROB>(h2, ltab), w, acc[r]);
                 }
             }
         }
@@ -302,11 +308,11 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int t = t0 + r * qq;
-            if (t < q) red[split * q + t] = fma(-kLn2Hi, ace[r], fma(-kLn2Lo, ace[r], acc[r]));
+            if (t < q) red[split * q + t] = acc[r];
         }
     __syncthreads();
-    p2l_finish<double, double>(red, ns, q, it_solo && it_solo[item], nr, nt, smem, srho, ttab + g_ttab[g],
-                               part + it_off[item], coef + g_off[g]);
+    p2l_finish<double, double>(red, ns, q, it_solo && it_solo[item], nr, nt, smem, reinterpret_cast<double*>(ltab),
+                               ttab + g_ttab[g], part + it_off[item], coef + g_off[g]);
 }
 
 template <int PROB, int R>
@@ -1059,6 +1065,19 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
         std::vector<LogEntry> lt(kLogTab);
         build_log_table(lt.data());
         d.logtab = dev_copy(lt);
+        // the octaves of every item's logarithm window
+        static_assert(kWinOct == kLogWindowOctaves, "the tree's windows are the kernels'");
+        if (t.it_win.size() != t.it_grid.size()) throw std::runtime_error("P2L items without logarithm windows");
+        int lo = 0, hi = 0;
+        for (size_t it = 0; it < t.it_win.size(); ++it) {
+            lo = it ? std::min(lo, t.it_win[it]) : t.it_win[it];
+            hi = it ? std::max(hi, t.it_win[it]) : t.it_win[it];
+        }
+        std::vector<LogEntry> wt((size_t)(hi - lo + kWinOct) * kWinBins);
+        build_log_window_table(lo, hi - lo + kWinOct, wt.data());
+        d.win_first = lo;
+        d.logwin = dev_copy(wt);
+        d.it_win = dev_copy(t.it_win);
     }
     d.gpt64 = dev_alloc<double>(3 * t.total_q);
     d.gpt32 = dev_alloc<float>(3 * t.total_q);
@@ -1075,7 +1094,7 @@ void free_tree(DeviceTree& d) {
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.it_solo, d.coef64,  d.part64, d.g_multi,  d.coef32, d.part32, d.ttab, d.g_ttab,
                     d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
-                    d.it_type, d.t_col, d.ptype};
+                    d.it_type, d.t_col, d.ptype, d.it_win, d.logwin};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -1089,7 +1108,7 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
-                           it_list, d.logtab, d.it_solo, d.coef64, d.ttab, d.g_ttab);
+                           it_list, d.it_win, d.logwin, d.win_first, d.it_solo, d.coef64, d.ttab, d.g_ttab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
                            d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,

@@ -51,6 +51,11 @@ struct DeviceTree {
     float* gpt32 = nullptr;
     // items whose grids keep more lanes busy with 4 (resp. 8) grid points per thread
     LogEntry* logtab = nullptr;  // FP64 logarithm table (kLogTab entries)
+    // the FP64 P2L's logarithm windows: per item its first octave, and the
+    // table of octaves win_first .. (kWinBins entries each) they draw from
+    int* it_win = nullptr;
+    LogEntry* logwin = nullptr;
+    int win_first = 0;
     int n_items4 = 0;
     int* items4 = nullptr;
     int* items8 = nullptr;

@@ -64,7 +64,65 @@ struct Box {
     std::vector<int> nbrs;
 };
 
+// Cuts a grid's run of n sources (their arclengths d from the cap centre, as
+// floats) into P2L items of at most spi sources each whose pairs' logarithm
+// arguments share one window of kLogWindowOctaves octaves; appends each
+// item's end (exclusive) and first octave.
+void cut_items(const float* d, size_t n, size_t spi, double R, double eps, int problem, std::vector<size_t>& ends,
+               std::vector<int>& first) {
+    constexpr double kRel = 1.0 / (1 << 20);  // covers the float rounding of d
+    size_t a = 0;
+    while (a < n) {
+        // the whole run of spi sources in one window (the common case)
+        const size_t b = std::min(n, a + spi);
+        const auto mm = std::minmax_element(d + a, d + b);
+        int lo, hi;
+        pair_octaves(*mm.first * (1.0 - kRel), *mm.second * (1.0 + kRel), R, eps, problem, lo, hi);
+        if (hi - lo < kLogWindowOctaves) {
+            ends.push_back(b);
+            first.push_back(lo);
+            a = b;
+            continue;
+        }
+        // else source by source
+        double dmin = d[a], dmax = d[a];
+        pair_octaves(dmin * (1.0 - kRel), dmax * (1.0 + kRel), R, eps, problem, lo, hi);
+        if (hi - lo >= kLogWindowOctaves) throw std::runtime_error("P2L source beyond one logarithm window");
+        size_t e = a + 1;
+        while (e < n && e - a < spi) {
+            if (d[e] < dmin || d[e] > dmax) {
+                const double nmin = std::min(dmin, (double)d[e]), nmax = std::max(dmax, (double)d[e]);
+                int l, h;
+                pair_octaves(nmin * (1.0 - kRel), nmax * (1.0 + kRel), R, eps, problem, l, h);
+                if (h - l >= kLogWindowOctaves) break;
+                dmin = nmin;
+                dmax = nmax;
+                lo = l;
+            }
+            ++e;
+        }
+        ends.push_back(e);
+        first.push_back(lo);
+        a = e;
+    }
+}
+
 }  // namespace
+
+void pair_octaves(double dlo, double dhi, double R, double eps, int problem, int& elo, int& ehi) {
+    // every pair's arclength lies in [dlo - R - eps, dhi + R + eps]; the
+    // kernel's x carries rounding far below the 2^-20 margin
+    const double tlo = std::max(dlo - R - eps, 0.0), thi = std::min(kPi, dhi + R + eps);
+    const double ulo = std::sin(0.5 * tlo), uhi = std::sin(0.5 * thi);
+    const double xlo = problem == 0 ? ulo * ulo + ulo : 1.0 + 1.0 / uhi;
+    const double xhi = problem == 0 ? uhi * uhi + uhi : 1.0 + 1.0 / ulo;
+    if (!(xlo > 0.0) || !std::isfinite(xhi)) throw std::runtime_error("P2L pair at zero distance");
+    int e;
+    std::frexp(xlo * (1.0 - std::ldexp(1.0, -20)), &e);
+    elo = e - 1;
+    std::frexp(xhi * (1.0 + std::ldexp(1.0, -20)), &e);
+    ehi = e - 1;
+}
 
 void grid_size(double rho, double tol, int& nr, int& nt) {
     // Fourier modes of a point source at distance rho R decay like rho^-k on the
@@ -186,6 +244,10 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     const double* F = frames.data();
     // grid staging
     std::vector<std::vector<int>> grid_src;
+    // the grid's P2L items: ends in its source list and logarithm windows
+    std::vector<std::vector<size_t>> grid_ends;
+    std::vector<std::vector<int>> grid_win;
+    std::vector<float> okd;   // arclengths of a box's grid sources from its cap centre
 
     // sources handed down from a parent whose cap was too close to them
     std::vector<std::vector<int>> deferred(lev[0].size()), deferred_next;
@@ -250,12 +312,14 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             // sources valid for a grid: the whole cap must lie in the source's
             // far-field region (arclength > 2 eps) and be well separated
             std::vector<int> ok, bad;
+            okd.clear();
             double rho = 1e300, dmin = 1e300;
             for (int j : src) {
                 const double d = geodesic(best, &F[(size_t)j * 9]);
                 const double ratio = (d - eps) / R;
                 if (d - R > 2.0 * eps * (1.0 + 1e-9) && ratio >= rho_min) {
                     ok.push_back(j);
+                    okd.push_back((float)d);
                     rho = std::min(rho, ratio);
                     dmin = std::min(dmin, d - R);
                 } else {
@@ -307,6 +371,15 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
                 out.g_nt.push_back(nt);
                 out.g_level.push_back(l);
                 out.g_table.push_back(table);
+                // items of at least kSrcPerItem sources, more where the grid
+                // and its outgoing table are small, so that every item carries
+                // about kItemPairs pair evaluations or more; cut further where
+                // the sources' logarithm arguments leave one window
+                const size_t qg = (size_t)nr * nt;
+                const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + qg * pt - 1) / (qg * pt));
+                grid_ends.emplace_back();
+                grid_win.emplace_back();
+                cut_items(okd.data(), ok.size(), spi, R, eps, tab.problem, grid_ends.back(), grid_win.back());
                 grid_src.push_back(std::move(ok));
                 for (int64_t q = m0; q < m0 + mc; ++q) l2t[sorted[q]].push_back(gid);
             }
@@ -335,15 +408,13 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         out.g_item0[g] = (int)out.it_grid.size();
         const std::vector<int>& s = grid_src[g];
         const int pg = out.g_table[g] == 0 ? p : tab.far[out.g_table[g] - 1].p;
-        // at least kSrcPerItem sources per item, more where the grid and its
-        // outgoing table are small, so that every item carries about
-        // kItemPairs pair evaluations or more
-        const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + (size_t)q * pg - 1) / ((size_t)q * pg));
-        for (size_t a = 0; a < s.size(); a += spi) {
-            const size_t e = std::min(s.size(), a + spi);
+        const std::vector<size_t>& ends = grid_ends[g];
+        const std::vector<int>& win = grid_win[g];
+        for (size_t k = 0, a = 0; k < ends.size(); a = ends[k], ++k) {
             out.it_grid.push_back(g);
             out.it_src0.push_back((int)(out.p2l_src.size() + a));
-            out.it_src1.push_back((int)(out.p2l_src.size() + e));
+            out.it_src1.push_back((int)(out.p2l_src.size() + ends[k]));
+            out.it_win.push_back(win[k]);
             out.it_off.push_back(poff);
             poff += q;
         }
@@ -370,8 +441,9 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     }
 }
 
-void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar) {
-    std::vector<int> it_grid, it_src0, it_src1, it_type, p2l_src;
+void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar, const std::vector<double>& frames, double eps,
+                         int problem) {
+    std::vector<int> it_grid, it_src0, it_src1, it_type, it_win, p2l_src;
     std::vector<int64_t> it_off;
     int64_t poff = 0;
     t.pairs_far = 0;
@@ -389,12 +461,17 @@ void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar) {
             while (e < src.size() && tl.ptype[src[e]] == ty) ++e;
             const int pg = tl.t_p[ty * tl.ntab + t.g_table[g]];
             const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + (size_t)q * pg - 1) / ((size_t)q * pg));
-            for (size_t b = a; b < e; b += spi) {
-                const size_t f = std::min(e, b + spi);
+            std::vector<size_t> ends;
+            std::vector<int> win;
+            std::vector<float> d(e - a);
+            for (size_t b = a; b < e; ++b) d[b - a] = (float)geodesic(&t.g_frame[(size_t)9 * g], &frames[(size_t)src[b] * 9]);
+            cut_items(d.data(), e - a, spi, t.g_R[g], eps, problem, ends, win);
+            for (size_t k = 0, b = a; k < ends.size(); b = a + ends[k], ++k) {
                 it_grid.push_back(g);
                 it_src0.push_back((int)(p2l_src.size() + b));
-                it_src1.push_back((int)(p2l_src.size() + f));
+                it_src1.push_back((int)(p2l_src.size() + a + ends[k]));
                 it_type.push_back(ty);
+                it_win.push_back(win[k]);
                 it_off.push_back(poff);
                 poff += q;
             }
@@ -408,6 +485,7 @@ void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar) {
     t.it_src0.swap(it_src0);
     t.it_src1.swap(it_src1);
     t.it_type.swap(it_type);
+    t.it_win.swap(it_win);
     t.it_off.swap(it_off);
     t.p2l_src.swap(p2l_src);
     t.total_partial = poff;
@@ -448,6 +526,7 @@ void append_tree(Tree& dst, const Tree& src, int64_t first) {
         dst.it_src1.push_back(s0 + src.it_src1[it]);
         dst.it_off.push_back(p0 + src.it_off[it]);
     }
+    dst.it_win.insert(dst.it_win.end(), src.it_win.begin(), src.it_win.end());
     for (int j : src.p2l_src) dst.p2l_src.push_back((int)(first + j));
     dst.it_cfg.insert(dst.it_cfg.end(), src.it_grid.size(), dst.ncfg);
     dst.g_cfg.insert(dst.g_cfg.end(), (size_t)src.ngrid, dst.ncfg);

@@ -33,6 +33,7 @@ constexpr int kMaxGridNr = 16;
 constexpr int kMaxGridNt = 256;
 constexpr int kSrcPerItem = 32;   // source patches per P2L work item (at least)
 constexpr size_t kItemPairs = size_t(1) << 18;  // pair evaluations per P2L work item (at least)
+constexpr int kLogWindowOctaves = 8;  // binary octaves of the FP64 pair logarithm's argument per P2L item
 
 struct Tree {
     int nlevels = 0;
@@ -50,6 +51,10 @@ struct Tree {
     std::vector<int> it_grid, it_src0, it_src1;
     std::vector<int64_t> it_off;          // offset of the item's partial sums
     std::vector<int> p2l_src;
+    // per item: the first of the kLogWindowOctaves binary octaves that hold the
+    // FP64 pair logarithm's argument x of every pair of the item (x in
+    // [2^it_win, 2^(it_win + kLogWindowOctaves)), bounded from the geometry)
+    std::vector<int> it_win;
     int64_t total_partial = 0;
     // direct lists (near field plus far sources summed directly), CSR over targets
     std::vector<int64_t> dl_ptr;
@@ -89,8 +94,17 @@ struct TypeLayout {
 // After build_tree on a layout of several radii (built with the largest radius
 // and a common ladder of outgoing-table distances): splits every P2L item so
 // that its sources share one type (it_type), and recounts the work with each
-// source's own skeleton sizes.
-void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar);
+// source's own skeleton sizes. frames, eps (the largest radius) and problem as
+// for build_tree.
+void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar, const std::vector<double>& frames, double eps,
+                         int problem);
+
+// The binary octaves [elo, ehi] of the FP64 pair logarithm's argument (x =
+// u^2 + u interior, 1 + 1/u exterior, u half the chord) between the points of
+// a grid (within arclength R of its cap centre) and the skeletons of patches
+// (within eps of their centres, at arclengths in [dlo, dhi] from the cap
+// centre).
+void pair_octaves(double dlo, double dhi, double R, double eps, int problem, int& elo, int& ehi);
 
 // A forest: several independent configurations in one patch numbering, each
 // contributing its own tree or all-pairs direct lists; the far-field kernels

@@ -81,6 +81,10 @@ int main(int argc, char** argv) {
             if (cnt[j] != want) { std::printf("FAIL pair (%ld,%ld) counted %d times\n", i, j, cnt[j]); return 1; }
         }
     }
+    if (forest.it_win.size() != forest.it_grid.size()) {
+        std::printf("FAIL the forest's items lost their logarithm windows\n");
+        return 1;
+    }
     std::printf("OK configurations %d patches %ld grids %d items %zu far %.4g near %.4g\n", B, NT, forest.ngrid,
                 forest.it_grid.size(), forest.pairs_far, forest.pairs_near);
     return 0;

@@ -7,12 +7,30 @@
 #include <cmath>
 #include <cstdio>
 #include <random>
+#include <vector>
 
 #include "greens.hpp"
+
+// The window of octaves e0 .. e0 + kWinOct - 1 as the far-field kernel loads it
+// from the table of octaves e_first .. (slot s of the window: octave
+// window_octave(e0, s)).
+static void load_window(const std::vector<nce::LogEntry>& all, int e_first, int e0, nce::LogEntry* win) {
+    for (int k = 0; k < nce::kWinTab; ++k) {
+        const int e = nce::window_octave(e0, k >> nce::kWinBinBits);
+        win[k] = all[(size_t)(e - e_first) * nce::kWinBins + (k & (nce::kWinBins - 1))];
+    }
+}
 
 int main() {
     static nce::LogEntry tab[nce::kLogTab];
     nce::build_log_table(tab);
+    // octaves -60 .. 60 of the windowed table
+    const int e_first = -60, noct = 121;
+    std::vector<nce::LogEntry> wall((size_t)noct * nce::kWinBins);
+    nce::build_log_window_table(e_first, noct, wall.data());
+    static nce::LogEntry win[nce::kWinTab];
+    double worst_win = 0;
+    int bad_slot = 0;
     std::mt19937_64 g(7);
     std::uniform_real_distribution<double> U(0.0, 1.0);
     double worst_log = 0, worst_gi = 0, worst_ge = 0, worst_si = 0, worst_se = 0, worst_grid = 0, worst_rsq = 0;
@@ -45,6 +63,24 @@ int main() {
             const long double ref = prob ? ge : gi;
             worst_grid = std::max(worst_grid, (double)(std::fabs(vg - ref) / std::max(std::fabs(ref), 1.0L)));
         }
+        // the windowed grid form: a window holding x's octave at a random slot
+        // (every slot is hit), absolute error of G against 2^-44
+        for (int prob = 0; prob < 2; ++prob) {
+            const double hh = 0.25 * d * d, w = 1.0 / std::sqrt(hh);
+            const double x = prob ? 1.0 + w : std::fma(hh * w, hh * w, hh * w);
+            int ex;
+            std::frexp(x, &ex);   // x in [2^(ex-1), 2^ex)
+            const int e0 = (ex - 1) - (int)(U(g) * nce::kWinOct);
+            load_window(wall, e_first, e0, win);
+            // the slot the index picks holds x's own octave
+            unsigned long long bits;
+            std::memcpy(&bits, &x, sizeof bits);
+            const int slot = (int)((bits >> 52) & (nce::kWinOct - 1));
+            if (nce::window_octave(e0, slot) != ex - 1) ++bad_slot;
+            const double vg = prob ? nce::green64_grid_win<1>(hh, win) : nce::green64_grid_win<0>(hh, win);
+            const long double ref = prob ? ge : gi;
+            worst_win = std::max(worst_win, (double)(std::fabs(vg - ref) / std::max(std::fabs(ref), 1.0L)));
+        }
         // first-order correction of an estimate at the largest error measured
         // for the gfx950 FP64 rsq (2^-24.2), either sign: about 1.5 d^2
         const double h2 = 0.25 * d * d;
@@ -59,8 +95,11 @@ int main() {
                 worst_gi, worst_ge, worst_si, worst_se);
     std::printf("grid form: G within %.3e (abs, or rel above 1); first-order rsq correction within %.3e\n", worst_grid,
                 worst_rsq);
+    std::printf("windowed grid form: G within %.3e; windows whose indexed slot missed x's octave: %d\n", worst_win,
+                bad_slot);
     return (worst_log < 4 && worst_gi < 6 && worst_ge < 6 && worst_si < 8 && worst_se < 8 &&
-            worst_grid < std::ldexp(1.0, -44) && worst_rsq < 5e-15)
+            worst_grid < std::ldexp(1.0, -44) && worst_rsq < 5e-15 && worst_win < std::ldexp(1.0, -44) &&
+            bad_slot == 0)
                ? 0
                : 1;
 }

@@ -3,13 +3,90 @@
 // verifies that every ordered pair of distinct patches is accounted for exactly
 // once (direct list or one interpolated grid whose P2L sources contain it),
 // that no patch sees itself, and that every grid lies in the far-field region
-// of each of its sources. Prints "OK <stats>" or the first violation.
+// of each of its sources, and that every P2L item's logarithm window holds the
+// argument x of the item's pairs (x = u^2 + u interior, 1 + 1/u exterior, u
+// half the chord) at the extreme configurations (grid point and skeleton point
+// on the great circle through the two centres, nearest and farthest) and at
+// random points of the cap and of the patch, for both problems. Prints
+// "OK <stats>" or the first violation.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <random>
 #include <vector>
 
 #include "tree_build.hpp"
+
+// the point at arclength r from unit vector c towards unit vector t (t not +-c)
+static void toward(const double* c, const double* t, double r, double* out) {
+    double d = c[0] * t[0] + c[1] * t[1] + c[2] * t[2];
+    double e[3] = {t[0] - d * c[0], t[1] - d * c[1], t[2] - d * c[2]};
+    const double n = std::sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    for (int k = 0; k < 3; ++k) out[k] = std::cos(r) * c[k] + std::sin(r) * e[k] / n;
+}
+
+// the point at arclength r from c in direction phi of the frame f (c, e1, e2)
+static void around(const double* f, double r, double phi, double* out) {
+    for (int k = 0; k < 3; ++k)
+        out[k] = std::cos(r) * f[k] + std::sin(r) * (std::cos(phi) * f[3 + k] + std::sin(phi) * f[6 + k]);
+}
+
+static int octave_of(const double* p, const double* q, int problem) {
+    const double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+    const double u = 0.5 * std::sqrt(dx * dx + dy * dy + dz * dz);
+    const double x = problem == 0 ? u * u + u : 1.0 + 1.0 / u;
+    int e;
+    std::frexp(x, &e);
+    return e - 1;
+}
+
+// frame (c, e1, e2) of a unit vector
+static void frame9(const double* c, double* f) {
+    double a[3] = {0, 0, 1};
+    if (std::fabs(c[2]) > 0.7) { a[0] = 1; a[2] = 0; }
+    const double d = a[0] * c[0] + a[1] * c[1] + a[2] * c[2];
+    double e1[3] = {a[0] - d * c[0], a[1] - d * c[1], a[2] - d * c[2]};
+    const double n = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]);
+    for (double& v : e1) v /= n;
+    const double e2[3] = {c[1] * e1[2] - c[2] * e1[1], c[2] * e1[0] - c[0] * e1[2], c[0] * e1[1] - c[1] * e1[0]};
+    for (int k = 0; k < 3; ++k) { f[k] = c[k]; f[3 + k] = e1[k]; f[6 + k] = e2[k]; }
+}
+
+// every item's window against its pairs; returns false at the first miss
+static bool check_windows(const nce::Tree& t, const std::vector<double>& fr, double eps, int problem) {
+    if (t.it_win.size() != t.it_grid.size()) { std::printf("FAIL items without windows\n"); return false; }
+    std::mt19937_64 g(11);
+    std::uniform_real_distribution<double> U(0.0, 1.0);
+    for (size_t it = 0; it < t.it_grid.size(); ++it) {
+        const int gi = t.it_grid[it], w0 = t.it_win[it];
+        const double* gc = &t.g_frame[9 * gi];
+        const double R = t.g_R[gi];
+        for (int s = t.it_src0[it]; s < t.it_src1[it]; ++s) {
+            const double* cj = &fr[9 * t.p2l_src[s]];
+            double fj[9], p[3], q[3];
+            frame9(cj, fj);
+            int oct[6];
+            toward(gc, cj, R, p);      // nearest pair
+            toward(cj, gc, eps, q);
+            oct[0] = octave_of(p, q, problem);
+            toward(gc, cj, -R, p);     // farthest pair
+            toward(cj, gc, -eps, q);
+            oct[1] = octave_of(p, q, problem);
+            for (int r = 2; r < 6; ++r) {
+                around(&t.g_frame[9 * gi], R * std::sqrt(U(g)), 2 * M_PI * U(g), p);
+                around(fj, eps * std::sqrt(U(g)), 2 * M_PI * U(g), q);
+                oct[r] = octave_of(p, q, problem);
+            }
+            for (int o : oct)
+                if (o < w0 || o >= w0 + nce::kLogWindowOctaves) {
+                    std::printf("FAIL problem %d item %zu source %d: octave %d outside window %d..%d\n", problem, it,
+                                t.p2l_src[s], o, w0, w0 + nce::kLogWindowOctaves - 1);
+                    return false;
+                }
+        }
+    }
+    return true;
+}
 
 int main(int argc, char** argv) {
     if (argc < 4) return 2;
@@ -57,6 +134,13 @@ int main(int argc, char** argv) {
             double d = std::atan2(std::sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2), c[0] * gc[0] + c[1] * gc[1] + c[2] * gc[2]);
             if (d - t.g_R[g] <= 2 * eps) { std::printf("FAIL grid %d not in far field of %d\n", g, j); return 1; }
         }
+    for (int problem = 0; problem < 2; ++problem) {
+        nce::PatchTables tp = tab;
+        tp.problem = problem;
+        nce::Tree tw;
+        nce::build_tree(fr, N, eps, tp, tol, tw);
+        if (!check_windows(tw, fr, eps, problem)) return 1;
+    }
     long maxdl = 0;
     for (long i = 0; i < N; ++i) maxdl = std::max(maxdl, (long)(t.dl_ptr[i + 1] - t.dl_ptr[i]));
     std::printf("OK levels %d grids %d items %zu far %.4g near %.4g interp %.4g maxq %d maxdl %ld\n", t.nlevels,
