@@ -188,6 +188,55 @@ constexpr int kStagePad = 64;  // >= the largest ns
 // far more than the reciprocal's error
 __device__ __forceinline__ int div_small(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
+// An item's sources by outgoing table (the tree sorts a grid's sources by
+// table, so they form at most kMaxTableRuns runs): run k stages the points
+// [pt0[k], pt0[k + 1]) of the item, sources src[s0[k] ..] with skeleton size
+// p[k], first skeleton offset toff[k] and strength column col[k].
+struct StageRuns {
+    int n;
+    int pt0[kMaxTableRuns + 1];
+    int s0[kMaxTableRuns], p[kMaxTableRuns], toff[kMaxTableRuns], col[kMaxTableRuns];
+    float inv[kMaxTableRuns];
+};
+
+// Fills sr for `item` (tb0: the first table index of the item's source type);
+// every thread of the block calls it. Returns the item's staged point count.
+__device__ __forceinline__ int load_runs(StageRuns& sr, const TabRuns& tr, int item, int src_end, int tb0,
+                                         const int* __restrict__ t_off, const int* __restrict__ t_col,
+                                         const int* __restrict__ t_p) {
+    const int r0 = tr.it_run0[item], nr = tr.it_run0[item + 1] - r0;
+    const int k = threadIdx.x;
+    if (k < nr) {
+        const int s = tr.run_src[r0 + k], e = k + 1 < nr ? tr.run_src[r0 + k + 1] : src_end;
+        const int tb = tb0 + tr.run_tab[r0 + k], pk = t_p[tb];
+        sr.s0[k] = s;
+        sr.p[k] = pk;
+        sr.toff[k] = t_off[tb];
+        sr.col[k] = t_col ? t_col[tb] : t_off[tb];
+        sr.inv[k] = __builtin_amdgcn_rcpf((float)pk);
+        sr.pt0[k + 1] = (e - s) * pk;   // the run's points, summed below
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sr.n = nr;
+        sr.pt0[0] = 0;
+        for (int j = 1; j <= nr; ++j) sr.pt0[j] += sr.pt0[j - 1];
+    }
+    __syncthreads();
+    return sr.pt0[nr];
+}
+
+// Staged point e of the item: its source's place in the source list, its
+// skeleton point's offset index and its strength column.
+__device__ __forceinline__ void run_point(const StageRuns& sr, int e, int& sidx, int& oidx, int& cidx) {
+    int k = 0;
+    while (k + 1 < sr.n && e >= sr.pt0[k + 1]) ++k;
+    const int el = e - sr.pt0[k], js = div_small(el, sr.inv[k]), m = el - js * sr.p[k];
+    sidx = sr.s0[k] + js;
+    oidx = sr.toff[k] + m;
+    cidx = sr.col[k] + m;
+}
+
 template <int R>
 __device__ __forceinline__ void p2l_layout(int q, int& qq, int& ns, int& split, int& t0) {
     qq = (q + R - 1) / R;
@@ -203,7 +252,7 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
                                                const double* __restrict__ g_T, const int* __restrict__ g_nr,
-                                               const int* __restrict__ g_nt, const int* __restrict__ g_table,
+                                               const int* __restrict__ g_nt, TabRuns tr,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const double* __restrict__ skel_off,
                                                const double* __restrict__ rho, int ptot, double* __restrict__ part,
@@ -237,8 +286,8 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     // outgoing table: the grid's, of the item's source type with several radii
-    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
-    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    __shared__ StageRuns sruns;
+    const int total = load_runs(sruns, tr, item, it_src1[item], it_type ? it_type[item] * ntab : 0, t_off, t_col, t_p);
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -258,23 +307,21 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
         }
         z2[r] = zx[r] * zx[r] + zy[r] * zy[r] + zz[r] * zz[r];
     }
-    const int s0 = it_src0[item];
-    const int total = (it_src1[item] - s0) * pt;
-    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStage64) {
         const int cl = min(kStage64, total - c0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
             double ax = 8.0, ay = 8.0, az = 8.0, w = 0.0;  // padding: far away, zero strength
             if (idx < cl) {
-                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
-                const int j = src[s0 + js];
+                int sidx, oidx, cidx;
+                run_point(sruns, c0 + idx, sidx, oidx, cidx);
+                const int j = src[sidx];
                 const double* fj = frames + 9 * (int64_t)j;
-                const double* o = skel_off + 3 * (int64_t)(toff + m);
+                const double* o = skel_off + 3 * (int64_t)oidx;
                 ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
                 ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
                 az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
-                w = rho[(int64_t)j * ptot + col + m];
+                w = rho[(int64_t)j * ptot + cidx];
             }
             // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a: grid points lie within the cap
             // and sources at least a cap radius beyond it, so the cancellation
@@ -320,7 +367,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 4 ? 7 
                                                const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                const int* __restrict__ src, const double* __restrict__ g_frame,
                                                const double* __restrict__ g_T, const int* __restrict__ g_nr,
-                                               const int* __restrict__ g_nt, const int* __restrict__ g_table,
+                                               const int* __restrict__ g_nt, TabRuns tr,
                                                const int* __restrict__ t_off, const int* __restrict__ t_p,
                                                const double* __restrict__ frames, const float* __restrict__ skel_off,
                                                const float* __restrict__ rho, int ptot, float* __restrict__ part,
@@ -342,8 +389,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 4 ? 7 
     const int g = it_grid[item];
     const int nr = g_nr[g], nt = g_nt[g], q = nr * nt;
     // outgoing table: the grid's, of the item's source type with several radii
-    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
-    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    __shared__ StageRuns sruns;
+    const int total = load_runs(sruns, tr, item, it_src1[item], it_type ? it_type[item] * ntab : 0, t_off, t_col, t_p);
     const double* fg = g_frame + 9 * (int64_t)g;
     int qq, ns, split, t0;
     p2l_layout<R>(q, qq, ns, split, t0);
@@ -365,23 +412,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == 4 ? 7 
         z2[r] = zx[r] * zx[r] + zy[r] * zy[r] + zz[r] * zz[r];
     }
     constexpr float kLn2 = 0.69314718055994530942f;
-    const int s0 = it_src0[item];
-    const int total = (it_src1[item] - s0) * pt;
-    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStage) {
         const int cl = min(kStage, total - c0);
         __syncthreads();
         for (int idx = threadIdx.x; idx < cl + ns; idx += blockDim.x) {
             float ax = 8.0f, ay = 8.0f, az = 8.0f, w = 0.0f;  // padding: far away, zero strength
             if (idx < cl) {
-                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
-                const int j = src[s0 + js];
+                int sidx, oidx, cidx;
+                run_point(sruns, c0 + idx, sidx, oidx, cidx);
+                const int j = src[sidx];
                 const double* fj = frames + 9 * (int64_t)j;
-                const float* o = skel_off + 3 * (int64_t)(toff + m);
+                const float* o = skel_off + 3 * (int64_t)oidx;
                 ax = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
                 ay = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
                 az = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
-                w = rho[(int64_t)j * ptot + col + m];
+                w = rho[(int64_t)j * ptot + cidx];
             }
             // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a (cancellation at most a factor 5,
             // as in the FP64 kernel)
@@ -450,7 +495,7 @@ __global__ __launch_bounds__(256) void k_p2l64_mfma(const int* __restrict__ it_g
                                                     const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                     const int* __restrict__ src, const double* __restrict__ g_frame,
                                                     const int* __restrict__ g_nr, const int* __restrict__ g_nt,
-                                                    const int* __restrict__ g_table, const int* __restrict__ t_off,
+                                                    TabRuns tr, const int* __restrict__ t_off,
                                                     const int* __restrict__ t_p, const double* __restrict__ frames,
                                                     const double* __restrict__ skel_off, const double* __restrict__ rho,
                                                     int ptot, double* __restrict__ part,
@@ -468,16 +513,13 @@ __global__ __launch_bounds__(256) void k_p2l64_mfma(const int* __restrict__ it_g
     for (int k = threadIdx.x; k < kLogTab; k += blockDim.x) ltab[k] = logtab[k];
     const int g = it_grid[item];
     const int q = g_nr[g] * g_nt[g];
-    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
-    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    __shared__ StageRuns sruns;
+    const int total = load_runs(sruns, tr, item, it_src1[item], it_type ? it_type[item] * ntab : 0, t_off, t_col, t_p);
     const double* fg = g_frame + 9 * (int64_t)g;
     const double* zg = gpt + 3 * g_off[g];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, kq = lane >> 4;
     const int nrt = (q + 15) >> 4;
     for (int t = threadIdx.x; t < q; t += blockDim.x) red[t] = 0.0;
-    const int s0 = it_src0[item];
-    const int total = (it_src1[item] - s0) * pt;
-    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStageM) {
         const int cl = min(kStageM, total - c0);
         const int cl16 = (cl + 15) & ~15;
@@ -485,14 +527,15 @@ __global__ __launch_bounds__(256) void k_p2l64_mfma(const int* __restrict__ it_g
         for (int idx = threadIdx.x; idx < cl16; idx += blockDim.x) {
             double ax = 8.0, ay = 8.0, az = 8.0, w = 0.0;  // padding: far away, zero strength
             if (idx < cl) {
-                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
-                const int j = src[s0 + js];
+                int sidx, oidx, cidx;
+                run_point(sruns, c0 + idx, sidx, oidx, cidx);
+                const int j = src[sidx];
                 const double* fj = frames + 9 * (int64_t)j;
-                const double* o = skel_off + 3 * (int64_t)(toff + m);
+                const double* o = skel_off + 3 * (int64_t)oidx;
                 ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
                 ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
                 az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
-                w = rho[(int64_t)j * ptot + col + m];
+                w = rho[(int64_t)j * ptot + cidx];
             }
             smem4[idx] = make_double4(-2.0 * ax, -2.0 * ay, -2.0 * az, ax * ax + ay * ay + az * az);
             srho[idx] = w;
@@ -555,7 +598,7 @@ __global__ __launch_bounds__(256) void k_p2l32_mfma(const int* __restrict__ it_g
                                                     const int* __restrict__ it_src1, const int64_t* __restrict__ it_off,
                                                     const int* __restrict__ src, const double* __restrict__ g_frame,
                                                     const int* __restrict__ g_nr, const int* __restrict__ g_nt,
-                                                    const int* __restrict__ g_table, const int* __restrict__ t_off,
+                                                    TabRuns tr, const int* __restrict__ t_off,
                                                     const int* __restrict__ t_p, const double* __restrict__ frames,
                                                     const float* __restrict__ skel_off, const float* __restrict__ rho,
                                                     int ptot, float* __restrict__ part,
@@ -570,17 +613,14 @@ __global__ __launch_bounds__(256) void k_p2l32_mfma(const int* __restrict__ it_g
     if (live && !live[it_cfg[item]]) return;
     const int g = it_grid[item];
     const int q = g_nr[g] * g_nt[g];
-    const int tb = it_type ? it_type[item] * ntab + g_table[g] : g_table[g];
-    const int toff = t_off[tb], col = t_col ? t_col[tb] : toff, pt = t_p[tb];
+    __shared__ StageRuns sruns;
+    const int total = load_runs(sruns, tr, item, it_src1[item], it_type ? it_type[item] * ntab : 0, t_off, t_col, t_p);
     const double* fg = g_frame + 9 * (int64_t)g;
     const float* zg = gpt + 3 * g_off[g];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, c = lane & 15, kq = lane >> 4;
     const int nrt = (q + 15) >> 4;
     for (int t = threadIdx.x; t < q; t += blockDim.x) red[t] = 0.0;
     constexpr float kLn2 = 0.69314718055994530942f;
-    const int s0 = it_src0[item];
-    const int total = (it_src1[item] - s0) * pt;
-    const float inv_pt = __builtin_amdgcn_rcpf((float)pt);
     for (int c0 = 0; c0 < total; c0 += kStage) {
         const int cl = min(kStage, total - c0);
         const int cl16 = (cl + 15) & ~15;
@@ -588,14 +628,15 @@ __global__ __launch_bounds__(256) void k_p2l32_mfma(const int* __restrict__ it_g
         for (int idx = threadIdx.x; idx < cl16; idx += blockDim.x) {
             float ax = 8.0f, ay = 8.0f, az = 8.0f, w = 0.0f;
             if (idx < cl) {
-                const int e = c0 + idx, js = div_small(e, inv_pt), m = e - js * pt;
-                const int j = src[s0 + js];
+                int sidx, oidx, cidx;
+                run_point(sruns, c0 + idx, sidx, oidx, cidx);
+                const int j = src[sidx];
                 const double* fj = frames + 9 * (int64_t)j;
-                const float* o = skel_off + 3 * (int64_t)(toff + m);
+                const float* o = skel_off + 3 * (int64_t)oidx;
                 ax = 0.5f * ((float)(fj[0] - fg[0]) + (o[0] * (float)fj[0] + o[1] * (float)fj[3] + o[2] * (float)fj[6]));
                 ay = 0.5f * ((float)(fj[1] - fg[1]) + (o[0] * (float)fj[1] + o[1] * (float)fj[4] + o[2] * (float)fj[7]));
                 az = 0.5f * ((float)(fj[2] - fg[2]) + (o[0] * (float)fj[2] + o[1] * (float)fj[5] + o[2] * (float)fj[8]));
-                w = rho[(int64_t)j * ptot + col + m];
+                w = rho[(int64_t)j * ptot + cidx];
             }
             smem4[idx] = make_float4(-2.0f * ax, -2.0f * ay, -2.0f * az, ax * ax + ay * ay + az * az);
             srho[idx] = w;
@@ -1079,6 +1120,24 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
         d.logwin = dev_copy(wt);
         d.it_win = dev_copy(t.it_win);
     }
+    {
+        // runs of one outgoing table in every item's sources
+        if (t.p2l_tab.size() != t.p2l_src.size()) throw std::runtime_error("P2L sources without outgoing tables");
+        std::vector<int> r0(t.it_grid.size() + 1, 0), rs, rt;
+        for (size_t it = 0; it < t.it_grid.size(); ++it) {
+            r0[it] = (int)rs.size();
+            for (int q = t.it_src0[it]; q < t.it_src1[it]; ++q)
+                if (q == t.it_src0[it] || t.p2l_tab[q] != t.p2l_tab[q - 1]) {
+                    rs.push_back(q);
+                    rt.push_back(t.p2l_tab[q]);
+                }
+            if ((int)rs.size() - r0[it] > kMaxTableRuns) throw std::runtime_error("P2L item with too many table runs");
+        }
+        r0.back() = (int)rs.size();
+        d.it_run0 = dev_copy(r0);
+        d.run_src = dev_copy(rs);
+        d.run_tab = dev_copy(rt);
+    }
     d.gpt64 = dev_alloc<double>(3 * t.total_q);
     d.gpt32 = dev_alloc<float>(3 * t.total_q);
     if (d.ngrid > 0) {
@@ -1094,7 +1153,7 @@ void free_tree(DeviceTree& d) {
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.it_solo, d.coef64,  d.part64, d.g_multi,  d.coef32, d.part32, d.ttab, d.g_ttab,
                     d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
-                    d.it_type, d.t_col, d.ptype, d.it_win, d.logwin};
+                    d.it_type, d.t_col, d.ptype, d.it_win, d.logwin, d.it_run0, d.run_src, d.run_tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -1106,12 +1165,12 @@ void launch_p2l(hipStream_t s, const DeviceTree& d, const double* frames, const 
     if (nblocks <= 0) return;
     if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((k_p2l64<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, TabRuns{d.it_run0, d.run_src, d.run_tab}, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
                            it_list, d.it_win, d.logwin, d.win_first, d.it_solo, d.coef64, d.ttab, d.g_ttab);
     else
         hipLaunchKernelGGL((k_p2l32<PROB, R>), dim3(nblocks), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_T, d.g_nr, d.g_nt, TabRuns{d.it_run0, d.run_src, d.run_tab}, d.t_off, d.t_p, frames,
                            skel_off, rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
                            it_list, d.it_solo, d.coef32, d.ttab, d.g_ttab);
 }
@@ -1121,12 +1180,12 @@ void launch_p2l_mfma(hipStream_t s, const DeviceTree& d, const double* frames, c
                      const int* live) {
     if constexpr (sizeof(T) == 8)
         hipLaunchKernelGGL((k_p2l64_mfma<PROB>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames, skel_off,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, TabRuns{d.it_run0, d.run_src, d.run_tab}, d.t_off, d.t_p, frames, skel_off,
                            rho, d.ptot, d.part64, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt64,
                            (const int*)nullptr, d.logtab);
     else
         hipLaunchKernelGGL((k_p2l32_mfma<PROB>), dim3(d.nitems), dim3(256), 0, s, d.it_grid, d.it_src0, d.it_src1,
-                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, d.g_table, d.t_off, d.t_p, frames, skel_off,
+                           d.it_off, d.p2l_src, d.g_frame, d.g_nr, d.g_nt, TabRuns{d.it_run0, d.run_src, d.run_tab}, d.t_off, d.t_p, frames, skel_off,
                            rho, d.ptot, d.part32, d.it_type, d.t_col, d.ntab, d.it_cfg, live, d.g_off, d.gpt32,
                            (const int*)nullptr);
 }

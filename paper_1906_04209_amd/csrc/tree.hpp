@@ -9,6 +9,13 @@
 
 namespace nce {
 
+// The run arrays of a DeviceTree as the P2L kernels take them.
+struct TabRuns {
+    const int* it_run0;
+    const int* run_src;
+    const int* run_tab;
+};
+
 struct DeviceTree {
     int ngrid = 0, nitems = 0;
     int64_t N = 0;
@@ -51,6 +58,12 @@ struct DeviceTree {
     float* gpt32 = nullptr;
     // items whose grids keep more lanes busy with 4 (resp. 8) grid points per thread
     LogEntry* logtab = nullptr;  // FP64 logarithm table (kLogTab entries)
+    // P2L items' sources by outgoing table: item i's runs are [it_run0[i],
+    // it_run0[i + 1]); run r starts at source run_src[r] (a place in p2l_src)
+    // and uses table run_tab[r] (0 = base, k = far[k - 1])
+    int* it_run0 = nullptr;
+    int* run_src = nullptr;
+    int* run_tab = nullptr;
     // the FP64 P2L's logarithm windows: per item its first octave, and the
     // table of octaves win_first .. (kWinBins entries each) they draw from
     int* it_win = nullptr;

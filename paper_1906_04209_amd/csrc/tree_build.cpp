@@ -6,7 +6,7 @@
 #include <array>
 #include <cmath>
 #include <stdexcept>
-#include <unordered_map>
+#include <string>
 
 namespace nce {
 
@@ -44,17 +44,6 @@ void frame_of(const double* c, double* f9) {
     }
 }
 
-struct CornerHash {
-    size_t operator()(const std::array<int64_t, 3>& a) const {
-        uint64_t h = 1469598103934665603ull;
-        for (int64_t v : a) {
-            h ^= (uint64_t)v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
-            h *= 1099511628211ull;
-        }
-        return (size_t)h;
-    }
-};
-
 struct Box {
     int64_t first, count;  // members: sorted[first .. first+count)
     int face;
@@ -65,16 +54,31 @@ struct Box {
 };
 
 // Cuts a grid's run of n sources (their arclengths d from the cap centre, as
-// floats) into P2L items of at most spi sources each whose pairs' logarithm
-// arguments share one window of kLogWindowOctaves octaves; appends each
+// floats; their outgoing tables tb, sorted; skeleton sizes ps) into P2L items
+// for a grid of q points: each takes sources until it holds at least
+// kSrcPerItem of them and kItemPairs pairs, and ends earlier where its
+// tables would form more than kMaxTableRuns runs or its pairs' logarithm
+// arguments would leave one window of kLogWindowOctaves octaves. Appends each
 // item's end (exclusive) and first octave.
-void cut_items(const float* d, size_t n, size_t spi, double R, double eps, int problem, std::vector<size_t>& ends,
-               std::vector<int>& first) {
+void cut_items(const float* d, const int* tb, const int* ps, size_t n, double q, double R, double eps, int problem,
+               std::vector<size_t>& ends, std::vector<int>& first) {
     constexpr double kRel = 1.0 / (1 << 20);  // covers the float rounding of d
     size_t a = 0;
     while (a < n) {
-        // the whole run of spi sources in one window (the common case)
-        const size_t b = std::min(n, a + spi);
+        // the natural end
+        size_t b = a;
+        int runs = 0;
+        double pairs = 0.0;
+        while (b < n) {
+            if (b == a || tb[b] != tb[b - 1]) {
+                if (runs == kMaxTableRuns) break;
+                ++runs;
+            }
+            pairs += q * ps[b];
+            ++b;
+            if (b - a >= (size_t)kSrcPerItem && pairs >= (double)kItemPairs) break;
+        }
+        // in one logarithm window (the common case)?
         const auto mm = std::minmax_element(d + a, d + b);
         int lo, hi;
         pair_octaves(*mm.first * (1.0 - kRel), *mm.second * (1.0 + kRel), R, eps, problem, lo, hi);
@@ -84,12 +88,12 @@ void cut_items(const float* d, size_t n, size_t spi, double R, double eps, int p
             a = b;
             continue;
         }
-        // else source by source
+        // else the longest prefix that is
         double dmin = d[a], dmax = d[a];
         pair_octaves(dmin * (1.0 - kRel), dmax * (1.0 + kRel), R, eps, problem, lo, hi);
         if (hi - lo >= kLogWindowOctaves) throw std::runtime_error("P2L source beyond one logarithm window");
         size_t e = a + 1;
-        while (e < n && e - a < spi) {
+        while (e < b) {
             if (d[e] < dmin || d[e] > dmax) {
                 const double nmin = std::min(dmin, (double)d[e]), nmax = std::max(dmax, (double)d[e]);
                 int l, h;
@@ -106,6 +110,41 @@ void cut_items(const float* d, size_t n, size_t spi, double R, double eps, int p
         a = e;
     }
 }
+
+// The cheapest outgoing table valid for targets at arclength >= dm from the
+// patch centre: 0 = base (valid beyond 2 eps), k = far[k - 1] (beyond D_k);
+// among equally cheap ones the first. The valid ladder tables are a prefix
+// (the ladder's D increase); its length is first guessed from the ladder's
+// spacing D_k = D_1 2^((k-1)/2) by the binary exponent of dm / D_1, then
+// corrected against the stored D, so any increasing ladder is chosen exactly.
+struct TableChooser {
+    std::vector<double> D;
+    std::vector<int> best;   // best[c]: the cheapest of tables 0 .. c
+    explicit TableChooser(const PatchTables& tab) {
+        int b = 0, pb = tab.p;
+        best.push_back(0);
+        for (size_t k = 0; k < tab.far.size(); ++k) {
+            if (k > 0 && !(tab.far[k].D > tab.far[k - 1].D)) throw std::runtime_error("ladder distances not increasing");
+            D.push_back(tab.far[k].D);
+            if (tab.far[k].p < pb) {
+                b = (int)k + 1;
+                pb = tab.far[k].p;
+            }
+            best.push_back(b);
+        }
+    }
+    int operator()(double dm) const {
+        const int n = (int)D.size();
+        if (n == 0 || !(dm >= D[0])) return 0;
+        int e;
+        const double m = std::frexp(dm / D[0], &e);   // dm / D_1 = m 2^e, m in [1/2, 1)
+        int c = 2 * (e - 1) + (m >= 0.70710678118654752 ? 2 : 1);
+        c = std::max(1, std::min(c, n));
+        while (c < n && D[c] <= dm) ++c;
+        while (c > 1 && D[c - 1] > dm) --c;
+        return best[c];
+    }
+};
 
 }  // namespace
 
@@ -210,10 +249,10 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             lev[l].push_back(std::move(bx));
             s = e;
         }
-        // neighbours: boxes whose closed regions share a lattice corner on the cube
+        // neighbours: boxes whose closed regions share a lattice corner on the
+        // cube (the four corners of every box, sorted, so that equal corners
+        // are adjacent)
         const int64_t S = 1ll << l;
-        std::unordered_map<std::array<int64_t, 3>, std::vector<int>, CornerHash> corners;
-        corners.reserve(lev[l].size() * 4);
         auto corner = [&](const Box& bx, int di, int dj) {
             const int a = bx.face / 2;
             const int64_t sg = (bx.face % 2 == 0) ? 1 : -1;
@@ -224,15 +263,24 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             P[cc] = 2 * (bx.iy + dj) - S;
             return P;
         };
-        for (int bi = 0; bi < (int)lev[l].size(); ++bi)
+        const int nbx = (int)lev[l].size();
+        std::vector<std::pair<std::array<int64_t, 3>, int>> cr;
+        cr.reserve((size_t)4 * nbx);
+        for (int bi = 0; bi < nbx; ++bi)
             for (int di = 0; di < 2; ++di)
-                for (int dj = 0; dj < 2; ++dj) corners[corner(lev[l][bi], di, dj)].push_back(bi);
-        for (int bi = 0; bi < (int)lev[l].size(); ++bi) {
+                for (int dj = 0; dj < 2; ++dj) cr.emplace_back(corner(lev[l][bi], di, dj), bi);
+        std::sort(cr.begin(), cr.end());
+        for (size_t a = 0; a < cr.size();) {
+            size_t e = a + 1;
+            while (e < cr.size() && cr[e].first == cr[a].first) ++e;
+            for (size_t x = a; x < e; ++x)
+                for (size_t y = a; y < e; ++y)
+                    if (cr[x].second != cr[y].second) lev[l][cr[x].second].nbrs.push_back(cr[y].second);
+            a = e;
+        }
+#pragma omp parallel for schedule(static)
+        for (int bi = 0; bi < nbx; ++bi) {
             std::vector<int>& nb = lev[l][bi].nbrs;
-            for (int di = 0; di < 2; ++di)
-                for (int dj = 0; dj < 2; ++dj)
-                    for (int o : corners[corner(lev[l][bi], di, dj)])
-                        if (o != bi) nb.push_back(o);
             std::sort(nb.begin(), nb.end());
             nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
         }
@@ -243,146 +291,197 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     std::vector<std::vector<int>> l2t(N);
     const double* F = frames.data();
     // grid staging
-    std::vector<std::vector<int>> grid_src;
+    std::vector<std::vector<int>> grid_src, grid_tab;   // a grid's sources and their outgoing tables
     // the grid's P2L items: ends in its source list and logarithm windows
     std::vector<std::vector<size_t>> grid_ends;
     std::vector<std::vector<int>> grid_win;
-    std::vector<float> okd;   // arclengths of a box's grid sources from its cap centre
+    std::vector<int> ptab(1, p);   // skeleton size per table
+    for (const FarTable& ft : tab.far) ptab.push_back(ft.p);
+    const TableChooser cheapest_table(tab);
+
+    // One box's far-field work at level l: its interaction list and deferred
+    // sources, its bounding cap, which sources its grid takes (sorted by
+    // table and cut into items) and which go to its children or to its
+    // members' direct lists. Touches only the box's own deferred list, its
+    // children's next lists and its members' direct lists, so the boxes of a
+    // level run in parallel; the grids are numbered afterwards in box order.
+    struct BoxGrid {
+        bool use = false;
+        double f9[9];
+        double R = 0;
+        int nr = 0, nt = 0, table = 0;
+        std::vector<int> src, tab;
+        std::vector<size_t> ends;
+        std::vector<int> win;
+    };
+    auto process_box = [&](int l, int gi, std::vector<std::vector<int>>& deferred,
+                           std::vector<std::vector<int>>& deferred_next, BoxGrid& bg) {
+        const Box& g = lev[l][gi];
+        // interaction list
+        std::vector<int> il;
+        if (l == 0) {
+            for (int o = 0; o < (int)lev[0].size(); ++o)
+                if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
+        } else {
+            const Box& P = lev[l - 1][g.parent];
+            std::vector<int> cand(P.children);
+            for (int pn : P.nbrs)
+                for (int ch : lev[l - 1][pn].children) cand.push_back(ch);
+            for (int o : cand)
+                if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
+        }
+        std::vector<int> src;
+        src.swap(deferred[gi]);
+        if (il.empty() && src.empty()) return;
+        for (int o : il)
+            for (int64_t q = lev[l][o].first; q < lev[l][o].first + lev[l][o].count; ++q) src.push_back(sorted[q]);
+        // bounding cap of the members' disks (Badoiu-Clarkson iteration, then dilation by eps)
+        double cc[3] = {0, 0, 0};
+        const int64_t m0 = g.first, mc = g.count;
+        for (int64_t q = m0; q < m0 + mc; ++q)
+            for (int k = 0; k < 3; ++k) cc[k] += F[(size_t)sorted[q] * 9 + k];
+        double nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
+        for (double& v : cc) v /= nn;
+        double best[3] = {cc[0], cc[1], cc[2]}, bestR = 1e300;
+        if (mc > 1) {
+            for (int it = 0; it < 40; ++it) {
+                double far = -1;
+                int64_t fi = m0;
+                for (int64_t q = m0; q < m0 + mc; ++q) {
+                    double d = geodesic(cc, &F[(size_t)sorted[q] * 9]);
+                    if (d > far) {
+                        far = d;
+                        fi = q;
+                    }
+                }
+                if (far < bestR) {
+                    bestR = far;
+                    best[0] = cc[0];
+                    best[1] = cc[1];
+                    best[2] = cc[2];
+                }
+                const double* fp = &F[(size_t)sorted[fi] * 9];
+                const double t = 1.0 / (it + 2.0);
+                for (int k = 0; k < 3; ++k) cc[k] += t * (fp[k] - cc[k]);
+                nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
+                for (double& v : cc) v /= nn;
+            }
+        } else {
+            bestR = 0.0;
+            for (int k = 0; k < 3; ++k) best[k] = F[(size_t)sorted[m0] * 9 + k];
+        }
+        const double R = bestR + eps;
+        // sources valid for a grid: the whole cap must lie in the source's
+        // far-field region (arclength > 2 eps) and be well separated
+        std::vector<int> ok, bad, okt;
+        std::vector<float> okd;   // their arclengths from the cap centre
+        double rho = 1e300, dmin = 1e300;
+        for (int j : src) {
+            const double d = geodesic(best, &F[(size_t)j * 9]);
+            const double ratio = (d - eps) / R;
+            if (d - R > 2.0 * eps * (1.0 + 1e-9) && ratio >= rho_min) {
+                ok.push_back(j);
+                okd.push_back((float)d);
+                // the source's own cheapest table valid over the whole cap
+                okt.push_back(cheapest_table(d - R));
+                rho = std::min(rho, ratio);
+                dmin = std::min(dmin, d - R);
+            } else {
+                bad.push_back(j);
+            }
+        }
+        bool use_grid = false;
+        int nr = 0, nt = 0, table = 0, pt = p;
+        if (!ok.empty()) {
+            // the table valid at the grid's closest source (the cost model's)
+            table = cheapest_table(dmin);
+            pt = ptab[table];
+            grid_size(rho, tol_grid, nr, nt);
+            const double q = (double)nr * nt;
+            if (nr <= kMaxGridNr && nt <= kMaxGridNt && q <= kMaxGridQ) {
+                const double cost_grid = ok.size() * q * pt * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
+                const double cost_direct = ok.size() * (double)mc * Kstar * p * cpair;
+                use_grid = cost_grid < cost_direct;
+            }
+        }
+        if (!use_grid) {
+            bad.insert(bad.end(), ok.begin(), ok.end());
+            ok.clear();
+        }
+        if (!bad.empty()) {
+            if (l < L) {
+                // retry at the children: smaller caps, larger distance ratios
+                for (int ch : g.children) {
+                    std::vector<int>& dn = deferred_next[ch];
+                    dn.insert(dn.end(), bad.begin(), bad.end());
+                }
+            } else {
+                for (int64_t q = m0; q < m0 + mc; ++q) {
+                    std::vector<int>& dl = direct[sorted[q]];
+                    dl.insert(dl.end(), bad.begin(), bad.end());
+                }
+            }
+        }
+        if (!use_grid) return;
+        bg.use = true;
+        frame_of(best, bg.f9);
+        bg.R = R;
+        bg.nr = nr;
+        bg.nt = nt;
+        bg.table = table;
+        // the sources counting-sorted by table (stable), so that an item's
+        // sources form few runs of one table, then cut into items
+        const size_t n = ok.size();
+        std::vector<int> tcount(ptab.size() + 1, 0), pss(n);
+        std::vector<float> ds(n);
+        for (int k : okt) ++tcount[k + 1];
+        for (size_t k = 1; k < tcount.size(); ++k) tcount[k] += tcount[k - 1];
+        bg.src.resize(n);
+        bg.tab.resize(n);
+        for (size_t a = 0; a < n; ++a) {
+            const int at = tcount[okt[a]]++;
+            bg.src[at] = ok[a];
+            bg.tab[at] = okt[a];
+            pss[at] = ptab[okt[a]];
+            ds[at] = okd[a];
+        }
+        cut_items(ds.data(), bg.tab.data(), pss.data(), n, (double)nr * nt, R, eps, tab.problem, bg.ends, bg.win);
+    };
 
     // sources handed down from a parent whose cap was too close to them
     std::vector<std::vector<int>> deferred(lev[0].size()), deferred_next;
     for (int l = 0; l <= L; ++l) {
         if (l < L) deferred_next.assign(lev[l + 1].size(), std::vector<int>());
-        for (int gi = 0; gi < (int)lev[l].size(); ++gi) {
+        const int nb = (int)lev[l].size();
+        std::vector<BoxGrid> bgs(nb);
+        std::string err;
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int gi = 0; gi < nb; ++gi) {
+            try {
+                process_box(l, gi, deferred, deferred_next, bgs[gi]);
+            } catch (const std::exception& e) {
+#pragma omp critical(tree_build_error)
+                if (err.empty()) err = e.what();
+            }
+        }
+        if (!err.empty()) throw std::runtime_error(err);
+        // the grids in box order
+        for (int gi = 0; gi < nb; ++gi) {
+            BoxGrid& bg = bgs[gi];
+            if (!bg.use) continue;
+            const int gid = out.ngrid++;
+            out.g_frame.insert(out.g_frame.end(), bg.f9, bg.f9 + 9);
+            out.g_R.push_back(bg.R);
+            out.g_nr.push_back(bg.nr);
+            out.g_nt.push_back(bg.nt);
+            out.g_level.push_back(l);
+            out.g_table.push_back(bg.table);
+            grid_src.push_back(std::move(bg.src));
+            grid_tab.push_back(std::move(bg.tab));
+            grid_ends.push_back(std::move(bg.ends));
+            grid_win.push_back(std::move(bg.win));
             const Box& g = lev[l][gi];
-            // interaction list
-            std::vector<int> il;
-            if (l == 0) {
-                for (int o = 0; o < (int)lev[0].size(); ++o)
-                    if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
-            } else {
-                const Box& P = lev[l - 1][g.parent];
-                std::vector<int> cand(P.children);
-                for (int pn : P.nbrs)
-                    for (int ch : lev[l - 1][pn].children) cand.push_back(ch);
-                for (int o : cand)
-                    if (o != gi && !std::binary_search(g.nbrs.begin(), g.nbrs.end(), o)) il.push_back(o);
-            }
-            std::vector<int> src;
-            src.swap(deferred[gi]);
-            if (il.empty() && src.empty()) continue;
-            for (int o : il)
-                for (int64_t q = lev[l][o].first; q < lev[l][o].first + lev[l][o].count; ++q) src.push_back(sorted[q]);
-            // bounding cap of the members' disks (Badoiu-Clarkson iteration, then dilation by eps)
-            double cc[3] = {0, 0, 0};
-            const int64_t m0 = g.first, mc = g.count;
-            for (int64_t q = m0; q < m0 + mc; ++q)
-                for (int k = 0; k < 3; ++k) cc[k] += F[(size_t)sorted[q] * 9 + k];
-            double nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
-            for (double& v : cc) v /= nn;
-            double best[3] = {cc[0], cc[1], cc[2]}, bestR = 1e300;
-            if (mc > 1) {
-                for (int it = 0; it < 40; ++it) {
-                    double far = -1;
-                    int64_t fi = m0;
-                    for (int64_t q = m0; q < m0 + mc; ++q) {
-                        double d = geodesic(cc, &F[(size_t)sorted[q] * 9]);
-                        if (d > far) {
-                            far = d;
-                            fi = q;
-                        }
-                    }
-                    if (far < bestR) {
-                        bestR = far;
-                        best[0] = cc[0];
-                        best[1] = cc[1];
-                        best[2] = cc[2];
-                    }
-                    const double* fp = &F[(size_t)sorted[fi] * 9];
-                    const double t = 1.0 / (it + 2.0);
-                    for (int k = 0; k < 3; ++k) cc[k] += t * (fp[k] - cc[k]);
-                    nn = std::sqrt(cc[0] * cc[0] + cc[1] * cc[1] + cc[2] * cc[2]);
-                    for (double& v : cc) v /= nn;
-                }
-            } else {
-                bestR = 0.0;
-                for (int k = 0; k < 3; ++k) best[k] = F[(size_t)sorted[m0] * 9 + k];
-            }
-            const double R = bestR + eps;
-            // sources valid for a grid: the whole cap must lie in the source's
-            // far-field region (arclength > 2 eps) and be well separated
-            std::vector<int> ok, bad;
-            okd.clear();
-            double rho = 1e300, dmin = 1e300;
-            for (int j : src) {
-                const double d = geodesic(best, &F[(size_t)j * 9]);
-                const double ratio = (d - eps) / R;
-                if (d - R > 2.0 * eps * (1.0 + 1e-9) && ratio >= rho_min) {
-                    ok.push_back(j);
-                    okd.push_back((float)d);
-                    rho = std::min(rho, ratio);
-                    dmin = std::min(dmin, d - R);
-                } else {
-                    bad.push_back(j);
-                }
-            }
-            bool use_grid = false;
-            int nr = 0, nt = 0, table = 0, pt = p;
-            if (!ok.empty()) {
-                // the cheapest outgoing table valid at the grid's closest point
-                for (size_t k = 0; k < tab.far.size(); ++k)
-                    if (tab.far[k].D <= dmin && tab.far[k].p < pt) {
-                        table = (int)k + 1;
-                        pt = tab.far[k].p;
-                    }
-                grid_size(rho, tol_grid, nr, nt);
-                const double q = (double)nr * nt;
-                if (nr <= kMaxGridNr && nt <= kMaxGridNt && q <= kMaxGridQ) {
-                    const double cost_grid = ok.size() * q * pt * cpair + mc * (double)Kstar * q + q * (nt + 2.0 * nr);
-                    const double cost_direct = ok.size() * (double)mc * Kstar * p * cpair;
-                    use_grid = cost_grid < cost_direct;
-                }
-            }
-            if (!use_grid) {
-                bad.insert(bad.end(), ok.begin(), ok.end());
-                ok.clear();
-            }
-            if (!bad.empty()) {
-                if (l < L) {
-                    // retry at the children: smaller caps, larger distance ratios
-                    for (int ch : g.children) {
-                        std::vector<int>& dn = deferred_next[ch];
-                        dn.insert(dn.end(), bad.begin(), bad.end());
-                    }
-                } else {
-                    for (int64_t q = m0; q < m0 + mc; ++q) {
-                        std::vector<int>& dl = direct[sorted[q]];
-                        dl.insert(dl.end(), bad.begin(), bad.end());
-                    }
-                }
-            }
-            if (use_grid) {
-                const int gid = out.ngrid++;
-                double f9[9];
-                frame_of(best, f9);
-                out.g_frame.insert(out.g_frame.end(), f9, f9 + 9);
-                out.g_R.push_back(R);
-                out.g_nr.push_back(nr);
-                out.g_nt.push_back(nt);
-                out.g_level.push_back(l);
-                out.g_table.push_back(table);
-                // items of at least kSrcPerItem sources, more where the grid
-                // and its outgoing table are small, so that every item carries
-                // about kItemPairs pair evaluations or more; cut further where
-                // the sources' logarithm arguments leave one window
-                const size_t qg = (size_t)nr * nt;
-                const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + qg * pt - 1) / (qg * pt));
-                grid_ends.emplace_back();
-                grid_win.emplace_back();
-                cut_items(okd.data(), ok.size(), spi, R, eps, tab.problem, grid_ends.back(), grid_win.back());
-                grid_src.push_back(std::move(ok));
-                for (int64_t q = m0; q < m0 + mc; ++q) l2t[sorted[q]].push_back(gid);
-            }
+            for (int64_t q = g.first; q < g.first + g.count; ++q) l2t[sorted[q]].push_back(gid);
         }
         if (l < L) deferred.swap(deferred_next);
     }
@@ -407,7 +506,6 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         qoff += q;
         out.g_item0[g] = (int)out.it_grid.size();
         const std::vector<int>& s = grid_src[g];
-        const int pg = out.g_table[g] == 0 ? p : tab.far[out.g_table[g] - 1].p;
         const std::vector<size_t>& ends = grid_ends[g];
         const std::vector<int>& win = grid_win[g];
         for (size_t k = 0, a = 0; k < ends.size(); a = ends[k], ++k) {
@@ -419,8 +517,9 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             poff += q;
         }
         out.p2l_src.insert(out.p2l_src.end(), s.begin(), s.end());
+        out.p2l_tab.insert(out.p2l_tab.end(), grid_tab[g].begin(), grid_tab[g].end());
         out.g_item1[g] = (int)out.it_grid.size();
-        out.pairs_far += (double)s.size() * q * pg;
+        for (int k : grid_tab[g]) out.pairs_far += (double)q * ptab[k];
     }
     out.total_q = qoff;
     out.total_partial = poff;
@@ -443,29 +542,37 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
 
 void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar, const std::vector<double>& frames, double eps,
                          int problem) {
-    std::vector<int> it_grid, it_src0, it_src1, it_type, it_win, p2l_src;
+    std::vector<int> it_grid, it_src0, it_src1, it_type, it_win, p2l_src, p2l_tab;
     std::vector<int64_t> it_off;
     int64_t poff = 0;
     t.pairs_far = 0;
     for (int g = 0; g < t.ngrid; ++g) {
         const int q = t.g_nr[g] * t.g_nt[g];
         const int first = t.it_src0[t.g_item0[g]], last = t.it_src1[t.g_item1[g] - 1];
-        // the grid's sources, stably grouped by type
-        std::vector<int> src(t.p2l_src.begin() + first, t.p2l_src.begin() + last);
-        std::stable_sort(src.begin(), src.end(), [&](int a, int b) { return tl.ptype[a] < tl.ptype[b]; });
+        // the grid's sources, stably grouped by type (each type's keep their
+        // order by table)
+        std::vector<int> ord((size_t)(last - first));
+        for (int a = 0; a < last - first; ++a) ord[a] = first + a;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int a, int b) { return tl.ptype[t.p2l_src[a]] < tl.ptype[t.p2l_src[b]]; });
+        std::vector<int> src(ord.size()), tbs(ord.size()), pss(ord.size());
+        std::vector<float> d(ord.size());
+        for (size_t a = 0; a < ord.size(); ++a) {
+            src[a] = t.p2l_src[ord[a]];
+            tbs[a] = t.p2l_tab[ord[a]];
+            pss[a] = tl.t_p[tl.ptype[src[a]] * tl.ntab + tbs[a]];
+            d[a] = (float)geodesic(&t.g_frame[(size_t)9 * g], &frames[(size_t)src[a] * 9]);
+        }
         t.g_item0[g] = (int)it_grid.size();
         size_t a = 0;
         while (a < src.size()) {
             const int ty = tl.ptype[src[a]];
             size_t e = a;
             while (e < src.size() && tl.ptype[src[e]] == ty) ++e;
-            const int pg = tl.t_p[ty * tl.ntab + t.g_table[g]];
-            const size_t spi = std::max<size_t>(kSrcPerItem, (kItemPairs + (size_t)q * pg - 1) / ((size_t)q * pg));
             std::vector<size_t> ends;
             std::vector<int> win;
-            std::vector<float> d(e - a);
-            for (size_t b = a; b < e; ++b) d[b - a] = (float)geodesic(&t.g_frame[(size_t)9 * g], &frames[(size_t)src[b] * 9]);
-            cut_items(d.data(), e - a, spi, t.g_R[g], eps, problem, ends, win);
+            cut_items(d.data() + a, tbs.data() + a, pss.data() + a, e - a, (double)q, t.g_R[g], eps, problem, ends,
+                      win);
             for (size_t k = 0, b = a; k < ends.size(); b = a + ends[k], ++k) {
                 it_grid.push_back(g);
                 it_src0.push_back((int)(p2l_src.size() + b));
@@ -475,10 +582,11 @@ void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar, const std::ve
                 it_off.push_back(poff);
                 poff += q;
             }
-            t.pairs_far += (double)(e - a) * q * pg;
+            for (size_t b = a; b < e; ++b) t.pairs_far += (double)q * pss[b];
             a = e;
         }
         p2l_src.insert(p2l_src.end(), src.begin(), src.end());
+        p2l_tab.insert(p2l_tab.end(), tbs.begin(), tbs.end());
         t.g_item1[g] = (int)it_grid.size();
     }
     t.it_grid.swap(it_grid);
@@ -488,6 +596,7 @@ void split_items_by_type(Tree& t, const TypeLayout& tl, int Kstar, const std::ve
     t.it_win.swap(it_win);
     t.it_off.swap(it_off);
     t.p2l_src.swap(p2l_src);
+    t.p2l_tab.swap(p2l_tab);
     t.total_partial = poff;
     t.pairs_near = 0;
     for (int64_t i = 0; i < t.N; ++i)
@@ -528,6 +637,7 @@ void append_tree(Tree& dst, const Tree& src, int64_t first) {
     }
     dst.it_win.insert(dst.it_win.end(), src.it_win.begin(), src.it_win.end());
     for (int j : src.p2l_src) dst.p2l_src.push_back((int)(first + j));
+    dst.p2l_tab.insert(dst.p2l_tab.end(), src.p2l_tab.begin(), src.p2l_tab.end());
     dst.it_cfg.insert(dst.it_cfg.end(), src.it_grid.size(), dst.ncfg);
     dst.g_cfg.insert(dst.g_cfg.end(), (size_t)src.ngrid, dst.ncfg);
     dst.pt_cfg.insert(dst.pt_cfg.end(), (size_t)src.N, dst.ncfg);

@@ -34,6 +34,7 @@ constexpr int kMaxGridNt = 256;
 constexpr int kSrcPerItem = 32;   // source patches per P2L work item (at least)
 constexpr size_t kItemPairs = size_t(1) << 18;  // pair evaluations per P2L work item (at least)
 constexpr int kLogWindowOctaves = 8;  // binary octaves of the FP64 pair logarithm's argument per P2L item
+constexpr int kMaxTableRuns = 8;      // runs of sources sharing one outgoing table per P2L item
 
 struct Tree {
     int nlevels = 0;
@@ -43,7 +44,7 @@ struct Tree {
     std::vector<double> g_frame;          // ngrid x 9: cap centre, e1, e2
     std::vector<double> g_R;              // cap radius (arclength)
     std::vector<int> g_nr, g_nt, g_level;
-    std::vector<int> g_table;             // outgoing table: 0 = base (D = 2 eps), k = far[k-1]
+    std::vector<int> g_table;             // outgoing table valid at the closest source: 0 = base (D = 2 eps), k = far[k-1]
     std::vector<int64_t> g_off;           // offset of the grid's q values
     std::vector<int> g_item0, g_item1;    // P2L items of the grid
     int64_t total_q = 0;
@@ -51,6 +52,11 @@ struct Tree {
     std::vector<int> it_grid, it_src0, it_src1;
     std::vector<int64_t> it_off;          // offset of the item's partial sums
     std::vector<int> p2l_src;
+    // the outgoing table of every P2L source (0 = base, k = far[k - 1]): each
+    // source's own cheapest table valid over its grid's whole cap; a grid's
+    // sources are sorted by it, so an item's sources form at most
+    // kMaxTableRuns runs of one table
+    std::vector<int> p2l_tab;
     // per item: the first of the kLogWindowOctaves binary octaves that hold the
     // FP64 pair logarithm's argument x of every pair of the item (x in
     // [2^it_win, 2^(it_win + kLogWindowOctaves)), bounded from the geometry)

@@ -81,8 +81,8 @@ int main(int argc, char** argv) {
             if (cnt[j] != want) { std::printf("FAIL pair (%ld,%ld) counted %d times\n", i, j, cnt[j]); return 1; }
         }
     }
-    if (forest.it_win.size() != forest.it_grid.size()) {
-        std::printf("FAIL the forest's items lost their logarithm windows\n");
+    if (forest.it_win.size() != forest.it_grid.size() || forest.p2l_tab.size() != forest.p2l_src.size()) {
+        std::printf("FAIL the forest lost its items' logarithm windows or sources' tables\n");
         return 1;
     }
     std::printf("OK configurations %d patches %ld grids %d items %zu far %.4g near %.4g\n", B, NT, forest.ngrid,

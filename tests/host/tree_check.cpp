@@ -7,10 +7,14 @@
 // argument x of the item's pairs (x = u^2 + u interior, 1 + 1/u exterior, u
 // half the chord) at the extreme configurations (grid point and skeleton point
 // on the great circle through the two centres, nearest and farthest) and at
-// random points of the cap and of the patch, for both problems. Prints
-// "OK <stats>" or the first violation.
+// random points of the cap and of the patch, for both problems, and that every
+// P2L source uses the cheapest table of a synthetic recompression ladder that
+// is valid over its grid's whole cap, a grid's sources sorted by table and at
+// most kMaxTableRuns runs of one table per item. Prints "OK <stats>" or the
+// first violation.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <random>
 #include <vector>
@@ -101,8 +105,38 @@ int main(int argc, char** argv) {
     nce::PatchTables tab;
     tab.Kstar = 512;
     tab.p = 200;
+    // a ladder of recompressions valid beyond D_k = 2 eps 2^(k/2), smaller
+    // with distance (two of equal size, as real ladders can have)
+    for (int k = 1; k <= 12; ++k) {
+        nce::FarTable ft;
+        ft.D = 2.0 * eps * std::pow(2.0, 0.5 * k);
+        ft.p = std::max(12, (int)(200 * std::pow(0.8, k)));
+        tab.far.push_back(ft);
+    }
     nce::Tree t;
     nce::build_tree(fr, N, eps, tab, tol, t);
+    if (t.p2l_tab.size() != t.p2l_src.size()) { std::printf("FAIL sources without tables\n"); return 1; }
+    for (size_t it = 0; it < t.it_grid.size(); ++it) {
+        const int g = t.it_grid[it];
+        int runs = 0;
+        for (int s = t.it_src0[it]; s < t.it_src1[it]; ++s) {
+            if (s == t.it_src0[it] || t.p2l_tab[s] != t.p2l_tab[s - 1]) ++runs;
+            if (s > t.it_src0[it] && t.p2l_tab[s] < t.p2l_tab[s - 1]) { std::printf("FAIL item %zu not sorted by table\n", it); return 1; }
+            const double* c = &fr[9 * t.p2l_src[s]];
+            const double* gc = &t.g_frame[9 * g];
+            double cr0 = c[1] * gc[2] - c[2] * gc[1], cr1 = c[2] * gc[0] - c[0] * gc[2], cr2 = c[0] * gc[1] - c[1] * gc[0];
+            const double dm = std::atan2(std::sqrt(cr0 * cr0 + cr1 * cr1 + cr2 * cr2), c[0] * gc[0] + c[1] * gc[1] + c[2] * gc[2]) - t.g_R[g];
+            const int k = t.p2l_tab[s];
+            if (k > 0 && tab.far[k - 1].D > dm) { std::printf("FAIL source %d of grid %d: table %d not valid over the cap\n", t.p2l_src[s], g, k); return 1; }
+            const int pk = k == 0 ? tab.p : tab.far[k - 1].p;
+            for (size_t kk = 0; kk < tab.far.size(); ++kk)
+                if (tab.far[kk].D <= dm && tab.far[kk].p < pk) { std::printf("FAIL source %d of grid %d: table %d not the cheapest\n", t.p2l_src[s], g, k); return 1; }
+        }
+        if (runs > nce::kMaxTableRuns) { std::printf("FAIL item %zu has %d table runs\n", it, runs); return 1; }
+        if (it + 1 < t.it_grid.size() && t.it_grid[it + 1] == g && t.p2l_tab[t.it_src0[it + 1]] < t.p2l_tab[t.it_src1[it] - 1]) {
+            std::printf("FAIL grid %d not sorted by table across items\n", g); return 1;
+        }
+    }
     // grid -> set of sources
     std::vector<std::vector<int>> gsrc(t.ngrid);
     for (size_t it = 0; it < t.it_grid.size(); ++it)
