@@ -773,7 +773,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
             if (ctx->has_tree32) {
                 if (tree) {
                     nce::Tree tr32;
-                    nce::build_tree(fr, nc, eps, t32, tol32, tr32);
+                    nce::build_tree(fr, nc, eps, t32, tol32, tr32, false);
                     nce::append_tree(ctx->tree32, tr32, f0);
                 } else {
                     nce::append_direct(ctx->tree32, f0, nc, ctx->Kstar, ctx->p32);
@@ -781,7 +781,7 @@ void init_ctx(nce_ctx* ctx, const double* centers, const std::vector<int64_t>& c
             }
         }
     } else if (ctx->has_tree32) {
-        nce::build_tree(ctx->frames, N, eps, t32, tol32, ctx->tree32);
+        nce::build_tree(ctx->frames, N, eps, t32, tol32, ctx->tree32, false);
     }
     if (ctx->use_tree) nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, ctx->tab_off, ctx->tab_p, s, ctx->dtree);
     if (ctx->has_tree32)

@@ -176,7 +176,7 @@ void grid_size(double rho, double tol, int& nr, int& nt) {
 }
 
 void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab, double tol_grid,
-                Tree& out) {
+                Tree& out, bool split_far) {
     out = Tree();
     out.N = N;
     const int Kstar = tab.Kstar, p = tab.p;
@@ -187,6 +187,10 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     // FP64 and the FP32 tolerances: 26 % fewer than at 2)
     const double rho_min = 3.0;
     const double cpair = 40.0;  // one Green's function pair in multiply-add units (cost model only)
+    // the split of a grid's sources by distance ratio, priced in interpolation
+    // multiply-adds from the measured FP64 rates (0.77 ns per P2L pair, 0.043 ns
+    // per interpolation multiply-add, about 100 of them per (node, grid) set-up)
+    const double kPairCost = 18.0, kNodeGridCost = 100.0;
 
     // 1. project to the cube, face-local keys, sort
     std::vector<uint64_t> key(N);
@@ -305,14 +309,17 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
     // members' direct lists. Touches only the box's own deferred list, its
     // children's next lists and its members' direct lists, so the boxes of a
     // level run in parallel; the grids are numbered afterwards in box order.
-    struct BoxGrid {
-        bool use = false;
+    struct GridOut {
         double f9[9];
         double R = 0;
         int nr = 0, nt = 0, table = 0;
         std::vector<int> src, tab;
         std::vector<size_t> ends;
         std::vector<int> win;
+    };
+    struct BoxGrid {
+        int n = 0;       // grids of the box: 0, 1, or 2 (near sources, far sources)
+        GridOut g[2];
     };
     auto process_box = [&](int l, int gi, std::vector<std::vector<int>>& deferred,
                            std::vector<std::vector<int>>& deferred_next, BoxGrid& bg) {
@@ -423,29 +430,82 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
             }
         }
         if (!use_grid) return;
-        bg.use = true;
-        frame_of(best, bg.f9);
-        bg.R = R;
-        bg.nr = nr;
-        bg.nt = nt;
-        bg.table = table;
-        // the sources counting-sorted by table (stable), so that an item's
-        // sources form few runs of one table, then cut into items
+        // A second, coarser grid for the far sources where that costs less:
+        // the grid is sized by its closest source's distance ratio, so
+        // sources at ratio >= tau can share a grid sized for tau instead,
+        // at the price of interpolating a second grid at the members' nodes.
+        // Priced in interpolation multiply-adds: a P2L pair kPairCost, a
+        // grid point per node 1, a (node, grid) set-up kNodeGridCost.
         const size_t n = ok.size();
-        std::vector<int> tcount(ptab.size() + 1, 0), pss(n);
-        std::vector<float> ds(n);
-        for (int k : okt) ++tcount[k + 1];
-        for (size_t k = 1; k < tcount.size(); ++k) tcount[k] += tcount[k - 1];
-        bg.src.resize(n);
-        bg.tab.resize(n);
-        for (size_t a = 0; a < n; ++a) {
-            const int at = tcount[okt[a]]++;
-            bg.src[at] = ok[a];
-            bg.tab[at] = okt[a];
-            pss[at] = ptab[okt[a]];
-            ds[at] = okd[a];
+        double P = 0.0;
+        for (int k : okt) P += ptab[k];
+        const double q0 = (double)nr * nt, nodes = (double)mc * Kstar;
+        double best_cost = kPairCost * q0 * P + nodes * (q0 + kNodeGridCost);
+        double tau_best = 0.0;
+        int nr_f = 0, nt_f = 0;
+        for (double tau : {4.0, 5.0, 6.0, 8.0}) {
+            if (!split_far) break;
+            double Pn = 0.0, Pf = 0.0, rf = 1e300;
+            for (size_t a = 0; a < n; ++a) {
+                const double ra = ((double)okd[a] - eps) / R;
+                if (ra >= tau) {
+                    Pf += ptab[okt[a]];
+                    rf = std::min(rf, ra);
+                } else {
+                    Pn += ptab[okt[a]];
+                }
+            }
+            if (Pn == 0.0 || Pf == 0.0) continue;
+            int nrf, ntf;
+            grid_size(rf, tol_grid, nrf, ntf);
+            const double qf = (double)nrf * ntf;
+            const double c = kPairCost * (q0 * Pn + qf * Pf) + nodes * (q0 + qf + 2.0 * kNodeGridCost);
+            if (c < best_cost) {
+                best_cost = c;
+                tau_best = tau;
+                nr_f = nrf;
+                nt_f = ntf;
+            }
         }
-        cut_items(ds.data(), bg.tab.data(), pss.data(), n, (double)nr * nt, R, eps, tab.problem, bg.ends, bg.win);
+        // the grids: sources counting-sorted by table (stable), so that an
+        // item's sources form few runs of one table, then cut into items
+        auto make_grid = [&](GridOut& go, int gnr, int gnt, bool far_part) {
+            frame_of(best, go.f9);
+            go.R = R;
+            go.nr = gnr;
+            go.nt = gnt;
+            std::vector<size_t> sel;
+            double dm = 1e300;
+            for (size_t a = 0; a < n; ++a) {
+                const bool is_far = tau_best > 0.0 && ((double)okd[a] - eps) / R >= tau_best;
+                if (is_far == far_part) {
+                    sel.push_back(a);
+                    dm = std::min(dm, (double)okd[a] - R);
+                }
+            }
+            go.table = cheapest_table(dm);
+            const size_t m = sel.size();
+            std::vector<int> tcount(ptab.size() + 1, 0), pss(m);
+            std::vector<float> ds(m);
+            for (size_t a : sel) ++tcount[okt[a] + 1];
+            for (size_t k = 1; k < tcount.size(); ++k) tcount[k] += tcount[k - 1];
+            go.src.resize(m);
+            go.tab.resize(m);
+            for (size_t a : sel) {
+                const int at = tcount[okt[a]]++;
+                go.src[at] = ok[a];
+                go.tab[at] = okt[a];
+                pss[at] = ptab[okt[a]];
+                ds[at] = okd[a];
+            }
+            cut_items(ds.data(), go.tab.data(), pss.data(), m, (double)gnr * gnt, R, eps, tab.problem, go.ends, go.win);
+        };
+        make_grid(bg.g[0], nr, nt, false);
+        bg.n = 1;
+        if (tau_best > 0.0) {
+            make_grid(bg.g[1], nr_f, nt_f, true);
+            bg.n = 2;
+        }
     };
 
     // sources handed down from a parent whose cap was too close to them
@@ -466,23 +526,23 @@ void build_tree(const std::vector<double>& frames, int64_t N, double eps, const 
         }
         if (!err.empty()) throw std::runtime_error(err);
         // the grids in box order
-        for (int gi = 0; gi < nb; ++gi) {
-            BoxGrid& bg = bgs[gi];
-            if (!bg.use) continue;
-            const int gid = out.ngrid++;
-            out.g_frame.insert(out.g_frame.end(), bg.f9, bg.f9 + 9);
-            out.g_R.push_back(bg.R);
-            out.g_nr.push_back(bg.nr);
-            out.g_nt.push_back(bg.nt);
-            out.g_level.push_back(l);
-            out.g_table.push_back(bg.table);
-            grid_src.push_back(std::move(bg.src));
-            grid_tab.push_back(std::move(bg.tab));
-            grid_ends.push_back(std::move(bg.ends));
-            grid_win.push_back(std::move(bg.win));
-            const Box& g = lev[l][gi];
-            for (int64_t q = g.first; q < g.first + g.count; ++q) l2t[sorted[q]].push_back(gid);
-        }
+        for (int gi = 0; gi < nb; ++gi)
+            for (int k = 0; k < bgs[gi].n; ++k) {
+                GridOut& go = bgs[gi].g[k];
+                const int gid = out.ngrid++;
+                out.g_frame.insert(out.g_frame.end(), go.f9, go.f9 + 9);
+                out.g_R.push_back(go.R);
+                out.g_nr.push_back(go.nr);
+                out.g_nt.push_back(go.nt);
+                out.g_level.push_back(l);
+                out.g_table.push_back(go.table);
+                grid_src.push_back(std::move(go.src));
+                grid_tab.push_back(std::move(go.tab));
+                grid_ends.push_back(std::move(go.ends));
+                grid_win.push_back(std::move(go.win));
+                const Box& g = lev[l][gi];
+                for (int64_t q = g.first; q < g.first + g.count; ++q) l2t[sorted[q]].push_back(gid);
+            }
         if (l < L) deferred.swap(deferred_next);
     }
     // 5. near field: neighbours at the finest level (one patch per box)

@@ -82,8 +82,11 @@ struct Tree {
 // distance ratio rho = (distance from the cap centre - eps) / R.
 void grid_size(double rho, double tol, int& nr, int& nt);
 
+// split_far: a box whose far sources cost less on a second, coarser grid
+// gets one (priced with the FP64 kernels' measured rates; the FP32 trees,
+// whose small grids gain nothing from it, pass false).
 void build_tree(const std::vector<double>& frames, int64_t N, double eps, const PatchTables& tab,
-                double tol_grid, Tree& out);
+                double tol_grid, Tree& out, bool split_far = true);
 
 // Several patch radii in one configuration: the type of every patch and, per
 // (type, outgoing table) with `ntab` tables per type, the first skeleton point

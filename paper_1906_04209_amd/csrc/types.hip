@@ -239,7 +239,7 @@ void init_ctx_types(nce_ctx* ctx, const double* centers, const double* radius, i
         nce::upload_tree(ctx->tree, ctx->Kstar, ctx->p, {}, {}, s, ctx->dtree, &ctx->tl);
     }
     if (ctx->has_tree32) {
-        nce::build_tree(ctx->frames, N, emax, ctx->tab32, tol32, ctx->tree32);
+        nce::build_tree(ctx->frames, N, emax, ctx->tab32, tol32, ctx->tree32, false);
         nce::split_items_by_type(ctx->tree32, ctx->tl32, ctx->Kstar, ctx->frames, emax, ctx->tab.problem);
         nce::upload_tree(ctx->tree32, ctx->Kstar, ctx->p32, {}, {}, s, ctx->dtree32, &ctx->tl32);
     }

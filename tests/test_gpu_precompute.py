@@ -3,8 +3,11 @@ azimuthal orders, Section 9.2; randomized ID on the device, Section 7.1)
 against the host precompute: the same one-patch solution and integral vector
 to rounding, and system applies that agree to the ID tolerance (the two IDs
 draw different sketches and may choose different skeletons, each reproducing
-the outgoing field to tol_id). Every other GPU test builds its tables on the
-GPU as well (the library's default), so the oracle parity tests cover it."""
+the outgoing field to tol_id). The tree's grids are at 1e-11: the tables'
+skeleton sizes enter the tree's cost model, so the two contexts may lay out
+different grids, and their interpolation errors must stay below the ID's.
+Every other GPU test builds its tables on the GPU as well (the library's
+default), so the oracle parity tests cover it."""
 import os
 import tempfile
 import time
@@ -31,7 +34,7 @@ def _ctx(c, eps, problem, host, tol_id, far):
     try:
         t0 = time.perf_counter()
         ctx = nce.Context(c, eps, problem=problem, tol_id=tol_id, far_field=far, tol_id_fp32=tol_id,
-                          cache_dir=tempfile.mkdtemp(prefix="nce_tab_"))
+                          tol_grid=1e-11, cache_dir=tempfile.mkdtemp(prefix="nce_tab_"))
         return ctx, time.perf_counter() - t0
     finally:
         if old is None:
