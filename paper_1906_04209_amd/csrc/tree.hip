@@ -810,7 +810,8 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
                                                     const int* __restrict__ g_nt, const int64_t* __restrict__ g_off,
                                                     const T* __restrict__ coef, T* __restrict__ U,
                                                     const int* __restrict__ pt_cfg, const int* __restrict__ live,
-                                                    const int* __restrict__ ptype, int node_stride, PApply<T> pa) {
+                                                    const int* __restrict__ ptype, int node_stride, PApply<T> pa,
+                                                    const int* __restrict__ g_same) {
     constexpr int kThreads = 512 / NPT;
     constexpr int kPre = (kMaxGridQ + kThreads - 1) / kThreads;  // coefficients per thread per grid
     // the grid coefficients' double buffer; at the end (fused P apply) the
@@ -848,6 +849,10 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
     int gn = a0 < a1 ? l2t_grid[a0] : 0;
     if (a0 < a1) fetch(gn);
     int buf = 0;
+    // stereographic polar coordinates of the nodes about the current cap; a
+    // grid over the same cap as the one before keeps them
+    T xs[NPT], ct[NPT], st[NPT];
+    int gprev = -2;
     for (int64_t aa = a0; aa < a1; ++aa) {
         const int g = gn;
 #pragma unroll
@@ -858,30 +863,33 @@ __global__ __launch_bounds__(512 / NPT) void k_l2t(int Kstar, const double* __re
             fetch(gn);
         }
         const int nr = g_nr[g], half = g_nt[g] / 2;
-        const double* fg = g_frame + 9 * (int64_t)g;
-        const T dcx = (T)(fi[0] - fg[0]), dcy = (T)(fi[1] - fg[1]), dcz = (T)(fi[2] - fg[2]);
-        const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
-        const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
-        const T invT = (T)(1.0 / g_T[g]);
-        // stereographic polar coordinates of every node about the grid's cap
-        // centre: for v = node - centre (both on the unit sphere) at angle
-        // phi, |v|^2 = 2 - 2 cos phi and the in-plane part has length sin phi,
-        // so tan(phi / 2) = (1 - cos phi) / sin phi = |v|^2 / (2 sin phi):
-        // one reciprocal square root per node and grid, no cancellation
-        T xs[NPT], ct[NPT], st[NPT];
+        const bool same_cap = g == gprev + 1 && g_same[g];
+        gprev = g;
+        if (!same_cap) {
+            const double* fg = g_frame + 9 * (int64_t)g;
+            const T dcx = (T)(fi[0] - fg[0]), dcy = (T)(fi[1] - fg[1]), dcz = (T)(fi[2] - fg[2]);
+            const T e1x = (T)fg[3], e1y = (T)fg[4], e1z = (T)fg[5];
+            const T e2x = (T)fg[6], e2y = (T)fg[7], e2z = (T)fg[8];
+            const T invT = (T)(1.0 / g_T[g]);
+            // stereographic polar coordinates of every node about the grid's cap
+            // centre: for v = node - centre (both on the unit sphere) at angle
+            // phi, |v|^2 = 2 - 2 cos phi and the in-plane part has length sin phi,
+            // so tan(phi / 2) = (1 - cos phi) / sin phi = |v|^2 / (2 sin phi):
+            // one reciprocal square root per node and grid, no cancellation
 #pragma unroll
-        for (int r = 0; r < NPT; ++r) {
-            const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
-            const T x1 = vx * e1x + vy * e1y + vz * e1z;
-            const T x2 = vx * e2x + vy * e2y + vz * e2z;
-            const T s = x1 * x1 + x2 * x2;
-            const bool off_axis = s > T(0);
-            const T w = rsqrt_t<T>(off_axis ? s : T(1));
-            ct[r] = off_axis ? x1 * w : T(1);
-            st[r] = off_axis ? x2 * w : T(0);
-            const T v2 = vx * vx + vy * vy + vz * vz;
-            const T x = off_axis ? T(0.5) * v2 * w * invT : T(0);
-            xs[r] = x > T(1) ? T(1) : x;
+            for (int r = 0; r < NPT; ++r) {
+                const T vx = dcx + ox[r], vy = dcy + oy[r], vz = dcz + oz[r];
+                const T x1 = vx * e1x + vy * e1y + vz * e1z;
+                const T x2 = vx * e2x + vy * e2y + vz * e2z;
+                const T s = x1 * x1 + x2 * x2;
+                const bool off_axis = s > T(0);
+                const T w = rsqrt_t<T>(off_axis ? s : T(1));
+                ct[r] = off_axis ? x1 * w : T(1);
+                st[r] = off_axis ? x2 * w : T(0);
+                const T v2 = vx * vx + vy * vy + vz * vz;
+                const T x = off_axis ? T(0.5) * v2 * w * invT : T(0);
+                xs[r] = x > T(1) ? T(1) : x;
+            }
         }
         const T* c = cs_all + buf * kL2tBuf;
         static_assert(kMaxGridNr == 16, "one case per radial order");
@@ -1121,6 +1129,16 @@ void upload_tree(const Tree& t, int Kstar, int p, const std::vector<int>& tab_of
         d.it_win = dev_copy(t.it_win);
     }
     {
+        // grids over the same cap as the grid before them (a box's near- and
+        // far-source grids): the interpolation keeps the nodes' polar coordinates
+        std::vector<int> same(t.ngrid, 0);
+        for (int g = 1; g < t.ngrid; ++g)
+            same[g] = t.g_R[g] == t.g_R[g - 1] &&
+                      std::equal(t.g_frame.begin() + 9 * (size_t)g, t.g_frame.begin() + 9 * (size_t)g + 9,
+                                 t.g_frame.begin() + 9 * (size_t)(g - 1));
+        d.g_same = dev_copy(same);
+    }
+    {
         // runs of one outgoing table in every item's sources
         if (t.p2l_tab.size() != t.p2l_src.size()) throw std::runtime_error("P2L sources without outgoing tables");
         std::vector<int> r0(t.it_grid.size() + 1, 0), rs, rt;
@@ -1153,7 +1171,7 @@ void free_tree(DeviceTree& d) {
                     d.it_grid, d.it_src0, d.it_src1, d.it_off,  d.p2l_src, d.dl_ptr, d.dl_src,
                     d.l2t_ptr, d.l2t_grid, d.it_solo, d.coef64,  d.part64, d.g_multi,  d.coef32, d.part32, d.ttab, d.g_ttab,
                     d.it_cfg, d.g_cfg, d.pt_cfg, d.gpt64, d.gpt32, d.items4, d.items8, d.logtab,
-                    d.it_type, d.t_col, d.ptype, d.it_win, d.logwin, d.it_run0, d.run_src, d.run_tab};
+                    d.it_type, d.t_col, d.ptype, d.it_win, d.logwin, d.it_run0, d.run_src, d.run_tab, d.g_same};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = DeviceTree();
@@ -1278,15 +1296,15 @@ hipError_t tree_interp(hipStream_t s, const DeviceTree& d, const double* frames,
     if (npt == 2)
         hipLaunchKernelGGL((k_l2t<T, 2>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride, p);
+                           d.ptype, d.node_stride, p, d.g_same);
     else if (npt == 4)
         hipLaunchKernelGGL((k_l2t<T, 4>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride, p);
+                           d.ptype, d.node_stride, p, d.g_same);
     else
         hipLaunchKernelGGL((k_l2t<T, 8>), dim3((unsigned)d.N), dim3(threads), 0, s, d.Kstar, frames, node_off,
                            d.l2t_ptr, d.l2t_grid, d.g_frame, d.g_T, d.g_nr, d.g_nt, d.g_off, coef, U, d.pt_cfg, live,
-                           d.ptype, d.node_stride, p);
+                           d.ptype, d.node_stride, p, d.g_same);
     return hipGetLastError();
 }
 template hipError_t tree_interp<double>(hipStream_t, const DeviceTree&, const double*, const double*, double*,

@@ -61,6 +61,7 @@ struct DeviceTree {
     // P2L items' sources by outgoing table: item i's runs are [it_run0[i],
     // it_run0[i + 1]); run r starts at source run_src[r] (a place in p2l_src)
     // and uses table run_tab[r] (0 = base, k = far[k - 1])
+    int* g_same = nullptr;   // per grid: 1 if its cap (frame and radius) is that of the grid before it
     int* it_run0 = nullptr;
     int* run_src = nullptr;
     int* run_tab = nullptr;
