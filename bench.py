@@ -47,7 +47,8 @@ LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels, per thread shape (4 or 8 grid points per thread, 0 = per-item
 # class: two launches over item lists, which read more through L2 misses).
-TRAFFIC = {}
+TRAFFIC = {("cfg5", "fp64", 4): 8.416e9, ("cfg5", "fp64", 8): 8.420e9, ("cfg5", "fp64", 0): 9.137e9,
+           ("cfg5", "fp32", 4): 5.374e9, ("cfg5", "fp32", 8): 5.171e9, ("cfg5", "fp32", 0): 5.396e9}
 # largest relative difference allowed between a mixed or warm-started solve's
 # scalar and the plain FP64 solve's (all solved to a 1e-8 residual)
 MIXED_SCALAR_TOL = 1e-6
