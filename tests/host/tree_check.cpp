@@ -175,9 +175,17 @@ int main(int argc, char** argv) {
         nce::build_tree(fr, N, eps, tp, tol, tw);
         if (!check_windows(tw, fr, eps, problem)) return 1;
     }
+    // boxes with a second grid for their far sources: two consecutive grids
+    // over the same cap, the second no larger than the first
+    int split = 0;
+    for (int g = 1; g < t.ngrid; ++g)
+        if (t.g_R[g] == t.g_R[g - 1] && std::equal(&t.g_frame[9 * g], &t.g_frame[9 * g] + 9, &t.g_frame[9 * (g - 1)])) {
+            ++split;
+            if (t.g_nr[g] * t.g_nt[g] > t.g_nr[g - 1] * t.g_nt[g - 1]) { std::printf("FAIL far-source grid %d larger than its box's first\n", g); return 1; }
+        }
     long maxdl = 0;
     for (long i = 0; i < N; ++i) maxdl = std::max(maxdl, (long)(t.dl_ptr[i + 1] - t.dl_ptr[i]));
-    std::printf("OK levels %d grids %d items %zu far %.4g near %.4g interp %.4g maxq %d maxdl %ld\n", t.nlevels,
-                t.ngrid, t.it_grid.size(), t.pairs_far, t.pairs_near, t.interp_fma, t.max_q, maxdl);
+    std::printf("OK levels %d grids %d items %zu far %.4g near %.4g interp %.4g maxq %d maxdl %ld split %d\n", t.nlevels,
+                t.ngrid, t.it_grid.size(), t.pairs_far, t.pairs_near, t.interp_fma, t.max_q, maxdl, split);
     return 0;
 }

@@ -36,7 +36,11 @@ def _run(exe, tmp_path, c, eps, tol=1e-8):
 
 @pytest.mark.parametrize("N,eps,seed", [(2, 0.1, 1), (10, 0.1, 1), (300, 0.02, 3), (2000, 0.005, 4)])
 def test_uniform_coverage(exe, tmp_path, N, eps, seed):
-    print(_run(exe, tmp_path, layouts.uniform_centers(N, eps, seed), eps))
+    out = _run(exe, tmp_path, layouts.uniform_centers(N, eps, seed), eps)
+    print(out)
+    if N >= 2000:
+        # the far-source grids are exercised (boxes with a second, coarser grid)
+        assert int(out.split("split ")[1].split()[0]) > 0
 
 
 def test_clustered_coverage(exe, tmp_path):
