@@ -244,12 +244,55 @@ void ensure_deflation(nce_ctx* ctx) {
     ctx->defl = std::move(d);
 }
 
+// The coarse model's apply through the configuration's tree, O(N log N) in
+// place of all pairs: the FP32 far- and near-field kernels on the FP64 tree's
+// geometry (its grids, items, direct and interpolation lists), with every
+// outgoing table replaced by one point at the patch centre carrying the charge
+// chi0_j a_j and one node per patch at its centre; y = a + (near sum +
+// interpolated grids). The tree never pairs a patch with itself.
+static void install_coarse_tree(nce_ctx* ctx) {
+    hipStream_t s = ctx->stream;
+    const int64_t N = ctx->N;
+    constexpr int kTabs = 64;   // more than any ladder's tables
+    ctx->d_ctab_off.upload(std::vector<int>(kTabs, 0), s);
+    ctx->d_ctab_p.upload(std::vector<int>(kTabs, 1), s);
+    ctx->d_c0.upload(std::vector<float>(3, 0.0f), s);
+    ctx->d_cq.alloc((size_t)N);
+    ctx->d_cu.alloc((size_t)N);
+    ctx->coarse->fast_apply = [ctx, N](hipStream_t st, const double* a, double* y) {
+        nce::DeviceTree v = ctx->dtree;   // a view: the tree's own arrays, one-point tables
+        v.t_off = ctx->d_ctab_off.p;
+        v.t_p = ctx->d_ctab_p.p;
+        v.t_col = nullptr;
+        v.it_type = nullptr;
+        v.ptype = nullptr;
+        v.node_stride = 0;
+        v.ptot = 1;
+        v.p = 1;
+        v.Kstar = 1;
+        const int problem = ctx->tab.problem;
+        const float* c0 = ctx->d_c0.p;
+        HIPCHK(ctx->coarse->charges32(st, (int)N, a, ctx->d_cq.p));
+        HIPCHK(nce::tree_far<float>(st, v, problem, ctx->d_frames.p, c0, ctx->d_cq.p, nullptr, 4));
+        HIPCHK(nce::tree_near<float>(st, v, problem, ctx->d_frames.p, c0, c0, ctx->d_cq.p, ctx->d_cu.p, nullptr));
+        HIPCHK(nce::tree_interp<float>(st, v, ctx->d_frames.p, c0, ctx->d_cu.p, nullptr, 2, nullptr));
+        HIPCHK(nce::CoarseSolver::finish32(st, (int)N, a, ctx->d_cu.p, y));
+    };
+}
+
 const double* coarse_amplitudes(nce_ctx* ctx) {
     if (ctx->coarse_iters >= 0) return ctx->d_a.p;
     const double chi0 = coarse_chi0(ctx);
     if (!ctx->coarse) {
         ctx->coarse = std::make_unique<nce::CoarseSolver>((int)ctx->N, ctx->tab.problem, chi0, 80);
         if (ctx->ntype > 1) ctx->coarse->set_charges(ctx->stream, coarse_charges(ctx));
+        // the tree's fixed costs (its work items and interpolation blocks are
+        // sized for full skeletons) outweigh the N^2 pair sum below about
+        // N = 2.5e5 (measured at N = 1e5: 8.3 ms per coarse apply through the
+        // tree, 3.8 ms over all pairs); NCE_COARSE_TREE = 1 / 0 forces either
+        const char* ev = std::getenv("NCE_COARSE_TREE");
+        const bool tree = ev ? std::strcmp(ev, "1") == 0 : ctx->N >= 250000;
+        if (tree && ctx->use_tree && ctx->cfg_first.size() == 2) install_coarse_tree(ctx);
     }
     ctx->d_a.alloc((size_t)ctx->N);
     // the deflation's smooth modes are the coarse model's own slow ones: it

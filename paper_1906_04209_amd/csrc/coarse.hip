@@ -131,7 +131,33 @@ __global__ void k_coarse_finish(int N, int nsplit, const double* __restrict__ pa
     y[i] = a[i] + scale * s;
 }
 
+// q_j = chi0_j a_j (FP32)
+__global__ void k_coarse_q32(int N, const double* __restrict__ a, const double* __restrict__ chi, double chi0,
+                             float* __restrict__ q) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) q[j] = (float)((chi ? chi[j] : chi0) * a[j]);
+}
+
+// y_i = a_i + u_i
+__global__ void k_coarse_add32(int N, const double* __restrict__ a, const float* __restrict__ u,
+                               double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) y[i] = a[i] + (double)u[i];
+}
+
 }  // namespace
+
+hipError_t CoarseSolver::charges32(hipStream_t s, int n, const double* a, float* q) const {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_q32, dim3((n + 255) / 256), dim3(256), 0, s, n, a, chi, chi0, q);
+    return hipGetLastError();
+}
+
+hipError_t CoarseSolver::finish32(hipStream_t s, int n, const double* a, const float* u, double* y) {
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse_add32, dim3((n + 255) / 256), dim3(256), 0, s, n, a, u, y);
+    return hipGetLastError();
+}
 
 // source splits for a layout of n centres: enough for >= 2048 blocks, each
 // split at least one tile
@@ -169,6 +195,10 @@ void CoarseSolver::set_charges(hipStream_t s, const std::vector<double>& chi0_pa
 
 void CoarseSolver::apply(hipStream_t s, int n, const double* frames, const double* a, double* y) {
     if (n < 1 || n > N) throw std::runtime_error("coarse apply: layout larger than the solver");
+    if (fast_apply && n == N) {
+        fast_apply(s, a, y);
+        return;
+    }
     const int nsplit = splits_for(n), chunk = (n + nsplit - 1) / nsplit;
     hipLaunchKernelGGL(k_coarse_src, dim3((n + 255) / 256), dim3(256), 0, s, n, frames, a, chi, src);
     const dim3 grid((n + 256 * kTgt - 1) / (256 * kTgt), nsplit);

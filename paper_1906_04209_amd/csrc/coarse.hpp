@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <vector>
 
 #include "deflate.hpp"
@@ -23,6 +24,9 @@ struct CoarseSolver {
     double* scal = nullptr;
     double* tmp = nullptr;   // N doubles: the preconditioned Krylov vector
     double* chi = nullptr;   // per-patch charges chi0_j (N doubles) after set_charges; else chi0 for all
+    // y = C a for the solver's own layout (n = N) by a faster route when set:
+    // the far field through the configuration's tree instead of all pairs
+    std::function<void(hipStream_t, const double*, double*)> fast_apply;
 
     CoarseSolver(int N, int problem, double chi0, int maxit);
     ~CoarseSolver();
@@ -35,6 +39,10 @@ struct CoarseSolver {
     // y = C a for a layout of n <= N centres (device vectors of n doubles);
     // frames: n x 9 device (c, e1, e2)
     void apply(hipStream_t s, int n, const double* frames, const double* a, double* y);
+    // The pieces of a tree apply of C: q = chi0_j a_j in FP32 (the sources'
+    // charges, n values), then y = a + u from the summed field u (n floats).
+    hipError_t charges32(hipStream_t s, int n, const double* a, float* q) const;
+    static hipError_t finish32(hipStream_t s, int n, const double* a, const float* u, double* y);
     // a = C^{-1} 1 to relative residual tol (GMRES); returns the iterations
     // used. With defl (built for this layout, n patches) GMRES runs on
     // C M^{-1} with the deflation's M^{-1} acting on the amplitudes.

@@ -135,6 +135,10 @@ struct nce_ctx {
     nce::Mlp* warm = nullptr;
     std::unique_ptr<nce::CoarseSolver> coarse;
     DevBuf<double> d_a;                 // coarse amplitudes a_i (valid when coarse_iters >= 0)
+    // the coarse model's apply through the tree: one-point tables and one node
+    // per patch (zero offsets, unit sizes), the FP32 charges and summed field
+    DevBuf<int> d_ctab_off, d_ctab_p;
+    DevBuf<float> d_c0, d_cq, d_cu;
     int coarse_iters = -1;
     DevBuf<float> d_feat;
     // coarse-space deflation of the FP32 inner solves (built at the first mixed solve)

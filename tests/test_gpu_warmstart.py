@@ -65,6 +65,41 @@ def test_coarse_solve_satisfies_its_equations(torch):
         assert iters >= 1
 
 
+def test_coarse_solve_through_the_tree(torch):
+    """With the tree (N = 3000; the library takes this route from N = 2.5e5
+    on, NCE_COARSE_TREE = 1 forces it) the coarse model's far field goes
+    through the tree's grids, each patch one point at its centre, instead of
+    all pairs: the closed-form equations are met to the same tolerance, and
+    the amplitudes match the all-pairs solve of the same layout."""
+    import os
+    import paper_1906_04209_amd as nce
+    from oracle import greens
+    N, eps = 3000, 0.005
+    c = layouts.uniform_centers(N, eps, 31)
+    d = np.linalg.norm(c[:, None, :] - c[None, :, :], axis=-1)
+    np.fill_diagonal(d, 1.0)
+    for prob in (nce.INTERIOR, nce.EXTERIOR):
+        os.environ["NCE_COARSE_TREE"] = "1"
+        try:
+            t = nce.Context(c, eps, problem=prob, tol_id=1e-11, tol_coarse=1e-6, far_field=nce.FAR_TREE)
+            a_t, it_t, chi0 = t.coarse(with_chi0=True)
+        finally:
+            os.environ.pop("NCE_COARSE_TREE", None)
+        a_t = a_t.cpu().numpy()
+        t.close()
+        r = nce.Context(c, eps, problem=prob, tol_id=1e-11, tol_coarse=1e-6, far_field=nce.FAR_DIRECT)
+        a_d, it_d = r.coarse()
+        a_d = a_d.cpu().numpy()
+        r.close()
+        G = greens.g_surface(d, prob)
+        np.fill_diagonal(G, 0.0)
+        res = np.linalg.norm(a_t + chi0 * (G @ a_t) - 1.0) / np.sqrt(N)
+        diff = np.max(np.abs(a_t - a_d)) / np.max(np.abs(a_d))
+        print(f"problem {prob}: tree coarse solve {it_t} iterations, residual {res:.2e}; all pairs {it_d} "
+              f"iterations; amplitudes differ by {diff:.2e}")
+        assert res < 1e-5 and diff < 1e-5
+
+
 def test_coarse_start_keeps_result_and_cuts_residual(torch):
     import paper_1906_04209_amd as nce
     c = layouts.uniform_centers(1000, 0.01, 90004)
