@@ -13,6 +13,7 @@
 // most kMaxTableRuns runs of one table per item. Prints "OK <stats>" or the
 // first violation.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <algorithm>
 #include <cstdlib>
@@ -185,7 +186,22 @@ int main(int argc, char** argv) {
         }
     long maxdl = 0;
     for (long i = 0; i < N; ++i) maxdl = std::max(maxdl, (long)(t.dl_ptr[i + 1] - t.dl_ptr[i]));
-    std::printf("OK levels %d grids %d items %zu far %.4g near %.4g interp %.4g maxq %d maxdl %ld split %d\n", t.nlevels,
-                t.ngrid, t.it_grid.size(), t.pairs_far, t.pairs_near, t.interp_fma, t.max_q, maxdl, split);
+    // FNV-1a over every array of the tree and its work counts: the build must
+    // give the same bytes whatever the number of threads
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t k = 0; k < n; ++k) h = (h ^ b[k]) * 1099511628211ull;
+    };
+    auto mixv = [&mix](const auto& v) { mix(v.data(), v.size() * sizeof(v[0])); };
+    mixv(t.g_frame); mixv(t.g_R); mixv(t.g_nr); mixv(t.g_nt); mixv(t.g_level); mixv(t.g_table); mixv(t.g_off);
+    mixv(t.g_item0); mixv(t.g_item1); mixv(t.it_grid); mixv(t.it_src0); mixv(t.it_src1); mixv(t.it_off);
+    mixv(t.p2l_src); mixv(t.p2l_tab); mixv(t.it_win); mixv(t.dl_ptr); mixv(t.dl_src); mixv(t.l2t_ptr);
+    mixv(t.l2t_grid);
+    const double counts[3] = {t.pairs_far, t.pairs_near, t.interp_fma};
+    mix(counts, sizeof(counts));
+    std::printf("OK levels %d grids %d items %zu far %.4g near %.4g interp %.4g maxq %d maxdl %ld split %d hash %016llx\n",
+                t.nlevels, t.ngrid, t.it_grid.size(), t.pairs_far, t.pairs_near, t.interp_fma, t.max_q, maxdl, split,
+                (unsigned long long)h);
     return 0;
 }

@@ -2,6 +2,7 @@
 ordered pair of patches is summed exactly once (near list or one interaction
 list on the target's ancestor path, as in Section 8 Step 3's note), every
 incoming grid covers its members and lies in its sources' far-field regions."""
+import os
 import subprocess
 from pathlib import Path
 
@@ -18,17 +19,21 @@ CSRC = ROOT / "paper_1906_04209_amd" / "csrc"
 def exe(tmp_path_factory):
     d = tmp_path_factory.mktemp("tree")
     out = d / "tree_check"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", str(CSRC), str(ROOT / "tests" / "host" / "tree_check.cpp"),
-                           str(CSRC / "tree_build.cpp"), "-o", str(out)])
+    # with OpenMP, as the library builds it: the boxes of a level are processed in parallel
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-I", str(CSRC),
+                           str(ROOT / "tests" / "host" / "tree_check.cpp"), str(CSRC / "tree_build.cpp"), "-o", str(out)])
     return out
 
 
-def _run(exe, tmp_path, c, eps, tol=1e-8):
+def _run(exe, tmp_path, c, eps, tol=1e-8, threads=None):
     f = tmp_path / "c.txt"
     with open(f, "w") as fh:
         fh.write(f"{len(c)}\n")
         np.savetxt(fh, c, fmt="%.17g")
-    r = subprocess.run([str(exe), str(f), repr(eps), repr(tol)], capture_output=True, text=True)
+    env = dict(os.environ)
+    if threads is not None:
+        env["OMP_NUM_THREADS"] = str(threads)
+    r = subprocess.run([str(exe), str(f), repr(eps), repr(tol)], capture_output=True, text=True, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert r.stdout.startswith("OK"), r.stdout
     return r.stdout
@@ -41,6 +46,17 @@ def test_uniform_coverage(exe, tmp_path, N, eps, seed):
     if N >= 2000:
         # the far-source grids are exercised (boxes with a second, coarser grid)
         assert int(out.split("split ")[1].split()[0]) > 0
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered"])
+def test_build_independent_of_thread_count(exe, tmp_path, kind):
+    """The parallel build (boxes of a level over OpenMP threads, grids numbered
+    afterwards in box order) gives the same tree, byte for byte, on one thread
+    and on eight."""
+    eps = 0.005
+    c = layouts.uniform_centers(2000, eps, 4) if kind == "uniform" else layouts.vmf_centers(1500, eps, 9)
+    hashes = {n: _run(exe, tmp_path, c, eps, threads=n).split("hash ")[1].split()[0] for n in (1, 8)}
+    assert hashes[1] == hashes[8], hashes
 
 
 def test_clustered_coverage(exe, tmp_path):
@@ -65,7 +81,7 @@ def test_cube_corner_and_edges(exe, tmp_path):
 def forest_exe(tmp_path_factory):
     d = tmp_path_factory.mktemp("forest")
     out = d / "forest_check"
-    subprocess.check_call(["g++", "-O2", "-std=c++17", "-I", str(CSRC), str(ROOT / "tests" / "host" / "forest_check.cpp"),
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-I", str(CSRC), str(ROOT / "tests" / "host" / "forest_check.cpp"),
                            str(CSRC / "tree_build.cpp"), "-o", str(out)])
     return out
 
