@@ -36,18 +36,18 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # Issue efficiency (a separate figure): the pair's minimal VALU instruction mix
 # at the grids' precision, priced in lane-cycles at the rates the issue-cost
 # probe measured on gfx950 (FP64 add/mul/fma 1.0, FP64 rsq 4.07, 32-bit ops
-# 0.6, FP32 transcendentals 2.06): FP64 18 FP64 ops (distance 4, first-order
-# rsqrt correction 4, d/2 1, argument 1, logarithm 6: reduction, degree-4
-# series 4, table term, with the binary exponent inside the table's window;
-# accumulation 2) + one rsq + two 32-bit table-index ops = 23.3; FP32 8 32-bit
-# ops + rsq + log2 = 8.9.
-C_PAIR_MIN = {"fp64": 18 * 1.0 + 4.07 + 2 * 0.6, "fp32": 8 * 0.6 + 2 * 2.06}
+# 0.6, FP32 transcendentals 2.06): FP64 16 FP64 ops (squared quarter-distance
+# 4, Newton step of the reciprocal square root 3, d/2 1, argument 1,
+# logarithm 5: reduction, degree-4 series in Horner form 3, table term, with
+# the binary exponent inside the table's window; accumulation 2) + one rsq +
+# two 32-bit table-index ops = 21.3; FP32 8 32-bit ops + rsq + log2 = 8.9.
+C_PAIR_MIN = {"fp64": 16 * 1.0 + 4.07 + 2 * 0.6, "fp32": 8 * 0.6 + 2 * 2.06}
 LANE_CYCLES_PER_S = 256 * 64 * 2.4e9
 # HBM bytes of the P2L step at N = 1e5 (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB, the
 # factors calibrated on a plain 256 MiB copy), measured with rocprofv3 on the
 # current kernels, per thread shape (4 or 8 grid points per thread, 0 = per-item
 # class: two launches over item lists, which read more through L2 misses).
-TRAFFIC = {("cfg5", "fp64", 4): 8.416e9, ("cfg5", "fp64", 8): 8.420e9, ("cfg5", "fp64", 0): 9.137e9,
+TRAFFIC = {("cfg5", "fp64", 4): 8.417e9, ("cfg5", "fp64", 8): 8.418e9, ("cfg5", "fp64", 0): 9.137e9,
            ("cfg5", "fp32", 4): 5.374e9, ("cfg5", "fp32", 8): 5.171e9, ("cfg5", "fp32", 0): 5.396e9}
 # largest relative difference allowed between a mixed or warm-started solve's
 # scalar and the plain FP64 solve's (all solved to a 1e-8 residual)

@@ -234,14 +234,28 @@ __host__ __device__ __forceinline__ int window_octave(int e0, int slot) {
     return e0 + ((slot - e0 - 1023) & (kWinOct - 1));
 }
 
+// The windowed grid form in the argument s = d^2 / 16 (the pair kernel keeps
+// its coordinates quarter-scaled, exact), given an estimate y0 of 1 / sqrt(s)
+// within about 2^-24 relative. One Newton step for 1 / sqrt(s) is
+// y0 (3 - s y0^2) / 2, and 1 / sqrt(s) = 4 / d = 2 w, so W = y0 (3 - p y0)
+// with p = s y0 is 4 w, the first-order corrected w = 2 / d scaled by four,
+// and u = d / 2 = s W / 4 = p (3 - p y0): three operations where the
+// correction of an estimate of w takes four before u. The 1/4 rides on the
+// fma that subtracts the table's t. The logarithm's series is taken in
+// Horner form: log(1 + 2v) = 2v - 2v^2 + (8/3) v^3 - 4 v^4 is
+// -v (v (2 - (8/3) v + 4 v^2) - 2), two fmas and no separate multiply after
+// its quadratic factor. x (u^2 + u, or 1 + w) and so the window are those of
+// the half-distance form.
 template <int PROB>
-__host__ __device__ __forceinline__ double green64_grid_win(double h2, const LogEntry* __restrict__ win) {
-    const double w = rsqrt64_grid(h2);
+__host__ __device__ __forceinline__ double green64_quarter_win(double s, double y0, const LogEntry* __restrict__ win) {
+    const double p = s * y0;
+    const double t = fma(-p, y0, 3.0);
+    const double W = y0 * t;  // 4 w
     double x;
     if (PROB == 1) {
-        x = 1.0 + w;
+        x = fma(W, 0.25, 1.0);
     } else {
-        const double u = h2 * w;
+        const double u = p * t;
         x = fma(u, u, u);
     }
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -253,8 +267,20 @@ __host__ __device__ __forceinline__ double green64_grid_win(double h2, const Log
 #endif
     const LogEntry& L = win[(hi >> (20 - kWinBinBits)) & (kWinTab - 1)];
     const double v = fma(x, L.r, -0.5);
-    const double q = fma(fma(v, 2.0, -4.0 / 3.0), v, 1.0);
-    return fma(-2.0, fma(-v * q, v, v), w - L.t);
+    const double q2 = fma(fma(v, 4.0, -8.0 / 3.0), v, 2.0);
+    return fma(v, fma(v, q2, -2.0), fma(W, 0.25, -L.t));
+}
+
+// The same with the estimate of 1 / sqrt(s) taken here: the hardware's on the
+// device, the exact value on the host.
+template <int PROB>
+__host__ __device__ __forceinline__ double green64_grid_win(double s, const LogEntry* __restrict__ win) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y0 = __builtin_amdgcn_rsq(s);
+#else
+    const double y0 = 1.0 / std::sqrt(s);
+#endif
+    return green64_quarter_win<PROB>(s, y0, win);
 }
 
 // G as a function of d^2 (FP64).

@@ -264,8 +264,8 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                                                const LogEntry* __restrict__ logwin, int win_first,
                                                const int* __restrict__ it_solo, double* __restrict__ coef,
                                                const double* __restrict__ ttab, const int* __restrict__ g_ttab) {
-    // staging (kStage64 points: (-2 a, |a|^2) with a the half-scaled offset
-    // from the cap centre, and the strengths) and, after the sums, the split
+    // staging (kStage64 points: (-2 a, |a|^2) with a the quarter-scaled
+    // offset from the cap centre, and the strengths) and, after the sums, the split
     // partials (ns q <= 256 R); the item's logarithm window, and after the
     // sums the transform's tables
     __shared__ double4 smem4[kStage64 + kStagePad];
@@ -299,11 +299,12 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
         acc[r] = 0.0;
         zx[r] = zy[r] = zz[r] = 0.0;
         if (active && t < q) {
-            // half-scaled offsets from the cap centre, precomputed per tree
+            // quarter-scaled offsets from the cap centre (the tree stores them
+            // half-scaled; the extra factor 1/2 is exact)
             const double* z = gpt + 3 * (g_off[g] + t);
-            zx[r] = z[0];
-            zy[r] = z[1];
-            zz[r] = z[2];
+            zx[r] = 0.5 * z[0];
+            zy[r] = 0.5 * z[1];
+            zz[r] = 0.5 * z[2];
         }
         z2[r] = zx[r] * zx[r] + zy[r] * zy[r] + zz[r] * zz[r];
     }
@@ -318,9 +319,9 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                 const int j = src[sidx];
                 const double* fj = frames + 9 * (int64_t)j;
                 const double* o = skel_off + 3 * (int64_t)oidx;
-                ax = 0.5 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
-                ay = 0.5 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
-                az = 0.5 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
+                ax = 0.25 * ((fj[0] - fg[0]) + (o[0] * fj[0] + o[1] * fj[3] + o[2] * fj[6]));
+                ay = 0.25 * ((fj[1] - fg[1]) + (o[0] * fj[1] + o[1] * fj[4] + o[2] * fj[7]));
+                az = 0.25 * ((fj[2] - fg[2]) + (o[0] * fj[2] + o[1] * fj[5] + o[2] * fj[8]));
                 w = rho[(int64_t)j * ptot + cidx];
             }
             // |z - a|^2 = |z|^2 + |a|^2 - 2 z.a: grid points lie within the cap
@@ -343,8 +344,9 @@ __global__ __launch_bounds__(256) void k_p2l64(const int* __restrict__ it_grid, 
                 const double w = *w_ptr;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const double h2 = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
-                    acc[r] = fma(green64_grid_win<PROB>(h2, ltab), w, acc[r]);
+                    // s = d^2 / 16
+                    const double s = fma(zx[r], a.x, fma(zy[r], a.y, fma(zz[r], a.z, a.w))) + z2[r];
+                    acc[r] = fma(green64_grid_win<PROB>(s, ltab), w, acc[r]);
                 }
             }
         }

@@ -77,9 +77,19 @@ int main() {
             std::memcpy(&bits, &x, sizeof bits);
             const int slot = (int)((bits >> 52) & (nce::kWinOct - 1));
             if (nce::window_octave(e0, slot) != ex - 1) ++bad_slot;
-            const double vg = prob ? nce::green64_grid_win<1>(hh, win) : nce::green64_grid_win<0>(hh, win);
+            // the kernel's argument is s = d^2 / 16; its estimate of 1 / sqrt(s)
+            // exact (the host build) and off by the largest error measured
+            // for the gfx950 FP64 rsq (2^-24.2), either sign
+            const double sq = 0.0625 * d * d;
+            const double vg = prob ? nce::green64_grid_win<1>(sq, win) : nce::green64_grid_win<0>(sq, win);
             const long double ref = prob ? ge : gi;
             worst_win = std::max(worst_win, (double)(std::fabs(vg - ref) / std::max(std::fabs(ref), 1.0L)));
+            const long double rs = 1.0L / std::sqrt((long double)sq);
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double y0 = (double)(rs * (1.0L + sgn * 5.2e-8L));
+                const double vq = prob ? nce::green64_quarter_win<1>(sq, y0, win) : nce::green64_quarter_win<0>(sq, y0, win);
+                worst_win = std::max(worst_win, (double)(std::fabs(vq - ref) / std::max(std::fabs(ref), 1.0L)));
+            }
         }
         // first-order correction of an estimate at the largest error measured
         // for the gfx950 FP64 rsq (2^-24.2), either sign: about 1.5 d^2
