@@ -239,7 +239,7 @@ __host__ __device__ __forceinline__ int window_octave(int e0, int slot) {
 // within about 2^-24 relative. One Newton step for 1 / sqrt(s) is
 // y0 (3 - s y0^2) / 2, and 1 / sqrt(s) = 4 / d = 2 w, so W = y0 (3 - p y0)
 // with p = s y0 is 4 w, the first-order corrected w = 2 / d scaled by four,
-// and u = d / 2 = s W / 4 = p (3 - p y0): three operations where the
+// and u = d / 2 = s W = p (3 - p y0): three operations where the
 // correction of an estimate of w takes four before u. The 1/4 rides on the
 // fma that subtracts the table's t. The logarithm's series is taken in
 // Horner form: log(1 + 2v) = 2v - 2v^2 + (8/3) v^3 - 4 v^4 is
